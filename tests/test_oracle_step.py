@@ -1,0 +1,125 @@
+"""Pins of the oracle's drift-kick-drift step (Sect. 3), the epicycle drift
+(Sect. 3.3) and the boundaries (Sect. 2.3) against closed forms, an
+independent ODE integration and conservation laws."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1110_4876_amd import inputs
+
+
+def _hill_rk4(state, omega, omega_z, T, nsub=4000):
+    """Hill's equations without perturbation, by classical RK4."""
+    y = np.array(state, dtype=np.float64)
+
+    def f(u):
+        x, yy, z, vx, vy, vz = u
+        return np.array([vx, vy, vz, 2 * omega * vy + 3 * omega ** 2 * x,
+                         -2 * omega * vx, -omega_z ** 2 * z])
+    h = T / nsub
+    for _ in range(nsub):
+        k1 = f(y); k2 = f(y + 0.5 * h * k1); k3 = f(y + 0.5 * h * k2); k4 = f(y + h * k3)
+        y = y + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+    return y
+
+
+def test_epicycle_drift_matches_rk4(orc):
+    om, omz = 1.3, 1.7
+    p = orc.make_params(drift=orc.EPICYCLE, omega=om, omega_z=omz, boundary=orc.OPEN,
+                        W=100.0, x0=(-50, -50, -50))
+    st0 = dict(x=[0.3], y=[-0.2], z=[0.05], vx=[0.1], vy=[-0.7], vz=[0.02])
+    tau = 0.9
+    got = orc.drift(p, st0, tau)
+    ref = _hill_rk4([0.3, -0.2, 0.05, 0.1, -0.7, 0.02], om, omz, tau)
+    for k, name in enumerate(("x", "y", "z", "vx", "vy", "vz")):
+        assert abs(got[name][0] - ref[k]) < 1e-12
+
+
+def test_epicycle_period(orc):
+    om = 0.8
+    p = orc.make_params(drift=orc.EPICYCLE, omega=om, omega_z=om, W=100.0,
+                        x0=(-50, -50, -50))
+    # guiding centre at rest (C = 0): a pure epicycle closes after 2 pi / Omega
+    st0 = dict(x=[0.4], y=[0.0], z=[0.1], vx=[0.0], vy=[-2 * om * 0.4], vz=[0.0])
+    got = orc.drift(p, st0, 2 * math.pi / om)
+    for name in ("x", "y", "z", "vx", "vy", "vz"):
+        assert abs(got[name][0] - st0[name][0]) < 1e-12
+
+
+def test_shear_flow_is_stationary(orc):
+    pr = inputs.sheet(200, seed=0)
+    om = pr.params["omega"]
+    p = orc.make_params(**dict(pr.params, G=0.0))
+    st = dict(x=pr.x, y=pr.y, z=np.zeros(pr.n), vx=np.zeros(pr.n), vy=-1.5 * om * pr.x,
+              vz=np.zeros(pr.n))
+    dt = pr.dt
+    out = orc.drift(p, st, dt)
+    np.testing.assert_allclose(out["x"], st["x"], rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(out["y"], st["y"] - 1.5 * om * pr.x * dt, rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(out["vy"], st["vy"], rtol=1e-12, atol=1e-15)
+
+
+def test_leapfrog_energy_error_is_second_order(orc):
+    pr = inputs.plummer(1024, seed=0, b=0.05)
+    p = orc.make_params(**pr.params)
+    e0 = orc.energy(p, pr.state(), pr.m)
+    errs = []
+    for dt in (4e-3, 2e-3, 1e-3):
+        # T = 0.5: a time short against the crossing time keeps close
+        # encounters rare, so the error is the smooth O(dt^2) term
+        st = orc.step(p, pr.state(), pr.m, 0.0, dt, int(round(0.5 / dt)), use_tree=False)
+        errs.append(abs(orc.energy(p, st, pr.m) - e0))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.0 < r1 < 5.0 and 3.0 < r2 < 5.0, (errs, r1, r2)
+
+
+def test_leapfrog_is_time_reversible(orc):
+    pr = inputs.plummer(256, seed=1, b=0.05)
+    p = orc.make_params(**pr.params)
+    fwd = orc.step(p, pr.state(), pr.m, 0.0, 1e-3, 50, use_tree=True)
+    back = orc.step(p, fwd, pr.m, 0.05, -1e-3, 50, use_tree=True)
+    for k in ("x", "y", "z"):
+        np.testing.assert_allclose(back[k], getattr(pr, k), rtol=0, atol=1e-12)
+
+
+def test_single_step_dkd_sequence(orc):
+    # one DKD step equals drift(dt/2), kick with the forces at the drifted
+    # positions, drift(dt/2)
+    pr = inputs.plummer(300, seed=2, b=0.02)
+    p = orc.make_params(**pr.params)
+    dt = pr.dt
+    st = orc.step(p, pr.state(), pr.m, 0.0, dt, 1, use_tree=False)
+    half = {k: getattr(pr, k) + getattr(pr, "v" + k) * dt / 2 for k in ("x", "y", "z")}
+    a = orc.direct(p, half["x"], half["y"], half["z"], pr.m)
+    v = {k: getattr(pr, "v" + k) + a[:, i] * dt for i, k in enumerate(("x", "y", "z"))}
+    for k in ("x", "y", "z"):
+        np.testing.assert_allclose(st[k], half[k] + v[k] * dt / 2, rtol=1e-15, atol=1e-15)
+        np.testing.assert_allclose(st["v" + k], v[k], rtol=1e-15, atol=1e-18)
+
+
+def test_shear_wrap_keeps_guiding_centre_velocity(orc):
+    # crossing the x face keeps vy + 1.5 Omega x unchanged and shifts y by
+    # the box offset (box large enough that y needs no second wrap)
+    pr = inputs.sheet(5000, seed=0)
+    W, om = pr.params["W"], pr.params["omega"]
+    p = orc.make_params(**pr.params)
+    st = dict(x=np.array([0.5 * W + 1.0, -0.5 * W - 2.0]), y=np.array([10.0, -20.0]),
+              z=np.array([0.0, 0.0]), vx=np.array([0.1, -0.1]),
+              vy=np.array([-1.5 * om * (0.5 * W + 1.0), -1.5 * om * (-0.5 * W - 2.0)]),
+              vz=np.array([0.0, 0.0]))
+    s = 0.3 * W
+    out = orc.boundary(p, st, s)
+    np.testing.assert_allclose(out["x"], [-0.5 * W + 1.0, 0.5 * W - 2.0], rtol=1e-14)
+    np.testing.assert_allclose(out["y"], [10.0 + s, -20.0 - s], rtol=1e-14)
+    np.testing.assert_allclose(out["vy"] + 1.5 * om * out["x"], st["vy"] + 1.5 * om * st["x"],
+                               rtol=1e-12, atol=1e-15)
+
+
+def test_open_boundary_removes_leaving_particles(orc):
+    p = orc.make_params(W=2.0, x0=(-1, -1, -1), boundary=orc.OPEN)
+    st = dict(x=np.array([0.9, 0.0]), y=np.zeros(2), z=np.zeros(2), vx=np.array([1.0, 0.0]),
+              vy=np.zeros(2), vz=np.zeros(2))
+    out = orc.step(p, st, np.array([1e-9, 1e-9]), 0.0, 0.2, 1, use_tree=True)
+    assert np.isnan(out["x"][0]) and out["vx"][0] == 0.0
+    assert np.isfinite(out["x"][1])
