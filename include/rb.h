@@ -1,0 +1,256 @@
+/*
+ * rb.h -- C ABI of librb: Barnes-Hut tree self-gravity on one AMD Instinct
+ * MI355X (gfx950), the hot path of the method of Rein & Liu (2012), REBOUND.
+ *
+ * Conventions for every entry point
+ *  - Particle arrays are DEVICE pointers to FP64 structure-of-arrays data in
+ *    the caller's order; the caller owns them (typically torch tensors).
+ *  - Output arrays (accelerations) are device pointers the caller owns.
+ *  - A context owns all GPU workspace: keys, permutations, nodes, moments,
+ *    interaction lists, schedules.  It is bound to one device and one HIP
+ *    stream given at creation; every call is asynchronous on that stream
+ *    unless its comment says it synchronises.
+ *  - Return value: RB_OK (0) or a negative RB_E* code.  rb_last_error()
+ *    returns a thread-local text with details of the last failure.  Faults
+ *    detected inside kernels (capacity overflow, a particle outside a
+ *    periodic box) raise a device error word that is reported by the next
+ *    synchronising call (rb_sync, rb_tree_info, rb_tree_export,
+ *    rb_state_save, rb_stats), like HIP's own deferred errors.
+ *  - Removed particles: a particle that leaves the root box through an open
+ *    face is removed from the simulation (Sect. 2.3).  It becomes a
+ *    tombstone: NaN position, zero velocity.  Tombstones (any particle with
+ *    a NaN coordinate) are excluded from the tree, feel no force and exert
+ *    none; n is never compacted.
+ */
+#ifndef RB_H
+#define RB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RB_OK 0
+#define RB_EINVAL (-1)        /* bad parameter, null pointer, size out of range */
+#define RB_ENOMEM (-2)        /* device or host allocation failed */
+#define RB_EHIP (-3)          /* HIP runtime error */
+#define RB_ECAPACITY (-4)     /* node, list or particle capacity exceeded */
+#define RB_EOUTSIDE (-5)      /* particle outside a periodic / shear box axis */
+#define RB_EUNSUPPORTED (-6)  /* valid request this library does not implement */
+#define RB_EIO (-7)           /* state file could not be read or written */
+
+typedef enum { RB_OPEN = 0, RB_PERIODIC = 1, RB_SHEAR = 2 } rb_boundary;
+typedef enum { RB_FP64 = 0, RB_FP32_MIXED = 1 } rb_precision;
+typedef enum { RB_DRIFT_LEAPFROG = 0, RB_DRIFT_EPICYCLE = 1 } rb_drift;
+
+/*
+ * Physical and numerical parameters (Sect. 2.3, 3, 4 of the paper).
+ *  G, softening     Eq. (1): G and the Plummer softening b (b >= 0).
+ *  theta            critical opening angle of Sect. 4.2: a cell of width w
+ *                   at distance R from its centre of mass is used as a whole
+ *                   when w^2 < theta^2 R^2.  theta = 0 gives direct
+ *                   summation through the tree.
+ *  quadrupole       0: mass and centre of mass only; 1: add the cell
+ *                   quadrupole (Hernquist 1987), as the paper's QUADRUPOLE
+ *                   switch.
+ *  leaf_size        most particles a leaf above the deepest level holds
+ *                   (paper: 1).  1..32.
+ *  group_size       FP32-mixed walk only: particles that share one
+ *                   interaction list (16, 32 or 64).
+ *  boundary         RB_OPEN: particles leaving the root box are removed.
+ *                   RB_PERIODIC: x and y wrap, z is open.
+ *                   RB_SHEAR: shear-periodic in x, periodic in y, z open;
+ *                   requires box_min[0] = -box_size / 2.
+ *  drift            RB_DRIFT_LEAPFROG: x += v tau (Sect. 3.1).
+ *                   RB_DRIFT_EPICYCLE: exact solution of Hill's equations
+ *                   without the perturbing force (Sect. 3.3).
+ *  precision        RB_FP64: per-particle FP64 walk, identical opening
+ *                   decisions to a plain FP64 Barnes-Hut walk.
+ *                   RB_FP32_MIXED: grouped walk, FP32 interaction
+ *                   arithmetic on node-relative coordinates, FP64
+ *                   positions, velocities, drift, ghost offsets and sums.
+ *  box_size, box_min  the cubic root box [box_min, box_min + box_size)^3
+ *                   (Sect. 2.3); one root box per system.
+ *  n_ghost          ghost-box rings in x and y (periodic / shear only,
+ *                   0..2); images are (ix W, iy W - ix s, 0), ix and iy in
+ *                   [-n_ghost, n_ghost], s the shear offset.
+ *  omega, omega_z   orbital and vertical epicyclic frequency.
+ *  node_factor      node capacity per particle (>= 1.5; 0 selects 3).
+ *  split_images     1: one walk work item per (group, image) pair, 0: one
+ *                   per group, -1: choose by size.
+ *  profile          1: record per-phase times and walk interaction counts
+ *                   (rb_stats); costs extra events and atomics.
+ *  use_graph        1: rb_step / rb_batch_step replay a captured HIP graph
+ *                   of one step.
+ */
+typedef struct {
+  double G;
+  double softening;
+  double theta;
+  int32_t quadrupole;
+  int32_t leaf_size;
+  int32_t group_size;
+  int32_t boundary;
+  int32_t drift;
+  int32_t precision;
+  double box_size;
+  double box_min[3];
+  int32_t n_ghost[2];
+  double omega;
+  double omega_z;
+  double node_factor;
+  int32_t split_images;
+  int32_t profile;
+  int32_t use_graph;
+  int32_t reserved[5];
+} rb_params;
+
+/* Device SoA of the particles, caller order, all FP64. */
+typedef struct {
+  double *x, *y, *z;
+  double *vx, *vy, *vz;
+  double *m;
+} rb_particles;
+
+/* Host buffers for rb_tree_export; each array holds n_nodes (node arrays)
+ * or n_live (keys, perm) entries, sizes from rb_tree_info.  Any pointer may
+ * be NULL to skip that field. */
+typedef struct {
+  uint64_t *keys;      /* sorted Morton keys of the live particles */
+  int64_t *perm;       /* Morton rank -> caller index */
+  int8_t *level;       /* node level, root = 0 */
+  uint64_t *prefix;    /* key >> 3 (21 - level) */
+  int64_t *first;      /* Morton rank of the node's first particle */
+  int64_t *count;      /* particles in the node */
+  int8_t *is_leaf;
+  int32_t *n_child;
+  int64_t *first_child;/* node index of the first child, -1 for leaves */
+  int64_t *skip;       /* next node after the subtree in depth-first order, -1 at the end */
+  double *M;           /* source mass */
+  double *com;         /* 3 per node: centre of mass */
+  double *Q;           /* 6 per node: xx xy xz yy yz zz traceless quadrupole */
+} rb_tree_host;
+
+/* Opaque context: owns the GPU workspace of one system or one batch. */
+typedef struct rb_ctx rb_ctx;
+
+/* Per-call interaction counts of the last walk (profile = 1). */
+typedef struct {
+  int64_t open_tests;   /* opening-criterion evaluations */
+  int64_t cells;        /* accepted multi-particle cells */
+  int64_t pp;           /* particle-particle terms */
+  int64_t list_cells;   /* FP32-mixed: cell entries evaluated (all lanes) */
+  int64_t list_pp;      /* FP32-mixed: particle entries evaluated */
+  double ms[16];        /* phase times in ms (see rb_phase_name) */
+} rb_stats_t;
+
+/* Defaults: theta 0.5, leaf 1, group 64, open box [-64, 64)^3, monopole. */
+void rb_params_default(rb_params *p);
+
+/*
+ * Create a context for one system of up to `capacity` particles on the
+ * current HIP device, issuing work on `hip_stream` (a hipStream_t; NULL =
+ * the null stream).  Allocates all workspace (about 0.6 kB per particle).
+ * Errors: RB_EINVAL for invalid parameters (see rb_params), RB_ENOMEM,
+ * RB_EUNSUPPORTED (n_ghost > 2).
+ */
+int rb_create(rb_ctx **ctx, const rb_params *p, int64_t capacity, void *hip_stream);
+
+/*
+ * Create a context for a batch of independent systems (shearing-sheet
+ * patches; Sect. 2.3 builds one tree per root box).  Patch k owns the
+ * caller slots [offsets[k], offsets[k+1]) of every particle array; its root
+ * box is box_size[k], box_min[3k..3k+2]; all other parameters are shared.
+ * offsets, box_size and box_min are HOST arrays copied at creation.
+ */
+int rb_batch_create(rb_ctx **ctx, const rb_params *p, int32_t n_patch,
+                    const int64_t *offsets, const double *box_size,
+                    const double *box_min, void *hip_stream);
+
+int rb_destroy(rb_ctx *ctx);
+
+/* Replace theta, quadrupole, precision, leaf_size, group_size, split_images,
+ * softening, G and profile of an existing context (box and boundary fixed). */
+int rb_set_params(rb_ctx *ctx, const rb_params *p);
+
+/*
+ * Build the octree of Sect. 4.2 for the n caller particles: Morton keys of
+ * the quantised positions q = floor((x - box_min) 2^21 / box_size), stable
+ * radix sort, canonical level-ordered topology, bottom-up mass, centre of
+ * mass and quadrupole.  Particles with index >= n_active are massless test
+ * particles (Sect. 4).  For a batch context n_active is ignored and all
+ * particles are massive.  Errors: RB_EINVAL (null, n > capacity or, for a
+ * batch, n != total), deferred RB_ECAPACITY / RB_EOUTSIDE.
+ */
+int rb_tree_build(rb_ctx *ctx, const rb_particles *p, int64_t n, int64_t n_active);
+
+/* Synchronise; report the node and live-particle counts of the last tree
+ * (for a batch: totals). */
+int rb_tree_info(rb_ctx *ctx, int64_t *n_nodes, int64_t *n_live);
+
+/* Synchronise and copy the last tree to host buffers (single system or
+ * patch `patch` of a batch; node indices are patch-local). */
+int rb_tree_export(rb_ctx *ctx, int32_t patch, rb_tree_host *out);
+
+/*
+ * Accelerations of Eq. (1) approximated by the tree walk of Sect. 4.2, with
+ * the ghost images of Sect. 2.3 at time t (shear offset
+ * remainder(1.5 omega W t, W)).  Builds the tree first.  ax, ay, az are
+ * device arrays of n entries in caller order.  FP64 precision reproduces
+ * the opening decisions of a plain per-particle walk; FP32-mixed uses the
+ * grouped walk.  n_active as in rb_tree_build.
+ */
+int rb_gravity(rb_ctx *ctx, const rb_particles *p, int64_t n, int64_t n_active,
+               double t, double *ax, double *ay, double *az);
+
+/*
+ * Eq. (1) by direct summation (Sect. 4.1) for n_targets caller indices
+ * `targets` (device int64), over all n sources and ghost images at time t.
+ * FP64.  Outputs a*[k] for target k (device arrays of n_targets).
+ */
+int rb_direct(rb_ctx *ctx, const rb_particles *p, int64_t n, int64_t n_active,
+              double t, const int64_t *targets, int64_t n_targets, double *ax,
+              double *ay, double *az);
+
+/*
+ * nsteps drift-kick-drift steps of Sect. 3 from time t with step dt: drift
+ * dt/2 (leap-frog or epicycle), boundaries, tree gravity at t + dt/2, kick
+ * v += a dt, drift dt/2, boundaries.  Updates x, y, z, vx, vy, vz in place,
+ * keeping the caller's order; m is read only.
+ */
+int rb_step(rb_ctx *ctx, rb_particles *p, int64_t n, int64_t n_active, double t,
+            double dt, int32_t nsteps);
+
+/* Batch forms: every patch steps / gets forces independently, one launch
+ * per kernel for all patches (work items ordered by patch cost). */
+int rb_batch_step(rb_ctx *ctx, rb_particles *p, double t, double dt, int32_t nsteps);
+int rb_batch_gravity(rb_ctx *ctx, const rb_particles *p, double t, double *ax,
+                     double *ay, double *az);
+
+/* Synchronise the context's stream and return any deferred device error. */
+int rb_sync(rb_ctx *ctx);
+
+/* Synchronise and return counts and phase times of the last call
+ * (profile = 1; zeros otherwise). */
+int rb_stats(rb_ctx *ctx, rb_stats_t *out);
+const char *rb_phase_name(int32_t phase);
+
+/*
+ * Checkpoint: write n particles (device SoA) plus t and the parameters to a
+ * binary file / read them back.  rb_state_load fills caller device arrays
+ * and *t; it fails with RB_EIO on a missing, short or foreign file and with
+ * RB_EINVAL if n differs.  Both synchronise.
+ */
+int rb_state_save(rb_ctx *ctx, const rb_particles *p, int64_t n, double t,
+                  const char *path);
+int rb_state_load(rb_ctx *ctx, rb_particles *p, int64_t n, double *t,
+                  const char *path);
+
+const char *rb_error_string(int code);
+const char *rb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

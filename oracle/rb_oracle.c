@@ -581,6 +581,7 @@ void orc_drift(const orc_params *p, int64_t n, double *x, double *y, double *z,
                double *vx, double *vy, double *vz, double tau) {
   if (p->drift == ORC_LEAPFROG) {
     for (int64_t i = 0; i < n; ++i) {
+      if (!(isfinite(x[i]) && isfinite(y[i]) && isfinite(z[i]))) continue; /* removed */
       x[i] = x[i] + vx[i] * tau;
       y[i] = y[i] + vy[i] * tau;
       z[i] = z[i] + vz[i] * tau;
@@ -591,6 +592,7 @@ void orc_drift(const orc_params *p, int64_t n, double *x, double *y, double *z,
   double c = cos(W * tau), sn = sin(W * tau);
   double cz = cos(Wz * tau), sz = sin(Wz * tau);
   for (int64_t i = 0; i < n; ++i) {
+    if (!(isfinite(x[i]) && isfinite(y[i]) && isfinite(z[i]))) continue; /* removed */
     double C = vy[i] + 2.0 * W * x[i];
     double xg = 2.0 * C / W;
     double dx = x[i] - xg;

@@ -1,0 +1,125 @@
+// rb_internal.h -- host-side context of librb and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/rb.h"
+#include "rb_common.h"
+
+// Walk work item: a run of consecutive sorted slots of one patch.
+struct WalkItem {
+  uint32_t start, end;  // slot range [start, end)
+  uint32_t patch;
+  uint32_t pad;
+};
+
+struct rb_ctx {
+  rb_params p;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool batch = false;
+  uint32_t P = 1;            // patches
+  uint64_t cap = 0;          // slots
+  uint64_t node_cap = 0;
+  int n_img = 1;             // ghost images
+  int img_split = 0;         // items per image (1) or all images per item (0)
+
+  // host mirrors
+  std::vector<uint32_t> h_starts;  // P + 1
+  std::vector<PatchInfo> h_patch;
+  std::vector<uint32_t> h_tile_start, h_tile_end, h_tile_patch, h_patch_tile0;
+
+  // patches and tiles (device)
+  PatchInfo *d_patch = nullptr;
+  uint32_t *d_starts = nullptr;   // P + 1
+  uint32_t *d_nlive = nullptr;    // P
+  uint32_t *d_root = nullptr;     // P
+  uint32_t n_tiles = 0, max_tiles_per_patch = 0;
+  uint32_t *d_tile_start = nullptr, *d_tile_end = nullptr, *d_tile_patch = nullptr;
+  uint32_t *d_patch_tile0 = nullptr;  // P + 1
+
+  // sort
+  uint64_t *d_key[2] = {nullptr, nullptr};
+  uint32_t *d_idx[2] = {nullptr, nullptr};
+  uint32_t *d_hist = nullptr;       // 256 * n_tiles
+  uint32_t *d_digit_tot = nullptr;  // 256 * P
+
+  // particles in sorted order (ping-pong for rb_step)
+  double *d_px[2][7] = {};          // x y z vx vy vz m
+  uint32_t *d_orig[2] = {nullptr, nullptr};
+  double *d_msrc = nullptr;         // source mass of sorted slots
+  int cur = 0;                      // buffer holding the sorted state
+
+  // topology
+  uint8_t *d_lcp = nullptr, *d_leaf = nullptr;
+  uint32_t *d_cnt = nullptr;        // 2 * 22 * n_tiles (starts, ends)
+  uint32_t *d_lev_tot = nullptr;    // 2 * 22
+  uint32_t *d_lev_off = nullptr;    // 23 (+1: node total)
+  uint32_t *d_nfirst = nullptr, *d_nlast = nullptr, *d_nchild = nullptr,
+           *d_nlastchild = nullptr, *d_nskip = nullptr;
+  uint8_t *d_nlevel = nullptr, *d_nleaf = nullptr;
+
+  // moments
+  NodeLink *d_link = nullptr;
+  double4 *d_mcom = nullptr;  // com.x com.y com.z M
+  double *d_S = nullptr;      // 3 per node
+  double *d_Q = nullptr;      // 6 per node
+
+  // walk
+  std::vector<WalkItem> h_items64, h_itemsg;
+  WalkItem *d_items64 = nullptr, *d_itemsg = nullptr;
+  int itemsg_size = 0;
+  double *d_acc = nullptr;    // (n_img or 1) * 3 * cap
+  float *d_accf = nullptr;
+
+  // per-call dynamic region [ctr | StepConst | schedule], uploaded from a
+  // pinned staging copy; schedule per step: s_half[P], s_end[P]
+  char *d_dyn = nullptr, *h_dyn = nullptr;
+  size_t dyn_bytes = 0;
+  hipEvent_t dyn_ev = nullptr;
+  StepConst *d_sc = nullptr;
+  double *d_sched = nullptr;
+  uint32_t sched_cap = 0;
+  uint32_t *d_ctr = nullptr;  // [step k, steps in this call]
+
+  uint32_t *d_err = nullptr;
+  unsigned long long *d_stats = nullptr;  // 8 counters
+
+  // profiling
+  hipEvent_t ev[16] = {};
+  int ev_used = 0;
+  float phase_ms[16] = {};
+
+  // graph of one step
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int graph_key = -1;
+
+  std::vector<void *> allocs;
+};
+
+// ---- launchers (each returns hipSuccess or the launch error) ----
+hipError_t launch_keys(rb_ctx *c, const double *x, const double *y, const double *z,
+                       double s_unused);
+hipError_t launch_sort(rb_ctx *c);
+hipError_t launch_permute_gravity(rb_ctx *c, const double *x, const double *y,
+                                  const double *z, const double *m, uint32_t n_active_single);
+hipError_t launch_permute_state(rb_ctx *c, int src, int dst);
+hipError_t launch_topology(rb_ctx *c);
+hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const double *sz);
+hipError_t launch_walk64(rb_ctx *c, const double *sx, const double *sy, const double *sz,
+                         const double *s_img);
+hipError_t launch_walk32(rb_ctx *c, const double *sx, const double *sy, const double *sz,
+                         const double *s_img);
+hipError_t launch_scatter_acc(rb_ctx *c, double *ax, double *ay, double *az);
+hipError_t launch_prologue(rb_ctx *c, const rb_particles *cp);
+hipError_t launch_post(rb_ctx *c, int buf);
+hipError_t launch_epilogue(rb_ctx *c, rb_particles *cp, int buf);
+hipError_t launch_advance(rb_ctx *c);
+hipError_t launch_direct(rb_ctx *c, const rb_particles *cp, uint32_t n, uint32_t n_active,
+                         const double *s_img, const int64_t *targets, uint32_t nt,
+                         double *ax, double *ay, double *az);
