@@ -79,8 +79,10 @@ typedef enum { RB_DRIFT_LEAPFROG = 0, RB_DRIFT_EPICYCLE = 1 } rb_drift;
  *  node_factor      node capacity per particle (>= 1.5; 0 selects 3).
  *  split_images     1: one walk work item per (group, image) pair, 0: one
  *                   per group, -1: choose by size.
- *  profile          1: record per-phase times and walk interaction counts
- *                   (rb_stats); costs extra events and atomics.
+ *  profile          bit 0: record per-phase times with HIP events on the
+ *                   context's stream; bit 1: count walk interactions
+ *                   (atomics in the walk); bit 2: time the walk kernel
+ *                   only.  All are read by rb_stats.
  *  use_graph        1: rb_step / rb_batch_step replay a captured HIP graph
  *                   of one step.
  */
@@ -143,6 +145,7 @@ typedef struct {
   int64_t list_cells;   /* FP32-mixed: cell entries evaluated (all lanes) */
   int64_t list_pp;      /* FP32-mixed: particle entries evaluated */
   double ms[16];        /* phase times in ms (see rb_phase_name) */
+  int64_t calls[16];    /* timed intervals per phase (e.g. walk launches) */
 } rb_stats_t;
 
 /* Defaults: theta 0.5, leaf 1, group 64, open box [-64, 64)^3, monopole. */

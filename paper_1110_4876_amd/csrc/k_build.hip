@@ -389,12 +389,15 @@ __global__ __launch_bounds__(256) void k_topo_write(
     uint32_t *__restrict__ nlast, uint32_t *__restrict__ nchild,
     uint32_t *__restrict__ nlastchild, uint32_t *__restrict__ nskip,
     uint8_t *__restrict__ nlevel, uint8_t *__restrict__ nleaf, uint32_t *__restrict__ root,
-    uint32_t *__restrict__ err) {
+    uint32_t *__restrict__ err, uint32_t *__restrict__ gctr) {
   __shared__ uint32_t lbase[RB_NLEV + 1];
   __shared__ uint32_t bs_off[RB_NLEV], be_off[RB_NLEV];
   __shared__ uint32_t run_s[RB_NLEV], run_e[RB_NLEV];
   __shared__ uint32_t ws[4][RB_NLEV], we[4][RB_NLEV];
   const uint32_t b = blockIdx.x, tid = threadIdx.x, w = tid >> 6;
+  // the grouped walk's counters (groups emitted, work items taken) restart
+  // with every tree, also when this tree fails its capacity check
+  if (b == 0 && tid < 2) gctr[tid] = 0;
   if (tid == 0) {
     uint32_t acc = 0;
     for (int l = 0; l < RB_NLEV; ++l) { lbase[l] = acc; acc += lev_tot[l]; }
@@ -511,7 +514,7 @@ hipError_t launch_topology(rb_ctx *c) {
                      c->P, c->d_lcp, c->d_leaf, c->n_tiles, c->d_cnt, c->d_lev_tot,
                      (uint32_t)c->node_cap, c->d_lev_off, c->d_nfirst, c->d_nlast,
                      c->d_nchild, c->d_nlastchild, c->d_nskip, c->d_nlevel, c->d_nleaf,
-                     c->d_root, c->d_err);
+                     c->d_root, c->d_err, c->d_gctr);
   return hipGetLastError();
 }
 
@@ -627,7 +630,8 @@ __global__ __launch_bounds__(256) void k_moments(
     lk.child_or_first = cf;
     lk.skip = nskip[id];
     lk.count = count;
-    lk.lvl = (uint32_t)level | (is_leaf ? 256u : 0u);
+    const uint32_t n_child = is_leaf ? 0u : nlastchild[id] - nchild[id] + 1u;
+    lk.lvl = (uint32_t)level | (is_leaf ? 256u : 0u) | (n_child << 9);
     link[id] = lk;
     mcom[id] = make_double4(c0, c1, c2, M);
     Sarr[3 * (size_t)id + 0] = S0;

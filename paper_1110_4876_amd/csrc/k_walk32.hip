@@ -1,7 +1,405 @@
-// k_walk32.hip -- grouped FP32-mixed tree walk (placeholder until written).
+// k_walk32.hip -- grouped FP32-mixed tree walk (a variant of the walk of
+// Sect. 4.2 of the paper).
+//
+// Groups are the maximal tree nodes holding at most G particles (G =
+// group_size), so each group is spatially compact; together they partition
+// the particles.  One wave serves one (group, image) work item, pulled from
+// a device queue by a persistent grid; 64 / 2^ceil(log2 n) lanes share each
+// of the group's n particles.  The wave walks the tree once for the whole
+// group: a node is accepted for every member at once when
+// w^2 < theta^2 R_min^2, R_min being the distance from the node's
+// image-shifted centre of mass to the group's bounding box -- no member is
+// closer, so every member would accept the node on its own.  Accepted cells
+// and the particles of single-particle or opened leaves go to LDS
+// interaction lists (ballot / mbcnt compaction), evaluated by all lanes
+// reading the same entry (LDS broadcast).
+//
+// Precision: traversal, opening test, image offsets and group-relative
+// positions are FP64.  List entries hold FP32 positions relative to the
+// group centre in units of the root-box side W, G M / W^2 and G Q / W^4, so
+// FP32 sees O(1) magnitudes.  Each list flush sums its terms in FP32 and
+// adds the block sum to an FP64 accumulator.
 #include "rb_internal.h"
 
-hipError_t launch_walk32(rb_ctx *, const double *, const double *, const double *,
+#define W32_SCAP 1024  // traversal stack entries per wave (node << 5 | image)
+#define W32_CL 128     // cell list capacity
+#define W32_PL 192     // particle list capacity
+#define W32_RESERVE (7 * RB_DEPTH + 8)
+
+__device__ __forceinline__ int w32_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ void w32_image(int im, int ngx, int ngy, int boundary, double W,
+                                          double s, double &ox, double &oy) {
+  if (boundary == RB_OPEN) { ox = 0.0; oy = 0.0; return; }
+  const int ny = 2 * ngy + 1;
+  const int ix = im / ny - ngx, iy = im % ny - ngy;
+  const double fx = (double)ix, fy = (double)iy;
+  const double sh = (boundary == RB_SHEAR) ? s : 0.0;
+  ox = fx * W;
+  oy = fy * W - fx * sh;
+}
+
+struct F3 {
+  float x, y, z;
+};
+
+__device__ __forceinline__ void w32_cell(const float4 a, const float4 q0, const float2 q1,
+                                         float px, float py, float pz, float b2, bool quad,
+                                         F3 &f) {
+  const float dx = a.x - px, dy = a.y - py, dz = a.z - pz;
+  const float r2 = dx * dx + dy * dy + dz * dz + b2;
+  const float ri = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+  const float u = ri * ri;
+  const float g = ri * u;
+  if (quad) {
+    // Q d and (d.Q.d) / rho^4, ordered to keep intermediates in range
+    const float qx = q0.x * dx + q0.y * dy + q0.z * dz;
+    const float qy = q0.y * dx + q0.w * dy + q1.x * dz;
+    const float qz = q0.z * dx + q1.x * dy + q1.y * dz;
+    const float dqd = ((dx * qx + dy * qy + dz * qz) * u) * u;
+    const float s = a.w + 2.5f * dqd;
+    f.x += g * (s * dx - qx * u);
+    f.y += g * (s * dy - qy * u);
+    f.z += g * (s * dz - qz * u);
+  } else {
+    const float h = g * a.w;
+    f.x += h * dx; f.y += h * dy; f.z += h * dz;
+  }
+}
+
+__device__ __forceinline__ void w32_part(const float4 a, float px, float py, float pz,
+                                         float b2, F3 &f) {
+  const float dx = a.x - px, dy = a.y - py, dz = a.z - pz;
+  const float r2 = dx * dx + dy * dy + dz * dz + b2;
+  // the member's own entry sits at d = 0 exactly: no self term
+  const float ri = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+  const float h = ri * ri * ri * a.w;
+  f.x += h * dx; f.y += h * dy; f.z += h * dz;
+}
+
+__device__ __forceinline__ void w32_eval_cells(const float4 *__restrict__ cpos,
+                                               const float4 *__restrict__ cq0,
+                                               const float2 *__restrict__ cq1, int cnt, int sub,
+                                               int lpp, float px, float py, float pz, float b2,
+                                               bool quad, double &ax, double &ay, double &az) {
+  F3 f = {0.f, 0.f, 0.f};
+  int e = sub;
+  for (; e + 3 * lpp < cnt; e += 4 * lpp) {
+    const float4 a0 = cpos[e], a1 = cpos[e + lpp], a2 = cpos[e + 2 * lpp], a3 = cpos[e + 3 * lpp];
+    float4 q00 = {}, q01 = {}, q02 = {}, q03 = {};
+    float2 q10 = {}, q11 = {}, q12 = {}, q13 = {};
+    if (quad) {
+      q00 = cq0[e]; q01 = cq0[e + lpp]; q02 = cq0[e + 2 * lpp]; q03 = cq0[e + 3 * lpp];
+      q10 = cq1[e]; q11 = cq1[e + lpp]; q12 = cq1[e + 2 * lpp]; q13 = cq1[e + 3 * lpp];
+    }
+    w32_cell(a0, q00, q10, px, py, pz, b2, quad, f);
+    w32_cell(a1, q01, q11, px, py, pz, b2, quad, f);
+    w32_cell(a2, q02, q12, px, py, pz, b2, quad, f);
+    w32_cell(a3, q03, q13, px, py, pz, b2, quad, f);
+  }
+  for (; e < cnt; e += lpp) {
+    float4 q0 = {};
+    float2 q1 = {};
+    if (quad) { q0 = cq0[e]; q1 = cq1[e]; }
+    w32_cell(cpos[e], q0, q1, px, py, pz, b2, quad, f);
+  }
+  ax += (double)f.x; ay += (double)f.y; az += (double)f.z;
+}
+
+__device__ __forceinline__ void w32_eval_parts(const float4 *__restrict__ ppos, int cnt, int sub,
+                                               int lpp, float px, float py, float pz, float b2,
+                                               double &ax, double &ay, double &az) {
+  F3 f = {0.f, 0.f, 0.f};
+  int e = sub;
+  for (; e + 3 * lpp < cnt; e += 4 * lpp) {
+    const float4 a0 = ppos[e], a1 = ppos[e + lpp], a2 = ppos[e + 2 * lpp], a3 = ppos[e + 3 * lpp];
+    w32_part(a0, px, py, pz, b2, f);
+    w32_part(a1, px, py, pz, b2, f);
+    w32_part(a2, px, py, pz, b2, f);
+    w32_part(a3, px, py, pz, b2, f);
+  }
+  for (; e < cnt; e += lpp) w32_part(ppos[e], px, py, pz, b2, f);
+  ax += (double)f.x; ay += (double)f.y; az += (double)f.z;
+}
+
+// groups: the children with at most G particles of nodes with more than G
+// (and roots with at most G).  Emission order is free: every group's result
+// depends only on its own particles and the tree.
+__global__ __launch_bounds__(256) void k_groups(
+    const uint32_t *__restrict__ lev_off, const uint32_t *__restrict__ nfirst,
+    const uint32_t *__restrict__ nlast, const uint32_t *__restrict__ nchild,
+    const uint32_t *__restrict__ nlastchild, const uint8_t *__restrict__ nleaf,
+    const uint8_t *__restrict__ nlevel, const uint32_t *__restrict__ starts, uint32_t P,
+    uint32_t G, WalkItem *__restrict__ groups, uint32_t *__restrict__ gctr) {
+  const uint32_t n_nodes = lev_off[RB_NLEV];
+  for (uint32_t id = blockIdx.x * blockDim.x + threadIdx.x; id < n_nodes;
+       id += gridDim.x * blockDim.x) {
+    const uint32_t f = nfirst[id], l = nlast[id];
+    const uint32_t cnt = l - f + 1;
+    if (cnt <= G) {
+      if (nlevel[id] == 0) {
+        const uint32_t g = atomicAdd(&gctr[0], 1u);
+        groups[g] = {f, l + 1, (P == 1) ? 0u : rb_patch_of(starts, P, f), 0u};
+      }
+      continue;
+    }
+    if (nleaf[id]) {
+      // a bucket leaf with more than G particles (deepest level): its runs
+      // of G consecutive particles are groups
+      const uint32_t p = (P == 1) ? 0u : rb_patch_of(starts, P, f);
+      for (uint32_t s = f; s <= l; s += G) {
+        const uint32_t g = atomicAdd(&gctr[0], 1u);
+        groups[g] = {s, (s + G <= l + 1) ? s + G : l + 1, p, 0u};
+      }
+      continue;
+    }
+    const uint32_t ca = nchild[id], cb = nlastchild[id];
+    for (uint32_t c = ca; c <= cb; ++c) {
+      const uint32_t cf = nfirst[c], cl = nlast[c];
+      if (cl - cf + 1 <= G) {
+        const uint32_t g = atomicAdd(&gctr[0], 1u);
+        groups[g] = {cf, cl + 1, (P == 1) ? 0u : rb_patch_of(starts, P, cf), 0u};
+      }
+    }
+  }
+}
+
+template <bool QUAD, bool STATS>
+__global__ __launch_bounds__(64) void k_walk32(
+    const WalkItem *__restrict__ groups, uint32_t *__restrict__ gctr, int img_split, int n_img,
+    int ngx, int ngy, int boundary, const PatchInfo *__restrict__ patch,
+    const uint32_t *__restrict__ root, const NodeLink *__restrict__ link,
+    const double4 *__restrict__ mcom, const double *__restrict__ Qarr,
+    const double *__restrict__ sx, const double *__restrict__ sy,
+    const double *__restrict__ sz, const double *__restrict__ msrc,
+    const double *__restrict__ sched, const uint32_t *__restrict__ ctr, uint32_t P,
+    double Gc, double soft, double theta2, double *__restrict__ acc, uint64_t cap,
+    unsigned long long *__restrict__ stats, uint32_t *__restrict__ err) {
+  __shared__ uint32_t stk[W32_SCAP];
+  __shared__ float4 cpos[W32_CL];
+  __shared__ float4 cq0[W32_CL];
+  __shared__ float2 cq1[W32_CL];
+  __shared__ float4 ppos[W32_PL];
+
+  const int lane = threadIdx.x;
+  const uint32_t n_groups = gctr[0];
+  const uint32_t per = img_split ? (uint32_t)n_img : 1u;
+  const uint32_t n_items = n_groups * per;
+  const double theta2d = theta2;
+  const uint32_t step = ctr[0];
+  unsigned long long n_cell = 0, n_pp = 0;
+  for (;;) {
+    uint32_t item = 0;
+    if (lane == 0) item = atomicAdd(&gctr[1], 1u);
+    item = (uint32_t)w32_uniform((int)__shfl(item, 0, 64));
+    if (item >= n_items) break;
+    // split items: all central images first (the heaviest), then the rest
+    const uint32_t gi = img_split ? item % n_groups : item;
+    const int im0 = img_split ? (int)((item / n_groups + (uint32_t)(n_img / 2)) % (uint32_t)n_img) : 0;
+    const int nim = img_split ? 1 : n_img;
+    const WalkItem grp = groups[gi];
+    const uint32_t p = grp.patch;
+    const double W = patch[p].W;
+    const int cnt = (int)(grp.end - grp.start);
+    const int gp = cnt <= 16 ? 16 : (cnt <= 32 ? 32 : 64);  // particle slots
+    const int lpp = 64 / gp;
+    const int pidx = lane % gp, sub = lane / gp;
+    const bool valid = pidx < cnt;
+    const uint32_t s = grp.start + (uint32_t)(valid ? pidx : 0);
+
+    double x = sx[s], y = sy[s], z = sz[s];
+    double lx = valid ? x : INFINITY, ly = valid ? y : INFINITY, lz = valid ? z : INFINITY;
+    double hx = valid ? x : -INFINITY, hy = valid ? y : -INFINITY, hz = valid ? z : -INFINITY;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      lx = fmin(lx, __shfl_xor(lx, d, 64)); ly = fmin(ly, __shfl_xor(ly, d, 64));
+      lz = fmin(lz, __shfl_xor(lz, d, 64)); hx = fmax(hx, __shfl_xor(hx, d, 64));
+      hy = fmax(hy, __shfl_xor(hy, d, 64)); hz = fmax(hz, __shfl_xor(hz, d, 64));
+    }
+    const double gx = 0.5 * (lx + hx), gy = 0.5 * (ly + hy), gz = 0.5 * (lz + hz);
+    const double invW = 1.0 / W;
+    const double gm_scale = Gc * invW * invW;
+    const double gq_scale = gm_scale * invW * invW;
+    const float b2 = (float)((soft * invW) * (soft * invW));
+    const float px = (float)((x - gx) * invW), py = (float)((y - gy) * invW),
+                pz = (float)((z - gz) * invW);
+    const double shear = sched[(size_t)step * 2 * P + p];
+    const uint32_t r0 = root[p];
+    double ax = 0.0, ay = 0.0, az = 0.0;
+
+    int sp = nim;
+    if (lane < nim) stk[lane] = (r0 << 5) | (uint32_t)(im0 + lane);
+    int cl = 0, pl = 0;
+    bool overflow = false;
+    while (sp > 0) {
+      // pop up to 64 entries; each may push 8 children.  Near the limit the
+      // wave pops one entry per round (depth first): that path needs at
+      // most 7 entries per level below, which W32_RESERVE keeps free.
+      int k = sp < 64 ? sp : 64;
+      if (sp + 7 * k > W32_SCAP - W32_RESERVE) {
+        k = (W32_SCAP - W32_RESERVE - sp) / 7;
+        if (k < 1) k = 1;
+      }
+      if (sp + 7 * k > W32_SCAP) { overflow = true; break; }
+      const int base = sp - k;
+      const bool has = lane < k;
+      const uint32_t e = has ? stk[base + lane] : 0u;
+      sp = base;
+      const uint32_t node = e >> 5;
+      const int im = (int)(e & 31u);
+      NodeLink lk = {0u, 0u, 0u, 0u};
+      double4 mc = make_double4(0.0, 0.0, 0.0, 0.0);
+      if (has) { lk = link[node]; mc = mcom[node]; }
+      const bool alive = has && mc.w != 0.0;
+      double ox = 0.0, oy = 0.0;
+      w32_image(im, ngx, ngy, boundary, W, shear, ox, oy);
+      const double cx = mc.x + ox, cy = mc.y + oy, cz = mc.z;
+      const bool leaf = (lk.lvl & 256u) != 0;
+      const bool single = alive && leaf && lk.count == 1;
+      const double dx = fmax(fmax(lx - cx, cx - hx), 0.0);
+      const double dy = fmax(fmax(ly - cy, cy - hy), 0.0);
+      const double dz = fmax(fmax(lz - cz, cz - hz), 0.0);
+      const double R2 = dx * dx + dy * dy + dz * dz;
+      const double w = ldexp(W, -(int)(lk.lvl & 255u));
+      const bool accept = alive && !single && (w * w < theta2d * R2);
+      const bool open_leaf = alive && !single && !accept && leaf;
+      const bool open_node = alive && !single && !accept && !leaf;
+
+      // children onto the stack
+      const uint32_t nc = open_node ? ((lk.lvl >> 9) & 15u) : 0u;
+      const uint32_t incl = rb_wave_incl_scan(nc);
+      const int tot = w32_uniform((int)__shfl(incl, 63, 64));
+      for (uint32_t q = 0; q < nc; ++q)
+        stk[sp + (int)(incl - nc + q)] = ((lk.child_or_first + q) << 5) | (uint32_t)im;
+      sp += tot;
+
+      // accepted cells
+      {
+        const uint64_t m = __ballot(accept);
+        if (accept) {
+          const int pos = cl + (int)rb_mbcnt(m);
+          cpos[pos] = make_float4((float)((cx - gx) * invW), (float)((cy - gy) * invW),
+                                  (float)((cz - gz) * invW), (float)(mc.w * gm_scale));
+          if (QUAD) {
+            const double *qq = Qarr + 6 * (size_t)node;
+            cq0[pos] = make_float4((float)(qq[0] * gq_scale), (float)(qq[1] * gq_scale),
+                                   (float)(qq[2] * gq_scale), (float)(qq[3] * gq_scale));
+            cq1[pos] = make_float2((float)(qq[4] * gq_scale), (float)(qq[5] * gq_scale));
+          }
+        }
+        cl += __popcll(m);
+      }
+      // single-particle leaves
+      {
+        const uint64_t m = __ballot(single);
+        if (single) {
+          const int pos = pl + (int)rb_mbcnt(m);
+          ppos[pos] = make_float4((float)((cx - gx) * invW), (float)((cy - gy) * invW),
+                                  (float)((cz - gz) * invW), (float)(mc.w * gm_scale));
+        }
+        pl += __popcll(m);
+      }
+      // opened bucket leaves: the wave expands them one after another
+      uint64_t bm = __ballot(open_leaf);
+      while (bm) {
+        const int src = __ffsll((long long)bm) - 1;
+        bm &= bm - 1;
+        const uint32_t first = __shfl(lk.child_or_first, src, 64);
+        const uint32_t count = __shfl(lk.count, src, 64);
+        const double bx = __shfl(ox, src, 64), by = __shfl(oy, src, 64);
+        for (uint32_t c0 = 0; c0 < count; c0 += 64) {
+          if (pl + 64 > W32_PL) {
+            w32_eval_parts(ppos, pl, sub, lpp, px, py, pz, b2, ax, ay, az);
+            if (STATS) n_pp += (unsigned long long)pl * (unsigned long long)cnt;
+            pl = 0;
+          }
+          const uint32_t j = first + c0 + (uint32_t)lane;
+          const bool inb = c0 + (uint32_t)lane < count;
+          const double mj = inb ? msrc[j] : 0.0;
+          const bool use = inb && mj != 0.0;
+          const uint64_t m = __ballot(use);
+          if (use) {
+            const int pos = pl + (int)rb_mbcnt(m);
+            ppos[pos] = make_float4((float)((sx[j] + bx - gx) * invW),
+                                    (float)((sy[j] + by - gy) * invW),
+                                    (float)((sz[j] - gz) * invW), (float)(mj * gm_scale));
+          }
+          pl += __popcll(m);
+        }
+      }
+      if (cl >= 64) {
+        w32_eval_cells(cpos, cq0, cq1, cl, sub, lpp, px, py, pz, b2, QUAD, ax, ay, az);
+        if (STATS) n_cell += (unsigned long long)cl * (unsigned long long)cnt;
+        cl = 0;
+      }
+      if (pl >= 64) {
+        w32_eval_parts(ppos, pl, sub, lpp, px, py, pz, b2, ax, ay, az);
+        if (STATS) n_pp += (unsigned long long)pl * (unsigned long long)cnt;
+        pl = 0;
+      }
+    }
+    if (overflow && lane == 0) atomicOr(err, RB_ERR_STACK);
+    if (cl > 0) {
+      w32_eval_cells(cpos, cq0, cq1, cl, sub, lpp, px, py, pz, b2, QUAD, ax, ay, az);
+      if (STATS) n_cell += (unsigned long long)cl * (unsigned long long)cnt;
+    }
+    if (pl > 0) {
+      w32_eval_parts(ppos, pl, sub, lpp, px, py, pz, b2, ax, ay, az);
+      if (STATS) n_pp += (unsigned long long)pl * (unsigned long long)cnt;
+    }
+    // lanes l, l + gp, ... hold partial sums of the same particle
+    for (int d = gp; d < 64; d <<= 1) {
+      ax += __shfl_xor(ax, d, 64); ay += __shfl_xor(ay, d, 64); az += __shfl_xor(az, d, 64);
+    }
+    if (sub == 0 && valid) {
+      double *a = acc + (size_t)(img_split ? im0 : 0) * 3 * cap;
+      a[s] = ax; a[cap + s] = ay; a[2 * cap + s] = az;
+    }
+  }
+  if (STATS && lane == 0) {
+    atomicAdd(&stats[3], n_cell);
+    atomicAdd(&stats[4], n_pp);
+  }
+}
+
+hipError_t launch_groups(rb_ctx *c) {
+  const uint32_t n = (uint32_t)c->h_starts[c->P];
+  if (n == 0) return hipSuccess;
+  unsigned grid = rb_div_up(c->node_cap, 256);
+  if (grid > 2048) grid = 2048;
+  hipLaunchKernelGGL(k_groups, dim3(grid), dim3(256), 0, c->stream, c->d_lev_off, c->d_nfirst,
+                     c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nleaf, c->d_nlevel,
+                     c->d_starts, c->P, (uint32_t)c->p.group_size, c->d_groups, c->d_gctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_walk32(rb_ctx *c, const double *sx, const double *sy, const double *sz,
                          const double *) {
-  return hipErrorNotSupported;
+  const uint32_t n = (uint32_t)c->h_starts[c->P];
+  if (n == 0) return hipSuccess;
+  if (c->node_cap >= (1ull << 27)) return hipErrorInvalidValue;  // stack entry packing
+  hipError_t e = launch_groups(c);
+  if (e != hipSuccess) return e;
+  // persistent grid: enough waves to fill every CU several times over, and
+  // never more than there can be work items
+  const uint64_t max_items = (uint64_t)n * (c->img_split ? (uint64_t)c->n_img : 1ull);
+  uint64_t grid = 256ull * 24ull;
+  if (grid > max_items) grid = max_items;
+  const double th2 = c->p.theta * c->p.theta;
+  const bool quad = c->p.quadrupole != 0, stats = (c->p.profile & 2) != 0;
+#define RB_W32_ARGS                                                                      \
+  c->d_groups, c->d_gctr, c->img_split, c->n_img, c->p.n_ghost[0], c->p.n_ghost[1],       \
+      c->p.boundary, c->d_patch, c->d_root, c->d_link, c->d_mcom, c->d_Q, sx, sy, sz,     \
+      c->d_msrc, c->d_sched, c->d_ctr, c->P, c->p.G, c->p.softening, th2, c->d_acc,       \
+      c->cap, c->d_stats, c->d_err
+  if (quad && stats)
+    hipLaunchKernelGGL((k_walk32<true, true>), dim3((unsigned)grid), dim3(64), 0, c->stream, RB_W32_ARGS);
+  else if (quad)
+    hipLaunchKernelGGL((k_walk32<true, false>), dim3((unsigned)grid), dim3(64), 0, c->stream, RB_W32_ARGS);
+  else if (stats)
+    hipLaunchKernelGGL((k_walk32<false, true>), dim3((unsigned)grid), dim3(64), 0, c->stream, RB_W32_ARGS);
+  else
+    hipLaunchKernelGGL((k_walk32<false, false>), dim3((unsigned)grid), dim3(64), 0, c->stream, RB_W32_ARGS);
+#undef RB_W32_ARGS
+  return hipGetLastError();
 }

@@ -172,7 +172,7 @@ hipError_t launch_walk64(rb_ctx *c, const double *sx, const double *sy, const do
   const unsigned grid = split ? n_items * (unsigned)c->n_img : n_items;
   const double b2 = c->p.softening * c->p.softening;
   const double th2 = c->p.theta * c->p.theta;
-  const bool quad = c->p.quadrupole != 0, stats = c->p.profile != 0;
+  const bool quad = c->p.quadrupole != 0, stats = (c->p.profile & 2) != 0;
 #define RB_WALK64_ARGS                                                                   \
   c->d_items64, split, c->n_img, c->p.n_ghost[0], c->p.n_ghost[1], c->p.boundary,        \
       c->d_patch, c->d_nlive, c->d_root, c->d_link, c->d_mcom, c->d_Q, sx, sy, sz,       \

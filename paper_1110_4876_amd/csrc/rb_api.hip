@@ -114,6 +114,17 @@ double shear_offset(const rb_params &p, double W, double t) {
   return remainder(1.5 * p.omega * W * t, W);
 }
 
+// One walk work item per (group, image) pair, or per group with all its
+// images.  The per-particle FP64 walk splits when its 64-particle items
+// would leave the chip idle; the grouped FP32 walk already draws from a
+// device queue and splits only on request.
+void set_split(rb_ctx *c) {
+  const int sp = c->p.split_images;
+  if (c->n_img <= 1 || sp == 0) { c->img_split = 0; return; }
+  if (sp == 1) { c->img_split = 1; return; }
+  c->img_split = (c->p.precision == RB_FP64 && c->h_items64.size() < 16384) ? 1 : 0;
+}
+
 // tiles of RB_TILE slots inside each patch; walk items of `g` slots
 int build_layout(rb_ctx *c) {
   const uint32_t P = c->P;
@@ -156,16 +167,10 @@ int build_layout(rb_ctx *c) {
     }
   };
   make_items(64, c->h_items64);
-  make_items((uint32_t)c->p.group_size, c->h_itemsg);
-  c->itemsg_size = c->p.group_size;
-  if (c->h_items64.size() > c->cap / 16 + 2 * P + 8 || c->h_itemsg.size() > c->cap / 16 + 2 * P + 8)
+  if (c->h_items64.size() > c->cap / 16 + 2 * P + 8)
     return fail(RB_ECAPACITY, "walk item table overflow");
   RB_TRY(upload_sync(c, c->d_items64, c->h_items64.data(), c->h_items64.size() * sizeof(WalkItem)));
-  RB_TRY(upload_sync(c, c->d_itemsg, c->h_itemsg.data(), c->h_itemsg.size() * sizeof(WalkItem)));
-  // split the images over work items when a walk would otherwise leave the
-  // chip idle
-  const int sp = c->p.split_images;
-  c->img_split = (c->n_img > 1) && (sp == 1 || (sp < 0 && c->h_items64.size() < 16384));
+  set_split(c);
   c->graph_key = -1;
   return RB_OK;
 }
@@ -233,7 +238,9 @@ int init_ctx(rb_ctx *c, const rb_params *p, uint32_t P, const int64_t *off, cons
   RB_TRY(dalloc(c, &c->d_S, 3 * nc));
   RB_TRY(dalloc(c, &c->d_Q, 6 * nc));
   RB_TRY(dalloc(c, &c->d_items64, max_items));
-  RB_TRY(dalloc(c, &c->d_itemsg, max_items));
+  RB_TRY(dalloc(c, &c->d_groups, cap));
+  RB_TRY(dalloc(c, &c->d_gctr, 4));
+  RB_HIP(hipMemsetAsync(c->d_gctr, 0, 16, c->stream));
   RB_TRY(dalloc(c, &c->d_acc, (uint64_t)c->n_img * 3 * cap));
   // per-call dynamic region: step counter (16 B), StepConst, schedule
   c->sched_cap = 1024;
@@ -368,7 +375,8 @@ hipEvent_t get_event(rb_ctx *c) {
 }
 
 int mark(rb_ctx *c, int phase, bool begin) {
-  if (!c->p.profile) return RB_OK;
+  // bit 0: every phase; bit 2: the walk only (lightest timing of a run)
+  if (!(c->p.profile & 1) && !((c->p.profile & 4) && phase == 5)) return RB_OK;
   EvPool &pl = g_pools[c];
   hipEvent_t e = get_event(c);
   if (!e) return fail(RB_EHIP, "hipEventCreate failed");
@@ -387,8 +395,10 @@ void resolve_timers(rb_ctx *c) {
   for (auto &q : pl.pending) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, q.second.first, q.second.second) == hipSuccess &&
-        q.first >= 0 && q.first < 16)
+        q.first >= 0 && q.first < 16) {
       c->phase_ms[q.first] += ms;
+      c->phase_calls[q.first] += 1;
+    }
     pl.free_ev.push_back(q.second.first);
     pl.free_ev.push_back(q.second.second);
   }
@@ -576,7 +586,9 @@ int rb_set_params(rb_ctx *c, const rb_params *p) {
   q.node_factor = nf;
   if (q.omega_z == 0.0) q.omega_z = q.omega;
   c->p = q;
-  if (q.group_size != old_group || q.split_images != old_split) RB_TRY(build_layout(c));
+  (void)old_group;
+  (void)old_split;
+  set_split(c);
   c->graph_key = -1;
   return RB_OK;
 }
@@ -731,9 +743,13 @@ int rb_stats(rb_ctx *c, rb_stats_t *out) {
   out->pp = (int64_t)s[2];
   out->list_cells = (int64_t)s[3];
   out->list_pp = (int64_t)s[4];
-  for (int k = 0; k < 16; ++k) out->ms[k] = c->phase_ms[k];
+  for (int k = 0; k < 16; ++k) {
+    out->ms[k] = c->phase_ms[k];
+    out->calls[k] = c->phase_calls[k];
+    c->phase_ms[k] = 0.0;
+    c->phase_calls[k] = 0;
+  }
   RB_HIP(hipMemset(c->d_stats, 0, sizeof(s)));
-  for (int k = 0; k < 16; ++k) c->phase_ms[k] = 0.f;
   return RB_OK;
 }
 

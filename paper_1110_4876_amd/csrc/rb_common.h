@@ -25,7 +25,8 @@ enum : uint32_t {
 
 // Walk link of a node: child_or_first = first child (internal) or first
 // sorted slot (leaf); skip = next node after the subtree in depth-first
-// order (RB_NONE at the end); count = particles; lvl = level | leaf << 8.
+// order (RB_NONE at the end); count = particles;
+// lvl = level | leaf << 8 | n_child << 9.
 struct __align__(16) NodeLink {
   uint32_t child_or_first;
   uint32_t skip;

@@ -70,11 +70,11 @@ struct rb_ctx {
   double *d_Q = nullptr;      // 6 per node
 
   // walk
-  std::vector<WalkItem> h_items64, h_itemsg;
-  WalkItem *d_items64 = nullptr, *d_itemsg = nullptr;
-  int itemsg_size = 0;
-  double *d_acc = nullptr;    // (n_img or 1) * 3 * cap
-  float *d_accf = nullptr;
+  std::vector<WalkItem> h_items64;  // FP64 walk: 64 Morton-consecutive slots
+  WalkItem *d_items64 = nullptr;
+  WalkItem *d_groups = nullptr;     // FP32 walk: groups emitted from the tree
+  uint32_t *d_gctr = nullptr;       // [groups emitted, work items taken]
+  double *d_acc = nullptr;          // (n_img or 1) * 3 * cap
 
   // per-call dynamic region [ctr | StepConst | schedule], uploaded from a
   // pinned staging copy; schedule per step: s_half[P], s_end[P]
@@ -92,7 +92,8 @@ struct rb_ctx {
   // profiling
   hipEvent_t ev[16] = {};
   int ev_used = 0;
-  float phase_ms[16] = {};
+  double phase_ms[16] = {};
+  int64_t phase_calls[16] = {};
 
   // graph of one step
   hipGraph_t graph = nullptr;

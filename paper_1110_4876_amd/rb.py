@@ -63,7 +63,8 @@ class rb_tree_host(ctypes.Structure):
 class rb_stats_t(ctypes.Structure):
     _fields_ = [("open_tests", ctypes.c_int64), ("cells", ctypes.c_int64),
                 ("pp", ctypes.c_int64), ("list_cells", ctypes.c_int64),
-                ("list_pp", ctypes.c_int64), ("ms", ctypes.c_double * 16)]
+                ("list_pp", ctypes.c_int64), ("ms", ctypes.c_double * 16),
+                ("calls", ctypes.c_int64 * 16)]
 
 
 class RBError(RuntimeError):
@@ -279,6 +280,7 @@ def rb_stats(ctx) -> dict:
     out = dict(open_tests=s.open_tests, cells=s.cells, pp=s.pp, list_cells=s.list_cells,
                list_pp=s.list_pp)
     out["ms"] = {name: s.ms[k] for k, name in enumerate(PHASES)}
+    out["calls"] = {name: int(s.calls[k]) for k, name in enumerate(PHASES)}
     return out
 
 
