@@ -269,8 +269,11 @@ void free_ctx(rb_ctx *c) {
   if (!c) return;
   if (c->h_dyn) (void)hipHostFree(c->h_dyn);
   if (c->dyn_ev) (void)hipEventDestroy(c->dyn_ev);
-  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-  if (c->graph) (void)hipGraphDestroy(c->graph);
+  for (int k = 0; k < 2; ++k) {
+    if (c->graph_exec[k]) (void)hipGraphExecDestroy(c->graph_exec[k]);
+    if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+  }
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (int k = 0; k < 16; ++k)
     if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
   for (void *v : c->allocs) (void)hipFree(v);
@@ -473,9 +476,67 @@ int report_device_errors(rb_ctx *c) {
   return RB_OK;
 }
 
+// the kernels of one step with the state in buffer src
+int step_kernels(rb_ctx *c, int src) {
+  const int dst = 1 - src;
+  RB_PHASE(PH_SORT, launch_sort(c));
+  RB_PHASE(PH_PERMUTE, launch_permute_state(c, src, dst));
+  RB_PHASE(PH_TOPO, launch_topology(c));
+  RB_PHASE(PH_MOMENTS, launch_moments(c, c->d_px[dst][0], c->d_px[dst][1], c->d_px[dst][2]));
+  RB_TRY(walk(c, dst));
+  RB_PHASE(PH_POST, launch_post(c, dst));
+  RB_LAUNCH(launch_advance(c));
+  return RB_OK;
+}
+
+void drop_graphs(rb_ctx *c) {
+  for (int k = 0; k < 2; ++k) {
+    if (c->graph_exec[k]) (void)hipGraphExecDestroy(c->graph_exec[k]);
+    if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+    c->graph_exec[k] = nullptr;
+    c->graph[k] = nullptr;
+  }
+}
+
+// Capture the two step graphs.  Every argument of the step kernels is fixed
+// for a context and buffer parity; the step index, times and shear offsets
+// are read from device memory, so one graph serves every step.  Timers are
+// not captured.
+// Capture happens on a private non-blocking stream (the caller's stream may
+// be the null stream, which cannot be captured); the graphs are then
+// launched on the context's stream.
+int capture_graphs(rb_ctx *c) {
+  drop_graphs(c);
+  if (!c->cap_stream) RB_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  const int32_t prof = c->p.profile;
+  hipStream_t saved = c->stream;
+  c->p.profile &= ~5;
+  c->stream = c->cap_stream;
+  int r = RB_OK;
+  for (int src = 0; src < 2 && r == RB_OK; ++src) {
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { r = fail(RB_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e)); break; }
+    r = step_kernels(c, src);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->stream, &g);  // always ends the capture
+    if (r == RB_OK && e != hipSuccess) r = fail(RB_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    if (r != RB_OK) { if (g) (void)hipGraphDestroy(g); break; }
+    c->graph[src] = g;
+    e = hipGraphInstantiate(&c->graph_exec[src], g, nullptr, nullptr, 0);
+    if (e != hipSuccess) r = fail(RB_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  c->stream = saved;
+  c->p.profile = prof;
+  if (r != RB_OK) { drop_graphs(c); return r; }
+  c->graph_key = 1;
+  return RB_OK;
+}
+
 int run_step(rb_ctx *c, rb_particles *p, double t, double dt, int32_t nsteps) {
   if (nsteps <= 0) return nsteps == 0 ? RB_OK : fail(RB_EINVAL, "nsteps must be >= 0");
   if (!isfinite(t) || !isfinite(dt)) return fail(RB_EINVAL, "t and dt must be finite");
+  const bool graphs = c->p.use_graph != 0;
+  if (graphs && c->graph_key < 0) RB_TRY(capture_graphs(c));
   int32_t done = 0;
   while (done < nsteps) {
     const int32_t chunk = std::min<int32_t>(nsteps - done, (int32_t)c->sched_cap);
@@ -485,15 +546,9 @@ int run_step(rb_ctx *c, rb_particles *p, double t, double dt, int32_t nsteps) {
     RB_PHASE(PH_KEYS, launch_prologue(c, p));
     int src = 0;
     for (int32_t k = 0; k < chunk; ++k) {
-      const int dst = 1 - src;
-      RB_PHASE(PH_SORT, launch_sort(c));
-      RB_PHASE(PH_PERMUTE, launch_permute_state(c, src, dst));
-      RB_PHASE(PH_TOPO, launch_topology(c));
-      RB_PHASE(PH_MOMENTS, launch_moments(c, c->d_px[dst][0], c->d_px[dst][1], c->d_px[dst][2]));
-      RB_TRY(walk(c, dst));
-      RB_PHASE(PH_POST, launch_post(c, dst));
-      RB_LAUNCH(launch_advance(c));
-      src = dst;
+      if (graphs) RB_HIP(hipGraphLaunch(c->graph_exec[src], c->stream));
+      else RB_TRY(step_kernels(c, src));
+      src = 1 - src;
     }
     RB_LAUNCH(launch_epilogue(c, p, src));
     RB_TRY(mark(c, PH_TOTAL, false));

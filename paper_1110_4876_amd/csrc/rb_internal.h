@@ -96,9 +96,12 @@ struct rb_ctx {
   int64_t phase_calls[16] = {};
 
   // graph of one step
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
+  // captured graphs of one step, for the two buffer parities (state in
+  // buffer 0 -> 1, and 1 -> 0); graph_key < 0 marks them stale
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
   int graph_key = -1;
+  hipStream_t cap_stream = nullptr;  // private stream used only for capture
 
   std::vector<void *> allocs;
 };

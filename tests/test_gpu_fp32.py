@@ -28,3 +28,107 @@ def test_theta_zero_precision_only(group):
         # FP32 unit roundoff 6e-8 per term, amplified by the cancellation of
         # in-plane forces (sum |a_j| / |sum a_j| ~ 10-100 in the sheet)
         assert rms_rel(a, ref) <= 1e-5, rms_rel(a, ref)
+
+
+def _sampled_direct(orc, pr, t, k, seed=0):
+    tg = inputs.sample_targets(pr.n, k, seed=seed)
+    p = orc.make_params(**pr.params)
+    return tg, orc.direct(p, pr.x, pr.y, pr.z, pr.m, n_active=pr.n_active,
+                          s=orc.shear_offset(p, t), targets=tg)
+
+
+def test_c1_operating_point_meets_gate(orc):
+    # the 50,000-particle ring patch: FP32-mixed, groups of 64, theta = 0.35
+    # meets rms <= 1e-4 against the FP64 direct sum (Eq. 1 over the images)
+    from gpu_util import Dev, gravity, make_ctx
+    from paper_1110_4876_amd import rb
+    from paper_1110_4876_amd.metrics import force_errors
+    pr = inputs.sheet(50000, seed=0).with_params(theta=0.35)
+    t = 0.5 * pr.dt
+    tg, ref = _sampled_direct(orc, pr, t, 1024)
+    ctx = make_ctx(pr, precision=rb.RB_FP32_MIXED)
+    try:
+        a = gravity(ctx, Dev(pr, with_v=False), pr.n, t)
+    finally:
+        rb.rb_destroy(ctx)
+    e = force_errors(a[tg], ref)
+    assert e["rms"] <= 1e-4, e
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.5, 0.7])
+def test_grouped_walk_is_no_less_accurate(orc, theta):
+    # the group criterion accepts a node only if every member would: at the
+    # same theta its error stays at or below the per-particle walk's
+    from gpu_util import Dev, gravity, make_ctx
+    from paper_1110_4876_amd import rb
+    from paper_1110_4876_amd.metrics import force_errors
+    pr = inputs.sheet(20000, seed=3).with_params(theta=theta)
+    t = 1234.0
+    tg, ref = _sampled_direct(orc, pr, t, 1024)
+    d = Dev(pr, with_v=False)
+    c64 = make_ctx(pr)
+    c32 = make_ctx(pr, precision=rb.RB_FP32_MIXED)
+    try:
+        e64 = force_errors(gravity(c64, d, pr.n, t)[tg], ref)["rms"]
+        e32 = force_errors(gravity(c32, d, pr.n, t)[tg], ref)["rms"]
+    finally:
+        rb.rb_destroy(c64)
+        rb.rb_destroy(c32)
+    assert e32 <= e64 * 1.05, (e32, e64)
+
+
+def test_plummer_quadrupole_gate(orc):
+    from gpu_util import Dev, gravity, make_ctx
+    from paper_1110_4876_amd import rb
+    from paper_1110_4876_amd.metrics import force_errors
+    pr = inputs.plummer(60000, seed=1, b=0.001, quadrupole=True).with_params(theta=0.35)
+    tg, ref = _sampled_direct(orc, pr, 0.0, 1024)
+    ctx = make_ctx(pr, precision=rb.RB_FP32_MIXED)
+    try:
+        a = gravity(ctx, Dev(pr, with_v=False), pr.n)
+    finally:
+        rb.rb_destroy(ctx)
+    assert force_errors(a[tg], ref)["rms"] <= 1e-4
+
+
+@pytest.mark.parametrize("leaf", [1, 8, 32])
+def test_buckets_test_particles_and_removed(orc, leaf):
+    # bucket leaves (opened and expanded by the wave), massless test
+    # particles and removed particles, at theta = 0 against the direct sum
+    from gpu_util import Dev, gravity, make_ctx, rms_rel
+    from paper_1110_4876_amd import rb
+    pr = inputs.plummer(5000, seed=7, b=0.01).with_params(theta=0.0)
+    pr.x[7] = np.nan
+    na = 4000
+    p = orc.make_params(**pr.params)
+    ref = orc.direct(p, pr.x, pr.y, pr.z, pr.m, n_active=na)
+    ctx = make_ctx(pr, precision=rb.RB_FP32_MIXED, leaf_size=leaf, group_size=16)
+    try:
+        a = gravity(ctx, Dev(pr, with_v=False), na)
+    finally:
+        rb.rb_destroy(ctx)
+    assert np.all(a[7] == 0)
+    keep = np.arange(pr.n) != 7
+    assert rms_rel(a[keep], ref[keep]) <= 1e-5
+
+
+def test_fp32_step_tracks_fp64_step():
+    # two steps of a ring patch at theta = 0 (every term direct): the kicks
+    # differ by FP32 rounding only (~1e-6 relative of the acceleration), so
+    # positions stay within 1e-9 of the box side
+    from gpu_util import Dev, make_ctx
+    from paper_1110_4876_amd import rb
+    pr = inputs.sheet(3000, seed=4).with_params(theta=0.0)
+    out = {}
+    for prec in (rb.RB_FP64, rb.RB_FP32_MIXED):
+        ctx = make_ctx(pr, precision=prec)
+        try:
+            d = Dev(pr)
+            rb.rb_step(ctx, d.parts, d.n, d.n, 0.0, pr.dt, 2)
+            rb.rb_sync(ctx)
+            out[prec] = d.state()
+        finally:
+            rb.rb_destroy(ctx)
+    W = pr.params["W"]
+    for k in ("x", "y", "z"):
+        assert np.abs(out[0][k] - out[1][k]).max() <= 1e-9 * W

@@ -126,3 +126,29 @@ def test_checkpoint_resume_is_bitwise():
         rb.rb_destroy(ctx)
     for k in sa:
         np.testing.assert_array_equal(sa[k], sc[k], err_msg=k)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_equals_eager(precision):
+    # the step captured once as a HIP graph and replayed: every replay (with
+    # eager work and synchronisations in between) matches eager launches
+    from gpu_util import Dev, gravity, make_ctx
+    from paper_1110_4876_amd import rb
+    pr = inputs.sheet(7000, seed=8)
+    ce = make_ctx(pr, precision=precision)
+    cg = make_ctx(pr, precision=precision, use_graph=1)
+    try:
+        a, b = Dev(pr), Dev(pr)
+        for call in range(3):
+            t0 = call * 4 * pr.dt
+            rb.rb_step(ce, a.parts, a.n, a.n, t0, pr.dt, 4)
+            rb.rb_step(cg, b.parts, b.n, b.n, t0, pr.dt, 4)
+            rb.rb_sync(ce)
+            rb.rb_sync(cg)
+            gravity(ce, Dev(pr, with_v=False), pr.n)  # eager work in between
+            sa, sb = a.state(), b.state()
+            for k in sa:
+                np.testing.assert_array_equal(sa[k], sb[k], err_msg=f"call {call} {k}")
+    finally:
+        rb.rb_destroy(ce)
+        rb.rb_destroy(cg)
