@@ -88,7 +88,8 @@ __global__ __launch_bounds__(256) void k_prologue(
     double *__restrict__ bx, double *__restrict__ by, double *__restrict__ bz,
     double *__restrict__ bvx, double *__restrict__ bvy, double *__restrict__ bvz,
     double *__restrict__ bm, uint32_t *__restrict__ orig, uint64_t *__restrict__ key,
-    uint32_t *__restrict__ idx, uint32_t *__restrict__ err) {
+    uint32_t *__restrict__ idx, uint32_t *__restrict__ err, uint32_t *__restrict__ hist0,
+    const uint32_t *__restrict__ patch_tile0, uint32_t tile) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const uint32_t p = (P == 1) ? 0 : rb_patch_of(starts, P, s);
@@ -104,8 +105,10 @@ __global__ __launch_bounds__(256) void k_prologue(
   bvx[s] = q.vx; bvy[s] = q.vy; bvz[s] = q.vz;
   bm[s] = m[s];
   orig[s] = s;
-  key[s] = rb_state_key(q, pi, boundary, err);
+  const uint64_t k = rb_state_key(q, pi, boundary, err);
+  key[s] = k;
   idx[s] = s;
+  rb_hist_add(hist0, patch_tile0, p, pi.start, tile, s, k);
 }
 
 hipError_t launch_prologue(rb_ctx *c, const rb_particles *cp) {
@@ -116,7 +119,7 @@ hipError_t launch_prologue(rb_ctx *c, const rb_particles *cp) {
                      cp->y, cp->z, cp->vx, cp->vy, cp->vz, cp->m, c->d_patch, c->d_starts,
                      c->P, n, c->p.boundary, c->p.drift, c->d_sc, c->d_sched, c->d_ctr, b[0],
                      b[1], b[2], b[3], b[4], b[5], b[6], c->d_orig[0], c->d_key[0],
-                     c->d_idx[0], c->d_err);
+                     c->d_idx[0], c->d_err, c->d_hist[0], c->d_patch_tile0, c->tile);
   return hipGetLastError();
 }
 
@@ -130,14 +133,17 @@ __global__ __launch_bounds__(256) void k_post(
     const PatchInfo *__restrict__ patch, const uint32_t *__restrict__ starts,
     const uint32_t *__restrict__ nlive, uint32_t P, uint32_t n, int boundary, int drift,
     const StepConst *__restrict__ scp, const double *__restrict__ sched,
-    const uint32_t *__restrict__ ctr, uint64_t *__restrict__ key,
-    uint32_t *__restrict__ idx, uint32_t *__restrict__ err) {
+    uint32_t *__restrict__ ctr, int slot, uint64_t *__restrict__ key,
+    uint32_t *__restrict__ idx, uint32_t *__restrict__ err, uint32_t *__restrict__ hist0,
+    const uint32_t *__restrict__ patch_tile0, uint32_t tile) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t k = ctr[slot], nsteps = ctr[2];
+  // the next step reads its index from the other slot
+  if (s == 0) ctr[1 - slot] = k + 1;
   if (s >= n) return;
   const uint32_t p = (P == 1) ? 0 : rb_patch_of(starts, P, s);
   const PatchInfo pi = patch[p];
   const StepConst sc = *scp;
-  const uint32_t k = ctr[0], nsteps = ctr[1];
   const bool has_next = k + 1 < nsteps;
   PState q{bx[s], by[s], bz[s], bvx[s], bvy[s], bvz[s]};
   const bool live = (s - pi.start) < nlive[p];
@@ -166,12 +172,14 @@ __global__ __launch_bounds__(256) void k_post(
     bvx[s] = q.vx; bvy[s] = q.vy; bvz[s] = q.vz;
   }
   if (has_next) {
-    key[s] = live ? rb_state_key(q, pi, boundary, err) : RB_KEY_DEAD;
+    const uint64_t k2 = live ? rb_state_key(q, pi, boundary, err) : RB_KEY_DEAD;
+    key[s] = k2;
     idx[s] = s;
+    rb_hist_add(hist0, patch_tile0, p, pi.start, tile, s, k2);
   }
 }
 
-hipError_t launch_post(rb_ctx *c, int buf) {
+hipError_t launch_post(rb_ctx *c, int buf, int slot) {
   const uint32_t n = (uint32_t)c->h_starts[c->P];
   if (n == 0) return hipSuccess;
   double *const *b = c->d_px[buf];
@@ -179,16 +187,8 @@ hipError_t launch_post(rb_ctx *c, int buf) {
   hipLaunchKernelGGL(k_post, dim3(rb_div_up(n, 256)), dim3(256), 0, c->stream, b[0], b[1],
                      b[2], b[3], b[4], b[5], c->d_acc, c->cap, n_acc, c->d_patch, c->d_starts,
                      c->d_nlive, c->P, n, c->p.boundary, c->p.drift, c->d_sc, c->d_sched,
-                     c->d_ctr, c->d_key[0], c->d_idx[0], c->d_err);
-  return hipGetLastError();
-}
-
-__global__ void k_advance(uint32_t *ctr) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) ctr[0] = ctr[0] + 1;
-}
-
-hipError_t launch_advance(rb_ctx *c) {
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->d_ctr);
+                     c->d_ctr, slot, c->d_key[0], c->d_idx[0], c->d_err, c->d_hist[0],
+                     c->d_patch_tile0, c->tile);
   return hipGetLastError();
 }
 

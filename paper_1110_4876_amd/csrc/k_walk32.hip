@@ -2,8 +2,8 @@
 // Sect. 4.2 of the paper).
 //
 // Groups are the maximal tree nodes holding at most G particles (G =
-// group_size), so each group is spatially compact; together they partition
-// the particles.  One wave serves one (group, image) work item, pulled from
+// group_size, emitted during the build), so each group is spatially compact;
+// together they partition the particles.  One wave serves one (group, image) work item, pulled from
 // a device queue by a persistent grid; 64 / 2^ceil(log2 n) lanes share each
 // of the group's n particles.  The wave walks the tree once for the whole
 // group: a node is accepted for every member at once when
@@ -122,48 +122,6 @@ __device__ __forceinline__ void w32_eval_parts(const float4 *__restrict__ ppos, 
   ax += (double)f.x; ay += (double)f.y; az += (double)f.z;
 }
 
-// groups: the children with at most G particles of nodes with more than G
-// (and roots with at most G).  Emission order is free: every group's result
-// depends only on its own particles and the tree.
-__global__ __launch_bounds__(256) void k_groups(
-    const uint32_t *__restrict__ lev_off, const uint32_t *__restrict__ nfirst,
-    const uint32_t *__restrict__ nlast, const uint32_t *__restrict__ nchild,
-    const uint32_t *__restrict__ nlastchild, const uint8_t *__restrict__ nleaf,
-    const uint8_t *__restrict__ nlevel, const uint32_t *__restrict__ starts, uint32_t P,
-    uint32_t G, WalkItem *__restrict__ groups, uint32_t *__restrict__ gctr) {
-  const uint32_t n_nodes = lev_off[RB_NLEV];
-  for (uint32_t id = blockIdx.x * blockDim.x + threadIdx.x; id < n_nodes;
-       id += gridDim.x * blockDim.x) {
-    const uint32_t f = nfirst[id], l = nlast[id];
-    const uint32_t cnt = l - f + 1;
-    if (cnt <= G) {
-      if (nlevel[id] == 0) {
-        const uint32_t g = atomicAdd(&gctr[0], 1u);
-        groups[g] = {f, l + 1, (P == 1) ? 0u : rb_patch_of(starts, P, f), 0u};
-      }
-      continue;
-    }
-    if (nleaf[id]) {
-      // a bucket leaf with more than G particles (deepest level): its runs
-      // of G consecutive particles are groups
-      const uint32_t p = (P == 1) ? 0u : rb_patch_of(starts, P, f);
-      for (uint32_t s = f; s <= l; s += G) {
-        const uint32_t g = atomicAdd(&gctr[0], 1u);
-        groups[g] = {s, (s + G <= l + 1) ? s + G : l + 1, p, 0u};
-      }
-      continue;
-    }
-    const uint32_t ca = nchild[id], cb = nlastchild[id];
-    for (uint32_t c = ca; c <= cb; ++c) {
-      const uint32_t cf = nfirst[c], cl = nlast[c];
-      if (cl - cf + 1 <= G) {
-        const uint32_t g = atomicAdd(&gctr[0], 1u);
-        groups[g] = {cf, cl + 1, (P == 1) ? 0u : rb_patch_of(starts, P, cf), 0u};
-      }
-    }
-  }
-}
-
 template <bool QUAD, bool STATS>
 __global__ __launch_bounds__(64) void k_walk32(
     const WalkItem *__restrict__ groups, uint32_t *__restrict__ gctr, int img_split, int n_img,
@@ -174,7 +132,7 @@ __global__ __launch_bounds__(64) void k_walk32(
     const double *__restrict__ sz, const double *__restrict__ msrc,
     const double *__restrict__ sched, const uint32_t *__restrict__ ctr, uint32_t P,
     double Gc, double soft, double theta2, double *__restrict__ acc, uint64_t cap,
-    unsigned long long *__restrict__ stats, uint32_t *__restrict__ err) {
+    unsigned long long *__restrict__ stats, uint32_t *__restrict__ err, int slot) {
   __shared__ uint32_t stk[W32_SCAP];
   __shared__ float4 cpos[W32_CL];
   __shared__ float4 cq0[W32_CL];
@@ -186,7 +144,7 @@ __global__ __launch_bounds__(64) void k_walk32(
   const uint32_t per = img_split ? (uint32_t)n_img : 1u;
   const uint32_t n_items = n_groups * per;
   const double theta2d = theta2;
-  const uint32_t step = ctr[0];
+  const uint32_t step = ctr[slot];
   unsigned long long n_cell = 0, n_pp = 0;
   for (;;) {
     uint32_t item = 0;
@@ -362,24 +320,11 @@ __global__ __launch_bounds__(64) void k_walk32(
   }
 }
 
-hipError_t launch_groups(rb_ctx *c) {
-  const uint32_t n = (uint32_t)c->h_starts[c->P];
-  if (n == 0) return hipSuccess;
-  unsigned grid = rb_div_up(c->node_cap, 256);
-  if (grid > 2048) grid = 2048;
-  hipLaunchKernelGGL(k_groups, dim3(grid), dim3(256), 0, c->stream, c->d_lev_off, c->d_nfirst,
-                     c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nleaf, c->d_nlevel,
-                     c->d_starts, c->P, (uint32_t)c->p.group_size, c->d_groups, c->d_gctr);
-  return hipGetLastError();
-}
-
 hipError_t launch_walk32(rb_ctx *c, const double *sx, const double *sy, const double *sz,
-                         const double *) {
+                         int slot) {
   const uint32_t n = (uint32_t)c->h_starts[c->P];
   if (n == 0) return hipSuccess;
   if (c->node_cap >= (1ull << 27)) return hipErrorInvalidValue;  // stack entry packing
-  hipError_t e = launch_groups(c);
-  if (e != hipSuccess) return e;
   // persistent grid: enough waves to fill every CU several times over, and
   // never more than there can be work items
   const uint64_t max_items = (uint64_t)n * (c->img_split ? (uint64_t)c->n_img : 1ull);
@@ -391,7 +336,7 @@ hipError_t launch_walk32(rb_ctx *c, const double *sx, const double *sy, const do
   c->d_groups, c->d_gctr, c->img_split, c->n_img, c->p.n_ghost[0], c->p.n_ghost[1],       \
       c->p.boundary, c->d_patch, c->d_root, c->d_link, c->d_mcom, c->d_Q, sx, sy, sz,     \
       c->d_msrc, c->d_sched, c->d_ctr, c->P, c->p.G, c->p.softening, th2, c->d_acc,       \
-      c->cap, c->d_stats, c->d_err
+      c->cap, c->d_stats, c->d_err, slot
   if (quad && stats)
     hipLaunchKernelGGL((k_walk32<true, true>), dim3((unsigned)grid), dim3(64), 0, c->stream, RB_W32_ARGS);
   else if (quad)

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(64) void k_walk64(
     const double *__restrict__ sched, const uint32_t *__restrict__ ctr, uint32_t P,
     double G, double b2, double theta2, double *__restrict__ acc, uint64_t cap,
     unsigned long long *__restrict__ stats, const uint32_t *__restrict__ lev_off,
-    uint32_t *__restrict__ err) {
+    uint32_t *__restrict__ err, int slot) {
   // a depth-first walk visits every node at most once per image: more
   // visits, or an index past the node count, mean inconsistent links
   const uint32_t n_nodes = lev_off[RB_NLEV];
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(64) void k_walk64(
   const uint32_t st = patch[p].start, nl = nlive[p];
   const uint32_t s = it.start + threadIdx.x;
   const bool valid = s < it.end && (s - st) < nl;
-  const double shear = sched[(size_t)ctr[0] * 2 * P + p];
+  const double shear = sched[(size_t)ctr[slot] * 2 * P + p];
   double px = 0.0, py = 0.0, pz = 0.0;
   if (valid) { px = sx[s]; py = sy[s]; pz = sz[s]; }
   const uint32_t r0 = valid ? root[p] : RB_NONE;
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(64) void k_walk64(
 }
 
 hipError_t launch_walk64(rb_ctx *c, const double *sx, const double *sy, const double *sz,
-                         const double *) {
+                         int slot) {
   const uint32_t n_items = (uint32_t)c->h_items64.size();
   if (n_items == 0) return hipSuccess;
   const int split = c->img_split;
@@ -177,7 +177,7 @@ hipError_t launch_walk64(rb_ctx *c, const double *sx, const double *sy, const do
   c->d_items64, split, c->n_img, c->p.n_ghost[0], c->p.n_ghost[1], c->p.boundary,        \
       c->d_patch, c->d_nlive, c->d_root, c->d_link, c->d_mcom, c->d_Q, sx, sy, sz,       \
       c->d_msrc, c->d_sched, c->d_ctr, c->P, c->p.G, b2, th2, c->d_acc, c->cap, c->d_stats, \
-      c->d_lev_off, c->d_err
+      c->d_lev_off, c->d_err, slot
   if (quad && stats)
     hipLaunchKernelGGL((k_walk64<true, true>), dim3(grid), dim3(64), 0, c->stream, RB_WALK64_ARGS);
   else if (quad)

@@ -131,13 +131,20 @@ int build_layout(rb_ctx *c) {
   c->h_tile_start.clear(); c->h_tile_end.clear(); c->h_tile_patch.clear();
   c->h_patch_tile0.assign(P + 1, 0);
   c->max_tiles_per_patch = 0;
+  // about 1024 tiles over the whole system (one wave each), 256..8192 slots
+  {
+    const uint64_t n = c->h_starts[P];
+    uint32_t t = RB_TILE_MIN;
+    while (t < RB_TILE_MAX && (uint64_t)t * 1024 < n) t <<= 1;
+    c->tile = t;
+  }
   for (uint32_t p = 0; p < P; ++p) {
     c->h_patch_tile0[p] = (uint32_t)c->h_tile_start.size();
     const uint32_t s0 = c->h_starts[p], s1 = c->h_starts[p + 1];
     uint32_t nt = 0;
-    for (uint32_t s = s0; s < s1; s += RB_TILE) {
+    for (uint32_t s = s0; s < s1; s += c->tile) {
       c->h_tile_start.push_back(s);
-      c->h_tile_end.push_back(std::min<uint32_t>(s + RB_TILE, s1));
+      c->h_tile_end.push_back(std::min<uint32_t>(s + c->tile, s1));
       c->h_tile_patch.push_back(p);
       ++nt;
     }
@@ -201,7 +208,7 @@ int init_ctx(rb_ctx *c, const rb_params *p, uint32_t P, const int64_t *off, cons
   const double nf = c->p.node_factor > 0.0 ? c->p.node_factor : 3.0;
   c->node_cap = (uint64_t)(nf * (double)cap) + 64 * (uint64_t)P + 64;
   if (c->node_cap > 0xFFFFFFF0ull) return fail(RB_ECAPACITY, "node capacity beyond 32-bit indices");
-  const uint64_t max_tiles = cap / RB_TILE + P + 1;
+  const uint64_t max_tiles = cap / RB_TILE_MIN + P + 1;
   const uint64_t max_items = cap / 16 + 2 * (uint64_t)P + 8;
   RB_TRY(dalloc(c, &c->d_patch, P));
   RB_TRY(dalloc(c, &c->d_starts, P + 1));
@@ -217,11 +224,13 @@ int init_ctx(rb_ctx *c, const rb_params *p, uint32_t P, const int64_t *off, cons
     for (int f = 0; f < 7; ++f) RB_TRY(dalloc(c, &c->d_px[b][f], cap));
     RB_TRY(dalloc(c, &c->d_orig[b], cap));
   }
-  RB_TRY(dalloc(c, &c->d_hist, 256 * max_tiles));
-  RB_TRY(dalloc(c, &c->d_digit_tot, 256 * (uint64_t)P));
+  for (int b = 0; b < 2; ++b) {
+    RB_TRY(dalloc(c, &c->d_hist[b], 2048 * max_tiles));
+    // the first pass counts into histogram 0, which every sort leaves zeroed
+    RB_HIP(hipMemsetAsync(c->d_hist[b], 0, 4 * 2048 * max_tiles, c->stream));
+  }
+  RB_TRY(dalloc(c, &c->d_digit_tot, 2048 * (uint64_t)P));
   RB_TRY(dalloc(c, &c->d_msrc, cap));
-  RB_TRY(dalloc(c, &c->d_lcp, cap + 1));
-  RB_TRY(dalloc(c, &c->d_leaf, cap + 1));
   RB_TRY(dalloc(c, &c->d_cnt, 2 * RB_NLEV * max_tiles));
   RB_TRY(dalloc(c, &c->d_lev_tot, 2 * RB_NLEV));
   RB_TRY(dalloc(c, &c->d_lev_off, RB_NLEV + 2));
@@ -240,6 +249,9 @@ int init_ctx(rb_ctx *c, const rb_params *p, uint32_t P, const int64_t *off, cons
   RB_TRY(dalloc(c, &c->d_items64, max_items));
   RB_TRY(dalloc(c, &c->d_groups, cap));
   RB_TRY(dalloc(c, &c->d_gctr, 4));
+  RB_TRY(dalloc(c, &c->d_large, nc));
+  RB_TRY(dalloc(c, &c->d_large_cnt, 32));
+  RB_HIP(hipMemsetAsync(c->d_large_cnt, 0, 128, c->stream));
   RB_HIP(hipMemsetAsync(c->d_gctr, 0, 16, c->stream));
   RB_TRY(dalloc(c, &c->d_acc, (uint64_t)c->n_img * 3 * cap));
   // per-call dynamic region: step counter (16 B), StepConst, schedule
@@ -317,7 +329,7 @@ int upload_schedule(rb_ctx *c, double t, double dt, int32_t nsteps) {
   // the staging buffer is reused: wait for the previous upload to land
   RB_HIP(hipEventSynchronize(c->dyn_ev));
   uint32_t *ctr = (uint32_t *)c->h_dyn;
-  ctr[0] = 0u; ctr[1] = rows; ctr[2] = 0u; ctr[3] = 0u;
+  ctr[0] = 0u; ctr[1] = 0u; ctr[2] = rows; ctr[3] = 0u;
   StepConst *sc = (StepConst *)(c->h_dyn + 64);
   double *sched = (double *)(c->h_dyn + 256);
   const double half = 0.5 * dt;
@@ -447,12 +459,14 @@ int build_tree(rb_ctx *c, const rb_particles *p) {
   return RB_OK;
 }
 
-int walk(rb_ctx *c, int buf) {
+// walk on the sorted state in buffer `buf`; `slot` selects the step-counter
+// entry holding this step's index
+int walk(rb_ctx *c, int buf, int slot) {
   double *const *b = c->d_px[buf];
   if (c->p.precision == RB_FP64) {
-    RB_PHASE(PH_WALK, launch_walk64(c, b[0], b[1], b[2], nullptr));
+    RB_PHASE(PH_WALK, launch_walk64(c, b[0], b[1], b[2], slot));
   } else {
-    RB_PHASE(PH_WALK, launch_walk32(c, b[0], b[1], b[2], nullptr));
+    RB_PHASE(PH_WALK, launch_walk32(c, b[0], b[1], b[2], slot));
   }
   return RB_OK;
 }
@@ -483,9 +497,8 @@ int step_kernels(rb_ctx *c, int src) {
   RB_PHASE(PH_PERMUTE, launch_permute_state(c, src, dst));
   RB_PHASE(PH_TOPO, launch_topology(c));
   RB_PHASE(PH_MOMENTS, launch_moments(c, c->d_px[dst][0], c->d_px[dst][1], c->d_px[dst][2]));
-  RB_TRY(walk(c, dst));
-  RB_PHASE(PH_POST, launch_post(c, dst));
-  RB_LAUNCH(launch_advance(c));
+  RB_TRY(walk(c, dst, src));
+  RB_PHASE(PH_POST, launch_post(c, dst, src));
   return RB_OK;
 }
 
@@ -739,7 +752,7 @@ int rb_gravity(rb_ctx *c, const rb_particles *p, int64_t n, int64_t n_active, do
   RB_TRY(upload_schedule(c, t, 0.0, 0));
   RB_TRY(mark(c, PH_TOTAL, true));
   RB_TRY(build_tree(c, p));
-  RB_TRY(walk(c, 0));
+  RB_TRY(walk(c, 0, 0));
   RB_PHASE(PH_POST, launch_scatter_acc(c, ax, ay, az));
   RB_TRY(mark(c, PH_TOTAL, false));
   return RB_OK;

@@ -9,9 +9,8 @@
 #define RB_NLEV (RB_DEPTH + 1)             // levels 0..21
 #define RB_NONE 0xFFFFFFFFu                // absent node / end of walk
 #define RB_KEY_DEAD 0xFFFFFFFFFFFFFFFFull  // key of a removed / outside particle
-#define RB_TILE 2048                       // slots per tile (sort, topology)
-#define RB_TILE_THREADS 256
-#define RB_TILE_ROUNDS (RB_TILE / RB_TILE_THREADS)
+#define RB_TILE_MIN 256                    // slots per sort / topology tile
+#define RB_TILE_MAX 8192
 #define RB_MAX_IMAGES 25                   // (2*2+1)^2 for two ghost rings
 
 // device error word bits (reported by the next synchronising call)
@@ -110,6 +109,17 @@ __device__ __forceinline__ bool rb_quantise(double xa, double x0, double W, doub
 
 __device__ __forceinline__ uint64_t rb_key(uint32_t qx, uint32_t qy, uint32_t qz) {
   return (rb_spread3(qx) << 2) | (rb_spread3(qy) << 1) | rb_spread3(qz);
+}
+
+// Count a freshly written key in the first sort pass's histogram: digit =
+// low 11 bits, at the tile of slot s; layout [patch][digit][tile-in-patch].
+__device__ __forceinline__ void rb_hist_add(uint32_t *__restrict__ hist0,
+                                            const uint32_t *__restrict__ patch_tile0,
+                                            uint32_t p, uint32_t start_p, uint32_t tile,
+                                            uint32_t s, uint64_t key) {
+  const uint32_t t0 = patch_tile0[p], nt = patch_tile0[p + 1] - t0;
+  const uint32_t d = (uint32_t)key & 2047u;
+  atomicAdd(&hist0[(size_t)2048 * t0 + (size_t)d * nt + (s - start_p) / tile], 1u);
 }
 
 // index of the patch holding slot s (binary search over patch starts)

@@ -45,8 +45,8 @@ struct rb_ctx {
   // sort
   uint64_t *d_key[2] = {nullptr, nullptr};
   uint32_t *d_idx[2] = {nullptr, nullptr};
-  uint32_t *d_hist = nullptr;       // 256 * n_tiles
-  uint32_t *d_digit_tot = nullptr;  // 256 * P
+  uint32_t *d_hist[2] = {nullptr, nullptr};  // 2048 * n_tiles each, double-buffered
+  uint32_t *d_digit_tot = nullptr;           // 2048 * P
 
   // particles in sorted order (ping-pong for rb_step)
   double *d_px[2][7] = {};          // x y z vx vy vz m
@@ -74,6 +74,8 @@ struct rb_ctx {
   WalkItem *d_items64 = nullptr;
   WalkItem *d_groups = nullptr;     // FP32 walk: groups emitted from the tree
   uint32_t *d_gctr = nullptr;       // [groups emitted, work items taken]
+  uint32_t *d_large = nullptr;      // nodes with more than G particles, by level
+  uint32_t *d_large_cnt = nullptr;  // 22 per-level counts
   double *d_acc = nullptr;          // (n_img or 1) * 3 * cap
 
   // per-call dynamic region [ctr | StepConst | schedule], uploaded from a
@@ -84,7 +86,9 @@ struct rb_ctx {
   StepConst *d_sc = nullptr;
   double *d_sched = nullptr;
   uint32_t sched_cap = 0;
-  uint32_t *d_ctr = nullptr;  // [step k, steps in this call]
+  // [step index read by even steps, by odd steps, steps in this call]
+  uint32_t *d_ctr = nullptr;
+  uint32_t tile = 0;          // slots per sort / topology tile
 
   uint32_t *d_err = nullptr;
   unsigned long long *d_stats = nullptr;  // 8 counters
@@ -115,15 +119,15 @@ hipError_t launch_permute_gravity(rb_ctx *c, const double *x, const double *y,
 hipError_t launch_permute_state(rb_ctx *c, int src, int dst);
 hipError_t launch_topology(rb_ctx *c);
 hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const double *sz);
+hipError_t launch_rowscan_levels(rb_ctx *c);
 hipError_t launch_walk64(rb_ctx *c, const double *sx, const double *sy, const double *sz,
-                         const double *s_img);
+                         int slot);
 hipError_t launch_walk32(rb_ctx *c, const double *sx, const double *sy, const double *sz,
-                         const double *s_img);
+                         int slot);
 hipError_t launch_scatter_acc(rb_ctx *c, double *ax, double *ay, double *az);
 hipError_t launch_prologue(rb_ctx *c, const rb_particles *cp);
-hipError_t launch_post(rb_ctx *c, int buf);
+hipError_t launch_post(rb_ctx *c, int buf, int slot);
 hipError_t launch_epilogue(rb_ctx *c, rb_particles *cp, int buf);
-hipError_t launch_advance(rb_ctx *c);
 hipError_t launch_direct(rb_ctx *c, const rb_particles *cp, uint32_t n, uint32_t n_active,
                          const double *s_img, const int64_t *targets, uint32_t nt,
                          double *ax, double *ay, double *az);
