@@ -27,7 +27,8 @@ __device__ __forceinline__ void rb_node_moments(
     const double *__restrict__ sy, const double *__restrict__ sz,
     const double *__restrict__ msrc, int quad, NodeLink *__restrict__ link,
     double4 *__restrict__ mcom, double *__restrict__ Sarr, double *__restrict__ Qarr,
-    uint32_t n_slots, uint32_t *__restrict__ err) {
+    float4 *__restrict__ qf0, float2 *__restrict__ qf1, uint32_t n_slots,
+    uint32_t *__restrict__ err) {
 #pragma clang fp contract(off)
   const uint32_t first = nfirst[id], last = nlast[id];
   const bool is_leaf = nleaf[id] != 0;
@@ -46,6 +47,8 @@ __device__ __forceinline__ void rb_node_moments(
     mcom[id] = make_double4(0.0, 0.0, 0.0, 0.0);
     Sarr[3 * (size_t)id] = Sarr[3 * (size_t)id + 1] = Sarr[3 * (size_t)id + 2] = 0.0;
     for (int a = 0; a < 6; ++a) Qarr[6 * (size_t)id + a] = 0.0;
+    qf0[id] = make_float4(0.f, 0.f, 0.f, 0.f);
+    qf1[id] = make_float2(0.f, 0.f);
     return;
   }
   double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0, c0, c1, c2;
@@ -123,11 +126,13 @@ __device__ __forceinline__ void rb_node_moments(
   Sarr[3 * (size_t)id + 2] = S2;
   double *q = Qarr + 6 * (size_t)id;
   q[0] = Q0; q[1] = Q1; q[2] = Q2; q[3] = Q3; q[4] = Q4; q[5] = Q5;
+  qf0[id] = make_float4((float)Q0, (float)Q1, (float)Q2, (float)Q3);
+  qf1[id] = make_float2((float)Q4, (float)Q5);
 }
 
 #define RB_MOMENT_ARGS                                                                 \
   nfirst, nlast, nchild, nlastchild, nskip, nleaf, sx, sy, sz, msrc, quad, link, mcom, \
-      Sarr, Qarr, n_slots, err
+      Sarr, Qarr, qf0, qf1, n_slots, err
 #define RB_MOMENT_PARAMS                                                               \
   const uint32_t *__restrict__ nfirst, const uint32_t *__restrict__ nlast,               \
       const uint32_t *__restrict__ nchild, const uint32_t *__restrict__ nlastchild,     \
@@ -135,7 +140,8 @@ __device__ __forceinline__ void rb_node_moments(
       const double *__restrict__ sx, const double *__restrict__ sy,                     \
       const double *__restrict__ sz, const double *__restrict__ msrc, int quad,         \
       NodeLink *__restrict__ link, double4 *__restrict__ mcom, double *__restrict__ Sarr, \
-      double *__restrict__ Qarr, uint32_t n_slots, uint32_t *__restrict__ err
+      double *__restrict__ Qarr, float4 *__restrict__ qf0, float2 *__restrict__ qf1,      \
+      uint32_t n_slots, uint32_t *__restrict__ err
 
 // Groups: the children with at most G particles of nodes with more than G,
 // and roots with at most G; a leaf with more than G particles (deepest
@@ -268,8 +274,8 @@ hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const d
                      c->d_starts, c->P, G, c->d_groups, c->d_gctr, c->d_large, c->d_large_cnt);
 #define RB_MARGS                                                                          \
   c->d_nfirst, c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nskip, c->d_nleaf, sx, sy, sz, \
-      c->d_msrc, c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, (uint32_t)c->cap,   \
-      c->d_err
+      c->d_msrc, c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, c->d_qf0, c->d_qf1,  \
+      (uint32_t)c->cap, c->d_err
   unsigned sgrid = rb_div_up(n, 16);
   if (sgrid > 8192) sgrid = 8192;
   hipLaunchKernelGGL(k_moments_small, dim3(sgrid), dim3(64), 0, c->stream, c->d_groups,

@@ -22,8 +22,9 @@
 #include "rb_internal.h"
 
 #define W32_SCAP 1024  // traversal stack entries per wave (node << 5 | image)
-#define W32_CL 128     // cell list capacity
-#define W32_PL 192     // particle list capacity
+#define W32_CL 96      // cell list capacity (flushed at >= 32 entries)
+#define W32_CFLUSH 32
+#define W32_PL 128     // particle list capacity (flushed at >= 64 entries)
 #define W32_RESERVE (7 * RB_DEPTH + 8)
 
 __device__ __forceinline__ int w32_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -84,18 +85,16 @@ __device__ __forceinline__ void w32_eval_cells(const float4 *__restrict__ cpos,
                                                bool quad, double &ax, double &ay, double &az) {
   F3 f = {0.f, 0.f, 0.f};
   int e = sub;
-  for (; e + 3 * lpp < cnt; e += 4 * lpp) {
-    const float4 a0 = cpos[e], a1 = cpos[e + lpp], a2 = cpos[e + 2 * lpp], a3 = cpos[e + 3 * lpp];
-    float4 q00 = {}, q01 = {}, q02 = {}, q03 = {};
-    float2 q10 = {}, q11 = {}, q12 = {}, q13 = {};
+  for (; e + lpp < cnt; e += 2 * lpp) {
+    const float4 a0 = cpos[e], a1 = cpos[e + lpp];
+    float4 q00 = {}, q01 = {};
+    float2 q10 = {}, q11 = {};
     if (quad) {
-      q00 = cq0[e]; q01 = cq0[e + lpp]; q02 = cq0[e + 2 * lpp]; q03 = cq0[e + 3 * lpp];
-      q10 = cq1[e]; q11 = cq1[e + lpp]; q12 = cq1[e + 2 * lpp]; q13 = cq1[e + 3 * lpp];
+      q00 = cq0[e]; q01 = cq0[e + lpp];
+      q10 = cq1[e]; q11 = cq1[e + lpp];
     }
     w32_cell(a0, q00, q10, px, py, pz, b2, quad, f);
     w32_cell(a1, q01, q11, px, py, pz, b2, quad, f);
-    w32_cell(a2, q02, q12, px, py, pz, b2, quad, f);
-    w32_cell(a3, q03, q13, px, py, pz, b2, quad, f);
   }
   for (; e < cnt; e += lpp) {
     float4 q0 = {};
@@ -123,11 +122,12 @@ __device__ __forceinline__ void w32_eval_parts(const float4 *__restrict__ ppos, 
 }
 
 template <bool QUAD, bool STATS>
-__global__ __launch_bounds__(64) void k_walk32(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_walk32(
     const WalkItem *__restrict__ groups, uint32_t *__restrict__ gctr, int img_split, int n_img,
     int ngx, int ngy, int boundary, const PatchInfo *__restrict__ patch,
     const uint32_t *__restrict__ root, const NodeLink *__restrict__ link,
-    const double4 *__restrict__ mcom, const double *__restrict__ Qarr,
+    const double4 *__restrict__ mcom, const float4 *__restrict__ qf0,
+    const float2 *__restrict__ qf1,
     const double *__restrict__ sx, const double *__restrict__ sy,
     const double *__restrict__ sz, const double *__restrict__ msrc,
     const double *__restrict__ sched, const uint32_t *__restrict__ ctr, uint32_t P,
@@ -189,25 +189,44 @@ __global__ __launch_bounds__(64) void k_walk32(
     if (lane < nim) stk[lane] = (r0 << 5) | (uint32_t)(im0 + lane);
     int cl = 0, pl = 0;
     bool overflow = false;
-    while (sp > 0) {
-      // pop up to 64 entries; each may push 8 children.  Near the limit the
-      // wave pops one entry per round (depth first): that path needs at
-      // most 7 entries per level below, which W32_RESERVE keeps free.
-      int k = sp < 64 ? sp : 64;
+    const float gqs = (float)gq_scale;
+    // Pop up to 64 entries; each may push 8 children.  Near the limit the
+    // wave pops one entry per round (depth first): that path needs at most 7
+    // entries per level below, which W32_RESERVE keeps free.  The node
+    // records of the next batch are requested before the current lists are
+    // evaluated, so their memory latency overlaps the arithmetic.
+    auto pop = [&](int &k, uint32_t &e, NodeLink &lk, double4 &mc, float4 &q0, float2 &q1) {
+      k = sp < 64 ? sp : 64;
       if (sp + 7 * k > W32_SCAP - W32_RESERVE) {
         k = (W32_SCAP - W32_RESERVE - sp) / 7;
-        if (k < 1) k = 1;
+        if (k < 1) k = (sp > 0) ? 1 : 0;
       }
-      if (sp + 7 * k > W32_SCAP) { overflow = true; break; }
       const int base = sp - k;
       const bool has = lane < k;
-      const uint32_t e = has ? stk[base + lane] : 0u;
+      e = has ? stk[base + lane] : 0u;
       sp = base;
-      const uint32_t node = e >> 5;
+      lk = {0u, 0u, 0u, 0u};
+      mc = make_double4(0.0, 0.0, 0.0, 0.0);
+      q0 = make_float4(0.f, 0.f, 0.f, 0.f);
+      q1 = make_float2(0.f, 0.f);
+      if (has) {
+        const uint32_t nd = e >> 5;
+        lk = link[nd];
+        mc = mcom[nd];
+        if (QUAD) { q0 = qf0[nd]; q1 = qf1[nd]; }
+      }
+    };
+    int k;
+    uint32_t e;
+    NodeLink lk;
+    double4 mc;
+    float4 q0;
+    float2 q1;
+    pop(k, e, lk, mc, q0, q1);
+    while (k > 0) {
+      if (sp + 8 * k > W32_SCAP) { overflow = true; break; }
+      const bool has = lane < k;
       const int im = (int)(e & 31u);
-      NodeLink lk = {0u, 0u, 0u, 0u};
-      double4 mc = make_double4(0.0, 0.0, 0.0, 0.0);
-      if (has) { lk = link[node]; mc = mcom[node]; }
       const bool alive = has && mc.w != 0.0;
       double ox = 0.0, oy = 0.0;
       w32_image(im, ngx, ngy, boundary, W, shear, ox, oy);
@@ -239,10 +258,8 @@ __global__ __launch_bounds__(64) void k_walk32(
           cpos[pos] = make_float4((float)((cx - gx) * invW), (float)((cy - gy) * invW),
                                   (float)((cz - gz) * invW), (float)(mc.w * gm_scale));
           if (QUAD) {
-            const double *qq = Qarr + 6 * (size_t)node;
-            cq0[pos] = make_float4((float)(qq[0] * gq_scale), (float)(qq[1] * gq_scale),
-                                   (float)(qq[2] * gq_scale), (float)(qq[3] * gq_scale));
-            cq1[pos] = make_float2((float)(qq[4] * gq_scale), (float)(qq[5] * gq_scale));
+            cq0[pos] = make_float4(q0.x * gqs, q0.y * gqs, q0.z * gqs, q0.w * gqs);
+            cq1[pos] = make_float2(q1.x * gqs, q1.y * gqs);
           }
         }
         cl += __popcll(m);
@@ -285,7 +302,9 @@ __global__ __launch_bounds__(64) void k_walk32(
           pl += __popcll(m);
         }
       }
-      if (cl >= 64) {
+      // next batch in flight while the lists are evaluated
+      pop(k, e, lk, mc, q0, q1);
+      if (cl >= W32_CFLUSH) {
         w32_eval_cells(cpos, cq0, cq1, cl, sub, lpp, px, py, pz, b2, QUAD, ax, ay, az);
         if (STATS) n_cell += (unsigned long long)cl * (unsigned long long)cnt;
         cl = 0;
@@ -334,7 +353,8 @@ hipError_t launch_walk32(rb_ctx *c, const double *sx, const double *sy, const do
   const bool quad = c->p.quadrupole != 0, stats = (c->p.profile & 2) != 0;
 #define RB_W32_ARGS                                                                      \
   c->d_groups, c->d_gctr, c->img_split, c->n_img, c->p.n_ghost[0], c->p.n_ghost[1],       \
-      c->p.boundary, c->d_patch, c->d_root, c->d_link, c->d_mcom, c->d_Q, sx, sy, sz,     \
+      c->p.boundary, c->d_patch, c->d_root, c->d_link, c->d_mcom, c->d_qf0, c->d_qf1, sx,  \
+      sy, sz,                                                                             \
       c->d_msrc, c->d_sched, c->d_ctr, c->P, c->p.G, c->p.softening, th2, c->d_acc,       \
       c->cap, c->d_stats, c->d_err, slot
   if (quad && stats)

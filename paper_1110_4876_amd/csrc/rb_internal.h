@@ -68,6 +68,8 @@ struct rb_ctx {
   double4 *d_mcom = nullptr;  // com.x com.y com.z M
   double *d_S = nullptr;      // 3 per node
   double *d_Q = nullptr;      // 6 per node
+  float4 *d_qf0 = nullptr;    // FP32 copy of Q for the grouped walk: xx xy xz yy
+  float2 *d_qf1 = nullptr;    //                                       yz zz
 
   // walk
   std::vector<WalkItem> h_items64;  // FP64 walk: 64 Morton-consecutive slots
