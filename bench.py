@@ -60,7 +60,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="sheet50k")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32"])
-    ap.add_argument("--theta", type=float, default=None, help="fix theta instead of searching")
+    ap.add_argument("--theta", type=float, default=None,
+                    help="fix theta (and the options below) instead of autotuning")
+    ap.add_argument("--leaf-size", type=int, default=1)
+    ap.add_argument("--group-size", type=int, default=64)
+    ap.add_argument("--split-images", type=int, default=-1)
+    ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -71,7 +76,7 @@ def main():
 
     import numpy as np
     import torch
-    from paper_1110_4876_amd import inputs, rb
+    from paper_1110_4876_amd import autotune, inputs, rb
     from paper_1110_4876_amd.metrics import force_errors
 
     torch.cuda.set_device(0)
@@ -116,46 +121,69 @@ def main():
     paths = ["fp64", "fp32"] if args.precision == "both" else [args.precision]
     for path in paths:
         prec = rb.RB_FP64 if path == "fp64" else rb.RB_FP32_MIXED
-        # operating point: largest theta with rms error <= 1e-4
-        chosen, err = None, None
-        cands = [args.theta] if args.theta else THETAS
+        # operating point: the autotuner's fastest (leaf, group, image split,
+        # launch mode) at its largest theta with rms error <= 1e-4; or a
+        # fixed theta with the library defaults
         try:
-            for th in cands:
-                ctx = rb.rb_create(rb.params_from_problem(pr.params, precision=prec, theta=th), n)
-                e = force_errors(accel(ctx), ref)
+            if args.theta:
+                cfg = dict(theta=args.theta, leaf_size=args.leaf_size,
+                           group_size=args.group_size, split_images=args.split_images,
+                           use_graph=args.graph)
+                ctx = rb.rb_create(rb.params_from_problem(
+                    pr.params, precision=prec, **{k: v for k, v in cfg.items()
+                                                  if k != "use_graph"}), n)
+                err = force_errors(accel(ctx), ref)
                 rb.rb_destroy(ctx)
-                log(f"[{path}] theta={th}: rms={e['rms']:.3e} max={e['max']:.3e}")
-                if e["rms"] <= RMS_TARGET or args.theta:
-                    chosen, err = th, e
-                    break
-        except rb.RBError as ex:
+            else:
+                t0 = time.perf_counter()
+                cfg = autotune.tune(pr, X, ref, tg, t_kick, precision=prec,
+                                    rms_target=RMS_TARGET, log=log)
+                err = cfg["errors"]
+                log(f"[{path}] tuned in {time.perf_counter() - t0:.1f} s")
+        except (rb.RBError, RuntimeError) as ex:
             log(f"[{path}] unavailable: {ex}")
             continue
-        if chosen is None:
-            log(f"[{path}] no theta in {cands} reaches rms <= {RMS_TARGET}")
-            continue
+        chosen = cfg["theta"]
+        log(f"[{path}] theta={chosen} leaf={cfg['leaf_size']} group={cfg['group_size']} "
+            f"split={cfg['split_images']} graph={cfg['use_graph']}: rms={err['rms']:.3e} "
+            f"max={err['max']:.3e}")
         st, flops = interactions(chosen)
-        # timed run: K steps in one call, walk launches timed with HIP events
-        p = rb.params_from_problem(pr.params, precision=prec, theta=chosen, profile=4)
-        ctx = rb.rb_create(p, n)
-        W = {k: v.clone() for k, v in X.items()}
-        pw = rb.particles(W["x"], W["y"], W["z"], W["m"], W["vx"], W["vy"], W["vz"])
-        rb.rb_step(ctx, pw, n, n, 0.0, pr.dt, args.warmup)
-        rb.rb_sync(ctx)
-        rb.rb_stats(ctx)  # discard warm-up timers
-        T = {k: v.clone() for k, v in X.items()}
-        pt = rb.particles(T["x"], T["y"], T["z"], T["m"], T["vx"], T["vy"], T["vz"])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rb.rb_step(ctx, pt, n, n, 0.0, pr.dt, args.steps)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        rb.rb_sync(ctx)
-        s2 = rb.rb_stats(ctx)
-        rb.rb_destroy(ctx)
+        # timed run: K steps in one call.  Eager launches carry HIP events
+        # around every walk launch; a graph replay carries none, so its walk
+        # launches are timed in a second, eager pass of the same K steps.
+        tuned = dict(theta=chosen, leaf_size=cfg["leaf_size"], group_size=cfg["group_size"],
+                     split_images=cfg["split_images"])
+
+        def run(use_graph, profile):
+            p = rb.params_from_problem(pr.params, precision=prec, use_graph=use_graph,
+                                       profile=profile, **tuned)
+            ctx = rb.rb_create(p, n)
+            W = {k: v.clone() for k, v in X.items()}
+            pw = rb.particles(W["x"], W["y"], W["z"], W["m"], W["vx"], W["vy"], W["vz"])
+            rb.rb_step(ctx, pw, n, n, 0.0, pr.dt, args.warmup)
+            rb.rb_sync(ctx)
+            rb.rb_stats(ctx)  # discard warm-up timers
+            T = {k: v.clone() for k, v in X.items()}
+            pt = rb.particles(T["x"], T["y"], T["z"], T["m"], T["vx"], T["vy"], T["vz"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rb.rb_step(ctx, pt, n, n, 0.0, pr.dt, args.steps)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rb.rb_sync(ctx)
+            s = rb.rb_stats(ctx)
+            rb.rb_destroy(ctx)
+            return t0, t1, s
+
+        t0, t1, s2 = run(cfg["use_graph"], 0 if cfg["use_graph"] else 4)
+        if cfg["use_graph"]:
+            _, _, s2 = run(0, 4)
         ms_step = (t1 - t0) * 1e3 / args.steps
         walk_ms = s2["ms"]["walk"] / max(1, s2["calls"]["walk"])
-        results[path] = dict(theta=chosen, errors=err, ms_per_step=ms_step,
+        results[path] = dict(theta=chosen, leaf_size=cfg["leaf_size"],
+                             group_size=cfg["group_size"] if path == "fp32" else None,
+                             split_images=cfg["split_images"], use_graph=cfg["use_graph"],
+                             errors=err, ms_per_step=ms_step,
                              particle_steps_per_s=n * args.steps / (t1 - t0),
                              walk_ms=walk_ms, walk_launches=s2["calls"]["walk"],
                              interactions=dict(open_tests=st["open_tests"], cells=st["cells"],
@@ -216,7 +244,8 @@ def main():
         "config": {"workload": wdesc, "n": n, "images": 9 if pr.params["boundary"] else 1,
                    "path": main_path, "theta": r["theta"],
                    "quadrupole": bool(pr.params["quadrupole"]),
-                   "leaf_size": int(pr.params.get("n_leaf", 1))},
+                   "leaf_size": r["leaf_size"], "group_size": r["group_size"],
+                   "split_images": r["split_images"], "hip_graph": bool(r["use_graph"])},
         "paths": {k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,

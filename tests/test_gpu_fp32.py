@@ -37,16 +37,25 @@ def _sampled_direct(orc, pr, t, k, seed=0):
                           s=orc.shear_offset(p, t), targets=tg)
 
 
-def test_c1_operating_point_meets_gate(orc):
-    # the 50,000-particle ring patch: FP32-mixed, groups of 64, theta = 0.35
+_C1_REF = {}
+
+
+@pytest.mark.parametrize("group,theta,split", [(64, 0.4, 0), (32, 0.4, 0), (32, 0.4, 1),
+                                               (16, 0.35, 0)])
+def test_c1_operating_point_meets_gate(orc, group, theta, split):
+    # the 50,000-particle ring patch in the launch shapes the benchmark's
+    # autotuner picks from: FP32-mixed at these (group, theta, image split)
     # meets rms <= 1e-4 against the FP64 direct sum (Eq. 1 over the images)
+    # on the benchmark's 4096 sampled targets
     from gpu_util import Dev, gravity, make_ctx
     from paper_1110_4876_amd import rb
     from paper_1110_4876_amd.metrics import force_errors
-    pr = inputs.sheet(50000, seed=0).with_params(theta=0.35)
+    pr = inputs.sheet(50000, seed=0).with_params(theta=theta)
     t = 0.5 * pr.dt
-    tg, ref = _sampled_direct(orc, pr, t, 1024)
-    ctx = make_ctx(pr, precision=rb.RB_FP32_MIXED)
+    if not _C1_REF:
+        _C1_REF["tg"], _C1_REF["ref"] = _sampled_direct(orc, pr, t, 4096)
+    tg, ref = _C1_REF["tg"], _C1_REF["ref"]
+    ctx = make_ctx(pr, precision=rb.RB_FP32_MIXED, group_size=group, split_images=split)
     try:
         a = gravity(ctx, Dev(pr, with_v=False), pr.n, t)
     finally:

@@ -161,17 +161,19 @@ def test_gravity_is_deterministic():
     np.testing.assert_array_equal(a, b)
 
 
-def test_c1_full_size_sampled(orc):
+@pytest.mark.parametrize("theta,split", [(0.3, 1), (0.3, 0), (0.5, -1)])
+def test_c1_full_size_sampled(orc, theta, split):
     # the 50,000-particle sheet patch at full size: sampled targets of the
-    # oracle walk against the GPU walk in the launch shape the benchmark uses
+    # oracle walk against the GPU walk, in the launch shapes the benchmark
+    # times (one work item per group and image, or all images per item)
     from gpu_util import Dev, gravity, make_ctx, rms_rel
     from paper_1110_4876_amd import rb
-    pr = inputs.sheet(50000, seed=0)
+    pr = inputs.sheet(50000, seed=0).with_params(theta=theta)
     t = 0.5 * pr.dt
     p = orc.make_params(**pr.params)
     tg = inputs.sample_targets(pr.n, 4096, seed=0)
     ref = orc.bh(p, pr.x, pr.y, pr.z, pr.m, s=orc.shear_offset(p, t), targets=tg)
-    ctx = make_ctx(pr)
+    ctx = make_ctx(pr, split_images=split)
     try:
         a = gravity(ctx, Dev(pr, with_v=False), pr.n, t)
     finally:
