@@ -2,21 +2,22 @@
 """Tree-gravity throughput on one MI355X: particle-steps/s of full
 drift-kick-drift steps (keys, sort, permute, topology, moments, walk, kick,
 drift) through the C ABI, FP32-mixed grouped walk against the plain FP64
-per-particle walk, each at the largest opening angle whose rms force error
-against the FP64 direct sum is <= 1e-4.
+per-particle walk, each at the autotuned operating point: the fastest
+(leaf size, group size, image split, launch mode) at the largest opening
+angle whose rms force error against the FP64 direct sum is <= 1e-4.
 
 Default workload: one shearing-sheet ring patch of 50,000 particles
 (radii dN/dR ~ R^-3 on [1, 4] m, 400 kg/m^3, optical depth 0.5,
 Omega = 1.95e-4 s^-1, 3x3 ghost boxes, quadrupoles, dt = 1e-3 2 pi / Omega),
-synthetic and seeded.  Prints one JSON line on stdout; diagnostics go to
-stderr.
+100 timed steps, synthetic and seeded.  Other workloads: sheet1m, plummer8m,
+batch256 (256 independent patches, one launch per kernel for all).
+Prints one JSON line on stdout; diagnostics go to stderr.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -26,8 +27,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "tree-gravity particle-steps/s, FP32-mixed vs FP64 plain, at rms force err ≤1e-4"
 RMS_TARGET = 1e-4
-THETAS = [0.7, 0.6, 0.55, 0.5, 0.47, 0.45, 0.42, 0.4, 0.37, 0.35, 0.32, 0.3, 0.28, 0.26,
-          0.24, 0.22, 0.2, 0.18, 0.16, 0.14]
 # algorithmic work per term (flops; rsqrt counted as one): opening test 9,
 # monopole (particle or cell) 20, quadrupole cell 56
 FLOP_OPEN, FLOP_MONO, FLOP_QUAD = 9, 20, 56
@@ -35,6 +34,9 @@ PEAK_F64 = 78.6e12    # 256 CU x 64 FP64 FMA lanes x 2 flop x 2.4 GHz
 PEAK_F32 = 157.3e12   # published, counts packed FP32 (dual FMA per lane)
 WALK_SRC = {"fp64": "paper_1110_4876_amd/csrc/k_walk64.hip",
             "fp32": "paper_1110_4876_amd/csrc/k_walk32.hip"}
+# workload -> (default steps, default warm-up steps)
+DEFAULT_STEPS = {"sheet50k": (100, 10), "sheet1m": (10, 2), "plummer8m": (10, 2),
+                 "batch256": (50, 5)}
 
 
 def log(*a):
@@ -44,21 +46,82 @@ def log(*a):
 def workload(name):
     from paper_1110_4876_amd import inputs
     if name == "sheet50k":
-        return inputs.sheet(50000, seed=0), "sheet50k: shearing-sheet patch N=50000, tau=0.5, 3x3 images, quadrupole, 100-step run"
+        return (inputs.sheet(50000, seed=0),
+                "sheet50k: shearing-sheet patch N=50000, tau=0.5, 3x3 images, quadrupole")
     if name == "sheet1m":
-        return inputs.sheet(1_000_000, seed=0), "sheet1m: shearing-sheet patch N=1000000, tau=0.5, 3x3 images, quadrupole"
+        return (inputs.sheet(1_000_000, seed=0),
+                "sheet1m: shearing-sheet patch N=1000000, tau=0.5, 3x3 images, quadrupole")
     if name == "plummer8m":
         return (inputs.plummer(1 << 23, seed=0, b=0.001, quadrupole=True, dt=1e-4),
                 "plummer8m: Plummer sphere N=8388608, b=0.001, open, quadrupole")
+    if name == "batch256":
+        return (inputs.batch(256, seed0=0),
+                "batch256: 256 shearing-sheet patches, N_p ~ U{2000..64000}, "
+                "tau_p ~ U(0.2, 1.0), 3x3 images, quadrupole")
     raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(system, theta, seconds):
+    """The oracle (FP64, insertion build, OpenMP walk) on a bounded sample."""
+    import numpy as np
+    import oracle
+    pr0 = system.problems[0]
+    if system.batch:
+        # whole patches, one after another, full DKD steps
+        done, t0 = 0, time.perf_counter()
+        k = 0
+        while True:
+            pr = system.problems[k % len(system.problems)]
+            op = oracle.make_params(**dict(pr.params, theta=theta))
+            oracle.step(op, pr.state(), pr.m, 0.0, pr.dt, 1, use_tree=True)
+            done += pr.n
+            k += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        dt = time.perf_counter() - t0
+        return {"value": done / dt, "unit": "particle-steps/s", "cores": oracle.num_threads(),
+                "kind": "oracle",
+                "sample": f"one full DKD step of each of the first {k} patches "
+                          f"({done} particle-steps), theta={theta}"}
+    if system.n <= 200_000:
+        op = oracle.make_params(**dict(pr0.params, theta=theta))
+        st = pr0.state()
+        steps, t0 = 0, time.perf_counter()
+        while True:
+            st = oracle.step(op, st, pr0.m, steps * pr0.dt, pr0.dt, 1, use_tree=True)
+            steps += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        dt = time.perf_counter() - t0
+        return {"value": system.n * steps / dt, "unit": "particle-steps/s",
+                "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"{steps} full DKD steps of the same {system.n}-particle system "
+                          f"with the oracle tree walk at theta={theta}"}
+    # large systems: one tree build, then the walk for a sample of targets;
+    # a step is estimated as build + walk time scaled to all particles
+    op = oracle.make_params(**dict(pr0.params, theta=theta))
+    t0 = time.perf_counter()
+    tree = oracle.Tree(op, pr0.x, pr0.y, pr0.z, pr0.m, pr0.n_active)
+    t_build = time.perf_counter() - t0
+    k = 4096
+    tg = np.sort(np.random.default_rng(1).choice(system.n, size=k, replace=False))
+    t1 = time.perf_counter()
+    tree.walk(s=0.0, targets=tg)
+    t_walk = time.perf_counter() - t1
+    per_step = t_build + t_walk * system.n / k
+    return {"value": system.n / per_step, "unit": "particle-steps/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"one oracle tree build ({t_build:.1f} s) plus the walk for {k} sampled "
+                      f"targets ({t_walk:.2f} s), scaled to one step of all {system.n} "
+                      f"particles, theta={theta}"}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="sheet50k")
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="sheet50k", choices=sorted(DEFAULT_STEPS))
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32"])
     ap.add_argument("--theta", type=float, default=None,
                     help="fix theta (and the options below) instead of autotuning")
@@ -68,129 +131,147 @@ def main():
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (the known-size "
+                         "kernel that scales the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    steps_d, warm_d = DEFAULT_STEPS[args.workload]
+    args.steps = steps_d if args.steps is None else args.steps
+    args.warmup = warm_d if args.warmup is None else args.warmup
 
-    import numpy as np
     import torch
-    from paper_1110_4876_amd import autotune, inputs, rb
+    from paper_1110_4876_amd import autotune, rb
     from paper_1110_4876_amd.metrics import force_errors
+    from paper_1110_4876_amd.system import System
 
     torch.cuda.set_device(0)
-    pr, wdesc = workload(args.workload)
-    n = pr.n
-    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")  # noqa: E731
-    X = {k: dev(getattr(pr, k)) for k in ("x", "y", "z", "vx", "vy", "vz", "m")}
-    parts0 = rb.particles(X["x"], X["y"], X["z"], X["m"], X["vx"], X["vy"], X["vz"])
-    t_kick = 0.5 * pr.dt
-    tg = inputs.sample_targets(n, 4096, seed=0)
-    tg_dev = torch.as_tensor(tg, device="cuda")
-
-    # reference: FP64 direct sum (Eq. 1 over all images) on the samples
-    ctx_ref = rb.rb_create(rb.params_from_problem(pr.params), n)
-    ax = torch.empty(len(tg), dtype=torch.float64, device="cuda")
-    ay, az = torch.empty_like(ax), torch.empty_like(ax)
-    rb.rb_direct(ctx_ref, parts0, n, n, t_kick, tg_dev, ax, ay, az)
-    rb.rb_sync(ctx_ref)
-    ref = torch.stack([ax, ay, az], 1).cpu().numpy()
-    rb.rb_destroy(ctx_ref)
-
-    def accel(ctx):
-        gx = torch.empty(n, dtype=torch.float64, device="cuda")
-        gy, gz = torch.empty_like(gx), torch.empty_like(gx)
-        rb.rb_gravity(ctx, parts0, n, n, t_kick, gx, gy, gz)
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_read_bytes": nbytes, "copy_write_bytes": nbytes, "launches": 5}))
+        return
+    prob, wdesc = workload(args.workload)
+    sysm = System(prob)
+    n = sysm.n
+    t_kick = 0.5 * sysm.dt
+    tg = sysm.sample_targets(4096, 16, seed=0)
+    # reference: FP64 direct sum (Eq. 1 over all images) on the samples, for
+    # the initial state and for a state at the end of a run as long as the
+    # timed one (advanced with the FP64 walk at theta 0.3); the operating
+    # point must meet the accuracy target on both
+    ref = sysm.direct(tg, t_kick)
+    late = sysm.clone()
+    ctx = sysm.create(rb.RB_FP64, theta=0.3)
+    try:
+        sysm.step(ctx, late, 0.0, args.steps)
         rb.rb_sync(ctx)
-        return torch.stack([gx, gy, gz], 1).cpu().numpy()[tg]
+    finally:
+        rb.rb_destroy(ctx)
+    t_late = (args.steps + 0.5) * sysm.dt
+    checks = [(late, t_late, sysm.direct(tg, t_late, late))]
+    quad = bool(sysm.params["quadrupole"])
 
     def interactions(theta):
-        """per-particle FP64 walk counts at theta (the algorithmic work)"""
-        p = rb.params_from_problem(pr.params, theta=theta, profile=2)
-        ctx = rb.rb_create(p, n)
-        accel(ctx)
-        s = rb.rb_stats(ctx)
-        rb.rb_destroy(ctx)
-        quad = bool(pr.params["quadrupole"])
+        """per-particle FP64 walk counts at theta, leaf 1 (the algorithmic work)"""
+        ctx = sysm.create(rb.RB_FP64, theta=theta, leaf_size=1, profile=2)
+        try:
+            sysm.gravity(ctx, t_kick)
+            s = rb.rb_stats(ctx)
+        finally:
+            rb.rb_destroy(ctx)
         flops = (FLOP_OPEN * s["open_tests"] + FLOP_MONO * s["pp"] +
                  (FLOP_QUAD if quad else FLOP_MONO) * s["cells"])
         return s, flops
+
+    def timed(prec, cfg, use_graph, profile):
+        """warm-up, then exactly K steps in one call from the initial state"""
+        knobs = {k: cfg[k] for k in ("theta", "leaf_size", "group_size", "split_images")}
+        ctx = sysm.create(prec, use_graph=use_graph, profile=profile, **knobs)
+        try:
+            W = sysm.clone()
+            sysm.step(ctx, W, 0.0, args.warmup)
+            rb.rb_sync(ctx)
+            rb.rb_stats(ctx)  # discard warm-up timers
+            T = sysm.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sysm.step(ctx, T, 0.0, args.steps)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rb.rb_sync(ctx)
+            s = rb.rb_stats(ctx)
+            t_end = args.steps * sysm.dt + t_kick
+        finally:
+            rb.rb_destroy(ctx)
+        return t1 - t0, s, T, t_end
 
     results = {}
     paths = ["fp64", "fp32"] if args.precision == "both" else [args.precision]
     for path in paths:
         prec = rb.RB_FP64 if path == "fp64" else rb.RB_FP32_MIXED
-        # operating point: the autotuner's fastest (leaf, group, image split,
-        # launch mode) at its largest theta with rms error <= 1e-4; or a
-        # fixed theta with the library defaults
         try:
             if args.theta:
                 cfg = dict(theta=args.theta, leaf_size=args.leaf_size,
                            group_size=args.group_size, split_images=args.split_images,
                            use_graph=args.graph)
-                ctx = rb.rb_create(rb.params_from_problem(
-                    pr.params, precision=prec, **{k: v for k, v in cfg.items()
-                                                  if k != "use_graph"}), n)
-                err = force_errors(accel(ctx), ref)
-                rb.rb_destroy(ctx)
+                ctx = sysm.create(prec, **{k: v for k, v in cfg.items() if k != "use_graph"})
+                try:
+                    err = force_errors(sysm.gravity(ctx, t_kick).cpu().numpy()[tg], ref)
+                    for X, t, r in checks:
+                        e = force_errors(sysm.gravity(ctx, t, X).cpu().numpy()[tg], r)
+                        err = e if e["rms"] > err["rms"] else err
+                finally:
+                    rb.rb_destroy(ctx)
             else:
-                t0 = time.perf_counter()
-                cfg = autotune.tune(pr, X, ref, tg, t_kick, precision=prec,
-                                    rms_target=RMS_TARGET, log=log)
+                c0 = time.perf_counter()
+                cfg = autotune.tune(sysm, ref, tg, t_kick, precision=prec,
+                                    rms_target=RMS_TARGET, log=log, checks=checks)
                 err = cfg["errors"]
-                log(f"[{path}] tuned in {time.perf_counter() - t0:.1f} s")
+                log(f"[{path}] tuned in {time.perf_counter() - c0:.1f} s")
         except (rb.RBError, RuntimeError) as ex:
             log(f"[{path}] unavailable: {ex}")
             continue
-        chosen = cfg["theta"]
-        log(f"[{path}] theta={chosen} leaf={cfg['leaf_size']} group={cfg['group_size']} "
+        log(f"[{path}] theta={cfg['theta']} leaf={cfg['leaf_size']} group={cfg['group_size']} "
             f"split={cfg['split_images']} graph={cfg['use_graph']}: rms={err['rms']:.3e} "
             f"max={err['max']:.3e}")
-        st, flops = interactions(chosen)
-        # timed run: K steps in one call.  Eager launches carry HIP events
-        # around every walk launch; a graph replay carries none, so its walk
-        # launches are timed in a second, eager pass of the same K steps.
-        tuned = dict(theta=chosen, leaf_size=cfg["leaf_size"], group_size=cfg["group_size"],
-                     split_images=cfg["split_images"])
-
-        def run(use_graph, profile):
-            p = rb.params_from_problem(pr.params, precision=prec, use_graph=use_graph,
-                                       profile=profile, **tuned)
-            ctx = rb.rb_create(p, n)
-            W = {k: v.clone() for k, v in X.items()}
-            pw = rb.particles(W["x"], W["y"], W["z"], W["m"], W["vx"], W["vy"], W["vz"])
-            rb.rb_step(ctx, pw, n, n, 0.0, pr.dt, args.warmup)
-            rb.rb_sync(ctx)
-            rb.rb_stats(ctx)  # discard warm-up timers
-            T = {k: v.clone() for k, v in X.items()}
-            pt = rb.particles(T["x"], T["y"], T["z"], T["m"], T["vx"], T["vy"], T["vz"])
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            rb.rb_step(ctx, pt, n, n, 0.0, pr.dt, args.steps)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            rb.rb_sync(ctx)
-            s = rb.rb_stats(ctx)
-            rb.rb_destroy(ctx)
-            return t0, t1, s
-
-        t0, t1, s2 = run(cfg["use_graph"], 0 if cfg["use_graph"] else 4)
+        st, flops = interactions(cfg["theta"])
+        # Eager launches carry HIP events around every walk launch; a graph
+        # replay carries none, so its walk launches are timed in a second,
+        # eager pass of the same K steps.
+        secs, s2, T, t_end = timed(prec, cfg, cfg["use_graph"], 0 if cfg["use_graph"] else 4)
         if cfg["use_graph"]:
-            _, _, s2 = run(0, 4)
-        ms_step = (t1 - t0) * 1e3 / args.steps
+            _, s2, _, _ = timed(prec, cfg, 0, 4)
+        # the accuracy gate again on the state at the end of the timed run
+        ctx = sysm.create(prec, **{k: cfg[k] for k in ("theta", "leaf_size", "group_size",
+                                                       "split_images")})
+        try:
+            a_end = sysm.gravity(ctx, t_end, T).cpu().numpy()[tg]
+        finally:
+            rb.rb_destroy(ctx)
+        err_end = force_errors(a_end, sysm.direct(tg, t_end, T))
+        ms_step = secs * 1e3 / args.steps
         walk_ms = s2["ms"]["walk"] / max(1, s2["calls"]["walk"])
-        results[path] = dict(theta=chosen, leaf_size=cfg["leaf_size"],
+        results[path] = dict(theta=cfg["theta"], leaf_size=cfg["leaf_size"],
                              group_size=cfg["group_size"] if path == "fp32" else None,
                              split_images=cfg["split_images"], use_graph=cfg["use_graph"],
-                             errors=err, ms_per_step=ms_step,
-                             particle_steps_per_s=n * args.steps / (t1 - t0),
+                             errors=err, errors_end_of_run=err_end, ms_per_step=ms_step,
+                             particle_steps_per_s=n * args.steps / secs,
                              walk_ms=walk_ms, walk_launches=s2["calls"]["walk"],
                              interactions=dict(open_tests=st["open_tests"], cells=st["cells"],
                                                pp=st["pp"]),
-                             algorithmic_flops_per_walk=flops)
-        log(f"[{path}] theta={chosen} {ms_step:.3f} ms/step, walk {walk_ms:.3f} ms, "
-            f"{results[path]['particle_steps_per_s']:.3e} particle-steps/s")
+                             algorithmic_flops_per_walk=flops,
+                             interactions_per_s=(st["cells"] + st["pp"]) / (walk_ms * 1e-3))
+        log(f"[{path}] {ms_step:.3f} ms/step, walk {walk_ms:.3f} ms, "
+            f"{results[path]['particle_steps_per_s']:.3e} particle-steps/s, "
+            f"end-of-run rms {err_end['rms']:.3e}")
 
     if not results:
         raise SystemExit("no path produced a result")
@@ -211,22 +292,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        op = oracle.make_params(**dict(pr.params, theta=r["theta"]))
-        st0 = pr.state()
-        steps = 0
-        c0 = time.perf_counter()
-        while True:
-            st0 = oracle.step(op, st0, pr.m, steps * pr.dt, pr.dt, 1, use_tree=True)
-            steps += 1
-            if time.perf_counter() - c0 >= args.cpu_seconds:
-                break
-        c1 = time.perf_counter()
-        cpu = {"value": n * steps / (c1 - c0), "unit": "particle-steps/s",
-               "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"{steps} full DKD steps of the same {n}-particle patch with the "
-                         f"oracle tree walk (FP64, insertion build, OpenMP over targets) "
-                         f"at theta={r['theta']}"}
+        cpu = cpu_baseline(sysm, r["theta"], args.cpu_seconds)
 
     out = {
         "metric": METRIC,
@@ -241,12 +307,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if main_path == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": wdesc, "n": n, "images": 9 if pr.params["boundary"] else 1,
-                   "path": main_path, "theta": r["theta"],
-                   "quadrupole": bool(pr.params["quadrupole"]),
+        "config": {"workload": wdesc, "n": n, "patches": len(sysm.problems),
+                   "images": 9 if sysm.params["boundary"] else 1,
+                   "path": main_path, "theta": r["theta"], "quadrupole": quad,
                    "leaf_size": r["leaf_size"], "group_size": r["group_size"],
                    "split_images": r["split_images"], "hip_graph": bool(r["use_graph"])},
-        "paths": {k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
+        "paths": results,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -1,12 +1,13 @@
-"""Autotuner for the tree walk: leaf size, walk group size (FP32-mixed path)
-and image schedule, each at the largest opening angle that keeps the rms
-force error at or below a target against a reference (normally the FP64
-direct sum on sampled particles).  Candidates are timed with full drift-kick-drift steps
-through the C ABI, so the build's share (which shrinks with larger leaves)
-counts as much as the walk's.
+"""Autotuner for the tree walk: leaf size, walk group size (FP32-mixed path),
+image schedule and launch mode, each at the largest opening angle that
+keeps the rms force error at or below a target against a reference
+(normally the FP64 direct sum on sampled particles).  Candidates are timed
+with full drift-kick-drift steps through the C ABI, so the build's share
+(which shrinks with larger leaves) counts as much as the walk's.
 
-The result is a plain dict; ``cache`` (a JSON path) stores results keyed by
-the workload signature and the GPU architecture.
+Works on a `System` (one particle set or a batch of patches).  The result is
+a plain dict; ``cache`` (a JSON path) stores results keyed by the workload
+signature, the GPU architecture and the accuracy target.
 """
 from __future__ import annotations
 
@@ -31,40 +32,31 @@ def _arch() -> str:
         return "unknown"
 
 
-def signature(problem) -> str:
-    p = problem.params
-    return (f"{problem.name}|n={problem.n}|W={p['W']:.6g}|b={p['b']:.3g}|quad={int(bool(p['quadrupole']))}"
-            f"|bnd={p['boundary']}|ng={tuple(p['ng'])}")
+def tune(system, ref, targets, t_kick, precision=rb.RB_FP32_MIXED, rms_target=1e-4,
+         leafs=(1, 2, 4, 8), groups=(16, 32, 64), splits=(0, 1), graphs=(0, 1), steps=20,
+         repeats=2, cache=None, log=None, checks=()):
+    """Search (leaf, group, split) x theta for one precision path, then time
+    each accepted candidate in every launch mode.
 
-
-def _accel(ctx, parts, n, t, targets):
-    import torch
-    ax = torch.empty(n, dtype=torch.float64, device="cuda")
-    ay, az = torch.empty_like(ax), torch.empty_like(ax)
-    rb.rb_gravity(ctx, parts, n, n, t, ax, ay, az)
-    rb.rb_sync(ctx)
-    return torch.stack([ax, ay, az], 1)[targets].cpu().numpy()
-
-
-def tune(problem, dev, ref, targets, t_kick, precision=None, rms_target=1e-4,
-         leafs=(1, 2, 4, 8), groups=(16, 32, 64), splits=(0, 1), graphs=(0, 1), steps=5,
-         repeats=2, cache=None, log=None):
-    """Search (leaf, group, split) x theta for one precision path (default
-    FP32-mixed; the FP64 per-particle walk has no group size).
-
-    dev: dict of device tensors x, y, z, vx, vy, vz, m (caller order).
-    ref: reference accelerations at `targets` (rows), time t_kick.
-    graphs: launch modes timed for each candidate (0 eager, 1 HIP-graph
-    replay of the step); they do not change the result.
+    system: a paper_1110_4876_amd.system.System.
+    ref: reference accelerations (rows) at `targets`, time t_kick, for the
+    system's initial state.
+    checks: further (state, time, reference) triples -- e.g. a state from
+    late in the run -- that every accepted candidate must also meet; the
+    reported errors are those of the worst check.
+    graphs: launch modes (0 eager, 1 HIP-graph replay of the step); the
+    first is timed for every candidate, the others for the three fastest.
+    They do not change the result.
+    The FP64 per-particle walk has no group size (only 64 is tried).
     Returns dict(leaf_size, group_size, split_images, use_graph, theta,
-    ms_per_step, errors, table).
+    ms_per_step, rms, max, errors, table).
     """
     import torch
-    if precision is None:
-        precision = rb.RB_FP32_MIXED
     if precision == rb.RB_FP64:
         groups = (64,)
-    key = f"{signature(problem)}|{_arch()}|prec={precision}|target={rms_target:g}"
+    if system.params["boundary"] == 0:
+        splits = (0,)  # one image: nothing to split
+    key = f"{system.signature()}|{_arch()}|prec={precision}|target={rms_target:g}"
     if cache and os.path.exists(cache):
         try:
             hit = json.load(open(cache)).get(key)
@@ -72,61 +64,98 @@ def tune(problem, dev, ref, targets, t_kick, precision=None, rms_target=1e-4,
                 return hit
         except (OSError, ValueError):
             pass
-    n = problem.n
-    parts = rb.particles(dev["x"], dev["y"], dev["z"], dev["m"], dev["vx"], dev["vy"], dev["vz"])
-    tg = torch.as_tensor(np.asarray(targets, dtype=np.int64), device="cuda")
+    targets = np.asarray(targets, dtype=np.int64)
+
+    all_checks = [(None, t_kick, ref)] + list(checks)
+
+    def error_at(th, knobs):
+        ctx = system.create(precision, theta=th, **knobs)
+        worst = None
+        try:
+            for X, t, r in all_checks:
+                a = system.gravity(ctx, t, X).cpu().numpy()[targets]
+                e = force_errors(a, r)
+                if worst is None or e["rms"] > worst["rms"]:
+                    worst = e
+                if worst["rms"] > rms_target:
+                    break
+        finally:
+            rb.rb_destroy(ctx)
+        return worst
+
+    def time_steps(knobs, th, graph):
+        ctx = system.create(precision, theta=th, use_graph=graph, **knobs)
+        try:
+            X = system.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            system.step(ctx, X, 0.0, 1)
+            rb.rb_sync(ctx)
+            first = time.perf_counter() - t0
+            # about 0.2 s of steps per repeat, between 2 and `steps`
+            k = int(min(steps, max(2, 0.2 / max(first, 1e-6))))
+            times = []
+            for _ in range(repeats):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                system.step(ctx, X, 0.0, k)
+                rb.rb_sync(ctx)
+                times.append((time.perf_counter() - t0) * 1e3 / k)
+        finally:
+            rb.rb_destroy(ctx)
+        return min(times)
+
+    # phase 1: for every (leaf, group, split), the largest theta on the grid
+    # meeting the target (local search from the last candidate's theta: the
+    # error grows with theta), timed with eager launches
     table = []
-    best = None
+    i_start = 0
     for leaf in leafs:
         for group in groups:
             for split in splits:
-                if problem.params["boundary"] == 0 and split:
-                    continue  # one image: nothing to split
-                chosen, err = None, None
-                for th in THETAS:
-                    p = rb.params_from_problem(problem.params, precision=precision,
-                                               theta=th, leaf_size=leaf, group_size=group,
-                                               split_images=split)
-                    ctx = rb.rb_create(p, n)
-                    try:
-                        e = force_errors(_accel(ctx, parts, n, t_kick, tg), ref)
-                    finally:
-                        rb.rb_destroy(ctx)
-                    if e["rms"] <= rms_target:
-                        chosen, err = th, e
-                        break
-                if chosen is None:
-                    continue
-                for graph in graphs:
-                    p = rb.params_from_problem(problem.params, precision=precision,
-                                               theta=chosen, leaf_size=leaf, group_size=group,
-                                               split_images=split, use_graph=graph)
-                    ctx = rb.rb_create(p, n)
-                    try:
-                        work = {k: v.clone() for k, v in dev.items()}
-                        wp = rb.particles(work["x"], work["y"], work["z"], work["m"],
-                                          work["vx"], work["vy"], work["vz"])
-                        rb.rb_step(ctx, wp, n, n, 0.0, problem.dt, 1)
-                        rb.rb_sync(ctx)
-                        times = []
-                        for _ in range(repeats):
-                            torch.cuda.synchronize()
-                            t0 = time.perf_counter()
-                            rb.rb_step(ctx, wp, n, n, 0.0, problem.dt, steps)
-                            rb.rb_sync(ctx)
-                            times.append((time.perf_counter() - t0) * 1e3 / steps)
-                    finally:
-                        rb.rb_destroy(ctx)
-                    ms = min(times)
-                    row = dict(leaf_size=leaf, group_size=group, split_images=split,
-                               use_graph=graph, theta=chosen, ms_per_step=ms, rms=err["rms"],
-                               max=err["max"])
-                    table.append(row)
-                    if log:
-                        log(f"[tune] leaf={leaf} group={group} split={split} graph={graph} "
-                            f"theta={chosen} rms={err['rms']:.2e} {ms:.3f} ms/step")
-                    if best is None or ms < best["ms_per_step"]:
-                        best = dict(row, errors=err)
+                knobs = dict(leaf_size=leaf, group_size=group, split_images=split)
+                errs = {}
+
+                def ok(i):
+                    if i not in errs:
+                        errs[i] = error_at(THETAS[i], knobs)
+                    return errs[i]["rms"] <= rms_target
+
+                i = i_start
+                if ok(i):
+                    while i > 0 and ok(i - 1):
+                        i -= 1
+                else:
+                    while i + 1 < len(THETAS) and not ok(i + 1):
+                        i += 1
+                    i += 1
+                    if i >= len(THETAS):
+                        continue
+                i_start = i
+                err = errs[i]
+                row = dict(knobs, use_graph=graphs[0], theta=THETAS[i],
+                           ms_per_step=time_steps(knobs, THETAS[i], graphs[0]),
+                           rms=err["rms"], max=err["max"], errors=err)
+                table.append(row)
+                if log:
+                    log(f"[tune] leaf={leaf} group={group} split={split} graph={graphs[0]} "
+                        f"theta={row['theta']} rms={err['rms']:.2e} "
+                        f"{row['ms_per_step']:.3f} ms/step")
+    # phase 2: the other launch modes for the three fastest candidates
+    for row in sorted(table, key=lambda r: r["ms_per_step"])[:3]:
+        for graph in graphs[1:]:
+            knobs = {k: row[k] for k in ("leaf_size", "group_size", "split_images")}
+            r2 = dict(row, use_graph=graph,
+                      ms_per_step=time_steps(knobs, row["theta"], graph))
+            table.append(r2)
+            if log:
+                log(f"[tune] leaf={r2['leaf_size']} group={r2['group_size']} "
+                    f"split={r2['split_images']} graph={graph} theta={r2['theta']} "
+                    f"{r2['ms_per_step']:.3f} ms/step")
+    best = min(table, key=lambda r: r["ms_per_step"]) if table else None
+    if best is not None:
+        best = dict(best)
+        table = [{k: v for k, v in r.items() if k != "errors"} for r in table]
     if best is None:
         raise RuntimeError("no candidate met the accuracy target")
     best["table"] = table

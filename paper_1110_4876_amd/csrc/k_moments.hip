@@ -19,6 +19,156 @@
 // deepest level first.  Three launches replace one launch per level.
 #include "rb_internal.h"
 
+// ---- the arithmetic of one node, shared by every kernel below so that all
+// of them round identically (contraction off) ----
+struct Mom {
+  double M, S0, S1, S2, c0, c1, c2, Q0, Q1, Q2, Q3, Q4, Q5;
+};
+
+__device__ __forceinline__ void mom_zero(Mom &a) {
+  a.M = a.S0 = a.S1 = a.S2 = a.c0 = a.c1 = a.c2 = 0.0;
+  a.Q0 = a.Q1 = a.Q2 = a.Q3 = a.Q4 = a.Q5 = 0.0;
+}
+
+// leaf, first sweep: M and S over the particles in slot order
+__device__ __forceinline__ void mom_leaf_ms(Mom &a, double m, double x, double y, double z) {
+#pragma clang fp contract(off)
+  a.M = a.M + m;
+  a.S0 = a.S0 + m * x;
+  a.S1 = a.S1 + m * y;
+  a.S2 = a.S2 + m * z;
+}
+
+// leaf centre of mass: the particle itself for a single-particle leaf
+__device__ __forceinline__ void mom_leaf_com(Mom &a, uint32_t count, double x0, double y0,
+                                             double z0) {
+#pragma clang fp contract(off)
+  if (a.M == 0.0) {
+    a.c0 = a.c1 = a.c2 = 0.0;
+  } else if (count == 1) {
+    a.c0 = x0; a.c1 = y0; a.c2 = z0;
+  } else {
+    a.c0 = a.S0 / a.M; a.c1 = a.S1 / a.M; a.c2 = a.S2 / a.M;
+  }
+}
+
+// leaf, second sweep (quadrupole, multi-particle leaves with mass only)
+__device__ __forceinline__ void mom_leaf_q(Mom &a, double m, double x, double y, double z) {
+#pragma clang fp contract(off)
+  const double a0 = x - a.c0, a1 = y - a.c1, a2 = z - a.c2;
+  const double ss = a0 * a0 + a1 * a1 + a2 * a2;
+  a.Q0 += m * (3.0 * a0 * a0 - ss);
+  a.Q1 += m * (3.0 * a0 * a1);
+  a.Q2 += m * (3.0 * a0 * a2);
+  a.Q3 += m * (3.0 * a1 * a1 - ss);
+  a.Q4 += m * (3.0 * a1 * a2);
+  a.Q5 += m * (3.0 * a2 * a2 - ss);
+}
+
+// internal node, first sweep: M and S over the children in octant order
+__device__ __forceinline__ void mom_child_ms(Mom &a, double M, double S0, double S1,
+                                             double S2) {
+#pragma clang fp contract(off)
+  a.M = a.M + M;
+  a.S0 = a.S0 + S0;
+  a.S1 = a.S1 + S1;
+  a.S2 = a.S2 + S2;
+}
+
+__device__ __forceinline__ void mom_internal_com(Mom &a) {
+#pragma clang fp contract(off)
+  if (a.M == 0.0) {
+    a.c0 = a.c1 = a.c2 = 0.0;
+  } else {
+    a.c0 = a.S0 / a.M; a.c1 = a.S1 / a.M; a.c2 = a.S2 / a.M;
+  }
+}
+
+// internal node, second sweep: parallel-axis sum of the children's Q
+__device__ __forceinline__ void mom_child_q(Mom &a, double M, double x, double y, double z,
+                                            const double q[6]) {
+#pragma clang fp contract(off)
+  const double d0 = x - a.c0, d1 = y - a.c1, d2 = z - a.c2;
+  const double dd = d0 * d0 + d1 * d1 + d2 * d2;
+  a.Q0 += q[0] + M * (3.0 * d0 * d0 - dd);
+  a.Q1 += q[1] + M * (3.0 * d0 * d1);
+  a.Q2 += q[2] + M * (3.0 * d0 * d2);
+  a.Q3 += q[3] + M * (3.0 * d1 * d1 - dd);
+  a.Q4 += q[4] + M * (3.0 * d1 * d2);
+  a.Q5 += q[5] + M * (3.0 * d2 * d2 - dd);
+}
+
+__device__ __forceinline__ void mom_store(uint32_t id, const Mom &a, NodeLink lk,
+                                          NodeLink *__restrict__ link,
+                                          double4 *__restrict__ mcom, double *__restrict__ Sarr,
+                                          double *__restrict__ Qarr, float4 *__restrict__ qf0,
+                                          float2 *__restrict__ qf1) {
+  link[id] = lk;
+  mcom[id] = make_double4(a.c0, a.c1, a.c2, a.M);
+  Sarr[3 * (size_t)id + 0] = a.S0;
+  Sarr[3 * (size_t)id + 1] = a.S1;
+  Sarr[3 * (size_t)id + 2] = a.S2;
+  double *q = Qarr + 6 * (size_t)id;
+  q[0] = a.Q0; q[1] = a.Q1; q[2] = a.Q2; q[3] = a.Q3; q[4] = a.Q4; q[5] = a.Q5;
+  qf0[id] = make_float4((float)a.Q0, (float)a.Q1, (float)a.Q2, (float)a.Q3);
+  qf1[id] = make_float2((float)a.Q4, (float)a.Q5);
+}
+
+// One node whose links are given (its children, if any, already done).
+__device__ __forceinline__ void rb_node_moments_at(
+    uint32_t id, int level, uint32_t first, uint32_t last, bool is_leaf, uint32_t ca,
+    uint32_t cb, uint32_t skip, uint32_t clo, uint32_t chi, const double *__restrict__ sx,
+    const double *__restrict__ sy, const double *__restrict__ sz,
+    const double *__restrict__ msrc, int quad, NodeLink *__restrict__ link,
+    double4 *__restrict__ mcom, double *__restrict__ Sarr, double *__restrict__ Qarr,
+    float4 *__restrict__ qf0, float2 *__restrict__ qf1, uint32_t n_slots,
+    uint32_t *__restrict__ err) {
+  // inconsistent links make the node massless and never opened
+  const bool bad = is_leaf ? !(first <= last && last < n_slots)
+                           : !(ca >= clo && ca <= cb && cb < chi);
+  NodeLink lk;
+  lk.skip = skip;
+  Mom a;
+  mom_zero(a);
+  if (bad) {
+    atomicOr(err, RB_ERR_TREE);
+    lk.child_or_first = RB_NONE;
+    lk.count = 0;
+    lk.lvl = (uint32_t)level | 256u;
+    mom_store(id, a, lk, link, mcom, Sarr, Qarr, qf0, qf1);
+    return;
+  }
+  const uint32_t count = last - first + 1;
+  uint32_t cf = 0, n_child = 0;
+  if (is_leaf) {
+    for (uint32_t s = first; s <= last; ++s) mom_leaf_ms(a, msrc[s], sx[s], sy[s], sz[s]);
+    mom_leaf_com(a, count, sx[first], sy[first], sz[first]);
+    if (quad && a.M != 0.0 && count > 1)
+      for (uint32_t s = first; s <= last; ++s) mom_leaf_q(a, msrc[s], sx[s], sy[s], sz[s]);
+    cf = first;
+  } else {
+    for (uint32_t ch = ca; ch <= cb; ++ch)
+      mom_child_ms(a, mcom[ch].w, Sarr[3 * (size_t)ch + 0], Sarr[3 * (size_t)ch + 1],
+                   Sarr[3 * (size_t)ch + 2]);
+    mom_internal_com(a);
+    if (quad) {
+      for (uint32_t ch = ca; ch <= cb; ++ch) {
+        const double4 cm = mcom[ch];
+        const double *q = Qarr + 6 * (size_t)ch;
+        const double qc[6] = {q[0], q[1], q[2], q[3], q[4], q[5]};
+        mom_child_q(a, cm.w, cm.x, cm.y, cm.z, qc);
+      }
+    }
+    cf = ca;
+    n_child = cb - ca + 1;
+  }
+  lk.child_or_first = cf;
+  lk.count = count;
+  lk.lvl = (uint32_t)level | (is_leaf ? 256u : 0u) | (n_child << 9);
+  mom_store(id, a, lk, link, mcom, Sarr, Qarr, qf0, qf1);
+}
+
+// One node from global memory.
 __device__ __forceinline__ void rb_node_moments(
     uint32_t id, int level, uint32_t clo, uint32_t chi, const uint32_t *__restrict__ nfirst,
     const uint32_t *__restrict__ nlast, const uint32_t *__restrict__ nchild,
@@ -29,105 +179,10 @@ __device__ __forceinline__ void rb_node_moments(
     double4 *__restrict__ mcom, double *__restrict__ Sarr, double *__restrict__ Qarr,
     float4 *__restrict__ qf0, float2 *__restrict__ qf1, uint32_t n_slots,
     uint32_t *__restrict__ err) {
-#pragma clang fp contract(off)
-  const uint32_t first = nfirst[id], last = nlast[id];
   const bool is_leaf = nleaf[id] != 0;
-  // inconsistent links make the node massless and never opened
-  const bool bad = is_leaf ? !(first <= last && last < n_slots)
-                           : !(nchild[id] >= clo && nchild[id] <= nlastchild[id] &&
-                               nlastchild[id] < chi);
-  if (bad) {
-    atomicOr(err, RB_ERR_TREE);
-    NodeLink lk;
-    lk.child_or_first = RB_NONE;
-    lk.skip = nskip[id];
-    lk.count = 0;
-    lk.lvl = (uint32_t)level | 256u;
-    link[id] = lk;
-    mcom[id] = make_double4(0.0, 0.0, 0.0, 0.0);
-    Sarr[3 * (size_t)id] = Sarr[3 * (size_t)id + 1] = Sarr[3 * (size_t)id + 2] = 0.0;
-    for (int a = 0; a < 6; ++a) Qarr[6 * (size_t)id + a] = 0.0;
-    qf0[id] = make_float4(0.f, 0.f, 0.f, 0.f);
-    qf1[id] = make_float2(0.f, 0.f);
-    return;
-  }
-  double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0, c0, c1, c2;
-  double Q0 = 0.0, Q1 = 0.0, Q2 = 0.0, Q3 = 0.0, Q4 = 0.0, Q5 = 0.0;
-  const uint32_t count = last - first + 1;
-  uint32_t cf = 0, n_child = 0;
-  if (is_leaf) {
-    for (uint32_t s = first; s <= last; ++s) {
-      const double m = msrc[s];
-      M = M + m;
-      S0 = S0 + m * sx[s];
-      S1 = S1 + m * sy[s];
-      S2 = S2 + m * sz[s];
-    }
-    if (M == 0.0) {
-      c0 = c1 = c2 = 0.0;
-    } else if (count == 1) {
-      c0 = sx[first]; c1 = sy[first]; c2 = sz[first];
-    } else {
-      c0 = S0 / M; c1 = S1 / M; c2 = S2 / M;
-      if (quad) {
-        for (uint32_t s = first; s <= last; ++s) {
-          const double m = msrc[s];
-          const double a0 = sx[s] - c0, a1 = sy[s] - c1, a2 = sz[s] - c2;
-          const double ss = a0 * a0 + a1 * a1 + a2 * a2;
-          Q0 += m * (3.0 * a0 * a0 - ss);
-          Q1 += m * (3.0 * a0 * a1);
-          Q2 += m * (3.0 * a0 * a2);
-          Q3 += m * (3.0 * a1 * a1 - ss);
-          Q4 += m * (3.0 * a1 * a2);
-          Q5 += m * (3.0 * a2 * a2 - ss);
-        }
-      }
-    }
-    cf = first;
-  } else {
-    const uint32_t ca = nchild[id], cb = nlastchild[id];
-    for (uint32_t ch = ca; ch <= cb; ++ch) {
-      M = M + mcom[ch].w;
-      S0 = S0 + Sarr[3 * (size_t)ch + 0];
-      S1 = S1 + Sarr[3 * (size_t)ch + 1];
-      S2 = S2 + Sarr[3 * (size_t)ch + 2];
-    }
-    if (M == 0.0) {
-      c0 = c1 = c2 = 0.0;
-    } else {
-      c0 = S0 / M; c1 = S1 / M; c2 = S2 / M;
-    }
-    if (quad) {
-      for (uint32_t ch = ca; ch <= cb; ++ch) {
-        const double4 cm = mcom[ch];
-        const double d0 = cm.x - c0, d1 = cm.y - c1, d2 = cm.z - c2;
-        const double dd = d0 * d0 + d1 * d1 + d2 * d2;
-        const double *q = Qarr + 6 * (size_t)ch;
-        Q0 += q[0] + cm.w * (3.0 * d0 * d0 - dd);
-        Q1 += q[1] + cm.w * (3.0 * d0 * d1);
-        Q2 += q[2] + cm.w * (3.0 * d0 * d2);
-        Q3 += q[3] + cm.w * (3.0 * d1 * d1 - dd);
-        Q4 += q[4] + cm.w * (3.0 * d1 * d2);
-        Q5 += q[5] + cm.w * (3.0 * d2 * d2 - dd);
-      }
-    }
-    cf = ca;
-    n_child = cb - ca + 1;
-  }
-  NodeLink lk;
-  lk.child_or_first = cf;
-  lk.skip = nskip[id];
-  lk.count = count;
-  lk.lvl = (uint32_t)level | (is_leaf ? 256u : 0u) | (n_child << 9);
-  link[id] = lk;
-  mcom[id] = make_double4(c0, c1, c2, M);
-  Sarr[3 * (size_t)id + 0] = S0;
-  Sarr[3 * (size_t)id + 1] = S1;
-  Sarr[3 * (size_t)id + 2] = S2;
-  double *q = Qarr + 6 * (size_t)id;
-  q[0] = Q0; q[1] = Q1; q[2] = Q2; q[3] = Q3; q[4] = Q4; q[5] = Q5;
-  qf0[id] = make_float4((float)Q0, (float)Q1, (float)Q2, (float)Q3);
-  qf1[id] = make_float2((float)Q4, (float)Q5);
+  rb_node_moments_at(id, level, nfirst[id], nlast[id], is_leaf, is_leaf ? 0u : nchild[id],
+                     is_leaf ? 0u : nlastchild[id], nskip[id], clo, chi, sx, sy, sz, msrc, quad,
+                     link, mcom, Sarr, Qarr, qf0, qf1, n_slots, err);
 }
 
 #define RB_MOMENT_ARGS                                                                 \
@@ -148,7 +203,8 @@ __device__ __forceinline__ void rb_node_moments(
 // level, or leaf_size > G) contributes runs of G particles.  group.pad is
 // the group's node (RB_NONE for such runs).  Nodes with more than G
 // particles are listed per level for the large-node pass.  Emission order is
-// free: every result depends only on the node itself.
+// free: every result depends only on the node itself.  Slots in the group
+// table and in the per-level lists are taken with one atomic per wave.
 __global__ __launch_bounds__(256) void k_groups(
     const uint32_t *__restrict__ lev_off, const uint32_t *__restrict__ nfirst,
     const uint32_t *__restrict__ nlast, const uint32_t *__restrict__ nchild,
@@ -157,97 +213,255 @@ __global__ __launch_bounds__(256) void k_groups(
     uint32_t G, WalkItem *__restrict__ groups, uint32_t *__restrict__ gctr,
     uint32_t *__restrict__ large, uint32_t *__restrict__ large_cnt) {
   const uint32_t n_nodes = lev_off[RB_NLEV];
-  for (uint32_t id = blockIdx.x * blockDim.x + threadIdx.x; id < n_nodes;
-       id += gridDim.x * blockDim.x) {
-    const uint32_t f = nfirst[id], l = nlast[id];
+  const uint32_t lane = rb_lane();
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n_nodes; base += gridDim.x * blockDim.x) {
+    const uint32_t id = base + threadIdx.x;
+    const bool in = id < n_nodes;
+    uint32_t f = 0, l = 0, lvl = 0;
+    bool leaf = false;
+    if (in) { f = nfirst[id]; l = nlast[id]; lvl = nlevel[id]; leaf = nleaf[id] != 0; }
     const uint32_t cnt = l - f + 1;
-    const uint32_t lvl = nlevel[id];
-    if (cnt <= G) {
-      if (lvl == 0) {
-        const uint32_t g = atomicAdd(&gctr[0], 1u);
-        groups[g] = {f, l + 1, (P == 1) ? 0u : rb_patch_of(starts, P, f), id};
-      }
-      continue;
+    const bool is_large = in && cnt > G;
+    uint32_t ca = 0, cb = 0, n_emit = 0;
+    if (in && !is_large && lvl == 0) n_emit = 1;
+    if (is_large && leaf) n_emit = (cnt + G - 1) / G;
+    if (is_large && !leaf) {
+      ca = nchild[id]; cb = nlastchild[id];
+      for (uint32_t c = ca; c <= cb && c < n_nodes; ++c)
+        if (nlast[c] - nfirst[c] + 1 <= G) ++n_emit;
     }
-    const uint32_t pos = atomicAdd(&large_cnt[lvl], 1u);
-    large[lev_off[lvl] + pos] = id;
-    const uint32_t p = (P == 1) ? 0u : rb_patch_of(starts, P, f);
-    if (nleaf[id]) {
-      for (uint32_t s = f; s <= l; s += G) {
-        const uint32_t g = atomicAdd(&gctr[0], 1u);
-        groups[g] = {s, (s + G <= l + 1) ? s + G : l + 1, p, RB_NONE};
+    // group slots: one atomic per wave
+    const uint32_t incl = rb_wave_incl_scan(n_emit);
+    const uint32_t total = __shfl(incl, 63, 64);
+    uint32_t gbase = 0;
+    if (lane == 63 && total) gbase = atomicAdd(&gctr[0], total);
+    gbase = __shfl(gbase, 63, 64);
+    uint32_t pos = gbase + incl - n_emit;
+    if (n_emit) {
+      const uint32_t p = (P == 1) ? 0u : rb_patch_of(starts, P, f);
+      if (!is_large) {
+        groups[pos] = {f, l + 1, p, id};
+      } else if (leaf) {
+        for (uint32_t s = f; s <= l; s += G) groups[pos++] = {s, (s + G <= l + 1) ? s + G : l + 1, p, RB_NONE};
+      } else {
+        for (uint32_t c = ca; c <= cb && c < n_nodes; ++c) {
+          const uint32_t cf = nfirst[c], cl = nlast[c];
+          if (cl - cf + 1 <= G) groups[pos++] = {cf, cl + 1, p, c};
+        }
       }
-      continue;
     }
-    const uint32_t ca = nchild[id], cb = nlastchild[id];
-    for (uint32_t c = ca; c <= cb; ++c) {
-      const uint32_t cf = nfirst[c], cl = nlast[c];
-      if (cl - cf + 1 <= G) {
-        const uint32_t g = atomicAdd(&gctr[0], 1u);
-        groups[g] = {cf, cl + 1, p, c};
-      }
+    // large-node lists: the lanes of one level share one atomic
+    uint64_t peers = __ballot(is_large);
+#pragma unroll
+    for (int bit = 0; bit < 5; ++bit) {
+      const bool on = (lvl >> bit) & 1u;
+      const uint64_t m = __ballot(is_large && on);
+      peers &= on ? m : ~m;
     }
+    const uint32_t leader = peers ? (uint32_t)(__ffsll((long long)peers) - 1) : lane;
+    uint32_t r = 0;
+    if (is_large && lane == leader) r = atomicAdd(&large_cnt[lvl], (uint32_t)__popcll(peers));
+    r = __shfl(r, (int)leader, 64);
+    if (is_large) large[lev_off[lvl] + r + rb_mbcnt(peers)] = id;
   }
 }
 
-// one wave per small subtree: level ranges top-down, moments bottom-up
-__global__ __launch_bounds__(64) void k_moments_small(
+// Moments of a group's subtree (a node with at most 64 particles), one wave
+// per group, without reading the tree level by level: every lane holds one
+// slot, finds from the sorted keys where cells begin and end at each level,
+// and takes its nodes' ids from the slot-major node list.  Levels are then
+// done bottom-up with the particles and the previous level's node values in
+// LDS; a node's leader lane (the lane of its first slot) sums its children
+// or particles in order, exactly as rb_node_moments does.
+__global__ __launch_bounds__(64) void k_moments_group(
     const WalkItem *__restrict__ groups, const uint32_t *__restrict__ gctr,
-    const uint32_t *__restrict__ lev_off, const uint8_t *__restrict__ nlevel,
-    RB_MOMENT_PARAMS) {
-  __shared__ uint32_t rlo[RB_NLEV], rhi[RB_NLEV];
+    const uint64_t *__restrict__ key, const uint32_t *__restrict__ starts,
+    const uint32_t *__restrict__ csr, const uint32_t *__restrict__ start_ids,
+    const uint32_t *__restrict__ nskip, const uint8_t *__restrict__ nlevel,
+    const uint32_t *__restrict__ lev_off, const double *__restrict__ sx,
+    const double *__restrict__ sy, const double *__restrict__ sz,
+    const double *__restrict__ msrc, int L, int quad, NodeLink *__restrict__ link,
+    double4 *__restrict__ mcom, double *__restrict__ Sarr, double *__restrict__ Qarr,
+    float4 *__restrict__ qf0, float2 *__restrict__ qf1, uint32_t *__restrict__ err) {
+  __shared__ double pv[4][64];   // x y z m of the group's slots
+  __shared__ double vv[13][64];  // M S com Q of the last level's nodes, by leader lane
+  __shared__ uint32_t ids[RB_NLEV][64];
+  __shared__ int s_lo[65];
   const uint32_t lane = threadIdx.x;
-  const uint32_t n_groups = gctr[0];
+  const uint32_t n_groups = gctr[0], n_nodes = lev_off[RB_NLEV];
   for (uint32_t gi = blockIdx.x; gi < n_groups; gi += gridDim.x) {
-    const uint32_t node = groups[gi].pad;
-    if (node == RB_NONE) continue;
-    const int top = nlevel[node];
-    uint32_t lo = node, hi = node;
-    int deepest = top;
-    bool ok = true;
-    for (int l = top; l <= RB_DEPTH; ++l) {
-      if (lane == 0) { rlo[l] = lo; rhi[l] = hi; }
-      deepest = l;
-      if (hi - lo >= 64) { ok = false; break; }  // more nodes than particles: bad links
-      const uint32_t id = lo + lane;
-      const bool in = id <= hi;
-      const bool internal = in && nleaf[id] == 0;
-      const uint64_t bm = __ballot(internal);
-      if (bm == 0) break;
-      const int fi = __ffsll((long long)bm) - 1;
-      const int li = 63 - __clzll((long long)bm);
-      const uint32_t a = internal ? nchild[id] : 0u;
-      const uint32_t z = internal ? nlastchild[id] : 0u;
-      lo = __shfl(a, fi, 64);
-      hi = __shfl(z, li, 64);
-      if (l == RB_DEPTH || hi < lo) { ok = false; break; }
-    }
-    if (!ok) {
+    const WalkItem it = groups[gi];
+    const uint32_t g = it.pad;
+    if (g == RB_NONE) continue;  // a run of a large leaf: no node of its own
+    const uint32_t f = it.start, cnt = it.end - it.start;
+    if (cnt == 0 || cnt > 64 || g >= n_nodes) {
       if (lane == 0) atomicOr(err, RB_ERR_TREE);
       continue;
     }
+    const uint32_t st = starts[it.patch];
+    const int l0 = nlevel[g];
+    // nodes ending at the group's last slot skip to where the group does
+    const uint32_t gskip = nskip[g];
+    const bool in = lane < cnt;
+    const uint32_t s = f + lane;
+    const uint64_t k = in ? key[s] : 0ull;
+    const uint64_t kf = (f > st) ? key[f - 1] : 0ull;
+    const uint32_t cs = in ? csr[s] : 0u;
+    pv[0][lane] = in ? sx[s] : 0.0;
+    pv[1][lane] = in ? sy[s] : 0.0;
+    pv[2][lane] = in ? sz[s] : 0.0;
+    pv[3][lane] = in ? msrc[s] : 0.0;
+    // c: octal digits shared with the previous slot (-1 at a patch start)
+    const uint64_t kp = __shfl_up(k, 1, 64);
+    int c;
+    if (lane == 0) c = (f > st) ? rb_lcp(kf, k) : -1;
+    else c = rb_lcp(kp, k);
+    // deepest level of the cell holding the slot (the group node itself is
+    // a leaf when it holds at most L particles)
+    int leaf = l0;
+    if (cnt > (uint32_t)L) {
+      const uint32_t src = (lane + (uint32_t)L < 64) ? lane + (uint32_t)L : lane;
+      const uint64_t kl = __shfl(k, (int)src, 64);
+      const int w = (lane + (uint32_t)L < cnt) ? rb_lcp(k, kl) : -1;
+      int D = w;
+      for (int d = 1; d <= L; ++d) {
+        const int v = __shfl_up(w, d, 64);
+        if (lane >= (uint32_t)d) D = v > D ? v : D;
+      }
+      leaf = D + 1 < RB_DEPTH ? D + 1 : RB_DEPTH;
+      if (leaf < l0) leaf = l0;
+    }
+    const int glo = c + 1;                      // first level starting at this slot
+    const int lo = (lane == 0) ? l0 : c + 1;    // first such level inside the group
+    // node ids of the lane's starts
+#pragma unroll
+    for (int l = 0; l < RB_NLEV; ++l) {
+      if (in && l >= lo && l <= leaf) {
+        const uint32_t q = cs + (uint32_t)(l - glo);
+        ids[l][lane] = (q < n_nodes) ? start_ids[q] : RB_NONE;
+      }
+    }
+    s_lo[lane] = lo;
+    int lmax = in ? leaf : 0;
+    for (int d = 32; d >= 1; d >>= 1) {
+      const int v = __shfl_xor(lmax, d, 64);
+      lmax = v > lmax ? v : lmax;
+    }
     __syncthreads();
-    for (int l = deepest; l >= top; --l) {
-      const uint32_t a = rlo[l], z = rhi[l];
-      const uint32_t clo = (l < RB_DEPTH) ? lev_off[l + 1] : 0u;
-      const uint32_t chi = (l < RB_DEPTH) ? lev_off[l + 2] : 0u;
-      if (a + lane <= z) rb_node_moments(a + lane, l, clo, chi, RB_MOMENT_ARGS);
-      // this level's results must be visible to the next level's reads
+    for (int l = lmax; l >= l0; --l) {
+      const bool lead = in && lo <= l && l <= leaf;
+      const uint64_t bnd = __ballot(in && lane > 0 && c < l);
+      const uint64_t above = (lane < 63) ? (bnd & (~0ull << (lane + 1))) : 0ull;
+      const uint32_t end = above ? (uint32_t)(__ffsll((long long)above) - 1) : cnt;
+      const bool is_leaf = lead && l == leaf;
+      const uint64_t nxt = (l < RB_DEPTH) ? __ballot(in && lo <= l + 1 && l + 1 <= leaf) : 0ull;
+      const uint64_t span = ((end >= 64) ? ~0ull : ((1ull << end) - 1ull)) & (~0ull << lane);
+      uint64_t kids = nxt & span;
+      Mom a;
+      mom_zero(a);
+      if (lead) {
+        if (is_leaf) {
+          for (uint32_t j = lane; j < end; ++j) mom_leaf_ms(a, pv[3][j], pv[0][j], pv[1][j], pv[2][j]);
+          mom_leaf_com(a, end - lane, pv[0][lane], pv[1][lane], pv[2][lane]);
+          if (quad && a.M != 0.0 && end - lane > 1)
+            for (uint32_t j = lane; j < end; ++j) mom_leaf_q(a, pv[3][j], pv[0][j], pv[1][j], pv[2][j]);
+        } else {
+          for (uint64_t m = kids; m; m &= m - 1) {
+            const int j = __ffsll((long long)m) - 1;
+            mom_child_ms(a, vv[0][j], vv[1][j], vv[2][j], vv[3][j]);
+          }
+          mom_internal_com(a);
+          if (quad) {
+            for (uint64_t m = kids; m; m &= m - 1) {
+              const int j = __ffsll((long long)m) - 1;
+              const double qc[6] = {vv[7][j], vv[8][j], vv[9][j], vv[10][j], vv[11][j], vv[12][j]};
+              mom_child_q(a, vv[0][j], vv[4][j], vv[5][j], vv[6][j], qc);
+            }
+          }
+        }
+      }
+      __syncthreads();  // every read of the deeper level is done
+      if (lead) {
+        vv[0][lane] = a.M; vv[1][lane] = a.S0; vv[2][lane] = a.S1; vv[3][lane] = a.S2;
+        vv[4][lane] = a.c0; vv[5][lane] = a.c1; vv[6][lane] = a.c2;
+        vv[7][lane] = a.Q0; vv[8][lane] = a.Q1; vv[9][lane] = a.Q2;
+        vv[10][lane] = a.Q3; vv[11][lane] = a.Q4; vv[12][lane] = a.Q5;
+        const uint32_t id = ids[l][lane];
+        const uint32_t first_child = is_leaf ? s : ids[l + 1][lane];
+        // the next node after the subtree: the shallowest node starting at
+        // the slot after this node's last one
+        const uint32_t skip = (end < cnt) ? ids[s_lo[end]][end] : gskip;
+        if (id < n_nodes && (is_leaf || first_child < n_nodes)) {
+          NodeLink lk;
+          lk.child_or_first = first_child;
+          lk.skip = skip;
+          lk.count = end - lane;
+          lk.lvl = (uint32_t)l | (is_leaf ? 256u : 0u) | ((uint32_t)__popcll(kids) << 9);
+          mom_store(id, a, lk, link, mcom, Sarr, Qarr, qf0, qf1);
+        } else {
+          atomicOr(err, RB_ERR_TREE);
+        }
+      }
       __syncthreads();
     }
   }
 }
 
-// large nodes, deepest level first: one block with a barrier per level
+// large nodes, deepest level first: one block with a barrier per non-empty
+// level.  The per-level counts and offsets are read once; when all large
+// nodes fit, their links are fetched into LDS up front, so that each level
+// waits only for its children's moments.
+#define ML_CAP 2048
 __global__ __launch_bounds__(1024) void k_moments_large(
     const uint32_t *__restrict__ large, const uint32_t *__restrict__ large_cnt,
     const uint32_t *__restrict__ lev_off, RB_MOMENT_PARAMS) {
+  __shared__ uint32_t s_cnt[RB_NLEV], s_off[RB_NLEV + 2], s_pos[RB_NLEV + 1];
+  __shared__ uint32_t l_id[ML_CAP], l_first[ML_CAP], l_last[ML_CAP], l_ca[ML_CAP],
+      l_cb[ML_CAP], l_skip[ML_CAP];
+  __shared__ uint8_t l_leaf[ML_CAP];
+  const uint32_t tid = threadIdx.x;
+  if (tid < RB_NLEV) s_cnt[tid] = large_cnt[tid];
+  if (tid < RB_NLEV + 2) s_off[tid] = lev_off[tid];
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t a = 0;
+    for (int l = 0; l < RB_NLEV; ++l) { s_pos[l] = a; a += s_cnt[l]; }
+    s_pos[RB_NLEV] = a;
+  }
+  __syncthreads();
+  const uint32_t total = s_pos[RB_NLEV];
+  const bool staged = total <= ML_CAP;
+  if (staged) {
+    for (uint32_t i = tid; i < total; i += blockDim.x) {
+      int l = 0;
+      while (l + 1 < RB_NLEV && s_pos[l + 1] <= i) ++l;
+      const uint32_t id = large[s_off[l] + (i - s_pos[l])];
+      const bool lf = nleaf[id] != 0;
+      l_id[i] = id;
+      l_first[i] = nfirst[id];
+      l_last[i] = nlast[id];
+      l_leaf[i] = lf ? 1 : 0;
+      l_ca[i] = lf ? 0u : nchild[id];
+      l_cb[i] = lf ? 0u : nlastchild[id];
+      l_skip[i] = nskip[id];
+    }
+    __syncthreads();
+  }
   for (int l = RB_DEPTH; l >= 0; --l) {
-    const uint32_t cnt = large_cnt[l], base = lev_off[l];
-    const uint32_t clo = (l < RB_DEPTH) ? lev_off[l + 1] : 0u;
-    const uint32_t chi = (l < RB_DEPTH) ? lev_off[l + 2] : 0u;
-    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x)
-      rb_node_moments(large[base + i], l, clo, chi, RB_MOMENT_ARGS);
+    const uint32_t cnt = s_cnt[l], base = s_off[l];
+    if (cnt == 0) continue;  // uniform over the block
+    const uint32_t clo = (l < RB_DEPTH) ? s_off[l + 1] : 0u;
+    const uint32_t chi = (l < RB_DEPTH) ? s_off[l + 2] : 0u;
+    for (uint32_t i = tid; i < cnt; i += blockDim.x) {
+      if (staged) {
+        const uint32_t k = s_pos[l] + i;
+        rb_node_moments_at(l_id[k], l, l_first[k], l_last[k], l_leaf[k] != 0, l_ca[k], l_cb[k],
+                           l_skip[k], clo, chi, sx, sy, sz, msrc, quad, link, mcom, Sarr, Qarr,
+                           qf0, qf1, n_slots, err);
+      } else {
+        rb_node_moments(large[base + i], l, clo, chi, RB_MOMENT_ARGS);
+      }
+    }
     __syncthreads();
   }
 }
@@ -277,9 +491,12 @@ hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const d
       c->d_msrc, c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, c->d_qf0, c->d_qf1,  \
       (uint32_t)c->cap, c->d_err
   unsigned sgrid = rb_div_up(n, 16);
-  if (sgrid > 8192) sgrid = 8192;
-  hipLaunchKernelGGL(k_moments_small, dim3(sgrid), dim3(64), 0, c->stream, c->d_groups,
-                     c->d_gctr, c->d_lev_off, c->d_nlevel, RB_MARGS);
+  if (sgrid > 262144) sgrid = 262144;
+  hipLaunchKernelGGL(k_moments_group, dim3(sgrid), dim3(64), 0, c->stream, c->d_groups,
+                     c->d_gctr, c->d_key[0], c->d_starts, c->d_csr, c->d_start_ids, c->d_nskip,
+                     c->d_nlevel, c->d_lev_off, sx, sy, sz, c->d_msrc, c->p.leaf_size,
+                     c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, c->d_qf0, c->d_qf1,
+                     c->d_err);
   if (n <= (1u << 22)) {
     hipLaunchKernelGGL(k_moments_large, dim3(1), dim3(1024), 0, c->stream, c->d_large,
                        c->d_large_cnt, c->d_lev_off, RB_MARGS);

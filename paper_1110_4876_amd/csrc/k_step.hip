@@ -119,7 +119,8 @@ hipError_t launch_prologue(rb_ctx *c, const rb_particles *cp) {
                      cp->y, cp->z, cp->vx, cp->vy, cp->vz, cp->m, c->d_patch, c->d_starts,
                      c->P, n, c->p.boundary, c->p.drift, c->d_sc, c->d_sched, c->d_ctr, b[0],
                      b[1], b[2], b[3], b[4], b[5], b[6], c->d_orig[0], c->d_key[0],
-                     c->d_idx[0], c->d_err, c->d_hist[0], c->d_patch_tile0, c->tile);
+                     c->d_idx[0], c->d_err,
+                     c->sort_small ? c->d_hist[0] : nullptr, c->d_patch_tile0, c->tile);
   return hipGetLastError();
 }
 
@@ -187,8 +188,8 @@ hipError_t launch_post(rb_ctx *c, int buf, int slot) {
   hipLaunchKernelGGL(k_post, dim3(rb_div_up(n, 256)), dim3(256), 0, c->stream, b[0], b[1],
                      b[2], b[3], b[4], b[5], c->d_acc, c->cap, n_acc, c->d_patch, c->d_starts,
                      c->d_nlive, c->P, n, c->p.boundary, c->p.drift, c->d_sc, c->d_sched,
-                     c->d_ctr, slot, c->d_key[0], c->d_idx[0], c->d_err, c->d_hist[0],
-                     c->d_patch_tile0, c->tile);
+                     c->d_ctr, slot, c->d_key[0], c->d_idx[0], c->d_err,
+                     c->sort_small ? c->d_hist[0] : nullptr, c->d_patch_tile0, c->tile);
   return hipGetLastError();
 }
 

@@ -20,7 +20,10 @@
 // One wave handles one tile of consecutive slots: count starts and ends per
 // level (k_topo_count), scan the counts (rowscan), then write every node's
 // first slot, last slot, first and last child and skip pointer
-// (k_topo_write).
+// (k_topo_write).  k_topo_write also lists the nodes slot by slot:
+// start_ids[csr[s] + (l - first start level of s)] is the node of level l
+// starting at slot s, so the moments can find a subtree's nodes from its
+// slots without walking down the levels.
 #include "rb_internal.h"
 
 struct TopoRange {
@@ -85,8 +88,12 @@ __global__ __launch_bounds__(64) void k_topo_write(
     uint32_t *__restrict__ nlast, uint32_t *__restrict__ nchild,
     uint32_t *__restrict__ nlastchild, uint32_t *__restrict__ nskip,
     uint8_t *__restrict__ nlevel, uint8_t *__restrict__ nleaf, uint32_t *__restrict__ root,
-    uint32_t *__restrict__ err, uint32_t *__restrict__ gctr, uint32_t *__restrict__ large_cnt) {
+    uint32_t *__restrict__ err, uint32_t *__restrict__ gctr, uint32_t *__restrict__ large_cnt,
+    uint32_t *__restrict__ sort_number, uint32_t *__restrict__ csr,
+    uint32_t *__restrict__ start_ids) {
   const uint32_t b = blockIdx.x, lane = threadIdx.x;
+  // the sort that produced these keys is complete: number the next one
+  if (b == 0 && lane == 0) sort_number[0] += 1u;
   // level offsets: lane l holds the first node of level l
   const uint32_t tot = (lane < RB_NLEV) ? lev_tot[lane] : 0u;
   const uint32_t lincl = rb_wave_incl_scan(tot);
@@ -127,6 +134,10 @@ __global__ __launch_bounds__(64) void k_topo_write(
     // Indices outside the level's range would mean inconsistent counts:
     // they are reported and never written.
     uint32_t prev = RB_NONE, eprev = RB_NONE, skip_to = RB_NONE;
+    // csr_s: nodes of all levels that start before slot s (the place of
+    // this slot's starts in the slot-major list start_ids)
+    uint32_t csr_s = 0;
+    uint32_t my_id[RB_NLEV];
 #pragma unroll
     for (int l = 0; l < RB_NLEV; ++l) {
       const bool in_s = l >= tr.lo_s && l <= tr.hi_s;
@@ -135,9 +146,12 @@ __global__ __launch_bounds__(64) void k_topo_write(
       const uint64_t be = __ballot(in_e);
       const uint32_t os = __shfl(off_s, l, 64), oe = __shfl(off_e, l, 64);
       const uint32_t lend = __shfl(lend_lane, l, 64);
+      csr_s += os + rb_mbcnt(bs) - __shfl(lbase_lane, l, 64);
+      my_id[l] = RB_NONE;
       if (in_s) {
         const uint32_t id = os + rb_mbcnt(bs);
         if (id < lend) {
+          my_id[l] = id;
           nfirst[id] = s;
           nlevel[id] = (uint8_t)l;
           const bool is_leaf = (l == tr.hi_s);
@@ -170,6 +184,16 @@ __global__ __launch_bounds__(64) void k_topo_write(
         off_e += (uint32_t)__popcll(be);
       }
     }
+    if (valid) {
+      csr[s] = csr_s;
+#pragma unroll
+      for (int l = 0; l < RB_NLEV; ++l) {
+        if (l >= tr.lo_s && l <= tr.hi_s) {
+          const uint32_t q = csr_s + (uint32_t)(l - tr.lo_s);
+          if (q < total) start_ids[q] = my_id[l];
+        }
+      }
+    }
   }
 }
 
@@ -187,6 +211,6 @@ hipError_t launch_topology(rb_ctx *c) {
                      c->P, L, c->n_tiles, c->d_cnt, c->d_lev_tot, (uint32_t)c->node_cap,
                      c->d_lev_off, c->d_nfirst, c->d_nlast, c->d_nchild, c->d_nlastchild,
                      c->d_nskip, c->d_nlevel, c->d_nleaf, c->d_root, c->d_err, c->d_gctr,
-                     c->d_large_cnt);
+                     c->d_large_cnt, c->d_sctl, c->d_csr, c->d_start_ids);
   return hipGetLastError();
 }

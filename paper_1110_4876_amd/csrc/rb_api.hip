@@ -131,7 +131,8 @@ int build_layout(rb_ctx *c) {
   c->h_tile_start.clear(); c->h_tile_end.clear(); c->h_tile_patch.clear();
   c->h_patch_tile0.assign(P + 1, 0);
   c->max_tiles_per_patch = 0;
-  // about 1024 tiles over the whole system (one wave each), 256..8192 slots
+  // topology: about 1024 tiles over the whole system (one wave each),
+  // 256..1024 slots
   {
     const uint64_t n = c->h_starts[P];
     uint32_t t = RB_TILE_MIN;
@@ -152,6 +153,39 @@ int build_layout(rb_ctx *c) {
   }
   c->h_patch_tile0[P] = (uint32_t)c->h_tile_start.size();
   c->n_tiles = (uint32_t)c->h_tile_start.size();
+  // small systems sort with the 11-bit per-tile-histogram sort over these
+  // tiles (all of 256 slots at this size)
+  c->sort_small = c->h_starts[P] <= c->small_sort_max && c->tile == RB_TILE_MIN;
+  // sort: tiles of 256 x R slots per 256-thread block; R grows with the
+  // system so that large sorts use fewer, fuller tiles
+  {
+    const uint64_t n = c->h_starts[P];
+    c->sort_rows = n < (1u << 18) ? 1 : n < (1u << 19) ? 2 : n < (1u << 20) ? 4 : 8;
+    const uint32_t st = 256u * (uint32_t)c->sort_rows;
+    c->h_stile_start.clear(); c->h_stile_end.clear(); c->h_stile_patch.clear();
+    c->h_spatch_tile0.assign(P + 1, 0);
+    for (uint32_t p = 0; p < P; ++p) {
+      c->h_spatch_tile0[p] = (uint32_t)c->h_stile_start.size();
+      const uint32_t s0 = c->h_starts[p], s1 = c->h_starts[p + 1];
+      for (uint32_t s = s0; s < s1; s += st) {
+        c->h_stile_start.push_back(s);
+        c->h_stile_end.push_back(std::min<uint32_t>(s + st, s1));
+        c->h_stile_patch.push_back(p);
+      }
+    }
+    c->h_spatch_tile0[P] = (uint32_t)c->h_stile_start.size();
+    c->n_stiles = (uint32_t)c->h_stile_start.size();
+    // histogram blocks: about 256 of them, at least 2048 keys each
+    {
+      const uint64_t per = std::max<uint64_t>(2048, (n + 255) / 256);
+      c->sort_hist_tiles = (uint32_t)std::max<uint64_t>(1, per / st);
+    }
+    const size_t ns = c->n_stiles;
+    RB_TRY(upload_sync(c, c->d_stile_start, c->h_stile_start.data(), ns * 4));
+    RB_TRY(upload_sync(c, c->d_stile_end, c->h_stile_end.data(), ns * 4));
+    RB_TRY(upload_sync(c, c->d_stile_patch, c->h_stile_patch.data(), ns * 4));
+    RB_TRY(upload_sync(c, c->d_spatch_tile0, c->h_spatch_tile0.data(), (P + 1) * 4));
+  }
   const size_t nt = c->n_tiles;
   RB_TRY(upload_sync(c, c->d_tile_start, c->h_tile_start.data(), nt * 4));
   RB_TRY(upload_sync(c, c->d_tile_end, c->h_tile_end.data(), nt * 4));
@@ -224,12 +258,31 @@ int init_ctx(rb_ctx *c, const rb_params *p, uint32_t P, const int64_t *off, cons
     for (int f = 0; f < 7; ++f) RB_TRY(dalloc(c, &c->d_px[b][f], cap));
     RB_TRY(dalloc(c, &c->d_orig[b], cap));
   }
-  for (int b = 0; b < 2; ++b) {
-    RB_TRY(dalloc(c, &c->d_hist[b], 2048 * max_tiles));
-    // the first pass counts into histogram 0, which every sort leaves zeroed
-    RB_HIP(hipMemsetAsync(c->d_hist[b], 0, 4 * 2048 * max_tiles, c->stream));
+  // sort tiles: at least 256 slots each, at most one partial tile per patch
+  const uint64_t max_stiles = cap / 256 + P + 1;
+  RB_TRY(dalloc(c, &c->d_stile_start, max_stiles));
+  RB_TRY(dalloc(c, &c->d_stile_end, max_stiles));
+  RB_TRY(dalloc(c, &c->d_stile_patch, max_stiles));
+  RB_TRY(dalloc(c, &c->d_spatch_tile0, P + 1));
+  RB_TRY(dalloc(c, &c->d_stot, 2 * 2048 * (uint64_t)P));
+  RB_TRY(dalloc(c, &c->d_sdesc, 256 * max_stiles));
+  RB_TRY(dalloc(c, &c->d_sctl, 4));
+  // totals start at zero (each sort clears the buffer the next one counts
+  // into); look-back words start with no valid flag
+  RB_HIP(hipMemsetAsync(c->d_stot, 0, 4 * 2 * 2048 * (size_t)P, c->stream));
+  RB_HIP(hipMemsetAsync(c->d_sdesc, 0, 8 * 256 * max_stiles, c->stream));
+  RB_HIP(hipMemsetAsync(c->d_sctl, 0, 16, c->stream));
+  // small-system sort: histograms for up to 2^18 slots in tiles of 256
+  c->small_sort_max = std::min<uint64_t>(cap, 1u << 18);
+  {
+    const uint64_t st = c->small_sort_max / RB_TILE_MIN + P + 1;
+    for (int b = 0; b < 2; ++b) {
+      RB_TRY(dalloc(c, &c->d_hist[b], 2048 * st));
+      // the first pass counts into histogram 0, which every sort leaves zeroed
+      RB_HIP(hipMemsetAsync(c->d_hist[b], 0, 4 * 2048 * st, c->stream));
+    }
+    RB_TRY(dalloc(c, &c->d_digit_tot, 2048 * (uint64_t)P));
   }
-  RB_TRY(dalloc(c, &c->d_digit_tot, 2048 * (uint64_t)P));
   RB_TRY(dalloc(c, &c->d_msrc, cap));
   RB_TRY(dalloc(c, &c->d_cnt, 2 * RB_NLEV * max_tiles));
   RB_TRY(dalloc(c, &c->d_lev_tot, 2 * RB_NLEV));
@@ -242,6 +295,8 @@ int init_ctx(rb_ctx *c, const rb_params *p, uint32_t P, const int64_t *off, cons
   RB_TRY(dalloc(c, &c->d_nskip, nc));
   RB_TRY(dalloc(c, &c->d_nlevel, nc));
   RB_TRY(dalloc(c, &c->d_nleaf, nc));
+  RB_TRY(dalloc(c, &c->d_csr, cap));
+  RB_TRY(dalloc(c, &c->d_start_ids, nc));
   RB_TRY(dalloc(c, &c->d_link, nc));
   RB_TRY(dalloc(c, &c->d_mcom, nc));
   RB_TRY(dalloc(c, &c->d_S, 3 * nc));
@@ -369,7 +424,7 @@ int upload_schedule(rb_ctx *c, double t, double dt, int32_t nsteps) {
 struct EvPool {
   std::vector<hipEvent_t> free_ev;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
-  hipEvent_t open_ev = nullptr;
+  hipEvent_t open_ev[16] = {};  // begin event of each phase (phases nest: total > others)
 };
 
 }  // namespace
@@ -397,12 +452,20 @@ int mark(rb_ctx *c, int phase, bool begin) {
   EvPool &pl = g_pools[c];
   hipEvent_t e = get_event(c);
   if (!e) return fail(RB_EHIP, "hipEventCreate failed");
-  RB_HIP(hipEventRecord(e, c->stream));
+  const hipError_t r = hipEventRecord(e, c->stream);
+  if (r != hipSuccess) {
+    pl.free_ev.push_back(e);
+    return fail(RB_EHIP, "hipEventRecord: %s", hipGetErrorString(r));
+  }
+  hipEvent_t &open = pl.open_ev[phase & 15];
   if (begin) {
-    pl.open_ev = e;
+    if (open) pl.free_ev.push_back(open);  // an unmatched begin: reuse its event
+    open = e;
+  } else if (open) {
+    pl.pending.push_back({phase, {open, e}});
+    open = nullptr;
   } else {
-    pl.pending.push_back({phase, {pl.open_ev, e}});
-    pl.open_ev = nullptr;
+    pl.free_ev.push_back(e);  // an end without a begin times nothing
   }
   return RB_OK;
 }
@@ -430,6 +493,8 @@ void drop_pool(rb_ctx *c) {
     (void)hipEventDestroy(q.second.second);
   }
   for (hipEvent_t e : it->second.free_ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : it->second.open_ev)
+    if (e) (void)hipEventDestroy(e);
   g_pools.erase(it);
 }
 
@@ -484,6 +549,7 @@ int report_device_errors(rb_ctx *c) {
                   (unsigned long long)c->node_cap);
     if (err & RB_ERR_STACK) return fail(RB_ECAPACITY, "FP32 walk traversal stack overflow");
     if (err & RB_ERR_TREE) return fail(RB_ECAPACITY, "inconsistent tree links (internal error)");
+    if (err & RB_ERR_SORT) return fail(RB_EHIP, "radix sort look-back timed out (internal error)");
     if (err & RB_ERR_INDEX) return fail(RB_EINVAL, "a target index lies outside [0, n)");
     if (err & RB_ERR_OUTSIDE)
       return fail(RB_EOUTSIDE, "a particle lies outside a periodic / shear box axis");

@@ -9,8 +9,8 @@
 #define RB_NLEV (RB_DEPTH + 1)             // levels 0..21
 #define RB_NONE 0xFFFFFFFFu                // absent node / end of walk
 #define RB_KEY_DEAD 0xFFFFFFFFFFFFFFFFull  // key of a removed / outside particle
-#define RB_TILE_MIN 256                    // slots per sort / topology tile
-#define RB_TILE_MAX 8192
+#define RB_TILE_MIN 256                    // slots per topology tile
+#define RB_TILE_MAX 1024
 #define RB_MAX_IMAGES 25                   // (2*2+1)^2 for two ghost rings
 
 // device error word bits (reported by the next synchronising call)
@@ -20,6 +20,7 @@ enum : uint32_t {
   RB_ERR_STACK = 4u,    // FP32 walk traversal stack full
   RB_ERR_TREE = 8u,     // inconsistent node links (guarded, never followed)
   RB_ERR_INDEX = 16u,   // a target index outside [0, n)
+  RB_ERR_SORT = 32u,    // a sort look-back wait gave up (result invalid)
 };
 
 // Walk link of a node: child_or_first = first child (internal) or first
@@ -111,12 +112,15 @@ __device__ __forceinline__ uint64_t rb_key(uint32_t qx, uint32_t qy, uint32_t qz
   return (rb_spread3(qx) << 2) | (rb_spread3(qy) << 1) | rb_spread3(qz);
 }
 
-// Count a freshly written key in the first sort pass's histogram: digit =
-// low 11 bits, at the tile of slot s; layout [patch][digit][tile-in-patch].
+// Small-system sort only: count a freshly written key in the first pass's
+// histogram (digit = low 11 bits, at the tile of slot s; layout
+// [patch][digit][tile-in-patch]).  hist0 is null when the large-system sort
+// is in use.
 __device__ __forceinline__ void rb_hist_add(uint32_t *__restrict__ hist0,
                                             const uint32_t *__restrict__ patch_tile0,
                                             uint32_t p, uint32_t start_p, uint32_t tile,
                                             uint32_t s, uint64_t key) {
+  if (!hist0) return;
   const uint32_t t0 = patch_tile0[p], nt = patch_tile0[p + 1] - t0;
   const uint32_t d = (uint32_t)key & 2047u;
   atomicAdd(&hist0[(size_t)2048 * t0 + (size_t)d * nt + (s - start_p) / tile], 1u);

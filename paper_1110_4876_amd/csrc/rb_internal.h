@@ -42,10 +42,22 @@ struct rb_ctx {
   uint32_t *d_tile_start = nullptr, *d_tile_end = nullptr, *d_tile_patch = nullptr;
   uint32_t *d_patch_tile0 = nullptr;  // P + 1
 
-  // sort
+  // sort: its own tiles of 256 * sort_rows slots (never crossing a patch)
   uint64_t *d_key[2] = {nullptr, nullptr};
   uint32_t *d_idx[2] = {nullptr, nullptr};
-  uint32_t *d_hist[2] = {nullptr, nullptr};  // 2048 * n_tiles each, double-buffered
+  std::vector<uint32_t> h_stile_start, h_stile_end, h_stile_patch, h_spatch_tile0;
+  uint32_t *d_stile_start = nullptr, *d_stile_end = nullptr, *d_stile_patch = nullptr;
+  uint32_t *d_spatch_tile0 = nullptr;  // P + 1
+  uint32_t n_stiles = 0;
+  int sort_rows = 1;                   // rows of 64 keys per wave (1, 2, 4, 8)
+  uint32_t sort_hist_tiles = 1;        // sort tiles counted per histogram block
+  uint32_t *d_stot = nullptr;          // 2 x P x 8 passes x 256 digit totals
+  uint64_t *d_sdesc = nullptr;         // look-back words, 256 per sort tile
+  uint32_t *d_sctl = nullptr;          // [sort number, tile counter A, B, pad]
+  // small systems: 11-bit sort over the topology tiles
+  bool sort_small = false;
+  uint64_t small_sort_max = 0;               // slots the small-sort buffers cover
+  uint32_t *d_hist[2] = {nullptr, nullptr};  // 2048 * tiles each, double-buffered
   uint32_t *d_digit_tot = nullptr;           // 2048 * P
 
   // particles in sorted order (ping-pong for rb_step)
@@ -62,6 +74,8 @@ struct rb_ctx {
   uint32_t *d_nfirst = nullptr, *d_nlast = nullptr, *d_nchild = nullptr,
            *d_nlastchild = nullptr, *d_nskip = nullptr;
   uint8_t *d_nlevel = nullptr, *d_nleaf = nullptr;
+  uint32_t *d_csr = nullptr;        // per slot: nodes starting at earlier slots
+  uint32_t *d_start_ids = nullptr;  // node ids in (start slot, level) order
 
   // moments
   NodeLink *d_link = nullptr;

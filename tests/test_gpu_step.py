@@ -152,3 +152,22 @@ def test_graph_replay_equals_eager(precision):
     finally:
         rb.rb_destroy(ce)
         rb.rb_destroy(cg)
+
+
+def test_phase_timers_across_calls():
+    # profile bit 0: nested phase timers (total around the others) stay
+    # balanced over several calls with rb_stats in between
+    from gpu_util import Dev, make_ctx
+    from paper_1110_4876_amd import rb
+    pr = inputs.sheet(3000, seed=8)
+    ctx = make_ctx(pr, profile=1)
+    try:
+        d = Dev(pr)
+        for call in range(4):
+            rb.rb_step(ctx, d.parts, d.n, d.n, 0.0, pr.dt, 3)
+            rb.rb_sync(ctx)
+            s = rb.rb_stats(ctx)
+            assert s["calls"]["walk"] == 3 and s["calls"]["total"] == 1, (call, s["calls"])
+            assert s["ms"]["total"] >= s["ms"]["walk"] > 0
+    finally:
+        rb.rb_destroy(ctx)

@@ -123,3 +123,42 @@ def test_tree_build_is_deterministic():
         rb.rb_destroy(ctx)
     for k in a:
         np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+@pytest.mark.parametrize("n", [300_000, 700_000, 1_200_000])
+def test_morton_order_at_large_sizes(orc, n):
+    # the radix sort's larger tile shapes (2, 4 and 8 rows per wave) and the
+    # topology at sizes beyond the oracle's insertion tree: sorted keys and
+    # permutation equal a stable sort of the oracle's keys; node counts
+    # per level equal the number of distinct prefixes of every level (with
+    # leaf size 1 a prefix is a node iff its parent holds more than one)
+    from gpu_util import Dev, export, make_ctx
+    from paper_1110_4876_amd import rb
+    pr = inputs.plummer(n, seed=9)
+    # a few exact duplicates and removed particles exercise ties and sentinels
+    pr.x[10:20] = pr.x[0]; pr.y[10:20] = pr.y[0]; pr.z[10:20] = pr.z[0]
+    pr.x[30:33] = np.nan
+    p = orc.make_params(**pr.params)
+    k = orc.keys(p, pr.x, pr.y, pr.z)
+    live = k != np.uint64(0xFFFFFFFFFFFFFFFF)
+    order = np.argsort(k, kind="stable")
+    ref_keys, ref_perm = k[order][: live.sum()], order[: live.sum()]
+    ctx = make_ctx(pr)
+    try:
+        rb.rb_tree_build(ctx, Dev(pr, with_v=False).parts, pr.n, pr.n)
+        g = export(ctx)
+    finally:
+        rb.rb_destroy(ctx)
+    np.testing.assert_array_equal(g["keys"], ref_keys)
+    np.testing.assert_array_equal(g["perm"], ref_perm)
+    # nodes per level: a level-l prefix is a node iff its level-(l-1) parent
+    # holds more than one particle
+    lv = g["level"]
+    for l in range(1, 22):
+        sh = np.uint64(3 * (21 - l))
+        pre = ref_keys >> sh
+        par = ref_keys >> np.uint64(3 * (22 - l))
+        up, pc = np.unique(par, return_counts=True)
+        uniq = np.unique(pre)
+        expect = int(np.isin(uniq >> np.uint64(3), up[pc > 1]).sum())
+        assert int(np.sum(lv == l)) == expect, l
