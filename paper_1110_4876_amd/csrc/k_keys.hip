@@ -45,7 +45,7 @@ hipError_t launch_keys(rb_ctx *c, const double *x, const double *y, const double
   hipLaunchKernelGGL(k_keys, dim3(rb_div_up(n, 256)), dim3(256), 0, c->stream, x, y, z,
                      c->d_patch, c->d_starts, c->P, n, c->p.boundary == RB_OPEN ? 1 : 0,
                      c->d_key[0], c->d_idx[0], c->d_err, c->sort_small ? c->d_hist[0] : nullptr,
-                     c->d_patch_tile0, c->tile);
+                     c->d_spatch_tile0, c->stile);
   return hipGetLastError();
 }
 

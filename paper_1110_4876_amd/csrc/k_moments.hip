@@ -412,7 +412,7 @@ __global__ __launch_bounds__(64) void k_moments_group(
 // nodes fit, their links are fetched into LDS up front, so that each level
 // waits only for its children's moments.
 #define ML_CAP 2048
-__global__ __launch_bounds__(1024) void k_moments_large(
+__global__ __launch_bounds__(512) void k_moments_large(
     const uint32_t *__restrict__ large, const uint32_t *__restrict__ large_cnt,
     const uint32_t *__restrict__ lev_off, RB_MOMENT_PARAMS) {
   __shared__ uint32_t s_cnt[RB_NLEV], s_off[RB_NLEV + 2], s_pos[RB_NLEV + 1];
@@ -447,20 +447,85 @@ __global__ __launch_bounds__(1024) void k_moments_large(
     }
     __syncthreads();
   }
+  // one thread per node; an internal node's (at most eight) children are
+  // all fetched before any sum, so a level costs one memory round trip
   for (int l = RB_DEPTH; l >= 0; --l) {
     const uint32_t cnt = s_cnt[l], base = s_off[l];
     if (cnt == 0) continue;  // uniform over the block
     const uint32_t clo = (l < RB_DEPTH) ? s_off[l + 1] : 0u;
     const uint32_t chi = (l < RB_DEPTH) ? s_off[l + 2] : 0u;
     for (uint32_t i = tid; i < cnt; i += blockDim.x) {
+      uint32_t id, first, last, ca = 0, cb = 0, skip;
+      bool leaf;
       if (staged) {
         const uint32_t k = s_pos[l] + i;
-        rb_node_moments_at(l_id[k], l, l_first[k], l_last[k], l_leaf[k] != 0, l_ca[k], l_cb[k],
-                           l_skip[k], clo, chi, sx, sy, sz, msrc, quad, link, mcom, Sarr, Qarr,
-                           qf0, qf1, n_slots, err);
+        id = l_id[k]; first = l_first[k]; last = l_last[k]; leaf = l_leaf[k] != 0;
+        ca = l_ca[k]; cb = l_cb[k]; skip = l_skip[k];
       } else {
-        rb_node_moments(large[base + i], l, clo, chi, RB_MOMENT_ARGS);
+        id = large[base + i];
+        leaf = nleaf[id] != 0;
+        first = nfirst[id]; last = nlast[id]; skip = nskip[id];
+        if (!leaf) { ca = nchild[id]; cb = nlastchild[id]; }
       }
+      const bool ok = !leaf && ca >= clo && ca <= cb && cb < chi && cb - ca < 8;
+      if (!ok) {  // leaves, and anything inconsistent (reported there)
+        rb_node_moments_at(id, l, first, last, leaf, ca, cb, skip, clo, chi, sx, sy, sz, msrc,
+                           quad, link, mcom, Sarr, Qarr, qf0, qf1, n_slots, err);
+        continue;
+      }
+      const uint32_t nch = cb - ca + 1;
+      // masses and sums of all children, positions and quadrupoles of the
+      // first four, in one round of loads; the other four's after the sums
+      double cm[8], cs[8][3], cx[4][3], cq[4][6];
+#pragma unroll
+      for (uint32_t j = 0; j < 8; ++j) {
+        if (j < nch) {
+          const uint32_t ch = ca + j;
+          const double4 m4 = mcom[ch];
+          cm[j] = m4.w;
+#pragma unroll
+          for (int b = 0; b < 3; ++b) cs[j][b] = Sarr[3 * (size_t)ch + b];
+          if (j < 4) {
+            cx[j][0] = m4.x; cx[j][1] = m4.y; cx[j][2] = m4.z;
+            if (quad) {
+#pragma unroll
+              for (int b = 0; b < 6; ++b) cq[j][b] = Qarr[6 * (size_t)ch + b];
+            }
+          }
+        }
+      }
+      Mom a;
+      mom_zero(a);
+#pragma unroll
+      for (uint32_t j = 0; j < 8; ++j)
+        if (j < nch) mom_child_ms(a, cm[j], cs[j][0], cs[j][1], cs[j][2]);
+      mom_internal_com(a);
+      if (quad) {
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j)
+          if (j < nch) mom_child_q(a, cm[j], cx[j][0], cx[j][1], cx[j][2], cq[j]);
+        if (nch > 4) {
+#pragma unroll
+          for (uint32_t j = 4; j < 8; ++j) {
+            if (j < nch) {
+              const uint32_t ch = ca + j;
+              const double4 m4 = mcom[ch];
+              cx[j - 4][0] = m4.x; cx[j - 4][1] = m4.y; cx[j - 4][2] = m4.z;
+#pragma unroll
+              for (int b = 0; b < 6; ++b) cq[j - 4][b] = Qarr[6 * (size_t)ch + b];
+            }
+          }
+#pragma unroll
+          for (uint32_t j = 4; j < 8; ++j)
+            if (j < nch) mom_child_q(a, cm[j], cx[j - 4][0], cx[j - 4][1], cx[j - 4][2], cq[j - 4]);
+        }
+      }
+      NodeLink lk;
+      lk.child_or_first = ca;
+      lk.skip = skip;
+      lk.count = last - first + 1;
+      lk.lvl = (uint32_t)l | (nch << 9);
+      mom_store(id, a, lk, link, mcom, Sarr, Qarr, qf0, qf1);
     }
     __syncthreads();
   }
@@ -498,7 +563,7 @@ hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const d
                      c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, c->d_qf0, c->d_qf1,
                      c->d_err);
   if (n <= (1u << 22)) {
-    hipLaunchKernelGGL(k_moments_large, dim3(1), dim3(1024), 0, c->stream, c->d_large,
+    hipLaunchKernelGGL(k_moments_large, dim3(1), dim3(512), 0, c->stream, c->d_large,
                        c->d_large_cnt, c->d_lev_off, RB_MARGS);
   } else {
     for (int l = RB_DEPTH; l >= 0; --l)

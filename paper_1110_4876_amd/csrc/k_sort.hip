@@ -266,7 +266,7 @@ __global__ __launch_bounds__(256) void k_sort_pass(
 
 // ---------------------------------------------------------------------------
 // Small systems (up to 2^18 slots): 6 passes of 11-bit digits, one wave per
-// tile of the topology's tiles, two launches per pass.  Digit counts per tile
+// tile of 256 slots, two launches per pass.  Digit counts per tile
 // live in [patch][digit][tile-in-patch] histograms, double-buffered: the
 // kernel that writes the keys counts the first digit (rb_hist_add), and each
 // scatter counts the next pass's digit at the key's destination tile.  Per
@@ -386,18 +386,18 @@ __global__ __launch_bounds__(64) void k_wsort_scatter(
 
 
 hipError_t launch_sort_small(rb_ctx *c) {
-  if (c->n_tiles == 0) return hipSuccess;
+  if (c->n_stiles == 0) return hipSuccess;
   int src = 0;
   for (int pass = 0; pass < WS_PASSES; ++pass) {
     const int shift = WS_BITS * pass;
     uint32_t *h = c->d_hist[pass & 1], *hn = c->d_hist[(pass + 1) & 1];
     const bool last = pass + 1 == WS_PASSES;
     hipLaunchKernelGGL(k_wsort_rowscan, dim3(WS_BINS * c->P), dim3(256), 0, c->stream, h,
-                       c->d_patch_tile0, c->d_digit_tot, hn);
-    hipLaunchKernelGGL(k_wsort_scatter, dim3(c->n_tiles), dim3(64), 0, c->stream,
+                       c->d_spatch_tile0, c->d_digit_tot, hn);
+    hipLaunchKernelGGL(k_wsort_scatter, dim3(c->n_stiles), dim3(64), 0, c->stream,
                        c->d_key[src], c->d_idx[src], c->d_key[1 - src], c->d_idx[1 - src],
-                       c->d_tile_start, c->d_tile_end, c->d_tile_patch, c->d_patch_tile0,
-                       c->d_starts, h, c->d_digit_tot, shift, c->tile, last ? nullptr : hn);
+                       c->d_stile_start, c->d_stile_end, c->d_stile_patch, c->d_spatch_tile0,
+                       c->d_starts, h, c->d_digit_tot, shift, c->stile, last ? nullptr : hn);
     src = 1 - src;
   }
   return hipGetLastError();  // an even number of passes: the result is in buffer 0

@@ -120,7 +120,7 @@ hipError_t launch_prologue(rb_ctx *c, const rb_particles *cp) {
                      c->P, n, c->p.boundary, c->p.drift, c->d_sc, c->d_sched, c->d_ctr, b[0],
                      b[1], b[2], b[3], b[4], b[5], b[6], c->d_orig[0], c->d_key[0],
                      c->d_idx[0], c->d_err,
-                     c->sort_small ? c->d_hist[0] : nullptr, c->d_patch_tile0, c->tile);
+                     c->sort_small ? c->d_hist[0] : nullptr, c->d_spatch_tile0, c->stile);
   return hipGetLastError();
 }
 
@@ -189,7 +189,7 @@ hipError_t launch_post(rb_ctx *c, int buf, int slot) {
                      b[2], b[3], b[4], b[5], c->d_acc, c->cap, n_acc, c->d_patch, c->d_starts,
                      c->d_nlive, c->P, n, c->p.boundary, c->p.drift, c->d_sc, c->d_sched,
                      c->d_ctr, slot, c->d_key[0], c->d_idx[0], c->d_err,
-                     c->sort_small ? c->d_hist[0] : nullptr, c->d_patch_tile0, c->tile);
+                     c->sort_small ? c->d_hist[0] : nullptr, c->d_spatch_tile0, c->stile);
   return hipGetLastError();
 }
 

@@ -132,7 +132,7 @@ int build_layout(rb_ctx *c) {
   c->h_patch_tile0.assign(P + 1, 0);
   c->max_tiles_per_patch = 0;
   // topology: about 1024 tiles over the whole system (one wave each),
-  // 256..1024 slots
+  // 128..1024 slots
   {
     const uint64_t n = c->h_starts[P];
     uint32_t t = RB_TILE_MIN;
@@ -153,15 +153,16 @@ int build_layout(rb_ctx *c) {
   }
   c->h_patch_tile0[P] = (uint32_t)c->h_tile_start.size();
   c->n_tiles = (uint32_t)c->h_tile_start.size();
-  // small systems sort with the 11-bit per-tile-histogram sort over these
-  // tiles (all of 256 slots at this size)
-  c->sort_small = c->h_starts[P] <= c->small_sort_max && c->tile == RB_TILE_MIN;
-  // sort: tiles of 256 x R slots per 256-thread block; R grows with the
-  // system so that large sorts use fewer, fuller tiles
+  // small systems sort with the 11-bit per-tile-histogram sort (one wave
+  // per 256-slot tile); larger ones with the look-back sort, tiles of
+  // 256 x R slots per 256-thread block, R growing with the system so that
+  // large sorts use fewer, fuller tiles
   {
     const uint64_t n = c->h_starts[P];
+    c->sort_small = n <= c->small_sort_max;
     c->sort_rows = n < (1u << 18) ? 1 : n < (1u << 19) ? 2 : n < (1u << 20) ? 4 : 8;
-    const uint32_t st = 256u * (uint32_t)c->sort_rows;
+    const uint32_t st = c->sort_small ? 256u : 256u * (uint32_t)c->sort_rows;
+    c->stile = st;
     c->h_stile_start.clear(); c->h_stile_end.clear(); c->h_stile_patch.clear();
     c->h_spatch_tile0.assign(P + 1, 0);
     for (uint32_t p = 0; p < P; ++p) {
@@ -275,7 +276,7 @@ int init_ctx(rb_ctx *c, const rb_params *p, uint32_t P, const int64_t *off, cons
   // small-system sort: histograms for up to 2^18 slots in tiles of 256
   c->small_sort_max = std::min<uint64_t>(cap, 1u << 18);
   {
-    const uint64_t st = c->small_sort_max / RB_TILE_MIN + P + 1;
+    const uint64_t st = c->small_sort_max / 256 + P + 1;
     for (int b = 0; b < 2; ++b) {
       RB_TRY(dalloc(c, &c->d_hist[b], 2048 * st));
       // the first pass counts into histogram 0, which every sort leaves zeroed

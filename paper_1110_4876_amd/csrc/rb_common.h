@@ -9,7 +9,7 @@
 #define RB_NLEV (RB_DEPTH + 1)             // levels 0..21
 #define RB_NONE 0xFFFFFFFFu                // absent node / end of walk
 #define RB_KEY_DEAD 0xFFFFFFFFFFFFFFFFull  // key of a removed / outside particle
-#define RB_TILE_MIN 256                    // slots per topology tile
+#define RB_TILE_MIN 128                    // slots per topology tile
 #define RB_TILE_MAX 1024
 #define RB_MAX_IMAGES 25                   // (2*2+1)^2 for two ghost rings
 

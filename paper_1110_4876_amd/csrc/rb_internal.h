@@ -50,6 +50,7 @@ struct rb_ctx {
   uint32_t *d_spatch_tile0 = nullptr;  // P + 1
   uint32_t n_stiles = 0;
   int sort_rows = 1;                   // rows of 64 keys per wave (1, 2, 4, 8)
+  uint32_t stile = 256;                // slots per sort tile
   uint32_t sort_hist_tiles = 1;        // sort tiles counted per histogram block
   uint32_t *d_stot = nullptr;          // 2 x P x 8 passes x 256 digit totals
   uint64_t *d_sdesc = nullptr;         // look-back words, 256 per sort tile
