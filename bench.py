@@ -35,6 +35,7 @@ PEAK_F32 = 157.3e12   # published, counts packed FP32 (dual FMA per lane)
 WALK_SRC = {"fp64": "paper_1110_4876_amd/csrc/k_walk64.hip",
             "fp32": "paper_1110_4876_amd/csrc/k_walk32.hip"}
 # workload -> (default steps, default warm-up steps)
+KNOBS = ("theta", "leaf_size", "group_size", "split_images", "walk_waves")
 DEFAULT_STEPS = {"sheet50k": (100, 10), "sheet1m": (10, 2), "plummer8m": (10, 2),
                  "batch256": (50, 5)}
 
@@ -129,6 +130,7 @@ def main():
     ap.add_argument("--group-size", type=int, default=64)
     ap.add_argument("--split-images", type=int, default=-1)
     ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--walk-waves", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -193,7 +195,7 @@ def main():
 
     def timed(prec, cfg, use_graph, profile):
         """warm-up, then exactly K steps in one call from the initial state"""
-        knobs = {k: cfg[k] for k in ("theta", "leaf_size", "group_size", "split_images")}
+        knobs = {k: cfg[k] for k in KNOBS}
         ctx = sysm.create(prec, use_graph=use_graph, profile=profile, **knobs)
         try:
             W = sysm.clone()
@@ -221,7 +223,7 @@ def main():
             if args.theta:
                 cfg = dict(theta=args.theta, leaf_size=args.leaf_size,
                            group_size=args.group_size, split_images=args.split_images,
-                           use_graph=args.graph)
+                           walk_waves=args.walk_waves, use_graph=args.graph)
                 ctx = sysm.create(prec, **{k: v for k, v in cfg.items() if k != "use_graph"})
                 try:
                     err = force_errors(sysm.gravity(ctx, t_kick).cpu().numpy()[tg], ref)
@@ -240,7 +242,8 @@ def main():
             log(f"[{path}] unavailable: {ex}")
             continue
         log(f"[{path}] theta={cfg['theta']} leaf={cfg['leaf_size']} group={cfg['group_size']} "
-            f"split={cfg['split_images']} graph={cfg['use_graph']}: rms={err['rms']:.3e} "
+            f"split={cfg['split_images']} waves={cfg['walk_waves']} graph={cfg['use_graph']}: "
+            f"rms={err['rms']:.3e} "
             f"max={err['max']:.3e}")
         st, flops = interactions(cfg["theta"])
         # Eager launches carry HIP events around every walk launch; a graph
@@ -250,8 +253,7 @@ def main():
         if cfg["use_graph"]:
             _, s2, _, _ = timed(prec, cfg, 0, 4)
         # the accuracy gate again on the state at the end of the timed run
-        ctx = sysm.create(prec, **{k: cfg[k] for k in ("theta", "leaf_size", "group_size",
-                                                       "split_images")})
+        ctx = sysm.create(prec, **{k: cfg[k] for k in KNOBS})
         try:
             a_end = sysm.gravity(ctx, t_end, T).cpu().numpy()[tg]
         finally:
@@ -262,6 +264,7 @@ def main():
         results[path] = dict(theta=cfg["theta"], leaf_size=cfg["leaf_size"],
                              group_size=cfg["group_size"] if path == "fp32" else None,
                              split_images=cfg["split_images"], use_graph=cfg["use_graph"],
+                             walk_waves=cfg["walk_waves"] if path == "fp32" else None,
                              errors=err, errors_end_of_run=err_end, ms_per_step=ms_step,
                              particle_steps_per_s=n * args.steps / secs,
                              walk_ms=walk_ms, walk_launches=s2["calls"]["walk"],
@@ -311,7 +314,8 @@ def main():
                    "images": 9 if sysm.params["boundary"] else 1,
                    "path": main_path, "theta": r["theta"], "quadrupole": quad,
                    "leaf_size": r["leaf_size"], "group_size": r["group_size"],
-                   "split_images": r["split_images"], "hip_graph": bool(r["use_graph"])},
+                   "split_images": r["split_images"], "walk_waves": r["walk_waves"],
+                   "hip_graph": bool(r["use_graph"])},
         "paths": results,
         "roofline": roofline,
         "cpu_baseline": cpu,

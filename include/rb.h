@@ -85,6 +85,10 @@ typedef enum { RB_DRIFT_LEAPFROG = 0, RB_DRIFT_EPICYCLE = 1 } rb_drift;
  *                   only.  All are read by rb_stats.
  *  use_graph        1: rb_step / rb_batch_step replay a captured HIP graph
  *                   of one step.
+ *  walk_waves       FP32-mixed walk only: waves that share one group's
+ *                   traversal (1, 2 or 4; 0 selects 1).  More waves shorten
+ *                   each group's chain of dependent steps when there are few
+ *                   groups for the chip.
  */
 typedef struct {
   double G;
@@ -105,7 +109,8 @@ typedef struct {
   int32_t split_images;
   int32_t profile;
   int32_t use_graph;
-  int32_t reserved[5];
+  int32_t walk_waves;
+  int32_t reserved[4];
 } rb_params;
 
 /* Device SoA of the particles, caller order, all FP64. */

@@ -34,7 +34,7 @@ def _arch() -> str:
 
 def tune(system, ref, targets, t_kick, precision=rb.RB_FP32_MIXED, rms_target=1e-4,
          leafs=(1, 2, 4, 8), groups=(16, 32, 64), splits=(0, 1), graphs=(0, 1), steps=20,
-         repeats=2, cache=None, log=None, checks=()):
+         repeats=2, cache=None, log=None, checks=(), waves=(1, 2, 4)):
     """Search (leaf, group, split) x theta for one precision path, then time
     each accepted candidate in every launch mode.
 
@@ -47,13 +47,17 @@ def tune(system, ref, targets, t_kick, precision=rb.RB_FP32_MIXED, rms_target=1e
     graphs: launch modes (0 eager, 1 HIP-graph replay of the step); the
     first is timed for every candidate, the others for the three fastest.
     They do not change the result.
-    The FP64 per-particle walk has no group size (only 64 is tried).
-    Returns dict(leaf_size, group_size, split_images, use_graph, theta,
-    ms_per_step, rms, max, errors, table).
+    waves: waves per group in the FP32-mixed walk (timing only: the same
+    cells are accepted whatever the count).
+    The FP64 per-particle walk has no group size or waves (only 64 and 1
+    are tried).
+    Returns dict(leaf_size, group_size, split_images, walk_waves, use_graph,
+    theta, ms_per_step, rms, max, errors, table).
     """
     import torch
     if precision == rb.RB_FP64:
         groups = (64,)
+        waves = (1,)
     if system.params["boundary"] == 0:
         splits = (0,)  # one image: nothing to split
     key = f"{system.signature()}|{_arch()}|prec={precision}|target={rms_target:g}"
@@ -133,24 +137,27 @@ def tune(system, ref, targets, t_kick, precision=rb.RB_FP32_MIXED, rms_target=1e
                         continue
                 i_start = i
                 err = errs[i]
-                row = dict(knobs, use_graph=graphs[0], theta=THETAS[i],
-                           ms_per_step=time_steps(knobs, THETAS[i], graphs[0]),
-                           rms=err["rms"], max=err["max"], errors=err)
-                table.append(row)
-                if log:
-                    log(f"[tune] leaf={leaf} group={group} split={split} graph={graphs[0]} "
-                        f"theta={row['theta']} rms={err['rms']:.2e} "
-                        f"{row['ms_per_step']:.3f} ms/step")
+                for nw in waves:
+                    kn = dict(knobs, walk_waves=nw)
+                    row = dict(kn, use_graph=graphs[0], theta=THETAS[i],
+                               ms_per_step=time_steps(kn, THETAS[i], graphs[0]),
+                               rms=err["rms"], max=err["max"], errors=err)
+                    table.append(row)
+                    if log:
+                        log(f"[tune] leaf={leaf} group={group} split={split} waves={nw} "
+                            f"graph={graphs[0]} theta={row['theta']} rms={err['rms']:.2e} "
+                            f"{row['ms_per_step']:.3f} ms/step")
     # phase 2: the other launch modes for the three fastest candidates
     for row in sorted(table, key=lambda r: r["ms_per_step"])[:3]:
         for graph in graphs[1:]:
-            knobs = {k: row[k] for k in ("leaf_size", "group_size", "split_images")}
+            knobs = {k: row[k] for k in ("leaf_size", "group_size", "split_images", "walk_waves")}
             r2 = dict(row, use_graph=graph,
                       ms_per_step=time_steps(knobs, row["theta"], graph))
             table.append(r2)
             if log:
                 log(f"[tune] leaf={r2['leaf_size']} group={r2['group_size']} "
-                    f"split={r2['split_images']} graph={graph} theta={r2['theta']} "
+                    f"split={r2['split_images']} waves={r2['walk_waves']} graph={graph} "
+                    f"theta={r2['theta']} "
                     f"{r2['ms_per_step']:.3f} ms/step")
     best = min(table, key=lambda r: r["ms_per_step"]) if table else None
     if best is not None:

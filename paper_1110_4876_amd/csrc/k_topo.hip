@@ -52,6 +52,18 @@ __device__ __forceinline__ TopoRange rb_topo_range(const uint64_t *__restrict__ 
   return r;
 }
 
+// the levels at which any lane of the wave starts or ends a node
+__device__ __forceinline__ void rb_topo_levels(const TopoRange &tr, bool valid, int &lmin,
+                                               int &lmax) {
+  lmin = valid ? min(tr.lo_s, tr.lo_e) : RB_NLEV;
+  lmax = valid ? max(tr.hi_s, tr.hi_e) : -1;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    lmin = min(lmin, __shfl_xor(lmin, d, 64));
+    lmax = max(lmax, __shfl_xor(lmax, d, 64));
+  }
+}
+
 __global__ __launch_bounds__(64) void k_topo_count(
     const uint64_t *__restrict__ key, const uint32_t *__restrict__ tile_start,
     const uint32_t *__restrict__ tile_end, const uint32_t *__restrict__ tile_patch,
@@ -66,8 +78,11 @@ __global__ __launch_bounds__(64) void k_topo_count(
     const bool valid = s < s1 && (s - st) < nl;
     TopoRange tr = {1, 0, 1, 0};
     if (valid) tr = rb_topo_range(key, st, s - st, nl, L);
+    int lmin, lmax;
+    rb_topo_levels(tr, valid, lmin, lmax);
 #pragma unroll
     for (int l = 0; l < RB_NLEV; ++l) {
+      if (l < lmin || l > lmax) continue;  // uniform: nothing starts or ends here
       const uint32_t ns = (uint32_t)__popcll(__ballot(l >= tr.lo_s && l <= tr.hi_s));
       const uint32_t ne = (uint32_t)__popcll(__ballot(l >= tr.lo_e && l <= tr.hi_e));
       if (lane == (uint32_t)l) { cs += ns; ce += ne; }
@@ -135,19 +150,28 @@ __global__ __launch_bounds__(64) void k_topo_write(
     // they are reported and never written.
     uint32_t prev = RB_NONE, eprev = RB_NONE, skip_to = RB_NONE;
     // csr_s: nodes of all levels that start before slot s (the place of
-    // this slot's starts in the slot-major list start_ids)
-    uint32_t csr_s = 0;
+    // this slot's starts in the slot-major list start_ids): the starts
+    // before this row of 64 slots, summed over the levels, plus those of
+    // the lanes below in the row
+    uint32_t csr_s;
+    {
+      const uint32_t v = (lane < RB_NLEV) ? off_s - lbase_lane : 0u;
+      csr_s = __shfl(rb_wave_incl_scan(v), 63, 64);
+    }
+    int lmin, lmax;
+    rb_topo_levels(tr, valid, lmin, lmax);
     uint32_t my_id[RB_NLEV];
 #pragma unroll
     for (int l = 0; l < RB_NLEV; ++l) {
+      my_id[l] = RB_NONE;
+      if (l < lmin || l > lmax) continue;  // uniform: nothing starts or ends here
       const bool in_s = l >= tr.lo_s && l <= tr.hi_s;
       const bool in_e = l >= tr.lo_e && l <= tr.hi_e;
       const uint64_t bs = __ballot(in_s);
       const uint64_t be = __ballot(in_e);
       const uint32_t os = __shfl(off_s, l, 64), oe = __shfl(off_e, l, 64);
       const uint32_t lend = __shfl(lend_lane, l, 64);
-      csr_s += os + rb_mbcnt(bs) - __shfl(lbase_lane, l, 64);
-      my_id[l] = RB_NONE;
+      csr_s += rb_mbcnt(bs);
       if (in_s) {
         const uint32_t id = os + rb_mbcnt(bs);
         if (id < lend) {

@@ -339,6 +339,246 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same walk with NW waves per group (one workgroup per work item).  The
+// traversal stack is shared: every round each wave takes up to 64 entries
+// of the batch, tests them, and the children are written back at offsets
+// fixed by the wave order, so the traversal (and every sum) is the same on
+// every run.  Each wave keeps its own interaction lists and evaluates them
+// for all of the group's particles; the waves' partial forces are added in
+// wave order at the end.  Two barriers per round; a group's chain of
+// dependent rounds is up to NW times shorter.
+#define W32M_SCAP 2048
+template <bool QUAD, bool STATS, int NW>
+__global__ __launch_bounds__(64 * NW) void k_walk32m(
+    const WalkItem *__restrict__ groups, uint32_t *__restrict__ gctr, int img_split, int n_img,
+    int ngx, int ngy, int boundary, const PatchInfo *__restrict__ patch,
+    const uint32_t *__restrict__ root, const NodeLink *__restrict__ link,
+    const double4 *__restrict__ mcom, const float4 *__restrict__ qf0,
+    const float2 *__restrict__ qf1, const double *__restrict__ sx,
+    const double *__restrict__ sy, const double *__restrict__ sz,
+    const double *__restrict__ msrc, const double *__restrict__ sched,
+    const uint32_t *__restrict__ ctr, uint32_t P, double Gc, double soft, double theta2,
+    double *__restrict__ acc, uint64_t cap, unsigned long long *__restrict__ stats,
+    uint32_t *__restrict__ err, int slot) {
+  __shared__ uint32_t stk[W32M_SCAP];
+  __shared__ float4 cpos_all[NW][W32_CL];
+  __shared__ float4 cq0_all[NW][W32_CL];
+  __shared__ float2 cq1_all[NW][W32_CL];
+  __shared__ float4 ppos_all[NW][W32_PL];
+  __shared__ uint32_t s_push[NW];
+  __shared__ uint32_t s_item;
+  __shared__ double s_red[NW][3][64];
+
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  float4 *cpos = cpos_all[w];
+  float4 *cq0 = cq0_all[w];
+  float2 *cq1 = cq1_all[w];
+  float4 *ppos = ppos_all[w];
+  const uint32_t n_groups = gctr[0];
+  const uint32_t per = img_split ? (uint32_t)n_img : 1u;
+  const uint32_t n_items = n_groups * per;
+  const double theta2d = theta2;
+  const uint32_t step = ctr[slot];
+  unsigned long long n_cell = 0, n_pp = 0;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&gctr[1], 1u);
+    __syncthreads();
+    const uint32_t item = s_item;
+    __syncthreads();  // every thread has read the item before it changes
+    if (item >= n_items) break;  // uniform over the block
+    const uint32_t gi = img_split ? item % n_groups : item;
+    const int im0 = img_split ? (int)((item / n_groups + (uint32_t)(n_img / 2)) % (uint32_t)n_img) : 0;
+    const int nim = img_split ? 1 : n_img;
+    const WalkItem grp = groups[gi];
+    const uint32_t p = grp.patch;
+    const double W = patch[p].W;
+    const int cnt = (int)(grp.end - grp.start);
+    const int gp = cnt <= 16 ? 16 : (cnt <= 32 ? 32 : 64);
+    const int lpp = 64 / gp;
+    const int pidx = lane % gp, sub = lane / gp;
+    const bool valid = pidx < cnt;
+    const uint32_t s = grp.start + (uint32_t)(valid ? pidx : 0);
+    double x = sx[s], y = sy[s], z = sz[s];
+    double lx = valid ? x : INFINITY, ly = valid ? y : INFINITY, lz = valid ? z : INFINITY;
+    double hx = valid ? x : -INFINITY, hy = valid ? y : -INFINITY, hz = valid ? z : -INFINITY;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      lx = fmin(lx, __shfl_xor(lx, d, 64)); ly = fmin(ly, __shfl_xor(ly, d, 64));
+      lz = fmin(lz, __shfl_xor(lz, d, 64)); hx = fmax(hx, __shfl_xor(hx, d, 64));
+      hy = fmax(hy, __shfl_xor(hy, d, 64)); hz = fmax(hz, __shfl_xor(hz, d, 64));
+    }
+    const double gx = 0.5 * (lx + hx), gy = 0.5 * (ly + hy), gz = 0.5 * (lz + hz);
+    const double invW = 1.0 / W;
+    const double gm_scale = Gc * invW * invW;
+    const double gq_scale = gm_scale * invW * invW;
+    const float b2 = (float)((soft * invW) * (soft * invW));
+    const float px = (float)((x - gx) * invW), py = (float)((y - gy) * invW),
+                pz = (float)((z - gz) * invW);
+    const double shear = sched[(size_t)step * 2 * P + p];
+    const uint32_t r0 = root[p];
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    if (w == 0 && lane < nim) stk[lane] = (r0 << 5) | (uint32_t)(im0 + lane);
+    int sp = nim;  // every wave keeps the same copy
+    int cl = 0, pl = 0;
+    bool overflow = false;
+    const float gqs = (float)gq_scale;
+    __syncthreads();
+    for (;;) {
+      // this round's batch: the top T entries, 64 per wave
+      int T = sp < 64 * NW ? sp : 64 * NW;
+      if (sp + 7 * T > W32M_SCAP - W32_RESERVE) {
+        T = (W32M_SCAP - W32_RESERVE - sp) / 7;
+        if (T < 1) T = (sp > 0) ? 1 : 0;
+      }
+      if (T == 0) break;  // uniform: sp is the same in every wave
+      const int base = sp - T;
+      const int k = T - 64 * w < 0 ? 0 : (T - 64 * w > 64 ? 64 : T - 64 * w);
+      const bool has = lane < k;
+      const uint32_t e = has ? stk[base + 64 * w + lane] : 0u;
+      NodeLink lk = {0u, 0u, 0u, 0u};
+      double4 mc = make_double4(0.0, 0.0, 0.0, 0.0);
+      float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f);
+      float2 q1 = make_float2(0.f, 0.f);
+      if (has) {
+        const uint32_t nd = e >> 5;
+        lk = link[nd];
+        mc = mcom[nd];
+        if (QUAD) { q0 = qf0[nd]; q1 = qf1[nd]; }
+      }
+      // full lists are evaluated while the node records are in flight
+      if (cl >= W32_CFLUSH) {
+        w32_eval_cells(cpos, cq0, cq1, cl, sub, lpp, px, py, pz, b2, QUAD, ax, ay, az);
+        if (STATS) n_cell += (unsigned long long)cl * (unsigned long long)cnt;
+        cl = 0;
+      }
+      if (pl >= 64) {
+        w32_eval_parts(ppos, pl, sub, lpp, px, py, pz, b2, ax, ay, az);
+        if (STATS) n_pp += (unsigned long long)pl * (unsigned long long)cnt;
+        pl = 0;
+      }
+      const int im = (int)(e & 31u);
+      const bool alive = has && mc.w != 0.0;
+      double ox = 0.0, oy = 0.0;
+      w32_image(im, ngx, ngy, boundary, W, shear, ox, oy);
+      const double cx = mc.x + ox, cy = mc.y + oy, cz = mc.z;
+      const bool leaf = (lk.lvl & 256u) != 0;
+      const bool single = alive && leaf && lk.count == 1;
+      const double dx = fmax(fmax(lx - cx, cx - hx), 0.0);
+      const double dy = fmax(fmax(ly - cy, cy - hy), 0.0);
+      const double dz = fmax(fmax(lz - cz, cz - hz), 0.0);
+      const double R2 = dx * dx + dy * dy + dz * dz;
+      const double wd = ldexp(W, -(int)(lk.lvl & 255u));
+      const bool accept = alive && !single && (wd * wd < theta2d * R2);
+      const bool open_leaf = alive && !single && !accept && leaf;
+      const bool open_node = alive && !single && !accept && !leaf;
+      const uint32_t nc = open_node ? ((lk.lvl >> 9) & 15u) : 0u;
+      const uint32_t incl = rb_wave_incl_scan(nc);
+      const uint32_t tot = (uint32_t)w32_uniform((int)__shfl(incl, 63, 64));
+      if (lane == 0) s_push[w] = tot;
+      __syncthreads();  // batch read everywhere, push counts known
+      uint32_t off = (uint32_t)base, all = 0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) {
+        const uint32_t t_q = s_push[q];
+        if (q < w) off += t_q;
+        all += t_q;
+      }
+      if ((uint32_t)base + all > W32M_SCAP) {
+        overflow = true;  // cannot happen with the reserve above; stop cleanly
+      } else {
+        for (uint32_t q = 0; q < nc; ++q)
+          stk[off + incl - nc + q] = ((lk.child_or_first + q) << 5) | (uint32_t)im;
+      }
+      sp = overflow ? 0 : base + (int)all;
+      // accepted cells
+      {
+        const uint64_t m = __ballot(accept);
+        if (accept) {
+          const int pos = cl + (int)rb_mbcnt(m);
+          cpos[pos] = make_float4((float)((cx - gx) * invW), (float)((cy - gy) * invW),
+                                  (float)((cz - gz) * invW), (float)(mc.w * gm_scale));
+          if (QUAD) {
+            cq0[pos] = make_float4(q0.x * gqs, q0.y * gqs, q0.z * gqs, q0.w * gqs);
+            cq1[pos] = make_float2(q1.x * gqs, q1.y * gqs);
+          }
+        }
+        cl += __popcll(m);
+      }
+      // single-particle leaves
+      {
+        const uint64_t m = __ballot(single);
+        if (single) {
+          const int pos = pl + (int)rb_mbcnt(m);
+          ppos[pos] = make_float4((float)((cx - gx) * invW), (float)((cy - gy) * invW),
+                                  (float)((cz - gz) * invW), (float)(mc.w * gm_scale));
+        }
+        pl += __popcll(m);
+      }
+      // opened bucket leaves: the wave expands them one after another
+      uint64_t bm = __ballot(open_leaf);
+      while (bm) {
+        const int src = __ffsll((long long)bm) - 1;
+        bm &= bm - 1;
+        const uint32_t first = __shfl(lk.child_or_first, src, 64);
+        const uint32_t count = __shfl(lk.count, src, 64);
+        const double bx = __shfl(ox, src, 64), by = __shfl(oy, src, 64);
+        for (uint32_t c0 = 0; c0 < count; c0 += 64) {
+          if (pl + 64 > W32_PL) {
+            w32_eval_parts(ppos, pl, sub, lpp, px, py, pz, b2, ax, ay, az);
+            if (STATS) n_pp += (unsigned long long)pl * (unsigned long long)cnt;
+            pl = 0;
+          }
+          const uint32_t j = first + c0 + (uint32_t)lane;
+          const bool inb = c0 + (uint32_t)lane < count;
+          const double mj = inb ? msrc[j] : 0.0;
+          const bool use = inb && mj != 0.0;
+          const uint64_t m = __ballot(use);
+          if (use) {
+            const int pos = pl + (int)rb_mbcnt(m);
+            ppos[pos] = make_float4((float)((sx[j] + bx - gx) * invW),
+                                    (float)((sy[j] + by - gy) * invW),
+                                    (float)((sz[j] - gz) * invW), (float)(mj * gm_scale));
+          }
+          pl += __popcll(m);
+        }
+      }
+      __syncthreads();  // children written before the next round reads them
+    }
+    if (overflow && threadIdx.x == 0) atomicOr(err, RB_ERR_STACK);
+    if (cl > 0) {
+      w32_eval_cells(cpos, cq0, cq1, cl, sub, lpp, px, py, pz, b2, QUAD, ax, ay, az);
+      if (STATS) n_cell += (unsigned long long)cl * (unsigned long long)cnt;
+    }
+    if (pl > 0) {
+      w32_eval_parts(ppos, pl, sub, lpp, px, py, pz, b2, ax, ay, az);
+      if (STATS) n_pp += (unsigned long long)pl * (unsigned long long)cnt;
+    }
+    for (int d = gp; d < 64; d <<= 1) {
+      ax += __shfl_xor(ax, d, 64); ay += __shfl_xor(ay, d, 64); az += __shfl_xor(az, d, 64);
+    }
+    // the waves' partial forces, added in wave order
+    s_red[w][0][lane] = ax; s_red[w][1][lane] = ay; s_red[w][2][lane] = az;
+    __syncthreads();
+    if (w == 0) {
+      double tx = 0.0, ty = 0.0, tz = 0.0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) {
+        tx += s_red[q][0][lane]; ty += s_red[q][1][lane]; tz += s_red[q][2][lane];
+      }
+      if (sub == 0 && valid) {
+        double *a = acc + (size_t)(img_split ? im0 : 0) * 3 * cap;
+        a[s] = tx; a[cap + s] = ty; a[2 * cap + s] = tz;
+      }
+    }
+    __syncthreads();  // s_red and the stack are reused by the next item
+  }
+  if (STATS && lane == 0) {
+    atomicAdd(&stats[3], n_cell);
+    atomicAdd(&stats[4], n_pp);
+  }
+}
+
 hipError_t launch_walk32(rb_ctx *c, const double *sx, const double *sy, const double *sz,
                          int slot) {
   const uint32_t n = (uint32_t)c->h_starts[c->P];
@@ -357,6 +597,22 @@ hipError_t launch_walk32(rb_ctx *c, const double *sx, const double *sy, const do
       sy, sz,                                                                             \
       c->d_msrc, c->d_sched, c->d_ctr, c->P, c->p.G, c->p.softening, th2, c->d_acc,       \
       c->cap, c->d_stats, c->d_err, slot
+  const int nw = c->p.walk_waves;
+  if (nw == 2 || nw == 4) {
+    // persistent grid of workgroups
+    uint64_t gridm = 256ull * (nw == 2 ? 8ull : 4ull);
+    if (gridm > max_items) gridm = max_items;
+    const dim3 gm((unsigned)gridm), bm(64 * nw);
+#define RB_W32M(Q, S)                                                                   \
+  if (nw == 2) hipLaunchKernelGGL((k_walk32m<Q, S, 2>), gm, bm, 0, c->stream, RB_W32_ARGS); \
+  else hipLaunchKernelGGL((k_walk32m<Q, S, 4>), gm, bm, 0, c->stream, RB_W32_ARGS);
+    if (quad && stats) { RB_W32M(true, true) }
+    else if (quad) { RB_W32M(true, false) }
+    else if (stats) { RB_W32M(false, true) }
+    else { RB_W32M(false, false) }
+#undef RB_W32M
+    return hipGetLastError();
+  }
   if (quad && stats)
     hipLaunchKernelGGL((k_walk32<true, true>), dim3((unsigned)grid), dim3(64), 0, c->stream, RB_W32_ARGS);
   else if (quad)

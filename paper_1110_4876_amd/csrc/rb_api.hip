@@ -97,6 +97,8 @@ int validate(const rb_params *p) {
   if (p->boundary == RB_SHEAR && !(p->omega >= 0.0)) return fail(RB_EINVAL, "bad omega");
   if (p->node_factor != 0.0 && !(p->node_factor >= 1.5))
     return fail(RB_EINVAL, "node_factor must be 0 or >= 1.5");
+  if (p->walk_waves != 0 && p->walk_waves != 1 && p->walk_waves != 2 && p->walk_waves != 4)
+    return fail(RB_EINVAL, "walk_waves must be 0, 1, 2 or 4");
   return RB_OK;
 }
 

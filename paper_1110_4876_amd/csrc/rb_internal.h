@@ -131,9 +131,9 @@ struct rb_ctx {
 hipError_t launch_keys(rb_ctx *c, const double *x, const double *y, const double *z,
                        double s_unused);
 hipError_t launch_sort(rb_ctx *c);
+hipError_t launch_permute_state(rb_ctx *c, int src, int dst);
 hipError_t launch_permute_gravity(rb_ctx *c, const double *x, const double *y,
                                   const double *z, const double *m, uint32_t n_active_single);
-hipError_t launch_permute_state(rb_ctx *c, int src, int dst);
 hipError_t launch_topology(rb_ctx *c);
 hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const double *sz);
 hipError_t launch_rowscan_levels(rb_ctx *c);

@@ -46,7 +46,8 @@ class rb_params(ctypes.Structure):
         ("split_images", ctypes.c_int32),
         ("profile", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("walk_waves", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 

@@ -141,3 +141,43 @@ def test_fp32_step_tracks_fp64_step():
     W = pr.params["W"]
     for k in ("x", "y", "z"):
         assert np.abs(out[0][k] - out[1][k]).max() <= 1e-9 * W
+
+
+@pytest.mark.parametrize("waves", [2, 4])
+def test_multi_wave_walk_matches_single_wave(orc, waves):
+    # several waves sharing one group's traversal accept the same cells; only
+    # the FP32 summation order differs.  Repeated runs are bitwise equal.
+    from gpu_util import Dev, gravity, make_ctx, rms_rel
+    from paper_1110_4876_amd import rb
+    for pr, t, G in ((inputs.sheet(20000, seed=5).with_params(theta=0.4), 321.0, 32),
+                     (inputs.plummer(20000, seed=6, b=0.01, quadrupole=True)
+                      .with_params(theta=0.5), 0.0, 64)):
+        d = Dev(pr, with_v=False)
+        c1 = make_ctx(pr, precision=rb.RB_FP32_MIXED, group_size=G)
+        cm = make_ctx(pr, precision=rb.RB_FP32_MIXED, group_size=G, walk_waves=waves)
+        try:
+            a1 = gravity(c1, d, pr.n, t)
+            am = gravity(cm, d, pr.n, t)
+            am2 = gravity(cm, d, pr.n, t)
+        finally:
+            rb.rb_destroy(c1)
+            rb.rb_destroy(cm)
+        np.testing.assert_array_equal(am, am2)
+        assert rms_rel(am, a1) <= 1e-6, rms_rel(am, a1)
+
+
+def test_multi_wave_theta_zero_precision(orc):
+    # theta = 0 with four waves: every term direct, FP32 rounding only
+    from gpu_util import Dev, gravity, make_ctx, rms_rel
+    from paper_1110_4876_amd import rb
+    pr = inputs.sheet(6000, seed=1).with_params(theta=0.0)
+    d = Dev(pr, with_v=False)
+    c64 = make_ctx(pr)
+    c32 = make_ctx(pr, precision=rb.RB_FP32_MIXED, group_size=32, walk_waves=4)
+    try:
+        ref = gravity(c64, d, pr.n, 300.0)
+        a = gravity(c32, d, pr.n, 300.0)
+    finally:
+        rb.rb_destroy(c64)
+        rb.rb_destroy(c32)
+    assert rms_rel(a, ref) <= 1e-5, rms_rel(a, ref)

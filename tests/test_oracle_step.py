@@ -123,3 +123,21 @@ def test_open_boundary_removes_leaving_particles(orc):
     out = orc.step(p, st, np.array([1e-9, 1e-9]), 0.0, 0.2, 1, use_tree=True)
     assert np.isnan(out["x"][0]) and out["vx"][0] == 0.0
     assert np.isfinite(out["x"][1])
+
+
+def test_energy_closed_forms(orc):
+    # two bodies: kinetic + softened pair potential written out by hand; a
+    # massless test particle adds kinetic energy only (its mass is not a
+    # source) and a removed particle (NaN position) adds nothing
+    G, b = 0.7, 0.05
+    p = orc.make_params(G=G, b=b, W=100.0, x0=(-50, -50, -50))
+    st = {"x": np.array([0.0, 1.0, 2.0, np.nan]), "y": np.array([0.0, 0.5, 0.0, 0.0]),
+          "z": np.array([0.0, -0.25, 0.0, 0.0]), "vx": np.array([1.0, 0.0, 0.3, 5.0]),
+          "vy": np.array([0.0, -2.0, 0.0, 5.0]), "vz": np.array([0.5, 0.0, 0.0, 5.0])}
+    m = np.array([2.0, 3.0, 4.0, 1.0])
+    # particle 2 is a test particle (index >= n_active = 2); particle 3 is removed
+    e = orc.energy(p, st, m, n_active=2)
+    r2 = 1.0 + 0.25 + 0.0625
+    ek = 0.5 * 2.0 * (1.0 + 0.25) + 0.5 * 3.0 * 4.0 + 0.5 * 4.0 * 0.09
+    ep = -G * 2.0 * 3.0 / math.sqrt(r2 + b * b)
+    assert abs(e - (ek + ep)) <= 1e-14 * abs(ek)
