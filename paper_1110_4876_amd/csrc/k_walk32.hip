@@ -3,9 +3,11 @@
 //
 // Groups are the maximal tree nodes holding at most G particles (G =
 // group_size, emitted during the build), so each group is spatially compact;
-// together they partition the particles.  One wave serves one (group, image) work item, pulled from
-// a device queue by a persistent grid; 64 / 2^ceil(log2 n) lanes share each
-// of the group's n particles.  The wave walks the tree once for the whole
+// together they partition the particles.  One wave serves one work item (a
+// group with all its images, or one (group, image) pair), pulled from a
+// device queue by a persistent grid of workgroups of four independent
+// waves; 64 / 2^ceil(log2 n) lanes share each of the group's n particles.
+// The image offsets of the item are tabulated in LDS once.  The wave walks the tree once for the whole
 // group: a node is accepted for every member at once when
 // w^2 < theta^2 R_min^2, R_min being the distance from the node's
 // image-shifted centre of mass to the group's bounding box -- no member is
@@ -26,6 +28,9 @@
 #define W32_CFLUSH 32
 #define W32_PL 128     // particle list capacity (flushed at >= 64 entries)
 #define W32_RESERVE (7 * RB_DEPTH + 8)
+#ifndef W32_CELL_PAIRS
+#define W32_CELL_PAIRS 1  // cells two at a time: more registers, better issue
+#endif
 
 __device__ __forceinline__ int w32_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -85,6 +90,7 @@ __device__ __forceinline__ void w32_eval_cells(const float4 *__restrict__ cpos,
                                                bool quad, double &ax, double &ay, double &az) {
   F3 f = {0.f, 0.f, 0.f};
   int e = sub;
+#if W32_CELL_PAIRS
   for (; e + lpp < cnt; e += 2 * lpp) {
     const float4 a0 = cpos[e], a1 = cpos[e + lpp];
     float4 q00 = {}, q01 = {};
@@ -96,6 +102,7 @@ __device__ __forceinline__ void w32_eval_cells(const float4 *__restrict__ cpos,
     w32_cell(a0, q00, q10, px, py, pz, b2, quad, f);
     w32_cell(a1, q01, q11, px, py, pz, b2, quad, f);
   }
+#endif
   for (; e < cnt; e += lpp) {
     float4 q0 = {};
     float2 q1 = {};
@@ -122,7 +129,7 @@ __device__ __forceinline__ void w32_eval_parts(const float4 *__restrict__ ppos, 
 }
 
 template <bool QUAD, bool STATS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_walk32(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_walk32(
     const WalkItem *__restrict__ groups, uint32_t *__restrict__ gctr, int img_split, int n_img,
     int ngx, int ngy, int boundary, const PatchInfo *__restrict__ patch,
     const uint32_t *__restrict__ root, const NodeLink *__restrict__ link,
@@ -133,13 +140,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     const double *__restrict__ sched, const uint32_t *__restrict__ ctr, uint32_t P,
     double Gc, double soft, double theta2, double *__restrict__ acc, uint64_t cap,
     unsigned long long *__restrict__ stats, uint32_t *__restrict__ err, int slot) {
-  __shared__ uint32_t stk[W32_SCAP];
-  __shared__ float4 cpos[W32_CL];
-  __shared__ float4 cq0[W32_CL];
-  __shared__ float2 cq1[W32_CL];
-  __shared__ float4 ppos[W32_PL];
+  // four independent waves per workgroup (fewer workgroups to dispatch),
+  // each with its own stack, lists and image table
+  __shared__ uint32_t stk_all[4][W32_SCAP];
+  __shared__ float4 cpos_all[4][W32_CL];
+  __shared__ float4 cq0_all[4][W32_CL];
+  __shared__ float2 cq1_all[4][W32_CL];
+  __shared__ float4 ppos_all[4][W32_PL];
+  __shared__ double2 img_all[4][RB_MAX_IMAGES];
 
-  const int lane = threadIdx.x;
+  // the wave index is uniform: keep it (and the LDS bases) in scalar registers
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint32_t *stk = stk_all[wv];
+  float4 *cpos = cpos_all[wv];
+  float4 *cq0 = cq0_all[wv];
+  float2 *cq1 = cq1_all[wv];
+  float4 *ppos = ppos_all[wv];
+  double2 *img = img_all[wv];
   const uint32_t n_groups = gctr[0];
   const uint32_t per = img_split ? (uint32_t)n_img : 1u;
   const uint32_t n_items = n_groups * per;
@@ -184,6 +201,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     const double shear = sched[(size_t)step * 2 * P + p];
     const uint32_t r0 = root[p];
     double ax = 0.0, ay = 0.0, az = 0.0;
+    if (lane < n_img) {
+      double ox, oy;
+      w32_image(lane, ngx, ngy, boundary, W, shear, ox, oy);
+      img[lane] = make_double2(ox, oy);
+    }
 
     int sp = nim;
     if (lane < nim) stk[lane] = (r0 << 5) | (uint32_t)(im0 + lane);
@@ -228,8 +250,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       const bool has = lane < k;
       const int im = (int)(e & 31u);
       const bool alive = has && mc.w != 0.0;
-      double ox = 0.0, oy = 0.0;
-      w32_image(im, ngx, ngy, boundary, W, shear, ox, oy);
+      const double2 io = img[im];
+      const double ox = io.x, oy = io.y;
       const double cx = mc.x + ox, cy = mc.y + oy, cz = mc.z;
       const bool leaf = (lk.lvl & 256u) != 0;
       const bool single = alive && leaf && lk.count == 1;
@@ -348,7 +370,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 // for all of the group's particles; the waves' partial forces are added in
 // wave order at the end.  Two barriers per round; a group's chain of
 // dependent rounds is up to NW times shorter.
-#define W32M_SCAP 2048
 template <bool QUAD, bool STATS, int NW>
 __global__ __launch_bounds__(64 * NW) void k_walk32m(
     const WalkItem *__restrict__ groups, uint32_t *__restrict__ gctr, int img_split, int n_img,
@@ -361,6 +382,7 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
     const uint32_t *__restrict__ ctr, uint32_t P, double Gc, double soft, double theta2,
     double *__restrict__ acc, uint64_t cap, unsigned long long *__restrict__ stats,
     uint32_t *__restrict__ err, int slot) {
+  constexpr int W32M_SCAP = 512 * NW + 512;  // batches of 64 NW, 8 children each, plus depth
   __shared__ uint32_t stk[W32M_SCAP];
   __shared__ float4 cpos_all[NW][W32_CL];
   __shared__ float4 cq0_all[NW][W32_CL];
@@ -368,9 +390,12 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
   __shared__ float4 ppos_all[NW][W32_PL];
   __shared__ uint32_t s_push[NW];
   __shared__ uint32_t s_item;
-  __shared__ double s_red[NW][3][64];
+  __shared__ double2 img[RB_MAX_IMAGES];
+  // the waves' partial forces, once the lists are no longer needed
+  static_assert(sizeof(cpos_all) >= NW * 3 * 64 * sizeof(double), "reduction space");
+  double(*s_red)[3][64] = reinterpret_cast<double(*)[3][64]>(&cpos_all[0][0]);
 
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float4 *cpos = cpos_all[w];
   float4 *cq0 = cq0_all[w];
   float2 *cq1 = cq1_all[w];
@@ -419,6 +444,11 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
     const uint32_t r0 = root[p];
     double ax = 0.0, ay = 0.0, az = 0.0;
     if (w == 0 && lane < nim) stk[lane] = (r0 << 5) | (uint32_t)(im0 + lane);
+    if (w == 0 && lane < n_img) {
+      double ox, oy;
+      w32_image(lane, ngx, ngy, boundary, W, shear, ox, oy);
+      img[lane] = make_double2(ox, oy);
+    }
     int sp = nim;  // every wave keeps the same copy
     int cl = 0, pl = 0;
     bool overflow = false;
@@ -459,8 +489,8 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
       }
       const int im = (int)(e & 31u);
       const bool alive = has && mc.w != 0.0;
-      double ox = 0.0, oy = 0.0;
-      w32_image(im, ngx, ngy, boundary, W, shear, ox, oy);
+      const double2 io = img[im];
+      const double ox = io.x, oy = io.y;
       const double cx = mc.x + ox, cy = mc.y + oy, cz = mc.z;
       const bool leaf = (lk.lvl & 256u) != 0;
       const bool single = alive && leaf && lk.count == 1;
@@ -557,7 +587,9 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
     for (int d = gp; d < 64; d <<= 1) {
       ax += __shfl_xor(ax, d, 64); ay += __shfl_xor(ay, d, 64); az += __shfl_xor(az, d, 64);
     }
-    // the waves' partial forces, added in wave order
+    // the waves' partial forces, added in wave order (every wave has
+    // finished its list evaluation before the lists' memory is reused)
+    __syncthreads();
     s_red[w][0][lane] = ax; s_red[w][1][lane] = ay; s_red[w][2][lane] = az;
     __syncthreads();
     if (w == 0) {
@@ -600,7 +632,7 @@ hipError_t launch_walk32(rb_ctx *c, const double *sx, const double *sy, const do
   const int nw = c->p.walk_waves;
   if (nw == 2 || nw == 4) {
     // persistent grid of workgroups
-    uint64_t gridm = 256ull * (nw == 2 ? 8ull : 4ull);
+    uint64_t gridm = 256ull * (nw == 2 ? 12ull : 6ull);
     if (gridm > max_items) gridm = max_items;
     const dim3 gm((unsigned)gridm), bm(64 * nw);
 #define RB_W32M(Q, S)                                                                   \
@@ -613,14 +645,15 @@ hipError_t launch_walk32(rb_ctx *c, const double *sx, const double *sy, const do
 #undef RB_W32M
     return hipGetLastError();
   }
+  const dim3 g4((unsigned)((grid + 3) / 4)), b4(256);  // four waves per workgroup
   if (quad && stats)
-    hipLaunchKernelGGL((k_walk32<true, true>), dim3((unsigned)grid), dim3(64), 0, c->stream, RB_W32_ARGS);
+    hipLaunchKernelGGL((k_walk32<true, true>), g4, b4, 0, c->stream, RB_W32_ARGS);
   else if (quad)
-    hipLaunchKernelGGL((k_walk32<true, false>), dim3((unsigned)grid), dim3(64), 0, c->stream, RB_W32_ARGS);
+    hipLaunchKernelGGL((k_walk32<true, false>), g4, b4, 0, c->stream, RB_W32_ARGS);
   else if (stats)
-    hipLaunchKernelGGL((k_walk32<false, true>), dim3((unsigned)grid), dim3(64), 0, c->stream, RB_W32_ARGS);
+    hipLaunchKernelGGL((k_walk32<false, true>), g4, b4, 0, c->stream, RB_W32_ARGS);
   else
-    hipLaunchKernelGGL((k_walk32<false, false>), dim3((unsigned)grid), dim3(64), 0, c->stream, RB_W32_ARGS);
+    hipLaunchKernelGGL((k_walk32<false, false>), g4, b4, 0, c->stream, RB_W32_ARGS);
 #undef RB_W32_ARGS
   return hipGetLastError();
 }
