@@ -15,9 +15,8 @@ __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ x,
                                               uint64_t *__restrict__ key,
                                               uint32_t *__restrict__ idx,
                                               uint32_t *__restrict__ err,
-                                              uint32_t *__restrict__ hist0,
-                                              const uint32_t *__restrict__ patch_tile0,
-                                              uint32_t tile) {
+                                              uint32_t *__restrict__ bcnt,
+                                              uint32_t *__restrict__ bctl) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   uint32_t p = (P == 1) ? 0 : rb_patch_of(starts, P, s);
@@ -35,7 +34,10 @@ __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ x,
   }
   key[s] = k;
   idx[s] = s;
-  rb_hist_add(hist0, patch_tile0, p, pi.start, tile, s, k);
+  if (bcnt) {
+    if (s == 0) bctl[0] = 0;  // segments of the bucket sort, counted anew
+    rb_bucket_add(bcnt, p, k);
+  }
 }
 
 hipError_t launch_keys(rb_ctx *c, const double *x, const double *y, const double *z,
@@ -44,8 +46,8 @@ hipError_t launch_keys(rb_ctx *c, const double *x, const double *y, const double
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_keys, dim3(rb_div_up(n, 256)), dim3(256), 0, c->stream, x, y, z,
                      c->d_patch, c->d_starts, c->P, n, c->p.boundary == RB_OPEN ? 1 : 0,
-                     c->d_key[0], c->d_idx[0], c->d_err, c->sort_small ? c->d_hist[0] : nullptr,
-                     c->d_spatch_tile0, c->stile);
+                     c->d_key[0], c->d_idx[0], c->d_err, c->sort_small ? c->d_bcnt : nullptr,
+                     c->d_bctl);
   return hipGetLastError();
 }
 

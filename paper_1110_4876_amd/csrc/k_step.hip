@@ -88,8 +88,8 @@ __global__ __launch_bounds__(256) void k_prologue(
     double *__restrict__ bx, double *__restrict__ by, double *__restrict__ bz,
     double *__restrict__ bvx, double *__restrict__ bvy, double *__restrict__ bvz,
     double *__restrict__ bm, uint32_t *__restrict__ orig, uint64_t *__restrict__ key,
-    uint32_t *__restrict__ idx, uint32_t *__restrict__ err, uint32_t *__restrict__ hist0,
-    const uint32_t *__restrict__ patch_tile0, uint32_t tile) {
+    uint32_t *__restrict__ idx, uint32_t *__restrict__ err, uint32_t *__restrict__ bcnt,
+    uint32_t *__restrict__ bctl) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const uint32_t p = (P == 1) ? 0 : rb_patch_of(starts, P, s);
@@ -108,7 +108,10 @@ __global__ __launch_bounds__(256) void k_prologue(
   const uint64_t k = rb_state_key(q, pi, boundary, err);
   key[s] = k;
   idx[s] = s;
-  rb_hist_add(hist0, patch_tile0, p, pi.start, tile, s, k);
+  if (bcnt) {
+    if (s == 0) bctl[0] = 0;  // segments of the bucket sort, counted anew
+    rb_bucket_add(bcnt, p, k);
+  }
 }
 
 hipError_t launch_prologue(rb_ctx *c, const rb_particles *cp) {
@@ -120,7 +123,7 @@ hipError_t launch_prologue(rb_ctx *c, const rb_particles *cp) {
                      c->P, n, c->p.boundary, c->p.drift, c->d_sc, c->d_sched, c->d_ctr, b[0],
                      b[1], b[2], b[3], b[4], b[5], b[6], c->d_orig[0], c->d_key[0],
                      c->d_idx[0], c->d_err,
-                     c->sort_small ? c->d_hist[0] : nullptr, c->d_spatch_tile0, c->stile);
+                     c->sort_small ? c->d_bcnt : nullptr, c->d_bctl);
   return hipGetLastError();
 }
 
@@ -135,8 +138,8 @@ __global__ __launch_bounds__(256) void k_post(
     const uint32_t *__restrict__ nlive, uint32_t P, uint32_t n, int boundary, int drift,
     const StepConst *__restrict__ scp, const double *__restrict__ sched,
     uint32_t *__restrict__ ctr, int slot, uint64_t *__restrict__ key,
-    uint32_t *__restrict__ idx, uint32_t *__restrict__ err, uint32_t *__restrict__ hist0,
-    const uint32_t *__restrict__ patch_tile0, uint32_t tile) {
+    uint32_t *__restrict__ idx, uint32_t *__restrict__ err, uint32_t *__restrict__ bcnt,
+    uint32_t *__restrict__ bctl) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t k = ctr[slot], nsteps = ctr[2];
   // the next step reads its index from the other slot
@@ -176,7 +179,10 @@ __global__ __launch_bounds__(256) void k_post(
     const uint64_t k2 = live ? rb_state_key(q, pi, boundary, err) : RB_KEY_DEAD;
     key[s] = k2;
     idx[s] = s;
-    rb_hist_add(hist0, patch_tile0, p, pi.start, tile, s, k2);
+    if (bcnt) {
+      if (s == 0) bctl[0] = 0;
+      rb_bucket_add(bcnt, p, k2);
+    }
   }
 }
 
@@ -189,7 +195,7 @@ hipError_t launch_post(rb_ctx *c, int buf, int slot) {
                      b[2], b[3], b[4], b[5], c->d_acc, c->cap, n_acc, c->d_patch, c->d_starts,
                      c->d_nlive, c->P, n, c->p.boundary, c->p.drift, c->d_sc, c->d_sched,
                      c->d_ctr, slot, c->d_key[0], c->d_idx[0], c->d_err,
-                     c->sort_small ? c->d_hist[0] : nullptr, c->d_spatch_tile0, c->stile);
+                     c->sort_small ? c->d_bcnt : nullptr, c->d_bctl);
   return hipGetLastError();
 }
 

@@ -155,10 +155,9 @@ int build_layout(rb_ctx *c) {
   }
   c->h_patch_tile0[P] = (uint32_t)c->h_tile_start.size();
   c->n_tiles = (uint32_t)c->h_tile_start.size();
-  // small systems sort with the 11-bit per-tile-histogram sort (one wave
-  // per 256-slot tile); larger ones with the look-back sort, tiles of
-  // 256 x R slots per 256-thread block, R growing with the system so that
-  // large sorts use fewer, fuller tiles
+  // small systems use the bucket sort; larger ones the look-back radix
+  // sort, tiles of 256 x R slots per 256-thread block, R growing with the
+  // system so that large sorts use fewer, fuller tiles
   {
     const uint64_t n = c->h_starts[P];
     c->sort_small = n <= c->small_sort_max;
@@ -275,17 +274,14 @@ int init_ctx(rb_ctx *c, const rb_params *p, uint32_t P, const int64_t *off, cons
   RB_HIP(hipMemsetAsync(c->d_stot, 0, 4 * 2 * 2048 * (size_t)P, c->stream));
   RB_HIP(hipMemsetAsync(c->d_sdesc, 0, 8 * 256 * max_stiles, c->stream));
   RB_HIP(hipMemsetAsync(c->d_sctl, 0, 16, c->stream));
-  // small-system sort: histograms for up to 2^18 slots in tiles of 256
+  // small-system bucket sort: up to 2^18 slots
   c->small_sort_max = std::min<uint64_t>(cap, 1u << 18);
-  {
-    const uint64_t st = c->small_sort_max / 256 + P + 1;
-    for (int b = 0; b < 2; ++b) {
-      RB_TRY(dalloc(c, &c->d_hist[b], 2048 * st));
-      // the first pass counts into histogram 0, which every sort leaves zeroed
-      RB_HIP(hipMemsetAsync(c->d_hist[b], 0, 4 * 2048 * st, c->stream));
-    }
-    RB_TRY(dalloc(c, &c->d_digit_tot, 2048 * (uint64_t)P));
-  }
+  RB_TRY(dalloc(c, &c->d_bcnt, (uint64_t)BS_NB * P));
+  RB_TRY(dalloc(c, &c->d_bcur, (uint64_t)BS_NB * P));
+  RB_TRY(dalloc(c, &c->d_bseg, c->small_sort_max + P + 1));
+  RB_TRY(dalloc(c, &c->d_bctl, 4));
+  RB_HIP(hipMemsetAsync(c->d_bcnt, 0, 4 * (size_t)BS_NB * P, c->stream));
+  RB_HIP(hipMemsetAsync(c->d_bctl, 0, 16, c->stream));
   RB_TRY(dalloc(c, &c->d_msrc, cap));
   RB_TRY(dalloc(c, &c->d_cnt, 2 * RB_NLEV * max_tiles));
   RB_TRY(dalloc(c, &c->d_lev_tot, 2 * RB_NLEV));

@@ -112,18 +112,32 @@ __device__ __forceinline__ uint64_t rb_key(uint32_t qx, uint32_t qy, uint32_t qz
   return (rb_spread3(qx) << 2) | (rb_spread3(qy) << 1) | rb_spread3(qz);
 }
 
-// Small-system sort only: count a freshly written key in the first pass's
-// histogram (digit = low 11 bits, at the tile of slot s; layout
-// [patch][digit][tile-in-patch]).  hist0 is null when the large-system sort
-// is in use.
-__device__ __forceinline__ void rb_hist_add(uint32_t *__restrict__ hist0,
-                                            const uint32_t *__restrict__ patch_tile0,
-                                            uint32_t p, uint32_t start_p, uint32_t tile,
-                                            uint32_t s, uint64_t key) {
-  if (!hist0) return;
-  const uint32_t t0 = patch_tile0[p], nt = patch_tile0[p + 1] - t0;
-  const uint32_t d = (uint32_t)key & 2047u;
-  atomicAdd(&hist0[(size_t)2048 * t0 + (size_t)d * nt + (s - start_p) / tile], 1u);
+// Small-system sort (k_bsort.hip): buckets of the top 12 key bits, and one
+// more for removed particles (all-ones key, sorted last).
+#define BS_BITS 12
+#define BS_NB ((1 << BS_BITS) + 1)
+#define BS_SHIFT (63 - BS_BITS)
+
+__device__ __forceinline__ uint32_t bs_bucket(uint64_t key) {
+  return key == RB_KEY_DEAD ? (uint32_t)(1 << BS_BITS) : (uint32_t)(key >> BS_SHIFT);
+}
+
+// Count a freshly written key in its (patch, bucket) counter, with one
+// atomic for the whole wave when it shares one bucket (neighbouring slots
+// usually do).  Every active lane of the wave calls it.
+__device__ __forceinline__ void rb_bucket_add(uint32_t *__restrict__ bcnt, uint32_t p,
+                                              uint64_t key) {
+  const uint32_t b = bs_bucket(key);
+  const uint64_t vm = __ballot(true);
+  const int first = __ffsll((long long)vm) - 1;
+  const uint32_t b0 = (uint32_t)__shfl((int)b, first, 64);
+  const uint32_t p0 = (uint32_t)__shfl((int)p, first, 64);
+  if (__ballot(b == b0 && p == p0) == vm) {
+    if (rb_lane() == (uint32_t)first)
+      atomicAdd(&bcnt[(size_t)p0 * BS_NB + b0], (uint32_t)__popcll(vm));
+    return;
+  }
+  atomicAdd(&bcnt[(size_t)p * BS_NB + b], 1u);
 }
 
 // index of the patch holding slot s (binary search over patch starts)

@@ -55,11 +55,13 @@ struct rb_ctx {
   uint32_t *d_stot = nullptr;          // 2 x P x 8 passes x 256 digit totals
   uint64_t *d_sdesc = nullptr;         // look-back words, 256 per sort tile
   uint32_t *d_sctl = nullptr;          // [sort number, tile counter A, B, pad]
-  // small systems: 11-bit sort over the topology tiles
+  // small systems: bucket sort (k_bsort.hip)
   bool sort_small = false;
-  uint64_t small_sort_max = 0;               // slots the small-sort buffers cover
-  uint32_t *d_hist[2] = {nullptr, nullptr};  // 2048 * tiles each, double-buffered
-  uint32_t *d_digit_tot = nullptr;           // 2048 * P
+  uint64_t small_sort_max = 0;  // slots the small-sort buffers cover
+  uint32_t *d_bcnt = nullptr;   // P x 4097 bucket counts (zero between sorts)
+  uint32_t *d_bcur = nullptr;   // P x 4097 scatter cursors
+  uint2 *d_bseg = nullptr;      // segments (first slot, patch)
+  uint32_t *d_bctl = nullptr;   // [segments, segments taken]
 
   // particles in sorted order (ping-pong for rb_step)
   double *d_px[2][7] = {};          // x y z vx vy vz m
@@ -131,6 +133,7 @@ struct rb_ctx {
 hipError_t launch_keys(rb_ctx *c, const double *x, const double *y, const double *z,
                        double s_unused);
 hipError_t launch_sort(rb_ctx *c);
+hipError_t launch_bsort(rb_ctx *c);
 hipError_t launch_permute_state(rb_ctx *c, int src, int dst);
 hipError_t launch_permute_gravity(rb_ctx *c, const double *x, const double *y,
                                   const double *z, const double *m, uint32_t n_active_single);

@@ -162,3 +162,35 @@ def test_morton_order_at_large_sizes(orc, n):
         uniq = np.unique(pre)
         expect = int(np.isin(uniq >> np.uint64(3), up[pc > 1]).sum())
         assert int(np.sum(lv == l)) == expect, l
+
+
+@pytest.mark.parametrize("n_dead", [0, 40, 700])
+def test_clustered_ties_and_removed(orc, n_dead):
+    # most particles inside one cell of level 4 (one bucket of the small-
+    # system sort larger than a segment), runs of equal keys, and removed
+    # particles in numbers below and above a segment: Morton order, ties in
+    # index order, and the topology still equal the oracle's
+    from gpu_util import Dev, export, make_ctx
+    from paper_1110_4876_amd import rb
+    rng = np.random.default_rng(17)
+    pr = inputs.plummer(6000, seed=8)
+    pr.x[:5000] = 3.0 + rng.uniform(0, 1.5, 5000)
+    pr.y[:5000] = 3.0 + rng.uniform(0, 1.5, 5000)
+    pr.z[:5000] = 3.0 + rng.uniform(0, 1.5, 5000)
+    for j in range(0, 600, 6):  # runs of six equal keys
+        pr.x[j + 1:j + 6] = pr.x[j]; pr.y[j + 1:j + 6] = pr.y[j]; pr.z[j + 1:j + 6] = pr.z[j]
+    pr.x[5000:5000 + n_dead] = np.nan
+    p = orc.make_params(**pr.params)
+    ref = orc.Tree(p, pr.x, pr.y, pr.z, pr.m).export()
+    ctx = make_ctx(pr)
+    try:
+        d = Dev(pr, with_v=False)
+        rb.rb_tree_build(ctx, d.parts, d.n, d.n)
+        nn, nl = rb.rb_tree_info(ctx)
+        g = export(ctx)
+    finally:
+        rb.rb_destroy(ctx)
+    assert nl == pr.n - n_dead
+    for k in ("keys", "perm", "level", "prefix", "first", "count", "is_leaf"):
+        np.testing.assert_array_equal(g[k], ref[k], err_msg=k)
+    np.testing.assert_array_equal(g["com"], ref["com"])
