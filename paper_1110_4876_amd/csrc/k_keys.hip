@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ x,
   idx[s] = s;
   if (bcnt) {
     if (s == 0) bctl[0] = 0;  // segments of the bucket sort, counted anew
-    rb_bucket_add(bcnt, p, k);
+    rb_bucket_add(bcnt, p, P, k);
   }
 }
 

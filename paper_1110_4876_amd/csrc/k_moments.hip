@@ -266,6 +266,11 @@ __global__ __launch_bounds__(256) void k_groups(
   }
 }
 
+__device__ __forceinline__ void rb_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Moments of a group's subtree (a node with at most 64 particles), one wave
 // per group, without reading the tree level by level: every lane holds one
 // slot, finds from the sorted keys where cells begin and end at each level,
@@ -273,7 +278,7 @@ __global__ __launch_bounds__(256) void k_groups(
 // done bottom-up with the particles and the previous level's node values in
 // LDS; a node's leader lane (the lane of its first slot) sums its children
 // or particles in order, exactly as rb_node_moments does.
-__global__ __launch_bounds__(64) void k_moments_group(
+__global__ __launch_bounds__(128) void k_moments_group(
     const WalkItem *__restrict__ groups, const uint32_t *__restrict__ gctr,
     const uint64_t *__restrict__ key, const uint32_t *__restrict__ starts,
     const uint32_t *__restrict__ csr, const uint32_t *__restrict__ start_ids,
@@ -283,13 +288,21 @@ __global__ __launch_bounds__(64) void k_moments_group(
     const double *__restrict__ msrc, int L, int quad, NodeLink *__restrict__ link,
     double4 *__restrict__ mcom, double *__restrict__ Sarr, double *__restrict__ Qarr,
     float4 *__restrict__ qf0, float2 *__restrict__ qf1, uint32_t *__restrict__ err) {
-  __shared__ double pv[4][64];   // x y z m of the group's slots
-  __shared__ double vv[13][64];  // M S com Q of the last level's nodes, by leader lane
-  __shared__ uint32_t ids[RB_NLEV][64];
-  __shared__ int s_lo[65];
-  const uint32_t lane = threadIdx.x;
+  // two independent waves per workgroup (fewer workgroups to dispatch),
+  // each with its own LDS slice; within a wave LDS accesses stay in order,
+  // so a wave-level fence orders its writes and reads
+  __shared__ double pv_all[2][4][64];   // x y z m of the group's slots
+  __shared__ double vv_all[2][13][64];  // M S com Q of the last level's nodes, by leader lane
+  __shared__ uint32_t ids_all[2][RB_NLEV][64];
+  __shared__ int s_lo_all[2][65];
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  double(*pv)[64] = pv_all[wv];
+  double(*vv)[64] = vv_all[wv];
+  uint32_t(*ids)[64] = ids_all[wv];
+  int *s_lo = s_lo_all[wv];
   const uint32_t n_groups = gctr[0], n_nodes = lev_off[RB_NLEV];
-  for (uint32_t gi = blockIdx.x; gi < n_groups; gi += gridDim.x) {
+  for (uint32_t gi = 2 * blockIdx.x + wv; gi < n_groups; gi += 2 * gridDim.x) {
     const WalkItem it = groups[gi];
     const uint32_t g = it.pad;
     if (g == RB_NONE) continue;  // a run of a large leaf: no node of its own
@@ -347,7 +360,7 @@ __global__ __launch_bounds__(64) void k_moments_group(
       const int v = __shfl_xor(lmax, d, 64);
       lmax = v > lmax ? v : lmax;
     }
-    __syncthreads();
+    rb_wave_sync();
     for (int l = lmax; l >= l0; --l) {
       const bool lead = in && lo <= l && l <= leaf;
       const uint64_t bnd = __ballot(in && lane > 0 && c < l);
@@ -380,7 +393,7 @@ __global__ __launch_bounds__(64) void k_moments_group(
           }
         }
       }
-      __syncthreads();  // every read of the deeper level is done
+      rb_wave_sync();  // every read of the deeper level is done
       if (lead) {
         vv[0][lane] = a.M; vv[1][lane] = a.S0; vv[2][lane] = a.S1; vv[3][lane] = a.S2;
         vv[4][lane] = a.c0; vv[5][lane] = a.c1; vv[6][lane] = a.c2;
@@ -402,7 +415,7 @@ __global__ __launch_bounds__(64) void k_moments_group(
           atomicOr(err, RB_ERR_TREE);
         }
       }
-      __syncthreads();
+      rb_wave_sync();
     }
   }
 }
@@ -555,9 +568,9 @@ hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const d
   c->d_nfirst, c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nskip, c->d_nleaf, sx, sy, sz, \
       c->d_msrc, c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, c->d_qf0, c->d_qf1,  \
       (uint32_t)c->cap, c->d_err
-  unsigned sgrid = rb_div_up(n, 16);
-  if (sgrid > 262144) sgrid = 262144;
-  hipLaunchKernelGGL(k_moments_group, dim3(sgrid), dim3(64), 0, c->stream, c->d_groups,
+  unsigned sgrid = rb_div_up(n, 32);  // two waves per workgroup
+  if (sgrid > 131072) sgrid = 131072;
+  hipLaunchKernelGGL(k_moments_group, dim3(sgrid), dim3(128), 0, c->stream, c->d_groups,
                      c->d_gctr, c->d_key[0], c->d_starts, c->d_csr, c->d_start_ids, c->d_nskip,
                      c->d_nlevel, c->d_lev_off, sx, sy, sz, c->d_msrc, c->p.leaf_size,
                      c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, c->d_qf0, c->d_qf1,

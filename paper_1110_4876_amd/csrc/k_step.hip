@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void k_prologue(
   idx[s] = s;
   if (bcnt) {
     if (s == 0) bctl[0] = 0;  // segments of the bucket sort, counted anew
-    rb_bucket_add(bcnt, p, k);
+    rb_bucket_add(bcnt, p, P, k);
   }
 }
 
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void k_post(
     idx[s] = s;
     if (bcnt) {
       if (s == 0) bctl[0] = 0;
-      rb_bucket_add(bcnt, p, k2);
+      rb_bucket_add(bcnt, p, P, k2);
     }
   }
 }

@@ -122,22 +122,29 @@ __device__ __forceinline__ uint32_t bs_bucket(uint64_t key) {
   return key == RB_KEY_DEAD ? (uint32_t)(1 << BS_BITS) : (uint32_t)(key >> BS_SHIFT);
 }
 
-// Count a freshly written key in its (patch, bucket) counter, with one
-// atomic for the whole wave when it shares one bucket (neighbouring slots
-// usually do).  Every active lane of the wave calls it.
+// Count a freshly written key in its (patch, bucket) counter: the lanes of
+// the wave holding the same (patch, bucket) add their count with one atomic
+// (neighbouring slots usually share one or two buckets).  Every active lane
+// of the wave calls it; P is the number of patches.
 __device__ __forceinline__ void rb_bucket_add(uint32_t *__restrict__ bcnt, uint32_t p,
-                                              uint64_t key) {
+                                              uint32_t P, uint64_t key) {
   const uint32_t b = bs_bucket(key);
-  const uint64_t vm = __ballot(true);
-  const int first = __ffsll((long long)vm) - 1;
-  const uint32_t b0 = (uint32_t)__shfl((int)b, first, 64);
-  const uint32_t p0 = (uint32_t)__shfl((int)p, first, 64);
-  if (__ballot(b == b0 && p == p0) == vm) {
-    if (rb_lane() == (uint32_t)first)
-      atomicAdd(&bcnt[(size_t)p0 * BS_NB + b0], (uint32_t)__popcll(vm));
-    return;
+  uint64_t peers = __ballot(true);
+#pragma unroll
+  for (int bit = 0; bit < BS_BITS + 1; ++bit) {
+    const bool on = (b >> bit) & 1u;
+    const uint64_t m = __ballot(on);
+    peers &= on ? m : ~m;
   }
-  atomicAdd(&bcnt[(size_t)p * BS_NB + b], 1u);
+  if (P > 1) {
+    const int pbits = 32 - __clz((int)(P - 1));
+    for (int bit = 0; bit < pbits; ++bit) {
+      const bool on = (p >> bit) & 1u;
+      const uint64_t m = __ballot(on);
+      peers &= on ? m : ~m;
+    }
+  }
+  if (rb_mbcnt(peers) == 0) atomicAdd(&bcnt[(size_t)p * BS_NB + b], (uint32_t)__popcll(peers));
 }
 
 // index of the patch holding slot s (binary search over patch starts)
