@@ -32,8 +32,11 @@ RMS_TARGET = 1e-4
 FLOP_OPEN, FLOP_MONO, FLOP_QUAD = 9, 20, 56
 PEAK_F64 = 78.6e12    # 256 CU x 64 FP64 FMA lanes x 2 flop x 2.4 GHz
 PEAK_F32 = 157.3e12   # published, counts packed FP32 (dual FMA per lane)
-WALK_SRC = {"fp64": "paper_1110_4876_amd/csrc/k_walk64.hip",
-            "fp32": "paper_1110_4876_amd/csrc/k_walk32.hip"}
+# sources whose hash keys a stored traffic measurement (walk kernel + node record)
+WALK_SRC = {"fp64": ("paper_1110_4876_amd/csrc/k_walk64.hip",
+                     "paper_1110_4876_amd/csrc/rb_common.h"),
+            "fp32": ("paper_1110_4876_amd/csrc/k_walk32.hip",
+                     "paper_1110_4876_amd/csrc/rb_common.h")}
 # workload -> (default steps, default warm-up steps)
 KNOBS = ("theta", "leaf_size", "group_size", "split_images", "walk_waves")
 DEFAULT_STEPS = {"sheet50k": (100, 10), "sheet1m": (10, 2), "plummer8m": (10, 2),
@@ -117,6 +120,71 @@ def cpu_baseline(system, theta, seconds):
                       f"particles, theta={theta}"}
 
 
+def walk_source_sha(path):
+    h = hashlib.sha256()
+    for f in WALK_SRC[path]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()
+
+
+def walk_kernel_name(path, walk_waves):
+    if path == "fp64":
+        return "k_walk64"
+    return "k_walk32m" if walk_waves and walk_waves > 1 else "k_walk32"
+
+
+def write_traffic(args):
+    """Turn four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE, KiB per
+    dispatch, for a plain device copy of known size and for the walk at the
+    operating point given by the knob options) into HBM bytes per walk
+    launch: each walk counter is scaled by true bytes / counter reading of
+    the copy.  Writes profiles/walk_<path>_<workload>_traffic.json."""
+    import csv
+    import glob
+
+    def values(d, counter, pat):
+        out = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if r["Counter_Name"] == counter and pat in r["Kernel_Name"]:
+                        out.append(float(r["Counter_Value"]))
+        if not out:
+            raise SystemExit(f"no {counter} rows for {pat} under {d}")
+        return out
+
+    cf, cw, wf, ww = args.write_traffic
+    path = args.precision if args.precision != "both" else "fp32"
+    copy_bytes = (args.calibrate_copy or 512) << 20
+    c_f = values(cf, "FETCH_SIZE", "copyBuffer")
+    c_w = values(cw, "WRITE_SIZE", "copyBuffer")
+    kname = walk_kernel_name(path, args.walk_waves)
+    w_f = values(wf, "FETCH_SIZE", kname + "<")
+    w_w = values(ww, "WRITE_SIZE", kname + "<")
+    mean = lambda v: sum(v) / len(v)
+    fs = copy_bytes / 1024 / mean(c_f)
+    ws = copy_bytes / 1024 / mean(c_w)
+    meta = {
+        "kernel": kname, "workload": args.workload,
+        "knobs": {"theta": args.theta, "leaf_size": args.leaf_size,
+                  "group_size": args.group_size, "split_images": args.split_images,
+                  "walk_waves": args.walk_waves},
+        "sources": list(WALK_SRC[path]), "source_sha256": walk_source_sha(path),
+        "fetch_kib_per_dispatch_raw": mean(w_f), "write_kib_per_dispatch_raw": mean(w_w),
+        "fetch_kib_min_max": [min(w_f), max(w_f)], "write_kib_min_max": [min(w_w), max(w_w)],
+        "copy_calibration": {"copy_bytes": copy_bytes, "fetch_kib_raw": mean(c_f),
+                             "write_kib_raw": mean(c_w), "fetch_scale": fs, "write_scale": ws},
+        "fetch_bytes_per_launch": mean(w_f) * 1024 * fs,
+        "write_bytes_per_launch": mean(w_w) * 1024 * ws,
+        "dispatches": len(w_f),
+    }
+    meta["bytes_per_launch"] = meta["fetch_bytes_per_launch"] + meta["write_bytes_per_launch"]
+    out = os.path.join(ROOT, "profiles", f"walk_{path}_{args.workload}_traffic.json")
+    with open(out, "w") as fh:
+        json.dump(meta, fh, indent=1)
+    print(json.dumps(meta))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,7 +204,14 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the known-size "
                          "kernel that scales the HBM byte counters) and exit")
+    ap.add_argument("--write-traffic", nargs=4, default=None,
+                    metavar=("COPY_FETCH", "COPY_WRITE", "WALK_FETCH", "WALK_WRITE"),
+                    help="only turn four rocprofv3 --pmc output folders into the stored "
+                         "walk traffic for the knobs given (runs without a GPU) and exit")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
@@ -285,13 +360,15 @@ def main():
     traffic = None
     tf = os.path.join(ROOT, "profiles", f"walk_{main_path}_{args.workload}_traffic.json")
     if os.path.exists(tf):
+        # only for the same kernel sources at the same operating point
         meta = json.load(open(tf))
-        src = open(os.path.join(ROOT, WALK_SRC[main_path]), "rb").read()
-        if meta.get("source_sha256") == hashlib.sha256(src).hexdigest():
+        knobs = {k: r[k] for k in KNOBS}
+        if (meta.get("source_sha256") == walk_source_sha(main_path) and
+                meta.get("knobs") == knobs):
             traffic = meta.get("bytes_per_launch")
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-                "kernel": "k_walk32" if main_path == "fp32" else "k_walk64"}
+                "kernel": walk_kernel_name(main_path, r["walk_waves"])}
 
     cpu = None
     if not args.no_cpu_baseline:

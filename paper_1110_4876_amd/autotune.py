@@ -43,7 +43,8 @@ def tune(system, ref, targets, t_kick, precision=rb.RB_FP32_MIXED, rms_target=1e
     system's initial state.
     checks: further (state, time, reference) triples -- e.g. a state from
     late in the run -- that every accepted candidate must also meet; the
-    reported errors are those of the worst check.
+    reported errors are those of the worst check.  Candidates are timed
+    from the initial state and from each check state (the mean is kept).
     graphs: launch modes (0 eager, 1 HIP-graph replay of the step); the
     first is timed for every candidate, the others for the three fastest.
     They do not change the result.
@@ -87,27 +88,35 @@ def tune(system, ref, targets, t_kick, precision=rb.RB_FP32_MIXED, rms_target=1e
             rb.rb_destroy(ctx)
         return worst
 
+    # Steps are timed from the initial state and from every check state:
+    # the cost of a step can change along a run (a sheet thickens, a
+    # cluster contracts), and the run as a whole is what is measured.
+    starts = [(None, 0.0)] + [(X, t) for X, t, _ in checks]
+
     def time_steps(knobs, th, graph):
         ctx = system.create(precision, theta=th, use_graph=graph, **knobs)
+        total = 0.0
         try:
-            X = system.clone()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            system.step(ctx, X, 0.0, 1)
-            rb.rb_sync(ctx)
-            first = time.perf_counter() - t0
-            # about 0.2 s of steps per repeat, between 2 and `steps`
-            k = int(min(steps, max(2, 0.2 / max(first, 1e-6))))
-            times = []
-            for _ in range(repeats):
+            for X0, t_start in starts:
+                X = system.clone() if X0 is None else {k: v.clone() for k, v in X0.items()}
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                system.step(ctx, X, 0.0, k)
+                system.step(ctx, X, t_start, 1)
                 rb.rb_sync(ctx)
-                times.append((time.perf_counter() - t0) * 1e3 / k)
+                first = time.perf_counter() - t0
+                # about 0.2 s of steps per repeat, between 2 and `steps`
+                k = int(min(steps, max(2, 0.2 / max(first, 1e-6))))
+                times = []
+                for _ in range(repeats):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    system.step(ctx, X, t_start, k)
+                    rb.rb_sync(ctx)
+                    times.append((time.perf_counter() - t0) * 1e3 / k)
+                total += min(times)
         finally:
             rb.rb_destroy(ctx)
-        return min(times)
+        return total / len(starts)
 
     # phase 1: for every (leaf, group, split), the largest theta on the grid
     # meeting the target (local search from the last candidate's theta: the

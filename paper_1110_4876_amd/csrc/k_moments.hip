@@ -101,8 +101,7 @@ __device__ __forceinline__ void mom_child_q(Mom &a, double M, double x, double y
 __device__ __forceinline__ void mom_store(uint32_t id, const Mom &a, NodeLink lk,
                                           NodeLink *__restrict__ link,
                                           double4 *__restrict__ mcom, double *__restrict__ Sarr,
-                                          double *__restrict__ Qarr, float4 *__restrict__ qf0,
-                                          float2 *__restrict__ qf1) {
+                                          double *__restrict__ Qarr, WNode *__restrict__ wn) {
   link[id] = lk;
   mcom[id] = make_double4(a.c0, a.c1, a.c2, a.M);
   Sarr[3 * (size_t)id + 0] = a.S0;
@@ -110,8 +109,16 @@ __device__ __forceinline__ void mom_store(uint32_t id, const Mom &a, NodeLink lk
   Sarr[3 * (size_t)id + 2] = a.S2;
   double *q = Qarr + 6 * (size_t)id;
   q[0] = a.Q0; q[1] = a.Q1; q[2] = a.Q2; q[3] = a.Q3; q[4] = a.Q4; q[5] = a.Q5;
-  qf0[id] = make_float4((float)a.Q0, (float)a.Q1, (float)a.Q2, (float)a.Q3);
-  qf1[id] = make_float2((float)a.Q4, (float)a.Q5);
+  if (wn) {
+    WNode r;
+    r.cx = a.c0; r.cy = a.c1; r.cz = a.c2; r.M = a.M;
+    r.child_or_first = lk.child_or_first;
+    r.count = lk.count;
+    r.lvl = lk.lvl;
+    r.qxx = (float)a.Q0; r.qxy = (float)a.Q1; r.qxz = (float)a.Q2;
+    r.qyy = (float)a.Q3; r.qyz = (float)a.Q4;
+    wn[id] = r;
+  }
 }
 
 // One node whose links are given (its children, if any, already done).
@@ -121,7 +128,7 @@ __device__ __forceinline__ void rb_node_moments_at(
     const double *__restrict__ sy, const double *__restrict__ sz,
     const double *__restrict__ msrc, int quad, NodeLink *__restrict__ link,
     double4 *__restrict__ mcom, double *__restrict__ Sarr, double *__restrict__ Qarr,
-    float4 *__restrict__ qf0, float2 *__restrict__ qf1, uint32_t n_slots,
+    WNode *__restrict__ wn, uint32_t n_slots,
     uint32_t *__restrict__ err) {
   // inconsistent links make the node massless and never opened
   const bool bad = is_leaf ? !(first <= last && last < n_slots)
@@ -135,7 +142,7 @@ __device__ __forceinline__ void rb_node_moments_at(
     lk.child_or_first = RB_NONE;
     lk.count = 0;
     lk.lvl = (uint32_t)level | 256u;
-    mom_store(id, a, lk, link, mcom, Sarr, Qarr, qf0, qf1);
+    mom_store(id, a, lk, link, mcom, Sarr, Qarr, wn);
     return;
   }
   const uint32_t count = last - first + 1;
@@ -165,7 +172,7 @@ __device__ __forceinline__ void rb_node_moments_at(
   lk.child_or_first = cf;
   lk.count = count;
   lk.lvl = (uint32_t)level | (is_leaf ? 256u : 0u) | (n_child << 9);
-  mom_store(id, a, lk, link, mcom, Sarr, Qarr, qf0, qf1);
+  mom_store(id, a, lk, link, mcom, Sarr, Qarr, wn);
 }
 
 // One node from global memory.
@@ -177,17 +184,17 @@ __device__ __forceinline__ void rb_node_moments(
     const double *__restrict__ sy, const double *__restrict__ sz,
     const double *__restrict__ msrc, int quad, NodeLink *__restrict__ link,
     double4 *__restrict__ mcom, double *__restrict__ Sarr, double *__restrict__ Qarr,
-    float4 *__restrict__ qf0, float2 *__restrict__ qf1, uint32_t n_slots,
+    WNode *__restrict__ wn, uint32_t n_slots,
     uint32_t *__restrict__ err) {
   const bool is_leaf = nleaf[id] != 0;
   rb_node_moments_at(id, level, nfirst[id], nlast[id], is_leaf, is_leaf ? 0u : nchild[id],
                      is_leaf ? 0u : nlastchild[id], nskip[id], clo, chi, sx, sy, sz, msrc, quad,
-                     link, mcom, Sarr, Qarr, qf0, qf1, n_slots, err);
+                     link, mcom, Sarr, Qarr, wn, n_slots, err);
 }
 
 #define RB_MOMENT_ARGS                                                                 \
   nfirst, nlast, nchild, nlastchild, nskip, nleaf, sx, sy, sz, msrc, quad, link, mcom, \
-      Sarr, Qarr, qf0, qf1, n_slots, err
+      Sarr, Qarr, wn, n_slots, err
 #define RB_MOMENT_PARAMS                                                               \
   const uint32_t *__restrict__ nfirst, const uint32_t *__restrict__ nlast,               \
       const uint32_t *__restrict__ nchild, const uint32_t *__restrict__ nlastchild,     \
@@ -195,23 +202,30 @@ __device__ __forceinline__ void rb_node_moments(
       const double *__restrict__ sx, const double *__restrict__ sy,                     \
       const double *__restrict__ sz, const double *__restrict__ msrc, int quad,         \
       NodeLink *__restrict__ link, double4 *__restrict__ mcom, double *__restrict__ Sarr, \
-      double *__restrict__ Qarr, float4 *__restrict__ qf0, float2 *__restrict__ qf1,      \
+      double *__restrict__ Qarr, WNode *__restrict__ wn,      \
       uint32_t n_slots, uint32_t *__restrict__ err
 
 // Groups: the children with at most G particles of nodes with more than G,
 // and roots with at most G; a leaf with more than G particles (deepest
 // level, or leaf_size > G) contributes runs of G particles.  group.pad is
-// the group's node (RB_NONE for such runs).  Nodes with more than G
-// particles are listed per level for the large-node pass.  Emission order is
-// free: every result depends only on the node itself.  Slots in the group
-// table and in the per-level lists are taken with one atomic per wave.
+// the group's node (RB_NONE for such runs).  These node groups carry the
+// moments pass.  The walk takes work items of its own: consecutive small
+// children of one node are packed into items of at most G particles (a run
+// ends at a large child or when the next child would overflow it), so that
+// an item fills the wave's lanes even when a node's octants hold few
+// particles each; an item is a Morton-contiguous slot range, and the walk
+// bounds it by its members' box.  Nodes with more than G particles are
+// listed per level for the large-node pass.  Emission order is free: every
+// result depends only on the node itself.  Slots in the tables and in the
+// per-level lists are taken with one atomic per wave.
 __global__ __launch_bounds__(256) void k_groups(
     const uint32_t *__restrict__ lev_off, const uint32_t *__restrict__ nfirst,
     const uint32_t *__restrict__ nlast, const uint32_t *__restrict__ nchild,
     const uint32_t *__restrict__ nlastchild, const uint8_t *__restrict__ nleaf,
     const uint8_t *__restrict__ nlevel, const uint32_t *__restrict__ starts, uint32_t P,
-    uint32_t G, WalkItem *__restrict__ groups, uint32_t *__restrict__ gctr,
-    uint32_t *__restrict__ large, uint32_t *__restrict__ large_cnt) {
+    uint32_t G, WalkItem *__restrict__ groups, WalkItem *__restrict__ witems,
+    uint32_t *__restrict__ gctr, uint32_t *__restrict__ large,
+    uint32_t *__restrict__ large_cnt) {
   const uint32_t n_nodes = lev_off[RB_NLEV];
   const uint32_t lane = rb_lane();
   for (uint32_t base = blockIdx.x * blockDim.x; base < n_nodes; base += gridDim.x * blockDim.x) {
@@ -222,32 +236,63 @@ __global__ __launch_bounds__(256) void k_groups(
     if (in) { f = nfirst[id]; l = nlast[id]; lvl = nlevel[id]; leaf = nleaf[id] != 0; }
     const uint32_t cnt = l - f + 1;
     const bool is_large = in && cnt > G;
-    uint32_t ca = 0, cb = 0, n_emit = 0;
-    if (in && !is_large && lvl == 0) n_emit = 1;
-    if (is_large && leaf) n_emit = (cnt + G - 1) / G;
+    uint32_t ca = 0, cb = 0, n_emit = 0, n_wemit = 0;
+    if (in && !is_large && lvl == 0) n_emit = n_wemit = 1;
+    if (is_large && leaf) n_emit = n_wemit = (cnt + G - 1) / G;
     if (is_large && !leaf) {
       ca = nchild[id]; cb = nlastchild[id];
-      for (uint32_t c = ca; c <= cb && c < n_nodes; ++c)
-        if (nlast[c] - nfirst[c] + 1 <= G) ++n_emit;
+      uint32_t run = 0;
+      for (uint32_t c = ca; c <= cb && c < n_nodes; ++c) {
+        const uint32_t cc = nlast[c] - nfirst[c] + 1;
+        if (cc <= G) {
+          ++n_emit;
+          if (run && run + cc > G) { ++n_wemit; run = 0; }
+          run += cc;
+        } else if (run) {
+          ++n_wemit;
+          run = 0;
+        }
+      }
+      if (run) ++n_wemit;
     }
-    // group slots: one atomic per wave
+    // table slots: one atomic per wave and table
     const uint32_t incl = rb_wave_incl_scan(n_emit);
     const uint32_t total = __shfl(incl, 63, 64);
-    uint32_t gbase = 0;
+    const uint32_t wincl = rb_wave_incl_scan(n_wemit);
+    const uint32_t wtotal = __shfl(wincl, 63, 64);
+    uint32_t gbase = 0, wbase = 0;
     if (lane == 63 && total) gbase = atomicAdd(&gctr[0], total);
+    if (lane == 63 && wtotal) wbase = atomicAdd(&gctr[2], wtotal);
     gbase = __shfl(gbase, 63, 64);
-    uint32_t pos = gbase + incl - n_emit;
+    wbase = __shfl(wbase, 63, 64);
+    uint32_t pos = gbase + incl - n_emit, wpos = wbase + wincl - n_wemit;
     if (n_emit) {
       const uint32_t p = (P == 1) ? 0u : rb_patch_of(starts, P, f);
       if (!is_large) {
         groups[pos] = {f, l + 1, p, id};
+        witems[wpos] = {f, l + 1, p, id};
       } else if (leaf) {
-        for (uint32_t s = f; s <= l; s += G) groups[pos++] = {s, (s + G <= l + 1) ? s + G : l + 1, p, RB_NONE};
-      } else {
-        for (uint32_t c = ca; c <= cb && c < n_nodes; ++c) {
-          const uint32_t cf = nfirst[c], cl = nlast[c];
-          if (cl - cf + 1 <= G) groups[pos++] = {cf, cl + 1, p, c};
+        for (uint32_t s = f; s <= l; s += G) {
+          const WalkItem it = {s, (s + G <= l + 1) ? s + G : l + 1, p, RB_NONE};
+          groups[pos++] = it;
+          witems[wpos++] = it;
         }
+      } else {
+        uint32_t run = 0, r0 = 0, r1 = 0;
+        for (uint32_t c = ca; c <= cb && c < n_nodes; ++c) {
+          const uint32_t cf = nfirst[c], cl = nlast[c], cc = cl - cf + 1;
+          if (cc <= G) {
+            groups[pos++] = {cf, cl + 1, p, c};
+            if (run && run + cc > G) { witems[wpos++] = {r0, r1, p, RB_NONE}; run = 0; }
+            if (!run) r0 = cf;
+            r1 = cl + 1;
+            run += cc;
+          } else if (run) {
+            witems[wpos++] = {r0, r1, p, RB_NONE};
+            run = 0;
+          }
+        }
+        if (run) witems[wpos++] = {r0, r1, p, RB_NONE};
       }
     }
     // large-node lists: the lanes of one level share one atomic
@@ -287,7 +332,7 @@ __global__ __launch_bounds__(128) void k_moments_group(
     const double *__restrict__ sy, const double *__restrict__ sz,
     const double *__restrict__ msrc, int L, int quad, NodeLink *__restrict__ link,
     double4 *__restrict__ mcom, double *__restrict__ Sarr, double *__restrict__ Qarr,
-    float4 *__restrict__ qf0, float2 *__restrict__ qf1, uint32_t *__restrict__ err) {
+    WNode *__restrict__ wn, uint32_t *__restrict__ err) {
   // two independent waves per workgroup (fewer workgroups to dispatch),
   // each with its own LDS slice; within a wave LDS accesses stay in order,
   // so a wave-level fence orders its writes and reads
@@ -410,7 +455,7 @@ __global__ __launch_bounds__(128) void k_moments_group(
           lk.skip = skip;
           lk.count = end - lane;
           lk.lvl = (uint32_t)l | (is_leaf ? 256u : 0u) | ((uint32_t)__popcll(kids) << 9);
-          mom_store(id, a, lk, link, mcom, Sarr, Qarr, qf0, qf1);
+          mom_store(id, a, lk, link, mcom, Sarr, Qarr, wn);
         } else {
           atomicOr(err, RB_ERR_TREE);
         }
@@ -425,6 +470,16 @@ __global__ __launch_bounds__(128) void k_moments_group(
 // nodes fit, their links are fetched into LDS up front, so that each level
 // waits only for its children's moments.
 #define ML_CAP 2048
+
+// Touch the 128-byte lines of doubles [a, b) of p with loads that skip the
+// CU's L1 (agent scope), leaving them in this XCD's L2.
+__device__ __forceinline__ uint64_t ml_touch(const double *p, uint32_t a, uint32_t b) {
+  uint64_t s = 0;
+  for (uint32_t d = a; d < b; d = (d | 15u) + 1u)
+    s ^= __hip_atomic_load(reinterpret_cast<uint64_t *>(const_cast<double *>(p + d)),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return s;
+}
 __global__ __launch_bounds__(512) void k_moments_large(
     const uint32_t *__restrict__ large, const uint32_t *__restrict__ large_cnt,
     const uint32_t *__restrict__ lev_off, RB_MOMENT_PARAMS) {
@@ -459,6 +514,19 @@ __global__ __launch_bounds__(512) void k_moments_large(
       l_skip[i] = nskip[id];
     }
     __syncthreads();
+    // The group pass wrote the lower children from every XCD: request all
+    // children's records now, in one round, so that each level below waits
+    // on L2 instead of memory.  (The loads only feed a store that never
+    // happens; a child written later in this kernel is read again then.)
+    uint64_t sink = 0;
+    for (uint32_t i = tid; i < total; i += blockDim.x) {
+      const uint32_t ca = l_ca[i], cb = l_cb[i];
+      if (l_leaf[i] || cb < ca || cb - ca >= 8 || cb >= s_off[RB_NLEV]) continue;
+      sink ^= ml_touch(reinterpret_cast<const double *>(mcom), 4 * ca, 4 * cb + 4);
+      sink ^= ml_touch(Sarr, 3 * ca, 3 * cb + 3);
+      if (quad) sink ^= ml_touch(Qarr, 6 * ca, 6 * cb + 6);
+    }
+    if (sink == 0x5eed5eed5eed5eedull) atomicOr(err, 0u);
   }
   // one thread per node; an internal node's (at most eight) children are
   // all fetched before any sum, so a level costs one memory round trip
@@ -483,7 +551,7 @@ __global__ __launch_bounds__(512) void k_moments_large(
       const bool ok = !leaf && ca >= clo && ca <= cb && cb < chi && cb - ca < 8;
       if (!ok) {  // leaves, and anything inconsistent (reported there)
         rb_node_moments_at(id, l, first, last, leaf, ca, cb, skip, clo, chi, sx, sy, sz, msrc,
-                           quad, link, mcom, Sarr, Qarr, qf0, qf1, n_slots, err);
+                           quad, link, mcom, Sarr, Qarr, wn, n_slots, err);
         continue;
       }
       const uint32_t nch = cb - ca + 1;
@@ -538,7 +606,7 @@ __global__ __launch_bounds__(512) void k_moments_large(
       lk.skip = skip;
       lk.count = last - first + 1;
       lk.lvl = (uint32_t)l | (nch << 9);
-      mom_store(id, a, lk, link, mcom, Sarr, Qarr, qf0, qf1);
+      mom_store(id, a, lk, link, mcom, Sarr, Qarr, wn);
     }
     __syncthreads();
   }
@@ -559,21 +627,24 @@ hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const d
   const uint32_t n = (uint32_t)c->h_starts[c->P];
   if (n == 0) return hipSuccess;
   const uint32_t G = (uint32_t)c->p.group_size;
+  // the grouped walk's node records are written only when it will run
+  WNode *const wnode = c->p.precision == RB_FP32_MIXED ? c->d_wnode : nullptr;
   unsigned grid = rb_div_up(c->node_cap, 256);
   if (grid > 2048) grid = 2048;
   hipLaunchKernelGGL(k_groups, dim3(grid), dim3(256), 0, c->stream, c->d_lev_off, c->d_nfirst,
                      c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nleaf, c->d_nlevel,
-                     c->d_starts, c->P, G, c->d_groups, c->d_gctr, c->d_large, c->d_large_cnt);
+                     c->d_starts, c->P, G, c->d_groups, c->d_witems, c->d_gctr, c->d_large,
+                     c->d_large_cnt);
 #define RB_MARGS                                                                          \
   c->d_nfirst, c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nskip, c->d_nleaf, sx, sy, sz, \
-      c->d_msrc, c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, c->d_qf0, c->d_qf1,  \
+      c->d_msrc, c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, wnode,              \
       (uint32_t)c->cap, c->d_err
   unsigned sgrid = rb_div_up(n, 32);  // two waves per workgroup
   if (sgrid > 131072) sgrid = 131072;
   hipLaunchKernelGGL(k_moments_group, dim3(sgrid), dim3(128), 0, c->stream, c->d_groups,
                      c->d_gctr, c->d_key[0], c->d_starts, c->d_csr, c->d_start_ids, c->d_nskip,
                      c->d_nlevel, c->d_lev_off, sx, sy, sz, c->d_msrc, c->p.leaf_size,
-                     c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, c->d_qf0, c->d_qf1,
+                     c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, wnode,
                      c->d_err);
   if (n <= (1u << 22)) {
     hipLaunchKernelGGL(k_moments_large, dim3(1), dim3(512), 0, c->stream, c->d_large,

@@ -114,9 +114,9 @@ __global__ __launch_bounds__(64) void k_topo_write(
   const uint32_t lincl = rb_wave_incl_scan(tot);
   const uint32_t lbase_lane = lincl - tot;
   const uint32_t total = __shfl(lincl, 63, 64);
-  // the grouped walk's counters (groups emitted, work items taken) restart
-  // with every tree, also when this tree fails its capacity check
-  if (b == 0 && lane < 2) gctr[lane] = 0;
+  // the grouped walk's counters (node groups emitted, work items taken,
+  // walk items emitted) restart with every tree, also when this tree fails its capacity check
+  if (b == 0 && lane < 4) gctr[lane] = 0;
   if (b == 0 && lane < RB_NLEV) large_cnt[lane] = 0;
   if (total > node_cap) {
     // nothing is written; the tree is left empty (no levels, no live

@@ -1,17 +1,19 @@
 // k_walk32.hip -- grouped FP32-mixed tree walk (a variant of the walk of
 // Sect. 4.2 of the paper).
 //
-// Groups are the maximal tree nodes holding at most G particles (G =
-// group_size, emitted during the build), so each group is spatially compact;
-// together they partition the particles.  One wave serves one work item (a
-// group with all its images, or one (group, image) pair), pulled from a
-// device queue by a persistent grid of workgroups of four independent
-// waves; 64 / 2^ceil(log2 n) lanes share each of the group's n particles.
-// The image offsets of the item are tabulated in LDS once.  The wave walks the tree once for the whole
-// group: a node is accepted for every member at once when
-// w^2 < theta^2 R_min^2, R_min being the distance from the node's
-// image-shifted centre of mass to the group's bounding box -- no member is
-// closer, so every member would accept the node on its own.  Accepted cells
+// Work items are Morton-contiguous runs of particles: consecutive children
+// of one node, each holding at most G particles (G = group_size), packed up
+// to G particles in all (emitted during the build), so each item is
+// spatially compact and the items partition the particles.  One wave serves
+// one work item (an item with all its images, or one (item, image) pair),
+// pulled from a device queue by a persistent grid of workgroups of four
+// independent waves; floor(64 / n) lanes share each of the item's n
+// particles.  The image offsets of the item are tabulated in LDS once.  The
+// wave walks the tree once for the whole group (the item's particles): a
+// node is accepted for every member at once when w^2 < theta^2 R_min^2,
+// R_min being the distance from the node's image-shifted centre of mass to
+// the group's bounding box -- no member is closer, so every member would
+// accept the node on its own.  Accepted cells
 // and the particles of single-particle or opened leaves go to LDS
 // interaction lists (ballot / mbcnt compaction), evaluated by all lanes
 // reading the same entry (LDS broadcast).
@@ -33,6 +35,13 @@
 #endif
 
 __device__ __forceinline__ int w32_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// a value equal in every lane, moved to scalar registers
+__device__ __forceinline__ double w32_uniform_d(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
 
 __device__ __forceinline__ void w32_image(int im, int ngx, int ngy, int boundary, double W,
                                           double s, double &ox, double &oy) {
@@ -43,6 +52,12 @@ __device__ __forceinline__ void w32_image(int im, int ngx, int ngy, int boundary
   const double sh = (boundary == RB_SHEAR) ? s : 0.0;
   ox = fx * W;
   oy = fy * W - fx * sh;
+}
+
+// order a wave's LDS writes before its later reads (a wave runs in lockstep)
+__device__ __forceinline__ void w32_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 struct F3 {
@@ -132,9 +147,7 @@ template <bool QUAD, bool STATS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_walk32(
     const WalkItem *__restrict__ groups, uint32_t *__restrict__ gctr, int img_split, int n_img,
     int ngx, int ngy, int boundary, const PatchInfo *__restrict__ patch,
-    const uint32_t *__restrict__ root, const NodeLink *__restrict__ link,
-    const double4 *__restrict__ mcom, const float4 *__restrict__ qf0,
-    const float2 *__restrict__ qf1,
+    const uint32_t *__restrict__ root, const WNode *__restrict__ wn,
     const double *__restrict__ sx, const double *__restrict__ sy,
     const double *__restrict__ sz, const double *__restrict__ msrc,
     const double *__restrict__ sched, const uint32_t *__restrict__ ctr, uint32_t P,
@@ -149,6 +162,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   __shared__ float4 ppos_all[4][W32_PL];
   __shared__ double2 img_all[4][RB_MAX_IMAGES];
 
+  static_assert(sizeof(cpos_all[0]) >= 3 * 64 * sizeof(double), "reduction space");
   // the wave index is uniform: keep it (and the LDS bases) in scalar registers
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint32_t *stk = stk_all[wv];
@@ -157,7 +171,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   float2 *cq1 = cq1_all[wv];
   float4 *ppos = ppos_all[wv];
   double2 *img = img_all[wv];
-  const uint32_t n_groups = gctr[0];
+  const uint32_t n_groups = gctr[2];  // walk items
   const uint32_t per = img_split ? (uint32_t)n_img : 1u;
   const uint32_t n_items = n_groups * per;
   const double theta2d = theta2;
@@ -176,11 +190,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const uint32_t p = grp.patch;
     const double W = patch[p].W;
     const int cnt = (int)(grp.end - grp.start);
-    const int gp = cnt <= 16 ? 16 : (cnt <= 32 ? 32 : 64);  // particle slots
-    const int lpp = 64 / gp;
-    const int pidx = lane % gp, sub = lane / gp;
-    const bool valid = pidx < cnt;
-    const uint32_t s = grp.start + (uint32_t)(valid ? pidx : 0);
+    if (cnt < 1 || cnt > 64) {  // never emitted
+      if (lane == 0) atomicOr(err, RB_ERR_TREE);
+      continue;
+    }
+    // lpp = floor(64 / cnt) lanes per member, lane = member + cnt * sub;
+    // the lanes past lpp * cnt repeat members and are left out of the sums
+    const int lpp = 64 / cnt;
+    const int pidx = lane % cnt, sub = lane / cnt;
+    const bool valid = sub < lpp;
+    const uint32_t s = grp.start + (uint32_t)pidx;
 
     double x = sx[s], y = sy[s], z = sz[s];
     double lx = valid ? x : INFINITY, ly = valid ? y : INFINITY, lz = valid ? z : INFINITY;
@@ -191,6 +210,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       lz = fmin(lz, __shfl_xor(lz, d, 64)); hx = fmax(hx, __shfl_xor(hx, d, 64));
       hy = fmax(hy, __shfl_xor(hy, d, 64)); hz = fmax(hz, __shfl_xor(hz, d, 64));
     }
+    // the box is the same in every lane
+    lx = w32_uniform_d(lx); ly = w32_uniform_d(ly); lz = w32_uniform_d(lz);
+    hx = w32_uniform_d(hx); hy = w32_uniform_d(hy); hz = w32_uniform_d(hz);
     const double gx = 0.5 * (lx + hx), gy = 0.5 * (ly + hy), gz = 0.5 * (lz + hz);
     const double invW = 1.0 / W;
     const double gm_scale = Gc * invW * invW;
@@ -233,9 +255,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       q1 = make_float2(0.f, 0.f);
       if (has) {
         const uint32_t nd = e >> 5;
-        lk = link[nd];
-        mc = mcom[nd];
-        if (QUAD) { q0 = qf0[nd]; q1 = qf1[nd]; }
+        const WNode r = wn[nd];  // one 64-byte line
+        lk.child_or_first = r.child_or_first;
+        lk.count = r.count;
+        lk.lvl = r.lvl;
+        mc = make_double4(r.cx, r.cy, r.cz, r.M);
+        if (QUAD) {
+          q0 = make_float4(r.qxx, r.qxy, r.qxz, r.qyy);
+          q1 = make_float2(r.qyz, -(r.qxx + r.qyy));
+        }
       }
     };
     int k;
@@ -346,14 +374,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       w32_eval_parts(ppos, pl, sub, lpp, px, py, pz, b2, ax, ay, az);
       if (STATS) n_pp += (unsigned long long)pl * (unsigned long long)cnt;
     }
-    // lanes l, l + gp, ... hold partial sums of the same particle
-    for (int d = gp; d < 64; d <<= 1) {
-      ax += __shfl_xor(ax, d, 64); ay += __shfl_xor(ay, d, 64); az += __shfl_xor(az, d, 64);
-    }
-    if (sub == 0 && valid) {
+    // lanes m, m + cnt, ... hold partial sums of member m: added in that
+    // order through the wave's cell list, which is no longer needed
+    double(*red)[64] = reinterpret_cast<double(*)[64]>(cpos);
+    w32_wave_sync();
+    red[0][lane] = ax; red[1][lane] = ay; red[2][lane] = az;
+    w32_wave_sync();
+    if (lane < cnt) {
+      double tx = red[0][lane], ty = red[1][lane], tz = red[2][lane];
+      for (int k = 1; k < lpp; ++k) {
+        tx += red[0][lane + k * cnt]; ty += red[1][lane + k * cnt]; tz += red[2][lane + k * cnt];
+      }
       double *a = acc + (size_t)(img_split ? im0 : 0) * 3 * cap;
-      a[s] = ax; a[cap + s] = ay; a[2 * cap + s] = az;
+      a[s] = tx; a[cap + s] = ty; a[2 * cap + s] = tz;
     }
+    w32_wave_sync();  // the list is rewritten by the next item
   }
   if (STATS && lane == 0) {
     atomicAdd(&stats[3], n_cell);
@@ -374,9 +409,7 @@ template <bool QUAD, bool STATS, int NW>
 __global__ __launch_bounds__(64 * NW) void k_walk32m(
     const WalkItem *__restrict__ groups, uint32_t *__restrict__ gctr, int img_split, int n_img,
     int ngx, int ngy, int boundary, const PatchInfo *__restrict__ patch,
-    const uint32_t *__restrict__ root, const NodeLink *__restrict__ link,
-    const double4 *__restrict__ mcom, const float4 *__restrict__ qf0,
-    const float2 *__restrict__ qf1, const double *__restrict__ sx,
+    const uint32_t *__restrict__ root, const WNode *__restrict__ wn, const double *__restrict__ sx,
     const double *__restrict__ sy, const double *__restrict__ sz,
     const double *__restrict__ msrc, const double *__restrict__ sched,
     const uint32_t *__restrict__ ctr, uint32_t P, double Gc, double soft, double theta2,
@@ -400,7 +433,7 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
   float4 *cq0 = cq0_all[w];
   float2 *cq1 = cq1_all[w];
   float4 *ppos = ppos_all[w];
-  const uint32_t n_groups = gctr[0];
+  const uint32_t n_groups = gctr[2];  // walk items
   const uint32_t per = img_split ? (uint32_t)n_img : 1u;
   const uint32_t n_items = n_groups * per;
   const double theta2d = theta2;
@@ -409,7 +442,7 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(&gctr[1], 1u);
     __syncthreads();
-    const uint32_t item = s_item;
+    const uint32_t item = (uint32_t)w32_uniform((int)s_item);
     __syncthreads();  // every thread has read the item before it changes
     if (item >= n_items) break;  // uniform over the block
     const uint32_t gi = img_split ? item % n_groups : item;
@@ -419,11 +452,16 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
     const uint32_t p = grp.patch;
     const double W = patch[p].W;
     const int cnt = (int)(grp.end - grp.start);
-    const int gp = cnt <= 16 ? 16 : (cnt <= 32 ? 32 : 64);
-    const int lpp = 64 / gp;
-    const int pidx = lane % gp, sub = lane / gp;
-    const bool valid = pidx < cnt;
-    const uint32_t s = grp.start + (uint32_t)(valid ? pidx : 0);
+    if (cnt < 1 || cnt > 64) {  // never emitted
+      if (lane == 0) atomicOr(err, RB_ERR_TREE);
+      continue;
+    }
+    // lpp = floor(64 / cnt) lanes per member, lane = member + cnt * sub;
+    // the lanes past lpp * cnt repeat members and are left out of the sums
+    const int lpp = 64 / cnt;
+    const int pidx = lane % cnt, sub = lane / cnt;
+    const bool valid = sub < lpp;
+    const uint32_t s = grp.start + (uint32_t)pidx;
     double x = sx[s], y = sy[s], z = sz[s];
     double lx = valid ? x : INFINITY, ly = valid ? y : INFINITY, lz = valid ? z : INFINITY;
     double hx = valid ? x : -INFINITY, hy = valid ? y : -INFINITY, hz = valid ? z : -INFINITY;
@@ -433,6 +471,9 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
       lz = fmin(lz, __shfl_xor(lz, d, 64)); hx = fmax(hx, __shfl_xor(hx, d, 64));
       hy = fmax(hy, __shfl_xor(hy, d, 64)); hz = fmax(hz, __shfl_xor(hz, d, 64));
     }
+    // the box is the same in every lane
+    lx = w32_uniform_d(lx); ly = w32_uniform_d(ly); lz = w32_uniform_d(lz);
+    hx = w32_uniform_d(hx); hy = w32_uniform_d(hy); hz = w32_uniform_d(hz);
     const double gx = 0.5 * (lx + hx), gy = 0.5 * (ly + hy), gz = 0.5 * (lz + hz);
     const double invW = 1.0 / W;
     const double gm_scale = Gc * invW * invW;
@@ -472,9 +513,15 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
       float2 q1 = make_float2(0.f, 0.f);
       if (has) {
         const uint32_t nd = e >> 5;
-        lk = link[nd];
-        mc = mcom[nd];
-        if (QUAD) { q0 = qf0[nd]; q1 = qf1[nd]; }
+        const WNode r = wn[nd];  // one 64-byte line
+        lk.child_or_first = r.child_or_first;
+        lk.count = r.count;
+        lk.lvl = r.lvl;
+        mc = make_double4(r.cx, r.cy, r.cz, r.M);
+        if (QUAD) {
+          q0 = make_float4(r.qxx, r.qxy, r.qxz, r.qyy);
+          q1 = make_float2(r.qyz, -(r.qxx + r.qyy));
+        }
       }
       // full lists are evaluated while the node records are in flight
       if (cl >= W32_CFLUSH) {
@@ -584,24 +631,23 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
       w32_eval_parts(ppos, pl, sub, lpp, px, py, pz, b2, ax, ay, az);
       if (STATS) n_pp += (unsigned long long)pl * (unsigned long long)cnt;
     }
-    for (int d = gp; d < 64; d <<= 1) {
-      ax += __shfl_xor(ax, d, 64); ay += __shfl_xor(ay, d, 64); az += __shfl_xor(az, d, 64);
-    }
-    // the waves' partial forces, added in wave order (every wave has
-    // finished its list evaluation before the lists' memory is reused)
+    // the partial forces of member m sit in lanes m, m + cnt, ... of every
+    // wave: added in wave order, then lane order (every wave has finished
+    // its list evaluation before the lists' memory is reused)
     __syncthreads();
     s_red[w][0][lane] = ax; s_red[w][1][lane] = ay; s_red[w][2][lane] = az;
     __syncthreads();
-    if (w == 0) {
+    if (w == 0 && lane < cnt) {
       double tx = 0.0, ty = 0.0, tz = 0.0;
 #pragma unroll
       for (int q = 0; q < NW; ++q) {
-        tx += s_red[q][0][lane]; ty += s_red[q][1][lane]; tz += s_red[q][2][lane];
+        for (int k = 0; k < lpp; ++k) {
+          tx += s_red[q][0][lane + k * cnt]; ty += s_red[q][1][lane + k * cnt];
+          tz += s_red[q][2][lane + k * cnt];
+        }
       }
-      if (sub == 0 && valid) {
-        double *a = acc + (size_t)(img_split ? im0 : 0) * 3 * cap;
-        a[s] = tx; a[cap + s] = ty; a[2 * cap + s] = tz;
-      }
+      double *a = acc + (size_t)(img_split ? im0 : 0) * 3 * cap;
+      a[s] = tx; a[cap + s] = ty; a[2 * cap + s] = tz;
     }
     __syncthreads();  // s_red and the stack are reused by the next item
   }
@@ -624,8 +670,8 @@ hipError_t launch_walk32(rb_ctx *c, const double *sx, const double *sy, const do
   const double th2 = c->p.theta * c->p.theta;
   const bool quad = c->p.quadrupole != 0, stats = (c->p.profile & 2) != 0;
 #define RB_W32_ARGS                                                                      \
-  c->d_groups, c->d_gctr, c->img_split, c->n_img, c->p.n_ghost[0], c->p.n_ghost[1],       \
-      c->p.boundary, c->d_patch, c->d_root, c->d_link, c->d_mcom, c->d_qf0, c->d_qf1, sx,  \
+  c->d_witems, c->d_gctr, c->img_split, c->n_img, c->p.n_ghost[0], c->p.n_ghost[1],       \
+      c->p.boundary, c->d_patch, c->d_root, c->d_wnode, sx,                               \
       sy, sz,                                                                             \
       c->d_msrc, c->d_sched, c->d_ctr, c->P, c->p.G, c->p.softening, th2, c->d_acc,       \
       c->cap, c->d_stats, c->d_err, slot

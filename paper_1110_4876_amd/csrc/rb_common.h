@@ -34,6 +34,16 @@ struct __align__(16) NodeLink {
   uint32_t lvl;
 };
 
+// The node as the FP32-mixed walk reads it: one 64-byte line.  Q is kept
+// as its five independent components (it is traceless: zz = -(xx + yy)).
+struct __align__(64) WNode {
+  double cx, cy, cz, M;     // centre of mass, mass
+  uint32_t child_or_first;  // as NodeLink
+  uint32_t count;
+  uint32_t lvl;
+  float qxx, qxy, qxz, qyy, qyz;
+};
+
 // Per-patch constants (device array, one entry per patch).
 struct PatchInfo {
   double W;        // root box side

@@ -85,14 +85,14 @@ struct rb_ctx {
   double4 *d_mcom = nullptr;  // com.x com.y com.z M
   double *d_S = nullptr;      // 3 per node
   double *d_Q = nullptr;      // 6 per node
-  float4 *d_qf0 = nullptr;    // FP32 copy of Q for the grouped walk: xx xy xz yy
-  float2 *d_qf1 = nullptr;    //                                       yz zz
+  WNode *d_wnode = nullptr;   // the grouped walk's node records (FP32-mixed only)
 
   // walk
   std::vector<WalkItem> h_items64;  // FP64 walk: 64 Morton-consecutive slots
   WalkItem *d_items64 = nullptr;
-  WalkItem *d_groups = nullptr;     // FP32 walk: groups emitted from the tree
-  uint32_t *d_gctr = nullptr;       // [groups emitted, work items taken]
+  WalkItem *d_groups = nullptr;     // node groups emitted from the tree (moments pass)
+  WalkItem *d_witems = nullptr;     // FP32 walk: packed work items
+  uint32_t *d_gctr = nullptr;       // [groups emitted, work items taken, items emitted, -]
   uint32_t *d_large = nullptr;      // nodes with more than G particles, by level
   uint32_t *d_large_cnt = nullptr;  // 22 per-level counts
   double *d_acc = nullptr;          // (n_img or 1) * 3 * cap
