@@ -7,9 +7,10 @@
 //                      (patch, bucket) (rb_bucket_add; bucket 4096 holds
 //                      removed particles, whose all-ones key sorts last);
 //   k_bsort_scan    -- per patch: bucket cursors, and segments: runs of
-//                      whole buckets that start in the same window of 512
-//                      slots (at most 1023 keys), a bucket above 512 keys
-//                      being a segment of its own;
+//                      whole buckets that start in the same window of 256
+//                      slots (at most 511 keys), a bucket above 256 keys
+//                      being a segment of its own (small segments keep
+//                      more CUs busy and networks short);
 //   k_bsort_scatter -- every key to its bucket (one atomic per bucket and
 //                      wave);
 //   k_bsort_local   -- per segment: a bitonic sort of (key, slot) held in
@@ -22,7 +23,7 @@
 // come back sorted to buffer 0.
 #include "rb_internal.h"
 
-#define BS_WIN 512   // segment window (slots)
+#define BS_WIN 256   // segment window (slots)
 #define BS_LDS 1024  // largest segment sorted by the bitonic network
 
 // lanes of the wave holding the same value in the low `bits` bits

@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void k_groups(
     const uint32_t *__restrict__ nlastchild, const uint8_t *__restrict__ nleaf,
     const uint8_t *__restrict__ nlevel, const uint32_t *__restrict__ starts, uint32_t P,
     uint32_t G, WalkItem *__restrict__ groups, WalkItem *__restrict__ witems,
-    uint32_t *__restrict__ gctr, uint32_t *__restrict__ large,
+    uint32_t *__restrict__ gctr, uint32_t *__restrict__ large, uint32_t *__restrict__ bottom,
     uint32_t *__restrict__ large_cnt) {
   const uint32_t n_nodes = lev_off[RB_NLEV];
   const uint32_t lane = rb_lane();
@@ -239,6 +239,7 @@ __global__ __launch_bounds__(256) void k_groups(
     uint32_t ca = 0, cb = 0, n_emit = 0, n_wemit = 0;
     if (in && !is_large && lvl == 0) n_emit = n_wemit = 1;
     if (is_large && leaf) n_emit = n_wemit = (cnt + G - 1) / G;
+    bool any_large = false;
     if (is_large && !leaf) {
       ca = nchild[id]; cb = nlastchild[id];
       uint32_t run = 0;
@@ -248,8 +249,9 @@ __global__ __launch_bounds__(256) void k_groups(
           ++n_emit;
           if (run && run + cc > G) { ++n_wemit; run = 0; }
           run += cc;
-        } else if (run) {
-          ++n_wemit;
+        } else {
+          any_large = true;
+          if (run) ++n_wemit;
           run = 0;
         }
       }
@@ -295,19 +297,28 @@ __global__ __launch_bounds__(256) void k_groups(
         if (run) witems[wpos++] = {r0, r1, p, RB_NONE};
       }
     }
-    // large-node lists: the lanes of one level share one atomic
-    uint64_t peers = __ballot(is_large);
+    // Large nodes without a large child (and large leaves) depend on node
+    // groups and particles only: one list for all levels.  The others are
+    // listed per level; the lanes of one level share one atomic.
+    const bool is_bottom = is_large && (leaf || !any_large);
+    const bool listed = is_large && !is_bottom;
+    const uint64_t bm = __ballot(is_bottom);
+    uint32_t bb = 0;
+    if (lane == 0 && bm) bb = atomicAdd(&large_cnt[RB_BOTTOM], (uint32_t)__popcll(bm));
+    bb = __shfl(bb, 0, 64);
+    if (is_bottom) bottom[bb + rb_mbcnt(bm)] = id;
+    uint64_t peers = __ballot(listed);
 #pragma unroll
     for (int bit = 0; bit < 5; ++bit) {
       const bool on = (lvl >> bit) & 1u;
-      const uint64_t m = __ballot(is_large && on);
+      const uint64_t m = __ballot(listed && on);
       peers &= on ? m : ~m;
     }
     const uint32_t leader = peers ? (uint32_t)(__ffsll((long long)peers) - 1) : lane;
     uint32_t r = 0;
-    if (is_large && lane == leader) r = atomicAdd(&large_cnt[lvl], (uint32_t)__popcll(peers));
+    if (listed && lane == leader) r = atomicAdd(&large_cnt[lvl], (uint32_t)__popcll(peers));
     r = __shfl(r, (int)leader, 64);
-    if (is_large) large[lev_off[lvl] + r + rb_mbcnt(peers)] = id;
+    if (listed) large[lev_off[lvl] + r + rb_mbcnt(peers)] = id;
   }
 }
 
@@ -471,6 +482,69 @@ __global__ __launch_bounds__(128) void k_moments_group(
 // waits only for its children's moments.
 #define ML_CAP 2048
 
+// An internal node from its (at most eight, consecutive) children: masses
+// and sums of all children, positions and quadrupoles of the first four in
+// one round of loads, the other four's after the sums.
+__device__ __forceinline__ void ml_internal(uint32_t id, int l, uint32_t first, uint32_t last,
+                                            uint32_t ca, uint32_t cb, uint32_t skip, int quad,
+                                            NodeLink *__restrict__ link,
+                                            double4 *__restrict__ mcom,
+                                            double *__restrict__ Sarr,
+                                            double *__restrict__ Qarr, WNode *__restrict__ wn) {
+  const uint32_t nch = cb - ca + 1;
+  double cm[8], cs[8][3], cx[4][3], cq[4][6];
+#pragma unroll
+  for (uint32_t j = 0; j < 8; ++j) {
+    if (j < nch) {
+      const uint32_t ch = ca + j;
+      const double4 m4 = mcom[ch];
+      cm[j] = m4.w;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) cs[j][b] = Sarr[3 * (size_t)ch + b];
+      if (j < 4) {
+        cx[j][0] = m4.x; cx[j][1] = m4.y; cx[j][2] = m4.z;
+        if (quad) {
+#pragma unroll
+          for (int b = 0; b < 6; ++b) cq[j][b] = Qarr[6 * (size_t)ch + b];
+        }
+      }
+    }
+  }
+  Mom a;
+  mom_zero(a);
+#pragma unroll
+  for (uint32_t j = 0; j < 8; ++j)
+    if (j < nch) mom_child_ms(a, cm[j], cs[j][0], cs[j][1], cs[j][2]);
+  mom_internal_com(a);
+  if (quad) {
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j)
+      if (j < nch) mom_child_q(a, cm[j], cx[j][0], cx[j][1], cx[j][2], cq[j]);
+    if (nch > 4) {
+#pragma unroll
+      for (uint32_t j = 4; j < 8; ++j) {
+        if (j < nch) {
+          const uint32_t ch = ca + j;
+          const double4 m4 = mcom[ch];
+          cx[j - 4][0] = m4.x; cx[j - 4][1] = m4.y; cx[j - 4][2] = m4.z;
+#pragma unroll
+          for (int b = 0; b < 6; ++b) cq[j - 4][b] = Qarr[6 * (size_t)ch + b];
+        }
+      }
+#pragma unroll
+      for (uint32_t j = 4; j < 8; ++j)
+        if (j < nch) mom_child_q(a, cm[j], cx[j - 4][0], cx[j - 4][1], cx[j - 4][2], cq[j - 4]);
+    }
+  }
+  NodeLink lk;
+  lk.child_or_first = ca;
+  lk.skip = skip;
+  lk.count = last - first + 1;
+  lk.lvl = (uint32_t)l | (nch << 9);
+  mom_store(id, a, lk, link, mcom, Sarr, Qarr, wn);
+}
+
+
 // Touch the 128-byte lines of doubles [a, b) of p with loads that skip the
 // CU's L1 (agent scope), leaving them in this XCD's L2.
 __device__ __forceinline__ uint64_t ml_touch(const double *p, uint32_t a, uint32_t b) {
@@ -554,65 +628,37 @@ __global__ __launch_bounds__(512) void k_moments_large(
                            quad, link, mcom, Sarr, Qarr, wn, n_slots, err);
         continue;
       }
-      const uint32_t nch = cb - ca + 1;
-      // masses and sums of all children, positions and quadrupoles of the
-      // first four, in one round of loads; the other four's after the sums
-      double cm[8], cs[8][3], cx[4][3], cq[4][6];
-#pragma unroll
-      for (uint32_t j = 0; j < 8; ++j) {
-        if (j < nch) {
-          const uint32_t ch = ca + j;
-          const double4 m4 = mcom[ch];
-          cm[j] = m4.w;
-#pragma unroll
-          for (int b = 0; b < 3; ++b) cs[j][b] = Sarr[3 * (size_t)ch + b];
-          if (j < 4) {
-            cx[j][0] = m4.x; cx[j][1] = m4.y; cx[j][2] = m4.z;
-            if (quad) {
-#pragma unroll
-              for (int b = 0; b < 6; ++b) cq[j][b] = Qarr[6 * (size_t)ch + b];
-            }
-          }
-        }
-      }
-      Mom a;
-      mom_zero(a);
-#pragma unroll
-      for (uint32_t j = 0; j < 8; ++j)
-        if (j < nch) mom_child_ms(a, cm[j], cs[j][0], cs[j][1], cs[j][2]);
-      mom_internal_com(a);
-      if (quad) {
-#pragma unroll
-        for (uint32_t j = 0; j < 4; ++j)
-          if (j < nch) mom_child_q(a, cm[j], cx[j][0], cx[j][1], cx[j][2], cq[j]);
-        if (nch > 4) {
-#pragma unroll
-          for (uint32_t j = 4; j < 8; ++j) {
-            if (j < nch) {
-              const uint32_t ch = ca + j;
-              const double4 m4 = mcom[ch];
-              cx[j - 4][0] = m4.x; cx[j - 4][1] = m4.y; cx[j - 4][2] = m4.z;
-#pragma unroll
-              for (int b = 0; b < 6; ++b) cq[j - 4][b] = Qarr[6 * (size_t)ch + b];
-            }
-          }
-#pragma unroll
-          for (uint32_t j = 4; j < 8; ++j)
-            if (j < nch) mom_child_q(a, cm[j], cx[j - 4][0], cx[j - 4][1], cx[j - 4][2], cq[j - 4]);
-        }
-      }
-      NodeLink lk;
-      lk.child_or_first = ca;
-      lk.skip = skip;
-      lk.count = last - first + 1;
-      lk.lvl = (uint32_t)l | (nch << 9);
-      mom_store(id, a, lk, link, mcom, Sarr, Qarr, wn);
+      ml_internal(id, l, first, last, ca, cb, skip, quad, link, mcom, Sarr, Qarr, wn);
     }
     __syncthreads();
   }
 }
 
 // large nodes of one level over the whole chip (large systems)
+// The bottom large nodes, one per thread, spread over many CUs (their
+// children's records are read from memory by each node's own thread).
+__global__ __launch_bounds__(64) void k_moments_bottom(const uint32_t *__restrict__ bottom,
+                                                       const uint32_t *__restrict__ large_cnt,
+                                                       const uint32_t *__restrict__ lev_off,
+                                                       const uint8_t *__restrict__ nlevel,
+                                                       RB_MOMENT_PARAMS) {
+  const uint32_t cnt = large_cnt[RB_BOTTOM];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+    const uint32_t id = bottom[i];
+    const int l = nlevel[id];
+    const bool leaf = nleaf[id] != 0;
+    const uint32_t first = nfirst[id], last = nlast[id], skip = nskip[id];
+    const uint32_t ca = leaf ? 0u : nchild[id], cb = leaf ? 0u : nlastchild[id];
+    const uint32_t clo = (l < RB_DEPTH) ? lev_off[l + 1] : 0u;
+    const uint32_t chi = (l < RB_DEPTH) ? lev_off[l + 2] : 0u;
+    if (!leaf && ca >= clo && ca <= cb && cb < chi && cb - ca < 8)
+      ml_internal(id, l, first, last, ca, cb, skip, quad, link, mcom, Sarr, Qarr, wn);
+    else  // leaves, and anything inconsistent (reported there)
+      rb_node_moments_at(id, l, first, last, leaf, ca, cb, skip, clo, chi, sx, sy, sz, msrc,
+                         quad, link, mcom, Sarr, Qarr, wn, n_slots, err);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_moments_large_level(
     int l, const uint32_t *__restrict__ large, const uint32_t *__restrict__ large_cnt,
     const uint32_t *__restrict__ lev_off, RB_MOMENT_PARAMS) {
@@ -634,7 +680,7 @@ hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const d
   hipLaunchKernelGGL(k_groups, dim3(grid), dim3(256), 0, c->stream, c->d_lev_off, c->d_nfirst,
                      c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nleaf, c->d_nlevel,
                      c->d_starts, c->P, G, c->d_groups, c->d_witems, c->d_gctr, c->d_large,
-                     c->d_large_cnt);
+                     c->d_bottom, c->d_large_cnt);
 #define RB_MARGS                                                                          \
   c->d_nfirst, c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nskip, c->d_nleaf, sx, sy, sz, \
       c->d_msrc, c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, wnode,              \
@@ -646,6 +692,11 @@ hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const d
                      c->d_nlevel, c->d_lev_off, sx, sy, sz, c->d_msrc, c->p.leaf_size,
                      c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, wnode,
                      c->d_err);
+  // bottom large nodes are disjoint subtrees of more than G particles each
+  unsigned bgrid = rb_div_up(n / (G + 1) + 1, 64);
+  if (bgrid > 2048) bgrid = 2048;
+  hipLaunchKernelGGL(k_moments_bottom, dim3(bgrid), dim3(64), 0, c->stream, c->d_bottom,
+                     c->d_large_cnt, c->d_lev_off, c->d_nlevel, RB_MARGS);
   if (n <= (1u << 22)) {
     hipLaunchKernelGGL(k_moments_large, dim3(1), dim3(512), 0, c->stream, c->d_large,
                        c->d_large_cnt, c->d_lev_off, RB_MARGS);

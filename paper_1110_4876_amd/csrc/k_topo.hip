@@ -117,7 +117,7 @@ __global__ __launch_bounds__(64) void k_topo_write(
   // the grouped walk's counters (node groups emitted, work items taken,
   // walk items emitted) restart with every tree, also when this tree fails its capacity check
   if (b == 0 && lane < 4) gctr[lane] = 0;
-  if (b == 0 && lane < RB_NLEV) large_cnt[lane] = 0;
+  if (b == 0 && lane < RB_LARGE_SLOTS) large_cnt[lane] = 0;
   if (total > node_cap) {
     // nothing is written; the tree is left empty (no levels, no live
     // particles) so that every later kernel of the step does no work

@@ -7,6 +7,8 @@
 
 #define RB_DEPTH 21                        // deepest octree level (63-bit keys)
 #define RB_NLEV (RB_DEPTH + 1)             // levels 0..21
+#define RB_BOTTOM 24       // counter slot of the bottom large-node list
+#define RB_LARGE_SLOTS 32  // large-node counters: one per level, then RB_BOTTOM
 #define RB_NONE 0xFFFFFFFFu                // absent node / end of walk
 #define RB_KEY_DEAD 0xFFFFFFFFFFFFFFFFull  // key of a removed / outside particle
 #define RB_TILE_MIN 128                    // slots per topology tile

@@ -94,7 +94,8 @@ struct rb_ctx {
   WalkItem *d_witems = nullptr;     // FP32 walk: packed work items
   uint32_t *d_gctr = nullptr;       // [groups emitted, work items taken, items emitted, -]
   uint32_t *d_large = nullptr;      // nodes with more than G particles, by level
-  uint32_t *d_large_cnt = nullptr;  // 22 per-level counts
+  uint32_t *d_bottom = nullptr;     // those without such a child (not in d_large)
+  uint32_t *d_large_cnt = nullptr;  // per-level counts, then the bottom count
   double *d_acc = nullptr;          // (n_img or 1) * 3 * cap
 
   // per-call dynamic region [ctr | StepConst | schedule], uploaded from a
