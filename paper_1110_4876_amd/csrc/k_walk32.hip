@@ -177,10 +177,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const double theta2d = theta2;
   const uint32_t step = ctr[slot];
   unsigned long long n_cell = 0, n_pp = 0;
+  // the first item of every wave is fixed by its position in the grid; the
+  // others come from the queue (one atomic each instead of one per wave at
+  // start-up, when they would all hit the one counter at once)
+  bool first = true;
   for (;;) {
-    uint32_t item = 0;
-    if (lane == 0) item = atomicAdd(&gctr[1], 1u);
-    item = (uint32_t)w32_uniform((int)__shfl(item, 0, 64));
+    uint32_t item = 4u * blockIdx.x + (uint32_t)wv;
+    if (!first) {
+      if (lane == 0) item = 4u * gridDim.x + atomicAdd(&gctr[1], 1u);
+      item = (uint32_t)w32_uniform((int)__shfl(item, 0, 64));
+    }
+    first = false;
     if (item >= n_items) break;
     // split items: all central images first (the heaviest), then the rest
     const uint32_t gi = img_split ? item % n_groups : item;
@@ -439,8 +446,12 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
   const double theta2d = theta2;
   const uint32_t step = ctr[slot];
   unsigned long long n_cell = 0, n_pp = 0;
+  // the first item of every workgroup is fixed by its position in the
+  // grid, the others come from the queue
+  bool first = true;
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&gctr[1], 1u);
+    if (threadIdx.x == 0) s_item = first ? blockIdx.x : gridDim.x + atomicAdd(&gctr[1], 1u);
+    first = false;
     __syncthreads();
     const uint32_t item = (uint32_t)w32_uniform((int)s_item);
     __syncthreads();  // every thread has read the item before it changes
