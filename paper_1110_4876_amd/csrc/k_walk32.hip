@@ -60,6 +60,12 @@ __device__ __forceinline__ void w32_wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// an interaction-list cell: position and G M, then G Q as (xx, xy, xz, yy)
+// and (yz, zz); one record per cell so that a lane reads it from one address
+struct W32Cell {
+  float4 pos, q0, q1;
+};
+
 struct F3 {
   float x, y, z;
 };
@@ -68,61 +74,64 @@ __device__ __forceinline__ void w32_cell(const float4 a, const float4 q0, const 
                                          float px, float py, float pz, float b2, bool quad,
                                          F3 &f) {
   const float dx = a.x - px, dy = a.y - py, dz = a.z - pz;
-  const float r2 = dx * dx + dy * dy + dz * dz + b2;
-  const float ri = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+  const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, b2)));
+  // an accepted cell's centre of mass lies outside the group's box by more
+  // than its width / theta (at least 2^-21 W / theta), so r2 > 0
+  const float ri = __builtin_amdgcn_rsqf(r2);
   const float u = ri * ri;
   const float g = ri * u;
   if (quad) {
     // Q d and (d.Q.d) / rho^4, ordered to keep intermediates in range
-    const float qx = q0.x * dx + q0.y * dy + q0.z * dz;
-    const float qy = q0.y * dx + q0.w * dy + q1.x * dz;
-    const float qz = q0.z * dx + q1.x * dy + q1.y * dz;
-    const float dqd = ((dx * qx + dy * qy + dz * qz) * u) * u;
-    const float s = a.w + 2.5f * dqd;
-    f.x += g * (s * dx - qx * u);
-    f.y += g * (s * dy - qy * u);
-    f.z += g * (s * dz - qz * u);
+    const float qx = fmaf(q0.x, dx, fmaf(q0.y, dy, q0.z * dz));
+    const float qy = fmaf(q0.y, dx, fmaf(q0.w, dy, q1.x * dz));
+    const float qz = fmaf(q0.z, dx, fmaf(q1.x, dy, q1.y * dz));
+    const float dqd = fmaf(dx, qx, fmaf(dy, qy, dz * qz));
+    const float s = fmaf((2.5f * u) * u, dqd, a.w);
+    const float gs = g * s, gu = g * u;
+    f.x = fmaf(-gu, qx, fmaf(gs, dx, f.x));
+    f.y = fmaf(-gu, qy, fmaf(gs, dy, f.y));
+    f.z = fmaf(-gu, qz, fmaf(gs, dz, f.z));
   } else {
     const float h = g * a.w;
-    f.x += h * dx; f.y += h * dy; f.z += h * dz;
+    f.x = fmaf(h, dx, f.x); f.y = fmaf(h, dy, f.y); f.z = fmaf(h, dz, f.z);
   }
 }
+
+// b2 carries a floor of 1e-20 (in units of W^2), so that the member's own
+// entry (d = 0) and exact duplicates add d * (finite) = 0 without a branch;
+// for any separation FP32 can resolve the floor changes nothing
+#define W32_R2_FLOOR 1e-20f
 
 __device__ __forceinline__ void w32_part(const float4 a, float px, float py, float pz,
                                          float b2, F3 &f) {
   const float dx = a.x - px, dy = a.y - py, dz = a.z - pz;
-  const float r2 = dx * dx + dy * dy + dz * dz + b2;
-  // the member's own entry sits at d = 0 exactly: no self term
-  const float ri = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
-  const float h = ri * ri * ri * a.w;
-  f.x += h * dx; f.y += h * dy; f.z += h * dz;
+  const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, b2)));
+  const float ri = __builtin_amdgcn_rsqf(r2);
+  const float h = (ri * ri) * (ri * a.w);
+  f.x = fmaf(h, dx, f.x); f.y = fmaf(h, dy, f.y); f.z = fmaf(h, dz, f.z);
 }
 
-__device__ __forceinline__ void w32_eval_cells(const float4 *__restrict__ cpos,
-                                               const float4 *__restrict__ cq0,
-                                               const float2 *__restrict__ cq1, int cnt, int sub,
+__device__ __forceinline__ void w32_eval_cells(const W32Cell *__restrict__ cel, int cnt, int sub,
                                                int lpp, float px, float py, float pz, float b2,
                                                bool quad, double &ax, double &ay, double &az) {
   F3 f = {0.f, 0.f, 0.f};
   int e = sub;
 #if W32_CELL_PAIRS
   for (; e + lpp < cnt; e += 2 * lpp) {
-    const float4 a0 = cpos[e], a1 = cpos[e + lpp];
-    float4 q00 = {}, q01 = {};
-    float2 q10 = {}, q11 = {};
+    const float4 a0 = cel[e].pos, a1 = cel[e + lpp].pos;
+    float4 q00 = {}, q01 = {}, q10 = {}, q11 = {};
     if (quad) {
-      q00 = cq0[e]; q01 = cq0[e + lpp];
-      q10 = cq1[e]; q11 = cq1[e + lpp];
+      q00 = cel[e].q0; q01 = cel[e + lpp].q0;
+      q10 = cel[e].q1; q11 = cel[e + lpp].q1;
     }
-    w32_cell(a0, q00, q10, px, py, pz, b2, quad, f);
-    w32_cell(a1, q01, q11, px, py, pz, b2, quad, f);
+    w32_cell(a0, q00, make_float2(q10.x, q10.y), px, py, pz, b2, quad, f);
+    w32_cell(a1, q01, make_float2(q11.x, q11.y), px, py, pz, b2, quad, f);
   }
 #endif
   for (; e < cnt; e += lpp) {
-    float4 q0 = {};
-    float2 q1 = {};
-    if (quad) { q0 = cq0[e]; q1 = cq1[e]; }
-    w32_cell(cpos[e], q0, q1, px, py, pz, b2, quad, f);
+    float4 q0 = {}, q1 = {};
+    if (quad) { q0 = cel[e].q0; q1 = cel[e].q1; }
+    w32_cell(cel[e].pos, q0, make_float2(q1.x, q1.y), px, py, pz, b2, quad, f);
   }
   ax += (double)f.x; ay += (double)f.y; az += (double)f.z;
 }
@@ -156,19 +165,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   // four independent waves per workgroup (fewer workgroups to dispatch),
   // each with its own stack, lists and image table
   __shared__ uint32_t stk_all[4][W32_SCAP];
-  __shared__ float4 cpos_all[4][W32_CL];
-  __shared__ float4 cq0_all[4][W32_CL];
-  __shared__ float2 cq1_all[4][W32_CL];
+  __shared__ W32Cell cel_all[4][W32_CL];
   __shared__ float4 ppos_all[4][W32_PL];
   __shared__ double2 img_all[4][RB_MAX_IMAGES];
 
-  static_assert(sizeof(cpos_all[0]) >= 3 * 64 * sizeof(double), "reduction space");
+  static_assert(sizeof(cel_all[0]) >= 3 * 64 * sizeof(double), "reduction space");
   // the wave index is uniform: keep it (and the LDS bases) in scalar registers
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint32_t *stk = stk_all[wv];
-  float4 *cpos = cpos_all[wv];
-  float4 *cq0 = cq0_all[wv];
-  float2 *cq1 = cq1_all[wv];
+  W32Cell *cel = cel_all[wv];
   float4 *ppos = ppos_all[wv];
   double2 *img = img_all[wv];
   const uint32_t n_groups = gctr[2];  // walk items
@@ -224,7 +229,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const double invW = 1.0 / W;
     const double gm_scale = Gc * invW * invW;
     const double gq_scale = gm_scale * invW * invW;
-    const float b2 = (float)((soft * invW) * (soft * invW));
+    const float b2 = (float)((soft * invW) * (soft * invW)) + W32_R2_FLOOR;
     const float px = (float)((x - gx) * invW), py = (float)((y - gy) * invW),
                 pz = (float)((z - gz) * invW);
     const double shear = sched[(size_t)step * 2 * P + p];
@@ -312,11 +317,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         const uint64_t m = __ballot(accept);
         if (accept) {
           const int pos = cl + (int)rb_mbcnt(m);
-          cpos[pos] = make_float4((float)((cx - gx) * invW), (float)((cy - gy) * invW),
-                                  (float)((cz - gz) * invW), (float)(mc.w * gm_scale));
+          cel[pos].pos = make_float4((float)((cx - gx) * invW), (float)((cy - gy) * invW),
+                                     (float)((cz - gz) * invW), (float)(mc.w * gm_scale));
           if (QUAD) {
-            cq0[pos] = make_float4(q0.x * gqs, q0.y * gqs, q0.z * gqs, q0.w * gqs);
-            cq1[pos] = make_float2(q1.x * gqs, q1.y * gqs);
+            cel[pos].q0 = make_float4(q0.x * gqs, q0.y * gqs, q0.z * gqs, q0.w * gqs);
+            cel[pos].q1 = make_float4(q1.x * gqs, q1.y * gqs, 0.f, 0.f);
           }
         }
         cl += __popcll(m);
@@ -362,7 +367,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       // next batch in flight while the lists are evaluated
       pop(k, e, lk, mc, q0, q1);
       if (cl >= W32_CFLUSH) {
-        w32_eval_cells(cpos, cq0, cq1, cl, sub, lpp, px, py, pz, b2, QUAD, ax, ay, az);
+        w32_eval_cells(cel, cl, sub, lpp, px, py, pz, b2, QUAD, ax, ay, az);
         if (STATS) n_cell += (unsigned long long)cl * (unsigned long long)cnt;
         cl = 0;
       }
@@ -374,7 +379,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     }
     if (overflow && lane == 0) atomicOr(err, RB_ERR_STACK);
     if (cl > 0) {
-      w32_eval_cells(cpos, cq0, cq1, cl, sub, lpp, px, py, pz, b2, QUAD, ax, ay, az);
+      w32_eval_cells(cel, cl, sub, lpp, px, py, pz, b2, QUAD, ax, ay, az);
       if (STATS) n_cell += (unsigned long long)cl * (unsigned long long)cnt;
     }
     if (pl > 0) {
@@ -383,7 +388,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     }
     // lanes m, m + cnt, ... hold partial sums of member m: added in that
     // order through the wave's cell list, which is no longer needed
-    double(*red)[64] = reinterpret_cast<double(*)[64]>(cpos);
+    double(*red)[64] = reinterpret_cast<double(*)[64]>(cel);
     w32_wave_sync();
     red[0][lane] = ax; red[1][lane] = ay; red[2][lane] = az;
     w32_wave_sync();
@@ -424,21 +429,17 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
     uint32_t *__restrict__ err, int slot) {
   constexpr int W32M_SCAP = 512 * NW + 512;  // batches of 64 NW, 8 children each, plus depth
   __shared__ uint32_t stk[W32M_SCAP];
-  __shared__ float4 cpos_all[NW][W32_CL];
-  __shared__ float4 cq0_all[NW][W32_CL];
-  __shared__ float2 cq1_all[NW][W32_CL];
+  __shared__ W32Cell cel_all[NW][W32_CL];
   __shared__ float4 ppos_all[NW][W32_PL];
   __shared__ uint32_t s_push[NW];
   __shared__ uint32_t s_item;
   __shared__ double2 img[RB_MAX_IMAGES];
   // the waves' partial forces, once the lists are no longer needed
-  static_assert(sizeof(cpos_all) >= NW * 3 * 64 * sizeof(double), "reduction space");
-  double(*s_red)[3][64] = reinterpret_cast<double(*)[3][64]>(&cpos_all[0][0]);
+  static_assert(sizeof(cel_all) >= NW * 3 * 64 * sizeof(double), "reduction space");
+  double(*s_red)[3][64] = reinterpret_cast<double(*)[3][64]>(&cel_all[0][0]);
 
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  float4 *cpos = cpos_all[w];
-  float4 *cq0 = cq0_all[w];
-  float2 *cq1 = cq1_all[w];
+  W32Cell *cel = cel_all[w];
   float4 *ppos = ppos_all[w];
   const uint32_t n_groups = gctr[2];  // walk items
   const uint32_t per = img_split ? (uint32_t)n_img : 1u;
@@ -489,7 +490,7 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
     const double invW = 1.0 / W;
     const double gm_scale = Gc * invW * invW;
     const double gq_scale = gm_scale * invW * invW;
-    const float b2 = (float)((soft * invW) * (soft * invW));
+    const float b2 = (float)((soft * invW) * (soft * invW)) + W32_R2_FLOOR;
     const float px = (float)((x - gx) * invW), py = (float)((y - gy) * invW),
                 pz = (float)((z - gz) * invW);
     const double shear = sched[(size_t)step * 2 * P + p];
@@ -536,7 +537,7 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
       }
       // full lists are evaluated while the node records are in flight
       if (cl >= W32_CFLUSH) {
-        w32_eval_cells(cpos, cq0, cq1, cl, sub, lpp, px, py, pz, b2, QUAD, ax, ay, az);
+        w32_eval_cells(cel, cl, sub, lpp, px, py, pz, b2, QUAD, ax, ay, az);
         if (STATS) n_cell += (unsigned long long)cl * (unsigned long long)cnt;
         cl = 0;
       }
@@ -584,11 +585,11 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
         const uint64_t m = __ballot(accept);
         if (accept) {
           const int pos = cl + (int)rb_mbcnt(m);
-          cpos[pos] = make_float4((float)((cx - gx) * invW), (float)((cy - gy) * invW),
-                                  (float)((cz - gz) * invW), (float)(mc.w * gm_scale));
+          cel[pos].pos = make_float4((float)((cx - gx) * invW), (float)((cy - gy) * invW),
+                                     (float)((cz - gz) * invW), (float)(mc.w * gm_scale));
           if (QUAD) {
-            cq0[pos] = make_float4(q0.x * gqs, q0.y * gqs, q0.z * gqs, q0.w * gqs);
-            cq1[pos] = make_float2(q1.x * gqs, q1.y * gqs);
+            cel[pos].q0 = make_float4(q0.x * gqs, q0.y * gqs, q0.z * gqs, q0.w * gqs);
+            cel[pos].q1 = make_float4(q1.x * gqs, q1.y * gqs, 0.f, 0.f);
           }
         }
         cl += __popcll(m);
@@ -635,7 +636,7 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
     }
     if (overflow && threadIdx.x == 0) atomicOr(err, RB_ERR_STACK);
     if (cl > 0) {
-      w32_eval_cells(cpos, cq0, cq1, cl, sub, lpp, px, py, pz, b2, QUAD, ax, ay, az);
+      w32_eval_cells(cel, cl, sub, lpp, px, py, pz, b2, QUAD, ax, ay, az);
       if (STATS) n_cell += (unsigned long long)cl * (unsigned long long)cnt;
     }
     if (pl > 0) {
