@@ -176,7 +176,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   W32Cell *cel = cel_all[wv];
   float4 *ppos = ppos_all[wv];
   double2 *img = img_all[wv];
-  const uint32_t n_groups = gctr[2];  // walk items
+  const uint32_t n_big = gctr[2];  // walk items: big ones at the front,
+  const uint32_t n_groups = n_big + gctr[3];  // small ones at the back
   const uint32_t per = img_split ? (uint32_t)n_img : 1u;
   const uint32_t n_items = n_groups * per;
   const double theta2d = theta2;
@@ -198,11 +199,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const uint32_t gi = img_split ? item % n_groups : item;
     const int im0 = img_split ? (int)((item / n_groups + (uint32_t)(n_img / 2)) % (uint32_t)n_img) : 0;
     const int nim = img_split ? 1 : n_img;
-    const WalkItem grp = groups[gi];
+    const WalkItem grp = groups[gi < n_big ? gi : (uint32_t)cap - 1u - (gi - n_big)];
     const uint32_t p = grp.patch;
     const double W = patch[p].W;
     const int cnt = (int)(grp.end - grp.start);
-    if (cnt < 1 || cnt > 64) {  // never emitted
+    if (cnt < 1 || cnt > 64 || grp.end > cap) {  // never emitted
       if (lane == 0) atomicOr(err, RB_ERR_TREE);
       continue;
     }
@@ -441,7 +442,8 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   W32Cell *cel = cel_all[w];
   float4 *ppos = ppos_all[w];
-  const uint32_t n_groups = gctr[2];  // walk items
+  const uint32_t n_big = gctr[2];  // walk items: big ones at the front,
+  const uint32_t n_groups = n_big + gctr[3];  // small ones at the back
   const uint32_t per = img_split ? (uint32_t)n_img : 1u;
   const uint32_t n_items = n_groups * per;
   const double theta2d = theta2;
@@ -460,11 +462,11 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
     const uint32_t gi = img_split ? item % n_groups : item;
     const int im0 = img_split ? (int)((item / n_groups + (uint32_t)(n_img / 2)) % (uint32_t)n_img) : 0;
     const int nim = img_split ? 1 : n_img;
-    const WalkItem grp = groups[gi];
+    const WalkItem grp = groups[gi < n_big ? gi : (uint32_t)cap - 1u - (gi - n_big)];
     const uint32_t p = grp.patch;
     const double W = patch[p].W;
     const int cnt = (int)(grp.end - grp.start);
-    if (cnt < 1 || cnt > 64) {  // never emitted
+    if (cnt < 1 || cnt > 64 || grp.end > cap) {  // never emitted
       if (lane == 0) atomicOr(err, RB_ERR_TREE);
       continue;
     }

@@ -92,7 +92,7 @@ struct rb_ctx {
   WalkItem *d_items64 = nullptr;
   WalkItem *d_groups = nullptr;     // node groups emitted from the tree (moments pass)
   WalkItem *d_witems = nullptr;     // FP32 walk: packed work items
-  uint32_t *d_gctr = nullptr;       // [groups emitted, work items taken, items emitted, -]
+  uint32_t *d_gctr = nullptr;       // [groups emitted, items taken, big items, small items]
   uint32_t *d_large = nullptr;      // nodes with more than G particles, by level
   uint32_t *d_bottom = nullptr;     // those without such a child (not in d_large)
   uint32_t *d_large_cnt = nullptr;  // per-level counts, then the bottom count
