@@ -215,17 +215,39 @@ __device__ __forceinline__ void rb_node_moments(
 // an item fills the wave's lanes even when a node's octants hold few
 // particles each; an item is a Morton-contiguous slot range, and the walk
 // bounds it by its members' box.  Items of more than G/2 particles are
-// listed from the front of the table (count gctr[2]), the others from the
-// back (count gctr[3]).  Nodes with more than G particles are
+// listed from the front of the table (count gctr[2]), those of more than
+// G/4 in a second table (gctr[3]), the others from the back of the first
+// (gctr[4]).  Nodes with more than G particles are
 // listed per level for the large-node pass.  Emission order is free: every
 // result depends only on the node itself.  Slots in the tables and in the
 // per-level lists are taken with one atomic per wave.
+// size class of a walk item: more than G/2 particles, more than G/4, the rest
+__device__ __forceinline__ void wi_tally(uint32_t half, uint32_t quarter, uint32_t &nb,
+                                         uint32_t &nm, uint32_t &ns, uint32_t sz) {
+  nb += sz > half ? 1u : 0u;
+  nm += (sz > quarter && sz <= half) ? 1u : 0u;
+  ns += sz <= quarter ? 1u : 0u;
+}
+
+__device__ __forceinline__ void wi_put(WalkItem *__restrict__ witems,
+                                       WalkItem *__restrict__ witems_mid, uint32_t wcap,
+                                       uint32_t half, uint32_t quarter, uint32_t &bpos,
+                                       uint32_t &mpos, uint32_t &spos, uint32_t a, uint32_t e,
+                                       uint32_t p, uint32_t node) {
+  const WalkItem it = {a, e, p, node};
+  const uint32_t sz = e - a;
+  if (sz > half) witems[bpos++] = it;
+  else if (sz > quarter) witems_mid[mpos++] = it;
+  else witems[wcap - 1u - spos++] = it;
+}
+
 __global__ __launch_bounds__(256) void k_groups(
     const uint32_t *__restrict__ lev_off, const uint32_t *__restrict__ nfirst,
     const uint32_t *__restrict__ nlast, const uint32_t *__restrict__ nchild,
     const uint32_t *__restrict__ nlastchild, const uint8_t *__restrict__ nleaf,
     const uint8_t *__restrict__ nlevel, const uint32_t *__restrict__ starts, uint32_t P,
-    uint32_t G, WalkItem *__restrict__ groups, WalkItem *__restrict__ witems, uint32_t wcap,
+    uint32_t G, WalkItem *__restrict__ groups, WalkItem *__restrict__ witems,
+    WalkItem *__restrict__ witems_mid, uint32_t wcap,
     uint32_t *__restrict__ gctr, uint32_t *__restrict__ large, uint32_t *__restrict__ bottom,
     uint32_t *__restrict__ large_cnt) {
   const uint32_t n_nodes = lev_off[RB_NLEV];
@@ -239,16 +261,20 @@ __global__ __launch_bounds__(256) void k_groups(
     const uint32_t cnt = l - f + 1;
     const bool is_large = in && cnt > G;
     uint32_t ca = 0, cb = 0, n_emit = 0;
-    // Walk items with more than G/2 particles fill the table from the front
-    // and the others from the back; the walk takes the front ones first, so
-    // the work left at the end of a walk is in small (cheap) items.
-    const uint32_t half = G / 2;
-    uint32_t n_big = 0, n_small = 0;
-    auto tally = [&](uint32_t sz) { if (sz > half) ++n_big; else ++n_small; };
-    if (in && !is_large && lvl == 0) { n_emit = 1; tally(cnt); }
+    // Walk items by size class: more than G/2 particles (front of the
+    // table), more than G/4 (second table), the rest (back of the table).
+    // The walk takes them in that order, so the work left at the end of a
+    // walk is in small (cheap) items.
+    const uint32_t half = G / 2, quarter = G / 4;
+    uint32_t n_big = 0, n_mid = 0, n_small = 0;
+    if (in && !is_large && lvl == 0) {
+      n_emit = 1;
+      wi_tally(half, quarter, n_big, n_mid, n_small, cnt);
+    }
     if (is_large && leaf) {
       n_emit = (cnt + G - 1) / G;
-      for (uint32_t s0 = 0; s0 < cnt; s0 += G) tally(cnt - s0 < G ? cnt - s0 : G);
+      for (uint32_t s0 = 0; s0 < cnt; s0 += G)
+        wi_tally(half, quarter, n_big, n_mid, n_small, cnt - s0 < G ? cnt - s0 : G);
     }
     bool any_large = false;
     if (is_large && !leaf) {
@@ -258,46 +284,52 @@ __global__ __launch_bounds__(256) void k_groups(
         const uint32_t cc = nlast[c] - nfirst[c] + 1;
         if (cc <= G) {
           ++n_emit;
-          if (run && run + cc > G) { tally(run); run = 0; }
+          if (run && run + cc > G) {
+            wi_tally(half, quarter, n_big, n_mid, n_small, run);
+            run = 0;
+          }
           run += cc;
         } else {
           any_large = true;
-          if (run) tally(run);
+          if (run) wi_tally(half, quarter, n_big, n_mid, n_small, run);
           run = 0;
         }
       }
-      if (run) tally(run);
+      if (run) wi_tally(half, quarter, n_big, n_mid, n_small, run);
     }
     // table slots: one atomic per wave and table
     const uint32_t incl = rb_wave_incl_scan(n_emit);
     const uint32_t total = __shfl(incl, 63, 64);
     const uint32_t bincl = rb_wave_incl_scan(n_big);
     const uint32_t btotal = __shfl(bincl, 63, 64);
+    const uint32_t mincl = rb_wave_incl_scan(n_mid);
+    const uint32_t mtotal = __shfl(mincl, 63, 64);
     const uint32_t sincl = rb_wave_incl_scan(n_small);
     const uint32_t stotal = __shfl(sincl, 63, 64);
-    uint32_t gbase = 0, bbase = 0, sbase = 0;
+    uint32_t gbase = 0, bbase = 0, mbase = 0, sbase = 0;
     if (lane == 63 && total) gbase = atomicAdd(&gctr[0], total);
     if (lane == 63 && btotal) bbase = atomicAdd(&gctr[2], btotal);
-    if (lane == 63 && stotal) sbase = atomicAdd(&gctr[3], stotal);
+    if (lane == 63 && mtotal) mbase = atomicAdd(&gctr[3], mtotal);
+    if (lane == 63 && stotal) sbase = atomicAdd(&gctr[4], stotal);
     gbase = __shfl(gbase, 63, 64);
     bbase = __shfl(bbase, 63, 64);
+    mbase = __shfl(mbase, 63, 64);
     sbase = __shfl(sbase, 63, 64);
     uint32_t pos = gbase + incl - n_emit;
-    uint32_t bpos = bbase + bincl - n_big, spos = sbase + sincl - n_small;
-    auto put = [&](const WalkItem &it) {
-      if (it.end - it.start > half) witems[bpos++] = it;
-      else witems[wcap - 1u - spos++] = it;
-    };
+    uint32_t bpos = bbase + bincl - n_big, mpos = mbase + mincl - n_mid;
+    uint32_t spos = sbase + sincl - n_small;
     if (n_emit) {
       const uint32_t p = (P == 1) ? 0u : rb_patch_of(starts, P, f);
       if (!is_large) {
         groups[pos] = {f, l + 1, p, id};
-        put({f, l + 1, p, id});
+        wi_put(witems, witems_mid, wcap, half, quarter, bpos, mpos, spos, f, l + 1, p,
+               id);
       } else if (leaf) {
         for (uint32_t s = f; s <= l; s += G) {
-          const WalkItem it = {s, (s + G <= l + 1) ? s + G : l + 1, p, RB_NONE};
-          groups[pos++] = it;
-          put(it);
+          const uint32_t e = (s + G <= l + 1) ? s + G : l + 1;
+          groups[pos++] = {s, e, p, RB_NONE};
+          wi_put(witems, witems_mid, wcap, half, quarter, bpos, mpos, spos, s, e, p,
+                 RB_NONE);
         }
       } else {
         uint32_t run = 0, r0 = 0, r1 = 0;
@@ -305,16 +337,22 @@ __global__ __launch_bounds__(256) void k_groups(
           const uint32_t cf = nfirst[c], cl = nlast[c], cc = cl - cf + 1;
           if (cc <= G) {
             groups[pos++] = {cf, cl + 1, p, c};
-            if (run && run + cc > G) { put({r0, r1, p, RB_NONE}); run = 0; }
+            if (run && run + cc > G) {
+              wi_put(witems, witems_mid, wcap, half, quarter, bpos, mpos, spos, r0, r1, p,
+                     RB_NONE);
+              run = 0;
+            }
             if (!run) r0 = cf;
             r1 = cl + 1;
             run += cc;
           } else if (run) {
-            put({r0, r1, p, RB_NONE});
+            wi_put(witems, witems_mid, wcap, half, quarter, bpos, mpos, spos, r0, r1, p,
+                   RB_NONE);
             run = 0;
           }
         }
-        if (run) put({r0, r1, p, RB_NONE});
+        if (run)
+          wi_put(witems, witems_mid, wcap, half, quarter, bpos, mpos, spos, r0, r1, p, RB_NONE);
       }
     }
     // Large nodes without a large child (and large leaves) depend on node
@@ -450,10 +488,12 @@ __global__ __launch_bounds__(128) void k_moments_group(
       mom_zero(a);
       if (lead) {
         if (is_leaf) {
-          for (uint32_t j = lane; j < end; ++j) mom_leaf_ms(a, pv[3][j], pv[0][j], pv[1][j], pv[2][j]);
+          for (uint32_t j = lane; j < end; ++j)
+            mom_leaf_ms(a, pv[3][j], pv[0][j], pv[1][j], pv[2][j]);
           mom_leaf_com(a, end - lane, pv[0][lane], pv[1][lane], pv[2][lane]);
           if (quad && a.M != 0.0 && end - lane > 1)
-            for (uint32_t j = lane; j < end; ++j) mom_leaf_q(a, pv[3][j], pv[0][j], pv[1][j], pv[2][j]);
+            for (uint32_t j = lane; j < end; ++j)
+              mom_leaf_q(a, pv[3][j], pv[0][j], pv[1][j], pv[2][j]);
         } else {
           for (uint64_t m = kids; m; m &= m - 1) {
             const int j = __ffsll((long long)m) - 1;
@@ -699,7 +739,8 @@ hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const d
   if (grid > 2048) grid = 2048;
   hipLaunchKernelGGL(k_groups, dim3(grid), dim3(256), 0, c->stream, c->d_lev_off, c->d_nfirst,
                      c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nleaf, c->d_nlevel,
-                     c->d_starts, c->P, G, c->d_groups, c->d_witems, (uint32_t)c->cap,
+                     c->d_starts, c->P, G, c->d_groups, c->d_witems, c->d_witems_mid,
+                     (uint32_t)c->cap,
                      c->d_gctr, c->d_large, c->d_bottom, c->d_large_cnt);
 #define RB_MARGS                                                                          \
   c->d_nfirst, c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nskip, c->d_nleaf, sx, sy, sz, \

@@ -115,8 +115,9 @@ __global__ __launch_bounds__(64) void k_topo_write(
   const uint32_t lbase_lane = lincl - tot;
   const uint32_t total = __shfl(lincl, 63, 64);
   // the grouped walk's counters (node groups emitted, work items taken,
-  // big and small walk items emitted) restart with every tree, also when this tree fails its capacity check
-  if (b == 0 && lane < 4) gctr[lane] = 0;
+  // walk items emitted per size class) restart with every tree, also when
+  // this tree fails its capacity check
+  if (b == 0 && lane < 8) gctr[lane] = 0;
   if (b == 0 && lane < RB_LARGE_SLOTS) large_cnt[lane] = 0;
   if (total > node_cap) {
     // nothing is written; the tree is left empty (no levels, no live

@@ -66,6 +66,17 @@ struct W32Cell {
   float4 pos, q0, q1;
 };
 
+// work item gi of the walk's order: big items (front of the first table),
+// middle-sized ones (second table), small ones (back of the first table)
+__device__ __forceinline__ WalkItem w32_item(const WalkItem *__restrict__ groups,
+                                             const WalkItem *__restrict__ groups_mid,
+                                             uint32_t gi, uint32_t n_big, uint32_t n_mid,
+                                             uint64_t cap) {
+  if (gi < n_big) return groups[gi];
+  if (gi < n_big + n_mid) return groups_mid[gi - n_big];
+  return groups[(uint32_t)cap - 1u - (gi - n_big - n_mid)];
+}
+
 struct F3 {
   float x, y, z;
 };
@@ -154,7 +165,8 @@ __device__ __forceinline__ void w32_eval_parts(const float4 *__restrict__ ppos, 
 
 template <bool QUAD, bool STATS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_walk32(
-    const WalkItem *__restrict__ groups, uint32_t *__restrict__ gctr, int img_split, int n_img,
+    const WalkItem *__restrict__ groups, const WalkItem *__restrict__ groups_mid,
+    uint32_t *__restrict__ gctr, int img_split, int n_img,
     int ngx, int ngy, int boundary, const PatchInfo *__restrict__ patch,
     const uint32_t *__restrict__ root, const WNode *__restrict__ wn,
     const double *__restrict__ sx, const double *__restrict__ sy,
@@ -176,8 +188,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   W32Cell *cel = cel_all[wv];
   float4 *ppos = ppos_all[wv];
   double2 *img = img_all[wv];
-  const uint32_t n_big = gctr[2];  // walk items: big ones at the front,
-  const uint32_t n_groups = n_big + gctr[3];  // small ones at the back
+  const uint32_t n_big = gctr[2], n_mid = gctr[3];  // walk items by size
+  const uint32_t n_groups = n_big + n_mid + gctr[4];
   const uint32_t per = img_split ? (uint32_t)n_img : 1u;
   const uint32_t n_items = n_groups * per;
   const double theta2d = theta2;
@@ -197,9 +209,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     if (item >= n_items) break;
     // split items: all central images first (the heaviest), then the rest
     const uint32_t gi = img_split ? item % n_groups : item;
-    const int im0 = img_split ? (int)((item / n_groups + (uint32_t)(n_img / 2)) % (uint32_t)n_img) : 0;
+    const int im0 =
+        img_split ? (int)((item / n_groups + (uint32_t)(n_img / 2)) % (uint32_t)n_img) : 0;
     const int nim = img_split ? 1 : n_img;
-    const WalkItem grp = groups[gi < n_big ? gi : (uint32_t)cap - 1u - (gi - n_big)];
+    const WalkItem grp = w32_item(groups, groups_mid, gi, n_big, n_mid, cap);
     const uint32_t p = grp.patch;
     const double W = patch[p].W;
     const int cnt = (int)(grp.end - grp.start);
@@ -420,7 +433,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 // dependent rounds is up to NW times shorter.
 template <bool QUAD, bool STATS, int NW>
 __global__ __launch_bounds__(64 * NW) void k_walk32m(
-    const WalkItem *__restrict__ groups, uint32_t *__restrict__ gctr, int img_split, int n_img,
+    const WalkItem *__restrict__ groups, const WalkItem *__restrict__ groups_mid,
+    uint32_t *__restrict__ gctr, int img_split, int n_img,
     int ngx, int ngy, int boundary, const PatchInfo *__restrict__ patch,
     const uint32_t *__restrict__ root, const WNode *__restrict__ wn, const double *__restrict__ sx,
     const double *__restrict__ sy, const double *__restrict__ sz,
@@ -442,8 +456,8 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   W32Cell *cel = cel_all[w];
   float4 *ppos = ppos_all[w];
-  const uint32_t n_big = gctr[2];  // walk items: big ones at the front,
-  const uint32_t n_groups = n_big + gctr[3];  // small ones at the back
+  const uint32_t n_big = gctr[2], n_mid = gctr[3];  // walk items by size
+  const uint32_t n_groups = n_big + n_mid + gctr[4];
   const uint32_t per = img_split ? (uint32_t)n_img : 1u;
   const uint32_t n_items = n_groups * per;
   const double theta2d = theta2;
@@ -460,9 +474,10 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
     __syncthreads();  // every thread has read the item before it changes
     if (item >= n_items) break;  // uniform over the block
     const uint32_t gi = img_split ? item % n_groups : item;
-    const int im0 = img_split ? (int)((item / n_groups + (uint32_t)(n_img / 2)) % (uint32_t)n_img) : 0;
+    const int im0 =
+        img_split ? (int)((item / n_groups + (uint32_t)(n_img / 2)) % (uint32_t)n_img) : 0;
     const int nim = img_split ? 1 : n_img;
-    const WalkItem grp = groups[gi < n_big ? gi : (uint32_t)cap - 1u - (gi - n_big)];
+    const WalkItem grp = w32_item(groups, groups_mid, gi, n_big, n_mid, cap);
     const uint32_t p = grp.patch;
     const double W = patch[p].W;
     const int cnt = (int)(grp.end - grp.start);
@@ -684,7 +699,8 @@ hipError_t launch_walk32(rb_ctx *c, const double *sx, const double *sy, const do
   const double th2 = c->p.theta * c->p.theta;
   const bool quad = c->p.quadrupole != 0, stats = (c->p.profile & 2) != 0;
 #define RB_W32_ARGS                                                                      \
-  c->d_witems, c->d_gctr, c->img_split, c->n_img, c->p.n_ghost[0], c->p.n_ghost[1],       \
+  c->d_witems, c->d_witems_mid, c->d_gctr, c->img_split, c->n_img, c->p.n_ghost[0],      \
+      c->p.n_ghost[1],                                                                    \
       c->p.boundary, c->d_patch, c->d_root, c->d_wnode, sx,                               \
       sy, sz,                                                                             \
       c->d_msrc, c->d_sched, c->d_ctr, c->P, c->p.G, c->p.softening, th2, c->d_acc,       \

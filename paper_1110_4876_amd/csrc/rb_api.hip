@@ -304,12 +304,13 @@ int init_ctx(rb_ctx *c, const rb_params *p, uint32_t P, const int64_t *off, cons
   RB_TRY(dalloc(c, &c->d_items64, max_items));
   RB_TRY(dalloc(c, &c->d_groups, cap));
   RB_TRY(dalloc(c, &c->d_witems, cap));
-  RB_TRY(dalloc(c, &c->d_gctr, 4));
+  RB_TRY(dalloc(c, &c->d_witems_mid, cap));
+  RB_TRY(dalloc(c, &c->d_gctr, 8));
   RB_TRY(dalloc(c, &c->d_large, nc));
   RB_TRY(dalloc(c, &c->d_bottom, nc));
   RB_TRY(dalloc(c, &c->d_large_cnt, RB_LARGE_SLOTS));
   RB_HIP(hipMemsetAsync(c->d_large_cnt, 0, 4 * RB_LARGE_SLOTS, c->stream));
-  RB_HIP(hipMemsetAsync(c->d_gctr, 0, 16, c->stream));
+  RB_HIP(hipMemsetAsync(c->d_gctr, 0, 32, c->stream));
   RB_TRY(dalloc(c, &c->d_acc, (uint64_t)c->n_img * 3 * cap));
   // per-call dynamic region: step counter (16 B), StepConst, schedule
   c->sched_cap = 1024;

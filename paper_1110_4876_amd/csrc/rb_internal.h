@@ -91,8 +91,9 @@ struct rb_ctx {
   std::vector<WalkItem> h_items64;  // FP64 walk: 64 Morton-consecutive slots
   WalkItem *d_items64 = nullptr;
   WalkItem *d_groups = nullptr;     // node groups emitted from the tree (moments pass)
-  WalkItem *d_witems = nullptr;     // FP32 walk: packed work items
-  uint32_t *d_gctr = nullptr;       // [groups emitted, items taken, big items, small items]
+  WalkItem *d_witems = nullptr;     // FP32 walk: packed work items (big ones, small ones)
+  WalkItem *d_witems_mid = nullptr; // FP32 walk: packed work items of middle size
+  uint32_t *d_gctr = nullptr;       // [groups emitted, items taken, big, middle, small items]
   uint32_t *d_large = nullptr;      // nodes with more than G particles, by level
   uint32_t *d_bottom = nullptr;     // those without such a child (not in d_large)
   uint32_t *d_large_cnt = nullptr;  // per-level counts, then the bottom count
