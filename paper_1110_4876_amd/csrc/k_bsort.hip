@@ -152,7 +152,7 @@ __device__ __forceinline__ uint32_t bs_digit(uint64_t k, uint32_t v, int q) {
 __device__ void bs_big(uint64_t *__restrict__ k1, uint32_t *__restrict__ v1,
                        uint64_t *__restrict__ k0, uint32_t *__restrict__ v0, uint32_t a,
                        uint32_t e, uint32_t *hist, uint32_t *wcnt /* [waves][256] */) {
-  const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t tid = threadIdx.x, w = tid >> 6;
   const uint32_t nw = blockDim.x >> 6;
   for (int q = 0; q < 9; ++q) {
     const uint64_t *ki = (q & 1) ? k0 : k1;

@@ -1,6 +1,6 @@
 // k_moments.hip -- bottom-up moments of the octree (Sect. 4.2 of the paper:
 // total mass and centre of mass updated from the bottom up; quadrupole of
-// Hernquist 1987), and the particle groups of the grouped walk.
+// Hernquist 1987), and the work items of the grouped walk.
 //
 // Every node gets, in this order of arithmetic:
 //   leaf:     M = sum m, S = sum m x over its slots in Morton order;
@@ -11,12 +11,13 @@
 // A node without source mass gets com = 0 and Q = 0.  Contraction is off so
 // that M, S and com round as a plain sequential sum would.
 //
-// Schedule: the maximal nodes holding at most G particles (G = group_size;
-// they are also the walk groups) root small subtrees, each handled by one
-// wave level by level from its deepest level up -- a subtree of at most 64
-// particles has at most 64 nodes per level.  The remaining "large" nodes
-// (more than G particles) are listed per level and computed afterwards,
-// deepest level first.  Three launches replace one launch per level.
+// Schedule: the maximal nodes holding at most G particles (G = group_size)
+// root small subtrees.  Consecutive siblings among them, packed up to G
+// particles, form the work items (also those of the grouped walk); each item
+// is handled by one wave level by level from its deepest level up -- a run
+// of at most 64 particles has at most 64 nodes per level.  The remaining
+// "large" nodes (more than G particles) follow: those without a large child
+// spread over many CUs, the others level by level, deepest first.
 #include "rb_internal.h"
 
 // ---- the arithmetic of one node, shared by every kernel below so that all
@@ -205,22 +206,20 @@ __device__ __forceinline__ void rb_node_moments(
       double *__restrict__ Qarr, WNode *__restrict__ wn,      \
       uint32_t n_slots, uint32_t *__restrict__ err
 
-// Groups: the children with at most G particles of nodes with more than G,
-// and roots with at most G; a leaf with more than G particles (deepest
-// level, or leaf_size > G) contributes runs of G particles.  group.pad is
-// the group's node (RB_NONE for such runs).  These node groups carry the
-// moments pass.  The walk takes work items of its own: consecutive small
-// children of one node are packed into items of at most G particles (a run
-// ends at a large child or when the next child would overflow it), so that
-// an item fills the wave's lanes even when a node's octants hold few
-// particles each; an item is a Morton-contiguous slot range, and the walk
-// bounds it by its members' box.  Items of more than G/2 particles are
-// listed from the front of the table (count gctr[2]), those of more than
-// G/4 in a second table (gctr[3]), the others from the back of the first
-// (gctr[4]).  Nodes with more than G particles are
-// listed per level for the large-node pass.  Emission order is free: every
-// result depends only on the node itself.  Slots in the tables and in the
-// per-level lists are taken with one atomic per wave.
+// Work items: the children with at most G particles of nodes with more
+// than G, and roots with at most G.  Consecutive such children of one node
+// are packed into items of at most G particles (a run ends at a large child
+// or when the next child would overflow it), so that an item fills a
+// wave's lanes even when a node's octants hold few particles each; item.node
+// is the run's last child.  A leaf with more than G particles (deepest
+// level, or leaf_size > G) contributes pieces of G particles (item.node =
+// RB_NONE).  An item is a Morton-contiguous slot range; the walk bounds it
+// by its members' box.  Items of more than G/2 particles are listed from the
+// front of the table (count gctr[2]), those of more than G/4 in a second
+// table (gctr[3]), the others from the back of the first (gctr[4]).  Nodes
+// with more than G particles are listed for the large-node passes.
+// Emission order is free: every result depends only on the node itself.
+// Slots in the tables and in the lists are taken with one atomic per wave.
 // size class of a walk item: more than G/2 particles, more than G/4, the rest
 __device__ __forceinline__ void wi_tally(uint32_t half, uint32_t quarter, uint32_t &nb,
                                          uint32_t &nm, uint32_t &ns, uint32_t sz) {
@@ -246,8 +245,7 @@ __global__ __launch_bounds__(256) void k_groups(
     const uint32_t *__restrict__ nlast, const uint32_t *__restrict__ nchild,
     const uint32_t *__restrict__ nlastchild, const uint8_t *__restrict__ nleaf,
     const uint8_t *__restrict__ nlevel, const uint32_t *__restrict__ starts, uint32_t P,
-    uint32_t G, WalkItem *__restrict__ groups, WalkItem *__restrict__ witems,
-    WalkItem *__restrict__ witems_mid, uint32_t wcap,
+    uint32_t G, WalkItem *__restrict__ witems, WalkItem *__restrict__ witems_mid, uint32_t wcap,
     uint32_t *__restrict__ gctr, uint32_t *__restrict__ large, uint32_t *__restrict__ bottom,
     uint32_t *__restrict__ large_cnt) {
   const uint32_t n_nodes = lev_off[RB_NLEV];
@@ -260,19 +258,15 @@ __global__ __launch_bounds__(256) void k_groups(
     if (in) { f = nfirst[id]; l = nlast[id]; lvl = nlevel[id]; leaf = nleaf[id] != 0; }
     const uint32_t cnt = l - f + 1;
     const bool is_large = in && cnt > G;
-    uint32_t ca = 0, cb = 0, n_emit = 0;
+    uint32_t ca = 0, cb = 0;
     // Walk items by size class: more than G/2 particles (front of the
     // table), more than G/4 (second table), the rest (back of the table).
     // The walk takes them in that order, so the work left at the end of a
     // walk is in small (cheap) items.
     const uint32_t half = G / 2, quarter = G / 4;
     uint32_t n_big = 0, n_mid = 0, n_small = 0;
-    if (in && !is_large && lvl == 0) {
-      n_emit = 1;
-      wi_tally(half, quarter, n_big, n_mid, n_small, cnt);
-    }
+    if (in && !is_large && lvl == 0) wi_tally(half, quarter, n_big, n_mid, n_small, cnt);
     if (is_large && leaf) {
-      n_emit = (cnt + G - 1) / G;
       for (uint32_t s0 = 0; s0 < cnt; s0 += G)
         wi_tally(half, quarter, n_big, n_mid, n_small, cnt - s0 < G ? cnt - s0 : G);
     }
@@ -283,7 +277,6 @@ __global__ __launch_bounds__(256) void k_groups(
       for (uint32_t c = ca; c <= cb && c < n_nodes; ++c) {
         const uint32_t cc = nlast[c] - nfirst[c] + 1;
         if (cc <= G) {
-          ++n_emit;
           if (run && run + cc > G) {
             wi_tally(half, quarter, n_big, n_mid, n_small, run);
             run = 0;
@@ -298,65 +291,58 @@ __global__ __launch_bounds__(256) void k_groups(
       if (run) wi_tally(half, quarter, n_big, n_mid, n_small, run);
     }
     // table slots: one atomic per wave and table
-    const uint32_t incl = rb_wave_incl_scan(n_emit);
-    const uint32_t total = __shfl(incl, 63, 64);
     const uint32_t bincl = rb_wave_incl_scan(n_big);
     const uint32_t btotal = __shfl(bincl, 63, 64);
     const uint32_t mincl = rb_wave_incl_scan(n_mid);
     const uint32_t mtotal = __shfl(mincl, 63, 64);
     const uint32_t sincl = rb_wave_incl_scan(n_small);
     const uint32_t stotal = __shfl(sincl, 63, 64);
-    uint32_t gbase = 0, bbase = 0, mbase = 0, sbase = 0;
-    if (lane == 63 && total) gbase = atomicAdd(&gctr[0], total);
+    uint32_t bbase = 0, mbase = 0, sbase = 0;
     if (lane == 63 && btotal) bbase = atomicAdd(&gctr[2], btotal);
     if (lane == 63 && mtotal) mbase = atomicAdd(&gctr[3], mtotal);
     if (lane == 63 && stotal) sbase = atomicAdd(&gctr[4], stotal);
-    gbase = __shfl(gbase, 63, 64);
     bbase = __shfl(bbase, 63, 64);
     mbase = __shfl(mbase, 63, 64);
     sbase = __shfl(sbase, 63, 64);
-    uint32_t pos = gbase + incl - n_emit;
     uint32_t bpos = bbase + bincl - n_big, mpos = mbase + mincl - n_mid;
     uint32_t spos = sbase + sincl - n_small;
-    if (n_emit) {
+    if (n_big + n_mid + n_small) {
       const uint32_t p = (P == 1) ? 0u : rb_patch_of(starts, P, f);
       if (!is_large) {
-        groups[pos] = {f, l + 1, p, id};
         wi_put(witems, witems_mid, wcap, half, quarter, bpos, mpos, spos, f, l + 1, p,
                id);
       } else if (leaf) {
         for (uint32_t s = f; s <= l; s += G) {
           const uint32_t e = (s + G <= l + 1) ? s + G : l + 1;
-          groups[pos++] = {s, e, p, RB_NONE};
           wi_put(witems, witems_mid, wcap, half, quarter, bpos, mpos, spos, s, e, p,
                  RB_NONE);
         }
       } else {
-        uint32_t run = 0, r0 = 0, r1 = 0;
+        uint32_t run = 0, r0 = 0, r1 = 0, rl = 0;
         for (uint32_t c = ca; c <= cb && c < n_nodes; ++c) {
           const uint32_t cf = nfirst[c], cl = nlast[c], cc = cl - cf + 1;
           if (cc <= G) {
-            groups[pos++] = {cf, cl + 1, p, c};
             if (run && run + cc > G) {
               wi_put(witems, witems_mid, wcap, half, quarter, bpos, mpos, spos, r0, r1, p,
-                     RB_NONE);
+                     rl);
               run = 0;
             }
             if (!run) r0 = cf;
             r1 = cl + 1;
+            rl = c;
             run += cc;
           } else if (run) {
             wi_put(witems, witems_mid, wcap, half, quarter, bpos, mpos, spos, r0, r1, p,
-                   RB_NONE);
+                   rl);
             run = 0;
           }
         }
         if (run)
-          wi_put(witems, witems_mid, wcap, half, quarter, bpos, mpos, spos, r0, r1, p, RB_NONE);
+          wi_put(witems, witems_mid, wcap, half, quarter, bpos, mpos, spos, r0, r1, p, rl);
       }
     }
-    // Large nodes without a large child (and large leaves) depend on node
-    // groups and particles only: one list for all levels.  The others are
+    // Large nodes without a large child (and large leaves) depend on the
+    // work items' subtrees and particles only: one list for all levels.  The others are
     // listed per level; the lanes of one level share one atomic.
     const bool is_bottom = is_large && (leaf || !any_large);
     const bool listed = is_large && !is_bottom;
@@ -385,16 +371,17 @@ __device__ __forceinline__ void rb_wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Moments of a group's subtree (a node with at most 64 particles), one wave
-// per group, without reading the tree level by level: every lane holds one
-// slot, finds from the sorted keys where cells begin and end at each level,
-// and takes its nodes' ids from the slot-major node list.  Levels are then
-// done bottom-up with the particles and the previous level's node values in
-// LDS; a node's leader lane (the lane of its first slot) sums its children
-// or particles in order, exactly as rb_node_moments does.
+// Moments of a work item's subtrees (consecutive siblings, at most 64
+// particles in all), one wave per item, without reading the tree level by
+// level: every lane holds one slot, finds from the sorted keys where cells
+// begin and end at each level, and takes its nodes' ids from the slot-major
+// node list.  Levels are then done bottom-up with the particles and the
+// previous level's node values in LDS; a node's leader lane (the lane of its
+// first slot) sums its children or particles in order, exactly as
+// rb_node_moments does.
 __global__ __launch_bounds__(128) void k_moments_group(
-    const WalkItem *__restrict__ groups, const uint32_t *__restrict__ gctr,
-    const uint64_t *__restrict__ key, const uint32_t *__restrict__ starts,
+    const WalkItem *__restrict__ items, const WalkItem *__restrict__ items_mid, uint64_t wcap,
+    const uint32_t *__restrict__ gctr, const uint64_t *__restrict__ key, const uint32_t *__restrict__ starts,
     const uint32_t *__restrict__ csr, const uint32_t *__restrict__ start_ids,
     const uint32_t *__restrict__ nskip, const uint8_t *__restrict__ nlevel,
     const uint32_t *__restrict__ lev_off, const double *__restrict__ sx,
@@ -415,10 +402,11 @@ __global__ __launch_bounds__(128) void k_moments_group(
   double(*vv)[64] = vv_all[wv];
   uint32_t(*ids)[64] = ids_all[wv];
   int *s_lo = s_lo_all[wv];
-  const uint32_t n_groups = gctr[0], n_nodes = lev_off[RB_NLEV];
-  for (uint32_t gi = 2 * blockIdx.x + wv; gi < n_groups; gi += 2 * gridDim.x) {
-    const WalkItem it = groups[gi];
-    const uint32_t g = it.pad;
+  const uint32_t n_big = gctr[2], n_mid = gctr[3], n_nodes = lev_off[RB_NLEV];
+  const uint32_t n_items = n_big + n_mid + gctr[4];
+  for (uint32_t gi = 2 * blockIdx.x + wv; gi < n_items; gi += 2 * gridDim.x) {
+    const WalkItem it = rb_walk_item(items, items_mid, gi, n_big, n_mid, wcap);
+    const uint32_t g = it.node;  // the run's last subtree root
     if (g == RB_NONE) continue;  // a run of a large leaf: no node of its own
     const uint32_t f = it.start, cnt = it.end - it.start;
     if (cnt == 0 || cnt > 64 || g >= n_nodes) {
@@ -739,8 +727,7 @@ hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const d
   if (grid > 2048) grid = 2048;
   hipLaunchKernelGGL(k_groups, dim3(grid), dim3(256), 0, c->stream, c->d_lev_off, c->d_nfirst,
                      c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nleaf, c->d_nlevel,
-                     c->d_starts, c->P, G, c->d_groups, c->d_witems, c->d_witems_mid,
-                     (uint32_t)c->cap,
+                     c->d_starts, c->P, G, c->d_witems, c->d_witems_mid, (uint32_t)c->cap,
                      c->d_gctr, c->d_large, c->d_bottom, c->d_large_cnt);
 #define RB_MARGS                                                                          \
   c->d_nfirst, c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nskip, c->d_nleaf, sx, sy, sz, \
@@ -748,8 +735,8 @@ hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const d
       (uint32_t)c->cap, c->d_err
   unsigned sgrid = rb_div_up(n, 32);  // two waves per workgroup
   if (sgrid > 131072) sgrid = 131072;
-  hipLaunchKernelGGL(k_moments_group, dim3(sgrid), dim3(128), 0, c->stream, c->d_groups,
-                     c->d_gctr, c->d_key[0], c->d_starts, c->d_csr, c->d_start_ids, c->d_nskip,
+  hipLaunchKernelGGL(k_moments_group, dim3(sgrid), dim3(128), 0, c->stream, c->d_witems,
+                     c->d_witems_mid, c->cap, c->d_gctr, c->d_key[0], c->d_starts, c->d_csr, c->d_start_ids, c->d_nskip,
                      c->d_nlevel, c->d_lev_off, sx, sy, sz, c->d_msrc, c->p.leaf_size,
                      c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, wnode,
                      c->d_err);

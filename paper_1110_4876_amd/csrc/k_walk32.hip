@@ -66,17 +66,6 @@ struct W32Cell {
   float4 pos, q0, q1;
 };
 
-// work item gi of the walk's order: big items (front of the first table),
-// middle-sized ones (second table), small ones (back of the first table)
-__device__ __forceinline__ WalkItem w32_item(const WalkItem *__restrict__ groups,
-                                             const WalkItem *__restrict__ groups_mid,
-                                             uint32_t gi, uint32_t n_big, uint32_t n_mid,
-                                             uint64_t cap) {
-  if (gi < n_big) return groups[gi];
-  if (gi < n_big + n_mid) return groups_mid[gi - n_big];
-  return groups[(uint32_t)cap - 1u - (gi - n_big - n_mid)];
-}
-
 struct F3 {
   float x, y, z;
 };
@@ -212,7 +201,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const int im0 =
         img_split ? (int)((item / n_groups + (uint32_t)(n_img / 2)) % (uint32_t)n_img) : 0;
     const int nim = img_split ? 1 : n_img;
-    const WalkItem grp = w32_item(groups, groups_mid, gi, n_big, n_mid, cap);
+    const WalkItem grp = rb_walk_item(groups, groups_mid, gi, n_big, n_mid, cap);
     const uint32_t p = grp.patch;
     const double W = patch[p].W;
     const int cnt = (int)(grp.end - grp.start);
@@ -477,7 +466,7 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
     const int im0 =
         img_split ? (int)((item / n_groups + (uint32_t)(n_img / 2)) % (uint32_t)n_img) : 0;
     const int nim = img_split ? 1 : n_img;
-    const WalkItem grp = w32_item(groups, groups_mid, gi, n_big, n_mid, cap);
+    const WalkItem grp = rb_walk_item(groups, groups_mid, gi, n_big, n_mid, cap);
     const uint32_t p = grp.patch;
     const double W = patch[p].W;
     const int cnt = (int)(grp.end - grp.start);

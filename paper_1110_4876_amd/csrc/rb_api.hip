@@ -302,7 +302,6 @@ int init_ctx(rb_ctx *c, const rb_params *p, uint32_t P, const int64_t *off, cons
   RB_TRY(dalloc(c, &c->d_Q, 6 * nc));
   RB_TRY(dalloc(c, &c->d_wnode, nc));
   RB_TRY(dalloc(c, &c->d_items64, max_items));
-  RB_TRY(dalloc(c, &c->d_groups, cap));
   RB_TRY(dalloc(c, &c->d_witems, cap));
   RB_TRY(dalloc(c, &c->d_witems_mid, cap));
   RB_TRY(dalloc(c, &c->d_gctr, 8));

@@ -10,12 +10,27 @@
 #include "../../include/rb.h"
 #include "rb_common.h"
 
-// Walk work item: a run of consecutive sorted slots of one patch.
+// Work item: a run of consecutive sorted slots of one patch.  For the
+// grouped walk and the moments pass, node is the last of the consecutive
+// sibling subtrees the run is made of (RB_NONE for a piece of a leaf with
+// more than G particles); the FP64 walk's items leave it unused.
 struct WalkItem {
   uint32_t start, end;  // slot range [start, end)
   uint32_t patch;
-  uint32_t pad;
+  uint32_t node;
 };
+
+// Item gi in the grouped walk's order: those of more than G/2 particles
+// (front of the first table), of more than G/4 (second table), the rest
+// (back of the first table, whose capacity is cap).
+__device__ __forceinline__ WalkItem rb_walk_item(const WalkItem *__restrict__ items,
+                                                 const WalkItem *__restrict__ items_mid,
+                                                 uint32_t gi, uint32_t n_big, uint32_t n_mid,
+                                                 uint64_t cap) {
+  if (gi < n_big) return items[gi];
+  if (gi < n_big + n_mid) return items_mid[gi - n_big];
+  return items[(uint32_t)cap - 1u - (gi - n_big - n_mid)];
+}
 
 struct rb_ctx {
   rb_params p;
@@ -90,7 +105,6 @@ struct rb_ctx {
   // walk
   std::vector<WalkItem> h_items64;  // FP64 walk: 64 Morton-consecutive slots
   WalkItem *d_items64 = nullptr;
-  WalkItem *d_groups = nullptr;     // node groups emitted from the tree (moments pass)
   WalkItem *d_witems = nullptr;     // FP32 walk: packed work items (big ones, small ones)
   WalkItem *d_witems_mid = nullptr; // FP32 walk: packed work items of middle size
   uint32_t *d_gctr = nullptr;       // [groups emitted, items taken, big, middle, small items]
