@@ -7,23 +7,25 @@
 //                      (patch, bucket) (rb_bucket_add; bucket 4096 holds
 //                      removed particles, whose all-ones key sorts last);
 //   k_bsort_scan    -- per patch: bucket cursors, and segments: runs of
-//                      whole buckets that start in the same window of 256
-//                      slots (at most 511 keys), a bucket above 256 keys
+//                      whole buckets that start in the same window of 64
+//                      slots (at most 127 keys), a bucket above 64 keys
 //                      being a segment of its own (small segments keep
 //                      more CUs busy and networks short);
 //   k_bsort_scatter -- every key to its bucket (one atomic per bucket and
 //                      wave);
 //   k_bsort_local   -- per segment: a bitonic sort of (key, slot) held in
-//                      registers (four rows of 256; partners within a wave
-//                      by shuffles, across rows in registers, across waves
-//                      through LDS), or, for a large bucket, eight-bit radix
-//                      passes over the slot and the low 51 key bits by one
-//                      workgroup in global memory.
+//                      registers, by one wave up to 512 keys (partners in
+//                      the same lane or swizzled across lanes), by a
+//                      workgroup up to 1024 (four rows of 256; partners
+//                      within a wave by shuffles, across rows in registers,
+//                      across waves through LDS), or, for a larger bucket,
+//                      eight-bit radix passes over the slot and the low 51
+//                      key bits by one workgroup in global memory.
 // Keys and slots arrive in buffer 0, go to their buckets in buffer 1 and
 // come back sorted to buffer 0.
 #include "rb_internal.h"
 
-#define BS_WIN 256   // segment window (slots)
+#define BS_WIN 64    // segment window (slots)
 #define BS_LDS 1024  // largest segment sorted by the bitonic network
 
 // lanes of the wave holding the same value in the low `bits` bits
@@ -161,7 +163,8 @@ __device__ void bs_big(uint64_t *__restrict__ k1, uint32_t *__restrict__ v1,
     uint32_t *vo = (q & 1) ? v1 : v0;
     for (uint32_t i = tid; i < 256; i += blockDim.x) hist[i] = 0;
     __syncthreads();
-    for (uint32_t s = a + tid; s < e; s += blockDim.x) atomicAdd(&hist[bs_digit(ki[s], vi[s], q)], 1u);
+    for (uint32_t s = a + tid; s < e; s += blockDim.x)
+      atomicAdd(&hist[bs_digit(ki[s], vi[s], q)], 1u);
     __syncthreads();
     if (tid < 64) {  // exclusive scan of the 256 bins, 4 per lane
       uint32_t h4[4], t = 0;
@@ -242,9 +245,111 @@ __device__ __forceinline__ void bs_stage_wave(uint64_t (&k)[4], uint32_t (&v)[4]
   bs_take(k, v, pk, pv, nr, tid, size, (uint32_t)S);
 }
 
-// One block of 256 threads per segment (persistent: segments are taken
-// from a counter).  Element i of the bitonic network lives in row i / 256 of
-// thread i % 256.
+// Bitonic network on (key, slot) pairs of one segment of at most 64 R
+// keys by one wave, lane-major: element e = lane R + r sits in register r of
+// the lane, so partners closer than R are in the same lane and the others
+// R-multiples of lanes apart (ds_swizzle below 32 lanes, a shuffle at 32).
+// The pairs are compared as (key, slot), so equal keys come out in slot
+// order and the padding (all-ones key, all-ones slot) last.
+template <int S>
+__device__ __forceinline__ void bs_lane_xor(uint64_t &k, uint32_t &v) {
+  if (S < 32) {
+    constexpr int pat = 0x1F | (S << 10);  // bit-mask mode: lane ^ S in each half
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)k, pat);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)(k >> 32), pat);
+    k = ((uint64_t)hi << 32) | lo;
+    v = (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, pat);
+  } else {
+    k = __shfl_xor(k, S, 64);
+    v = (uint32_t)__shfl_xor((int)v, S, 64);
+  }
+}
+
+template <int R, int S>
+__device__ __forceinline__ void bs_wave_lanes(uint64_t (&k)[R], uint32_t (&v)[R], uint32_t lane,
+                                              uint32_t size) {
+  // partners S lanes apart: element stride S * R
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    uint64_t pk = k[r];
+    uint32_t pv = v[r];
+    bs_lane_xor<S>(pk, pv);
+    const uint32_t e = lane * R + (uint32_t)r;
+    const bool asc = (e & size) == 0;
+    const bool lower = (e & (uint32_t)(S * R)) == 0;
+    if ((lower == asc) == bs_less(pk, pv, k[r], v[r])) { k[r] = pk; v[r] = pv; }
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void bs_wave_sort(const uint64_t *__restrict__ k1,
+                                             const uint32_t *__restrict__ v1,
+                                             uint64_t *__restrict__ k0, uint32_t *__restrict__ v0,
+                                             uint32_t a, uint32_t m, uint32_t lane) {
+  uint64_t k[R];
+  uint32_t v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t e = lane * R + (uint32_t)r;
+    k[r] = e < m ? k1[a + e] : ~0ull;
+    v[r] = e < m ? v1[a + e] : ~0u;
+  }
+#pragma unroll
+  for (uint32_t size = 2; size <= 64u * R; size <<= 1) {
+#pragma unroll
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride >= (uint32_t)R) {
+        switch (stride / R) {
+          case 1: bs_wave_lanes<R, 1>(k, v, lane, size); break;
+          case 2: bs_wave_lanes<R, 2>(k, v, lane, size); break;
+          case 4: bs_wave_lanes<R, 4>(k, v, lane, size); break;
+          case 8: bs_wave_lanes<R, 8>(k, v, lane, size); break;
+          case 16: bs_wave_lanes<R, 16>(k, v, lane, size); break;
+          default: bs_wave_lanes<R, 32>(k, v, lane, size); break;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int r2 = r | (int)stride;
+          if ((r & (int)stride) == 0 && r2 < R) {
+            const bool asc = ((lane * R + (uint32_t)r) & size) == 0;
+            if (bs_less(k[r2], v[r2], k[r], v[r]) == asc) {
+              const uint64_t tk = k[r]; k[r] = k[r2]; k[r2] = tk;
+              const uint32_t tv = v[r]; v[r] = v[r2]; v[r2] = tv;
+            }
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t e = lane * R + (uint32_t)r;
+    if (e < m) { k0[a + e] = k[r]; v0[a + e] = v[r]; }
+  }
+}
+
+// slot range [a, e) of segment i
+__device__ __forceinline__ void bs_segment(const uint2 *__restrict__ seg,
+                                           const uint32_t *__restrict__ starts, uint32_t nseg,
+                                           uint32_t i, uint32_t &a, uint32_t &e) {
+  const uint2 me = seg[i];
+  a = me.x;
+  e = starts[me.y + 1];
+  if (i + 1 < nseg) {
+    const uint2 nx = seg[i + 1];
+    if (nx.y == me.y) e = nx.x;
+  }
+}
+
+#define BS_WAVE_MAX 512  // segments up to this size are sorted by one wave
+
+// Persistent workgroups of four waves take segments four at a time (the
+// first four by grid position, the rest from a counter): each wave sorts
+// one segment of up to BS_WAVE_MAX keys on its own, then the workgroup sorts
+// the larger ones of the four together: a bitonic network over four rows of
+// 256 (element i in row i / 256 of thread i % 256) up to BS_LDS keys, with
+// equal keys put in slot order afterwards, or radix passes beyond.
 __global__ __launch_bounds__(256) void k_bsort_local(
     uint64_t *__restrict__ k1, uint32_t *__restrict__ v1, uint64_t *__restrict__ k0,
     uint32_t *__restrict__ v0, const uint2 *__restrict__ seg, uint32_t *__restrict__ ctl,
@@ -252,128 +357,147 @@ __global__ __launch_bounds__(256) void k_bsort_local(
   __shared__ uint64_t sk[BS_LDS];
   __shared__ uint32_t sv[BS_LDS];
   __shared__ uint32_t s_i;
-  const uint32_t tid = threadIdx.x;
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
+  const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));
   const uint32_t nseg = ctl[0];
+  bool first = true;
   for (;;) {
-    if (tid == 0) s_i = atomicAdd(&ctl[1], 1u);
+    if (tid == 0) s_i = first ? 4u * blockIdx.x : 4u * gridDim.x + atomicAdd(&ctl[1], 4u);
+    first = false;
     __syncthreads();
-    const uint32_t i = s_i;
+    const uint32_t i0 = s_i;
     __syncthreads();
-    if (i >= nseg) break;  // uniform over the block
-    const uint2 me = seg[i];
-    const uint32_t a = me.x, p = me.y;
-    uint32_t e = starts[p + 1];
-    if (i + 1 < nseg) {
-      const uint2 nx = seg[i + 1];
-      if (nx.y == p) e = nx.x;
+    if (i0 >= nseg) break;  // uniform over the block
+    {
+      const uint32_t i = i0 + w;
+      if (i < nseg) {
+        uint32_t a, e;
+        bs_segment(seg, starts, nseg, i, a, e);
+        const uint32_t m = e - a;
+        if (m == 1) {
+          if (lane == 0) { k0[a] = k1[a]; v0[a] = v1[a]; }
+        } else if (m <= 64) {
+          bs_wave_sort<1>(k1, v1, k0, v0, a, m, lane);
+        } else if (m <= 128) {
+          bs_wave_sort<2>(k1, v1, k0, v0, a, m, lane);
+        } else if (m <= 256) {
+          bs_wave_sort<4>(k1, v1, k0, v0, a, m, lane);
+        } else if (m <= BS_WAVE_MAX) {
+          bs_wave_sort<8>(k1, v1, k0, v0, a, m, lane);
+        }
+      }
     }
-    const uint32_t m = e - a;
-    if (m <= 1) {
-      if (m == 1 && tid == 0) { k0[a] = k1[a]; v0[a] = v1[a]; }
-      continue;
-    }
-    if (m > BS_LDS) {
-      // the LDS arrays serve as the radix scratch of the large-bucket path
-      uint32_t *scratch = reinterpret_cast<uint32_t *>(sk);
-      bs_big(k1, v1, k0, v0, a, e, scratch, scratch + 256);
-      continue;
-    }
-    uint32_t n2 = 256;
-    while (n2 < m) n2 <<= 1;
-    const int nr = (int)(n2 >> 8);  // rows in use (1, 2 or 4)
-    uint64_t k[4];
-    uint32_t v[4];
-    // removed particles' all-ones keys become all-ones minus one, so that
-    // the padding (all ones) sorts after them (live keys are below 2^63)
+    for (uint32_t q = 0; q < 4; ++q) {
+      const uint32_t i = i0 + q;
+      if (i >= nseg) break;  // uniform
+      uint32_t a, e;
+      bs_segment(seg, starts, nseg, i, a, e);
+      const uint32_t m = e - a;
+      if (m <= BS_WAVE_MAX) continue;  // uniform: done by a wave above
+      if (m > BS_LDS) {
+        // the LDS arrays serve as the radix scratch of the large-bucket path
+        uint32_t *scratch = reinterpret_cast<uint32_t *>(sk);
+        bs_big(k1, v1, k0, v0, a, e, scratch, scratch + 256);
+        __syncthreads();  // LDS reused by the next segment
+        continue;
+      }
+      uint32_t n2 = 256;
+      while (n2 < m) n2 <<= 1;
+      const int nr = (int)(n2 >> 8);  // rows in use (1, 2 or 4)
+      uint64_t k[4];
+      uint32_t v[4];
+      // removed particles' all-ones keys become all-ones minus one, so that
+      // the padding (all ones) sorts after them (live keys are below 2^63)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const uint32_t j = (uint32_t)r * 256 + tid;
-      const bool in = r < nr && j < m;
-      const uint64_t kk = in ? k1[a + j] : RB_KEY_DEAD;
-      k[r] = in && kk == RB_KEY_DEAD ? RB_KEY_DEAD - 1ull : kk;
-      v[r] = in ? v1[a + j] : 0xFFFFFFFFu;
-    }
-    // the network orders the keys; equal keys (rare) are put in slot order
-    // afterwards
-    for (uint32_t size = 2; size <= n2; size <<= 1) {
-      for (uint32_t stride = size >> 1; stride >= 64; stride >>= 1) {
-        if (stride >= 256) {  // partner in another row of the same thread
-          const int rs = (int)(stride >> 8);
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t j = (uint32_t)r * 256 + tid;
+        const bool in = r < nr && j < m;
+        const uint64_t kk = in ? k1[a + j] : RB_KEY_DEAD;
+        k[r] = in && kk == RB_KEY_DEAD ? RB_KEY_DEAD - 1ull : kk;
+        v[r] = in ? v1[a + j] : 0xFFFFFFFFu;
+      }
+      // the network orders the keys; equal keys (rare) are put in slot order
+      // afterwards
+      for (uint32_t size = 2; size <= n2; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride >= 64; stride >>= 1) {
+          if (stride >= 256) {  // partner in another row of the same thread
+            const int rs = (int)(stride >> 8);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int rr = r ^ rs;
-            if (r < nr && r < rr) {
-              const bool asc = ((((uint32_t)r * 256 + tid) & size) == 0);
-              if ((k[rr] < k[r]) == asc) {
-                const uint64_t tk = k[r]; k[r] = k[rr]; k[rr] = tk;
-                const uint32_t tv = v[r]; v[r] = v[rr]; v[rr] = tv;
+            for (int r = 0; r < 4; ++r) {
+              const int rr = r ^ rs;
+              if (r < nr && r < rr) {
+                const bool asc = ((((uint32_t)r * 256 + tid) & size) == 0);
+                if ((k[rr] < k[r]) == asc) {
+                  const uint64_t tk = k[r]; k[r] = k[rr]; k[rr] = tk;
+                  const uint32_t tv = v[r]; v[r] = v[rr]; v[rr] = tv;
+                }
               }
             }
+          } else {  // partner in another wave: through LDS
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (r < nr) { sk[r * 256 + tid] = k[r]; sv[r * 256 + tid] = v[r]; }
+            __syncthreads();
+            uint64_t pk[4];
+            uint32_t pv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (r < nr) {
+                pk[r] = sk[(r * 256 + tid) ^ stride];
+                pv[r] = sv[(r * 256 + tid) ^ stride];
+              }
+            __syncthreads();
+            bs_take(k, v, pk, pv, nr, tid, size, stride);
           }
-        } else {  // partner in another wave: through LDS
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (r < nr) { sk[r * 256 + tid] = k[r]; sv[r * 256 + tid] = v[r]; }
-          __syncthreads();
-          uint64_t pk[4];
-          uint32_t pv[4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (r < nr) {
-              pk[r] = sk[(r * 256 + tid) ^ stride];
-              pv[r] = sv[(r * 256 + tid) ^ stride];
-            }
-          __syncthreads();
-          bs_take(k, v, pk, pv, nr, tid, size, stride);
         }
+        // partners inside the wave: constant strides
+        if (size >= 64) bs_stage_wave<32>(k, v, nr, tid, size);
+        if (size >= 32) bs_stage_wave<16>(k, v, nr, tid, size);
+        if (size >= 16) bs_stage_wave<8>(k, v, nr, tid, size);
+        if (size >= 8) bs_stage_wave<4>(k, v, nr, tid, size);
+        if (size >= 4) bs_stage_wave<2>(k, v, nr, tid, size);
+        bs_stage_wave<1>(k, v, nr, tid, size);
       }
-      // partners inside the wave: constant strides
-      if (size >= 64) bs_stage_wave<32>(k, v, nr, tid, size);
-      if (size >= 32) bs_stage_wave<16>(k, v, nr, tid, size);
-      if (size >= 16) bs_stage_wave<8>(k, v, nr, tid, size);
-      if (size >= 8) bs_stage_wave<4>(k, v, nr, tid, size);
-      if (size >= 4) bs_stage_wave<2>(k, v, nr, tid, size);
-      bs_stage_wave<1>(k, v, nr, tid, size);
-    }
-    // equal keys in slot order: odd-even passes over runs of equal keys
-    // until nothing moves (at most the run length)
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (r < nr) { sk[r * 256 + tid] = k[r]; sv[r * 256 + tid] = v[r]; }
-    __syncthreads();
-    bool ties = false;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const uint32_t j = (uint32_t)r * 256 + tid;
-      if (r < nr && j > 0 && j < m && sk[j - 1] == sk[j]) ties = true;
-    }
-    if (__syncthreads_or(ties)) {
-      for (uint32_t it = 0; it < m; ++it) {
-        bool moved = false;
-        for (int ph = 0; ph < 2; ++ph) {
-          for (uint32_t j = 2 * tid + (uint32_t)ph; j + 1 < m; j += 2 * blockDim.x) {
-            if (sk[j] == sk[j + 1] && sv[j + 1] < sv[j]) {
-              const uint32_t t = sv[j]; sv[j] = sv[j + 1]; sv[j + 1] = t;
-              moved = true;
-            }
-          }
-          __syncthreads();
-        }
-        if (!__syncthreads_or(moved)) break;
-      }
+      // equal keys in slot order: odd-even passes over runs of equal keys
+      // until nothing moves (at most the run length)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        if (r < nr) { k[r] = sk[r * 256 + tid]; v[r] = sv[r * 256 + tid]; }
-    }
+        if (r < nr) { sk[r * 256 + tid] = k[r]; sv[r * 256 + tid] = v[r]; }
+      __syncthreads();
+      bool ties = false;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const uint32_t j = (uint32_t)r * 256 + tid;
-      if (r < nr && j < m) {
-        k0[a + j] = k[r] == RB_KEY_DEAD - 1ull ? RB_KEY_DEAD : k[r];
-        v0[a + j] = v[r];
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t j = (uint32_t)r * 256 + tid;
+        if (r < nr && j > 0 && j < m && sk[j - 1] == sk[j]) ties = true;
       }
+      if (__syncthreads_or(ties)) {
+        for (uint32_t it = 0; it < m; ++it) {
+          bool moved = false;
+          for (int ph = 0; ph < 2; ++ph) {
+            for (uint32_t j = 2 * tid + (uint32_t)ph; j + 1 < m; j += 2 * blockDim.x) {
+              if (sk[j] == sk[j + 1] && sv[j + 1] < sv[j]) {
+                const uint32_t t = sv[j]; sv[j] = sv[j + 1]; sv[j + 1] = t;
+                moved = true;
+              }
+            }
+            __syncthreads();
+          }
+          if (!__syncthreads_or(moved)) break;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (r < nr) { k[r] = sk[r * 256 + tid]; v[r] = sv[r * 256 + tid]; }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t j = (uint32_t)r * 256 + tid;
+        if (r < nr && j < m) {
+          k0[a + j] = k[r] == RB_KEY_DEAD - 1ull ? RB_KEY_DEAD : k[r];
+          v0[a + j] = v[r];
+        }
+      }
+      __syncthreads();  // LDS reused by the next segment
     }
-    __syncthreads();  // LDS reused by the next segment
   }
 }
 

@@ -11,7 +11,7 @@
 #define RB_LARGE_SLOTS 32  // large-node counters: one per level, then RB_BOTTOM
 #define RB_NONE 0xFFFFFFFFu                // absent node / end of walk
 #define RB_KEY_DEAD 0xFFFFFFFFFFFFFFFFull  // key of a removed / outside particle
-#define RB_TILE_MIN 128                    // slots per topology tile
+#define RB_TILE_MIN 64                     // slots per topology tile
 #define RB_TILE_MAX 1024
 #define RB_MAX_IMAGES 25                   // (2*2+1)^2 for two ghost rings
 
