@@ -271,11 +271,24 @@ __global__ __launch_bounds__(256) void k_groups(
         wi_tally(half, quarter, n_big, n_mid, n_small, cnt - s0 < G ? cnt - s0 : G);
     }
     bool any_large = false;
+    // the (at most eight, consecutive) children's slot ranges, all requested
+    // at once
+    uint32_t nch = 0, chf[8], chl[8];
     if (is_large && !leaf) {
       ca = nchild[id]; cb = nlastchild[id];
+      if (ca <= cb && cb - ca < 8 && cb < n_nodes) nch = cb - ca + 1;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < 8; ++j) {
+      chf[j] = j < nch ? nfirst[ca + j] : 0u;
+      chl[j] = j < nch ? nlast[ca + j] : 0u;
+    }
+    if (is_large && !leaf) {
       uint32_t run = 0;
-      for (uint32_t c = ca; c <= cb && c < n_nodes; ++c) {
-        const uint32_t cc = nlast[c] - nfirst[c] + 1;
+#pragma unroll
+      for (uint32_t j = 0; j < 8; ++j) {
+        if (j >= nch) break;
+        const uint32_t cc = chl[j] - chf[j] + 1;
         if (cc <= G) {
           if (run && run + cc > G) {
             wi_tally(half, quarter, n_big, n_mid, n_small, run);
@@ -319,8 +332,10 @@ __global__ __launch_bounds__(256) void k_groups(
         }
       } else {
         uint32_t run = 0, r0 = 0, r1 = 0, rl = 0;
-        for (uint32_t c = ca; c <= cb && c < n_nodes; ++c) {
-          const uint32_t cf = nfirst[c], cl = nlast[c], cc = cl - cf + 1;
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) {
+          if (j >= nch) break;
+          const uint32_t c = ca + j, cf = chf[j], cl = chl[j], cc = cl - cf + 1;
           if (cc <= G) {
             if (run && run + cc > G) {
               wi_put(witems, witems_mid, wcap, half, quarter, bpos, mpos, spos, r0, r1, p,
@@ -530,9 +545,8 @@ __global__ __launch_bounds__(128) void k_moments_group(
 // waits only for its children's moments.
 #define ML_CAP 2048
 
-// An internal node from its (at most eight, consecutive) children: masses
-// and sums of all children, positions and quadrupoles of the first four in
-// one round of loads, the other four's after the sums.
+// An internal node from its (at most eight, consecutive) children, whose
+// records are all requested in one round of loads.
 __device__ __forceinline__ void ml_internal(uint32_t id, int l, uint32_t first, uint32_t last,
                                             uint32_t ca, uint32_t cb, uint32_t skip, int quad,
                                             NodeLink *__restrict__ link,
@@ -540,21 +554,19 @@ __device__ __forceinline__ void ml_internal(uint32_t id, int l, uint32_t first, 
                                             double *__restrict__ Sarr,
                                             double *__restrict__ Qarr, WNode *__restrict__ wn) {
   const uint32_t nch = cb - ca + 1;
-  double cm[8], cs[8][3], cx[4][3], cq[4][6];
+  double cm[8], cs[8][3], cx[8][3], cq[8][6];
 #pragma unroll
   for (uint32_t j = 0; j < 8; ++j) {
     if (j < nch) {
       const uint32_t ch = ca + j;
       const double4 m4 = mcom[ch];
       cm[j] = m4.w;
+      cx[j][0] = m4.x; cx[j][1] = m4.y; cx[j][2] = m4.z;
 #pragma unroll
       for (int b = 0; b < 3; ++b) cs[j][b] = Sarr[3 * (size_t)ch + b];
-      if (j < 4) {
-        cx[j][0] = m4.x; cx[j][1] = m4.y; cx[j][2] = m4.z;
-        if (quad) {
+      if (quad) {
 #pragma unroll
-          for (int b = 0; b < 6; ++b) cq[j][b] = Qarr[6 * (size_t)ch + b];
-        }
+        for (int b = 0; b < 6; ++b) cq[j][b] = Qarr[6 * (size_t)ch + b];
       }
     }
   }
@@ -566,23 +578,8 @@ __device__ __forceinline__ void ml_internal(uint32_t id, int l, uint32_t first, 
   mom_internal_com(a);
   if (quad) {
 #pragma unroll
-    for (uint32_t j = 0; j < 4; ++j)
+    for (uint32_t j = 0; j < 8; ++j)
       if (j < nch) mom_child_q(a, cm[j], cx[j][0], cx[j][1], cx[j][2], cq[j]);
-    if (nch > 4) {
-#pragma unroll
-      for (uint32_t j = 4; j < 8; ++j) {
-        if (j < nch) {
-          const uint32_t ch = ca + j;
-          const double4 m4 = mcom[ch];
-          cx[j - 4][0] = m4.x; cx[j - 4][1] = m4.y; cx[j - 4][2] = m4.z;
-#pragma unroll
-          for (int b = 0; b < 6; ++b) cq[j - 4][b] = Qarr[6 * (size_t)ch + b];
-        }
-      }
-#pragma unroll
-      for (uint32_t j = 4; j < 8; ++j)
-        if (j < nch) mom_child_q(a, cm[j], cx[j - 4][0], cx[j - 4][1], cx[j - 4][2], cq[j - 4]);
-    }
   }
   NodeLink lk;
   lk.child_or_first = ca;
