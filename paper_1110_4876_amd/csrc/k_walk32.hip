@@ -420,8 +420,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 // for all of the group's particles; the waves' partial forces are added in
 // wave order at the end.  Two barriers per round; a group's chain of
 // dependent rounds is up to NW times shorter.
+// list capacities of the multi-wave walk: a list is evaluated at the start
+// of a round once it holds W32M_CFLUSH cells (W32M_PFLUSH particles), while
+// that round's node records are in flight; a round adds at most 64 entries
+// per wave.  Evaluating every round's entries in the next round keeps the
+// lists (and LDS) small and spreads the arithmetic evenly over the rounds.
+#ifndef W32M_CL
+#define W32M_CL 64
+#define W32M_CFLUSH 1
+#define W32M_PL 64
+#define W32M_PFLUSH 1
+#endif
+#ifndef W32M_WAVES_PER_EU
+#define W32M_WAVES_PER_EU 4
+#endif
+static_assert(W32M_CL >= W32M_CFLUSH - 1 + 64 && W32M_PL >= W32M_PFLUSH - 1 + 64,
+              "a round's appends must fit after a partial list");
+
 template <bool QUAD, bool STATS, int NW>
-__global__ __launch_bounds__(64 * NW) void k_walk32m(
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W32M_WAVES_PER_EU, 8))) void k_walk32m(
     const WalkItem *__restrict__ groups, const WalkItem *__restrict__ groups_mid,
     uint32_t *__restrict__ gctr, int img_split, int n_img,
     int ngx, int ngy, int boundary, const PatchInfo *__restrict__ patch,
@@ -433,8 +450,8 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
     uint32_t *__restrict__ err, int slot) {
   constexpr int W32M_SCAP = 512 * NW + 512;  // batches of 64 NW, 8 children each, plus depth
   __shared__ uint32_t stk[W32M_SCAP];
-  __shared__ W32Cell cel_all[NW][W32_CL];
-  __shared__ float4 ppos_all[NW][W32_PL];
+  __shared__ W32Cell cel_all[NW][W32M_CL];
+  __shared__ float4 ppos_all[NW][W32M_PL];
   __shared__ uint32_t s_push[NW];
   __shared__ uint32_t s_item;
   __shared__ double2 img[RB_MAX_IMAGES];
@@ -542,12 +559,12 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
         }
       }
       // full lists are evaluated while the node records are in flight
-      if (cl >= W32_CFLUSH) {
+      if (cl >= W32M_CFLUSH) {
         w32_eval_cells(cel, cl, sub, lpp, px, py, pz, b2, QUAD, ax, ay, az);
         if (STATS) n_cell += (unsigned long long)cl * (unsigned long long)cnt;
         cl = 0;
       }
-      if (pl >= 64) {
+      if (pl >= W32M_PFLUSH) {
         w32_eval_parts(ppos, pl, sub, lpp, px, py, pz, b2, ax, ay, az);
         if (STATS) n_pp += (unsigned long long)pl * (unsigned long long)cnt;
         pl = 0;
@@ -619,7 +636,7 @@ __global__ __launch_bounds__(64 * NW) void k_walk32m(
         const uint32_t count = __shfl(lk.count, src, 64);
         const double bx = __shfl(ox, src, 64), by = __shfl(oy, src, 64);
         for (uint32_t c0 = 0; c0 < count; c0 += 64) {
-          if (pl + 64 > W32_PL) {
+          if (pl + 64 > W32M_PL) {
             w32_eval_parts(ppos, pl, sub, lpp, px, py, pz, b2, ax, ay, az);
             if (STATS) n_pp += (unsigned long long)pl * (unsigned long long)cnt;
             pl = 0;
