@@ -14,7 +14,10 @@ What each function follows in the paper (Rein & Liu 2012, REBOUND):
     angle theta = w / R;
   * ``step`` -- the drift-kick-drift step of Sect. 3 with the leap-frog
     (Sect. 3.1) or exact epicycle (Sect. 3.3) drift and the boundaries of
-    Sect. 2.3.
+    Sect. 2.3;
+  * ``collide`` -- the collisions of Sect. 5 at the end of a step:
+    overlapping pairs over the ghost boxes, a randomly ordered queue,
+    hard-sphere resolution with a normal coefficient of restitution.
 """
 from __future__ import annotations
 
@@ -95,6 +98,11 @@ def lib():
         L.orc_energy.argtypes = [P, i64, i64, vp, vp, vp, vp, vp, vp, vp]
         L.orc_energy.restype = ctypes.c_double
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_splitmix64.argtypes = [ctypes.c_uint64]
+        L.orc_splitmix64.restype = ctypes.c_uint64
+        L.orc_collide.argtypes = [P, i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_uint64, vp, i64, vp]
+        L.orc_collide.restype = i64
         _lib = L
         del dp
     return _lib
@@ -259,3 +267,27 @@ def energy(p: Params, state: dict, m, n_active=None) -> float:
     na = n if n_active is None else int(n_active)
     return float(lib().orc_energy(ctypes.byref(p), n, na, *[_ptr(s[k]) for k in
                  ("x", "y", "z", "vx", "vy", "vz")], _ptr(m)))
+
+
+def splitmix64(x: int) -> int:
+    """The finalising mix of the splitmix64 generator (one output for state x)."""
+    return int(lib().orc_splitmix64(ctypes.c_uint64(x & 0xFFFFFFFFFFFFFFFF)))
+
+
+def collide(p: Params, state: dict, m, radius, t: float, eps: float, seed: int,
+            cap: int = None):
+    """Collisions at time t (Sect. 5): returns (codes in queue order, number
+    of pairs, number resolved, new state).  A code is i 2^35 + j 2^7 + k for
+    particles i < j overlapping through ghost image k of j."""
+    s = {k: _f64(state[k]).copy() for k in ("x", "y", "z", "vx", "vy", "vz")}
+    m, radius = _f64(m), _f64(radius)
+    n = len(m)
+    cap = 16 * n + 16 if cap is None else int(cap)
+    codes = np.zeros(max(cap, 1), dtype=np.uint64)
+    nres = np.zeros(1, dtype=np.int64)
+    s_off = shear_offset(p, t)
+    cnt = lib().orc_collide(ctypes.byref(p), n, *[_ptr(s[k]) for k in
+                            ("x", "y", "z", "vx", "vy", "vz")], _ptr(m), _ptr(radius),
+                            float(s_off), float(eps), ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF),
+                            _ptr(codes), cap, _ptr(nres))
+    return codes[:min(int(cnt), cap)].copy(), int(cnt), int(nres[0]), s

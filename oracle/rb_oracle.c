@@ -698,3 +698,130 @@ double orc_energy(const orc_params *p, int64_t n, int64_t n_active,
   }
   return ek + ep;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Collisions (Sect. 5): detection of overlapping pairs at the end of a step,
+ * a random order for the collision queue, and hard-sphere resolution with a
+ * normal coefficient of restitution (v_n' = -eps v_n, v_t' = v_t), in that
+ * order, one collision after the other.
+ *
+ * Detection is the plain definition the tree search of Eq. (3) reaches:
+ * every pair (i < j) of live particles and every ghost image k of j with
+ * |x_j + o_k - x_i| < R_i + R_j.  A pair is coded c = i 2^35 + j 2^7 + k.
+ * The queue's random order is ascending h(c) = splitmix64(seed + c), the
+ * generator's finalising mix (Steele, Lea & Flood 2014), which is a bijection
+ * of 64-bit integers, so the order is total.  A queued collision is resolved
+ * only while the particles approach each other (d . u < 0, d = x_j + o_k -
+ * x_i, u = v_j + w_k - v_i, w_k the image's shear velocity (0, -3/2 Omega W
+ * ix, 0)); momentum is conserved and the normal relative velocity becomes
+ * -eps times itself.                                                      */
+
+uint64_t orc_splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+typedef struct {
+  uint64_t h, code;
+} orc_coll;
+
+static int orc_coll_cmp(const void *a, const void *b) {
+  const orc_coll *x = (const orc_coll *)a, *y = (const orc_coll *)b;
+  return (x->h > y->h) - (x->h < y->h);
+}
+
+int64_t orc_collide(const orc_params *p, int64_t n, const double *x, const double *y,
+                    const double *z, double *vx, double *vy, double *vz, const double *m,
+                    const double *R, double s, double eps, uint64_t seed, uint64_t *codes,
+                    int64_t cap, int64_t *n_resolved) {
+  double o[ORC_MAX_IMAGES][3];
+  int zero = 0;
+  const int ni = orc_images(p, s, o, &zero);
+  double w[ORC_MAX_IMAGES];  /* y velocity of each image relative to the box */
+  {
+    int k = 0;
+    for (int ix = -p->ng[0]; ix <= p->ng[0]; ++ix)
+      for (int iy = -p->ng[1]; iy <= p->ng[1]; ++iy) {
+        w[k++] = (p->boundary == ORC_SHEAR) ? -1.5 * p->omega * p->W * (double)ix : 0.0;
+      }
+    if (p->boundary == ORC_OPEN) w[0] = 0.0;
+  }
+  uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+  orc_keys(p, n, x, y, z, keys);
+  /* detection: all pairs, all images (brute force; counted, then written,
+   * both passes parallel over i) */
+  int64_t *per = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) {
+    if (keys[i] == UINT64_MAX) continue;
+    int64_t c = 0;
+    for (int64_t j = i + 1; j < n; ++j) {
+      if (keys[j] == UINT64_MAX) continue;
+      const double sum = R[i] + R[j];
+      for (int k = 0; k < ni; ++k) {
+        const double d0 = (x[j] + o[k][0]) - x[i];
+        const double d1 = (y[j] + o[k][1]) - y[i];
+        const double d2 = (z[j] + o[k][2]) - z[i];
+        if (d0 * d0 + d1 * d1 + d2 * d2 < sum * sum) ++c;
+      }
+    }
+    per[i + 1] = c;
+  }
+  for (int64_t i = 0; i < n; ++i) per[i + 1] += per[i];
+  const int64_t count = per[n];
+  int64_t stored = 0;
+  orc_coll *q = (orc_coll *)malloc(sizeof(orc_coll) * (size_t)(count > 0 ? count : 1));
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) {
+    if (keys[i] == UINT64_MAX) continue;
+    int64_t at = per[i];
+    for (int64_t j = i + 1; j < n; ++j) {
+      if (keys[j] == UINT64_MAX) continue;
+      const double sum = R[i] + R[j];
+      for (int k = 0; k < ni; ++k) {
+        const double d0 = (x[j] + o[k][0]) - x[i];
+        const double d1 = (y[j] + o[k][1]) - y[i];
+        const double d2 = (z[j] + o[k][2]) - z[i];
+        if (d0 * d0 + d1 * d1 + d2 * d2 < sum * sum) {
+          const uint64_t c = ((uint64_t)i << 35) | ((uint64_t)j << 7) | (uint64_t)k;
+          q[at].code = c;
+          q[at].h = orc_splitmix64(seed + c);
+          ++at;
+        }
+      }
+    }
+  }
+  free(per);
+  qsort(q, (size_t)count, sizeof(orc_coll), orc_coll_cmp);
+  /* resolution in queue order */
+  int64_t res = 0;
+  for (int64_t c = 0; c < count; ++c) {
+    const int64_t i = (int64_t)(q[c].code >> 35);
+    const int64_t j = (int64_t)((q[c].code >> 7) & ((1ull << 28) - 1ull));
+    const int k = (int)(q[c].code & 127ull);
+    if (stored < cap) codes[stored++] = q[c].code;
+    const double d0 = (x[j] + o[k][0]) - x[i];
+    const double d1 = (y[j] + o[k][1]) - y[i];
+    const double d2 = (z[j] + o[k][2]) - z[i];
+    const double u0 = vx[j] - vx[i];
+    const double u1 = (vy[j] + w[k]) - vy[i];
+    const double u2 = vz[j] - vz[i];
+    if (!(d0 * u0 + d1 * u1 + d2 * u2 < 0.0)) continue;  /* not approaching */
+    const double M = m[i] + m[j];
+    if (!(M > 0.0)) continue;
+    const double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    const double n0 = d0 / dist, n1 = d1 / dist, n2 = d2 / dist;
+    const double vn = n0 * u0 + n1 * u1 + n2 * u2;
+    const double f = (1.0 + eps) * vn;
+    const double fi = (m[j] / M) * f, fj = (m[i] / M) * f;
+    vx[i] = vx[i] + fi * n0; vy[i] = vy[i] + fi * n1; vz[i] = vz[i] + fi * n2;
+    vx[j] = vx[j] - fj * n0; vy[j] = vy[j] - fj * n1; vz[j] = vz[j] - fj * n2;
+    ++res;
+  }
+  if (n_resolved) *n_resolved = res;
+  free(q);
+  free(keys);
+  return count;
+}

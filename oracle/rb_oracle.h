@@ -13,7 +13,9 @@
  *     with bottom-up mass / centre of mass and Hernquist quadrupole moments;
  *   - the per-particle tree walk with opening angle theta = w/R;
  *   - the drift-kick-drift step of Sect. 3 with the leap-frog drift (3.1) or
- *     the exact epicycle drift used by the symplectic epicycle integrator (3.3).
+ *     the exact epicycle drift used by the symplectic epicycle integrator (3.3);
+ *   - the collisions of Sect. 5: overlapping pairs at the end of a step, a
+ *     randomly ordered queue, hard-sphere resolution with restitution.
  */
 #ifndef RB_ORACLE_H
 #define RB_ORACLE_H
@@ -89,6 +91,18 @@ double orc_energy(const orc_params *p, int64_t n, int64_t n_active,
                   const double *vx, const double *vy, const double *vz,
                   const double *m);
 int orc_num_threads(void);
+
+/* Collisions at the end of a step (Sect. 5): detects every overlapping pair
+ * (i < j, ghost image k of j), orders the queue by splitmix64(seed + code)
+ * with code = i 2^35 + j 2^7 + k, resolves the approaching ones in that
+ * order (hard spheres, restitution eps), updating v in place.  Writes the
+ * first `cap` codes in queue order; returns the number of pairs and sets
+ * *n_resolved.  s is the shear offset of the ghost boxes.                  */
+uint64_t orc_splitmix64(uint64_t x);
+int64_t orc_collide(const orc_params *p, int64_t n, const double *x, const double *y,
+                    const double *z, double *vx, double *vy, double *vz, const double *m,
+                    const double *R, double s, double eps, uint64_t seed, uint64_t *codes,
+                    int64_t cap, int64_t *n_resolved);
 
 #ifdef __cplusplus
 }
