@@ -236,6 +236,36 @@ int rb_batch_step(rb_ctx *ctx, rb_particles *p, double t, double dt, int32_t nst
 int rb_batch_gravity(rb_ctx *ctx, const rb_particles *p, double t, double *ax,
                      double *ay, double *az);
 
+/*
+ * Collisions at the end of a step (Sect. 5 of the paper), at time t with the
+ * positions and velocities of p (caller order, device): builds the octree
+ * and finds every pair of live particles i < j (caller indices) that
+ * overlap through ghost image k of j, |x_j + o_k - x_i| < R_i + R_j, by the
+ * tree search of Eq. (3) (descend while the distance to the cell centre is
+ * below R_i + R_max + (sqrt 3 / 2) w).  The pairs form a queue in the order
+ * of ascending splitmix64(seed + code), code = i 2^35 + j 2^7 + k (images
+ * numbered as for gravity, ix outer, iy inner); a queued pair that is
+ * approaching at its turn (d . u < 0, relative velocity u including the
+ * image's shear velocity -3/2 omega W ix) is resolved as free-slip hard
+ * spheres: the normal relative velocity becomes -epsilon times itself, the
+ * tangential one is kept, momentum is conserved.  vx, vy, vz change in
+ * place; x, y, z do not.
+ *  radius     device FP64, n entries, caller order.
+ *  epsilon    coefficient of restitution in [0, 1].
+ *  seed       any 64-bit value; the caller varies it from step to step.
+ *  n_pairs, n_resolved  host outputs (may be NULL): pairs found, pairs
+ *             resolved.
+ *  codes, codes_cap     optional host buffer for the found codes (in no
+ *             particular order; NULL / 0 to skip).
+ * For a batch context n is the total and pairs stay inside their patches.
+ * Synchronises.  Errors: RB_EINVAL (null pointer, epsilon, n), RB_EUNSUPPORTED
+ * (capacity >= 2^28), RB_ECAPACITY (more than 8 pairs per particle), and
+ * the deferred errors of the tree build.
+ */
+int rb_collide(rb_ctx *ctx, rb_particles *p, const double *radius, int64_t n, double t,
+               double epsilon, uint64_t seed, int64_t *n_pairs, int64_t *n_resolved,
+               uint64_t *codes, int64_t codes_cap);
+
 /* Synchronise the context's stream and return any deferred device error. */
 int rb_sync(rb_ctx *ctx);
 

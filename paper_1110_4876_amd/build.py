@@ -22,8 +22,9 @@ ARCH = os.environ.get("RB_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result"]
-# host-side schedule arithmetic must not be contracted
-PER_FILE = {"rb_api.hip": ["-ffp-contract=off"]}
+# host-side schedule arithmetic and the collision tests and updates must not
+# be contracted
+PER_FILE = {"rb_api.hip": ["-ffp-contract=off"], "k_collide.hip": ["-ffp-contract=off"]}
 
 
 def hipcc() -> str:

@@ -499,9 +499,9 @@ void drop_pool(rb_ctx *c) {
 }
 
 enum { PH_KEYS = 0, PH_SORT, PH_PERMUTE, PH_TOPO, PH_MOMENTS, PH_WALK, PH_POST, PH_DIRECT,
-       PH_TOTAL, PH_COUNT };
+       PH_COLLIDE, PH_TOTAL, PH_COUNT };
 const char *g_phase_names[] = {"keys", "sort", "permute", "topology", "moments", "walk",
-                               "kick_drift", "direct", "total"};
+                               "kick_drift", "direct", "collide", "total"};
 
 #define RB_LAUNCH(expr)                                                              \
   do {                                                                               \
@@ -550,6 +550,7 @@ int report_device_errors(rb_ctx *c) {
     if (err & RB_ERR_STACK) return fail(RB_ECAPACITY, "FP32 walk traversal stack overflow");
     if (err & RB_ERR_TREE) return fail(RB_ECAPACITY, "inconsistent tree links (internal error)");
     if (err & RB_ERR_SORT) return fail(RB_EHIP, "radix sort look-back timed out (internal error)");
+    if (err & RB_ERR_COLL) return fail(RB_ECAPACITY, "collision queue capacity exceeded");
     if (err & RB_ERR_INDEX) return fail(RB_EINVAL, "a target index lies outside [0, n)");
     if (err & RB_ERR_OUTSIDE)
       return fail(RB_EOUTSIDE, "a particle lies outside a periodic / shear box axis");
@@ -861,6 +862,67 @@ int rb_batch_step(rb_ctx *c, rb_particles *p, double t, double dt, int32_t nstep
   if (!c->batch) return fail(RB_EINVAL, "not a batch context");
   RB_TRY(check_particles(p, true));
   return run_step(c, p, t, dt, nsteps);
+}
+
+int rb_collide(rb_ctx *c, rb_particles *p, const double *radius, int64_t n, double t,
+               double epsilon, uint64_t seed, int64_t *n_pairs, int64_t *n_resolved,
+               uint64_t *codes, int64_t codes_cap) {
+  if (!c) return fail(RB_EINVAL, "null context");
+  RB_TRY(check_particles(p, true));
+  if (!radius) return fail(RB_EINVAL, "null radius array");
+  if (!isfinite(t)) return fail(RB_EINVAL, "t must be finite");
+  if (!(epsilon >= 0.0 && epsilon <= 1.0)) return fail(RB_EINVAL, "epsilon outside [0, 1]");
+  if (codes_cap < 0 || (codes_cap > 0 && !codes)) return fail(RB_EINVAL, "bad code buffer");
+  if (c->batch) {
+    if (n != (int64_t)c->h_starts[c->P]) return fail(RB_EINVAL, "n must be the batch total");
+  } else {
+    RB_TRY(set_single_n(c, n, n));
+  }
+  if (c->cap >= (1ull << 28)) return fail(RB_EUNSUPPORTED, "pair codes need n < 2^28");
+  if (!c->d_cq[0]) {
+    c->cq_cap = 8 * c->cap + 1024;
+    RB_TRY(dalloc(c, &c->d_cq[0], c->cq_cap));
+    RB_TRY(dalloc(c, &c->d_cq[1], c->cq_cap));
+    RB_TRY(dalloc(c, &c->d_ccnt, 4));
+    RB_TRY(dalloc(c, &c->d_cbest, c->cap));
+    RB_TRY(dalloc(c, &c->d_cmax, 1));
+    RB_TRY(dalloc(c, &c->d_cres, 1));
+    RB_HIP(hipMemsetAsync(c->d_cbest, 0xFF, 8 * c->cap, c->stream));
+  }
+  RB_HIP(hipMemsetAsync(c->d_ccnt, 0, 16, c->stream));
+  RB_HIP(hipMemsetAsync(c->d_cmax, 0, 8, c->stream));
+  RB_HIP(hipMemsetAsync(c->d_cres, 0, 8, c->stream));
+  RB_TRY(mark(c, PH_TOTAL, true));
+  RB_PHASE(PH_KEYS, launch_keys(c, p->x, p->y, p->z, 0.0));
+  RB_PHASE(PH_SORT, launch_sort(c));
+  RB_PHASE(PH_PERMUTE, launch_permute_gravity(c, p->x, p->y, p->z, p->m, 0));
+  RB_PHASE(PH_TOPO, launch_topology(c));
+  RB_PHASE(PH_COLLIDE, launch_coll_detect(c, radius, t));
+  uint32_t cnt = 0;
+  RB_HIP(hipMemcpyAsync(&cnt, c->d_ccnt, 4, hipMemcpyDeviceToHost, c->stream));
+  RB_HIP(hipStreamSynchronize(c->stream));
+  RB_TRY(report_device_errors(c));
+  const uint32_t pairs = cnt;
+  if (codes_cap > 0 && pairs > 0)
+    RB_HIP(hipMemcpy(codes, c->d_cq[0], 8 * (size_t)std::min<int64_t>(pairs, codes_cap),
+                     hipMemcpyDeviceToHost));
+  // rounds: each resolves at least the collision first in the whole queue
+  int a = 0;
+  for (uint32_t round = 0; cnt > 0; ++round) {
+    if (round > pairs) return fail(RB_EHIP, "collision rounds did not finish (internal error)");
+    RB_HIP(hipMemsetAsync(c->d_ccnt + (1 - a), 0, 4, c->stream));
+    RB_PHASE(PH_COLLIDE, launch_coll_round(c, a, p, t, epsilon, seed, cnt));
+    RB_HIP(hipMemcpyAsync(&cnt, c->d_ccnt + (1 - a), 4, hipMemcpyDeviceToHost, c->stream));
+    RB_HIP(hipStreamSynchronize(c->stream));
+    a = 1 - a;
+  }
+  unsigned long long res = 0;
+  RB_HIP(hipMemcpyAsync(&res, c->d_cres, 8, hipMemcpyDeviceToHost, c->stream));
+  RB_TRY(mark(c, PH_TOTAL, false));
+  RB_HIP(hipStreamSynchronize(c->stream));
+  if (n_pairs) *n_pairs = (int64_t)pairs;
+  if (n_resolved) *n_resolved = (int64_t)res;
+  return report_device_errors(c);
 }
 
 int rb_sync(rb_ctx *c) {

@@ -23,6 +23,7 @@ enum : uint32_t {
   RB_ERR_TREE = 8u,     // inconsistent node links (guarded, never followed)
   RB_ERR_INDEX = 16u,   // a target index outside [0, n)
   RB_ERR_SORT = 32u,    // a sort look-back wait gave up (result invalid)
+  RB_ERR_COLL = 64u,    // collision queue full
 };
 
 // Walk link of a node: child_or_first = first child (internal) or first

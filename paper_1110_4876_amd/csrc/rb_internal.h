@@ -111,6 +111,15 @@ struct rb_ctx {
   uint32_t *d_large = nullptr;      // nodes with more than G particles, by level
   uint32_t *d_bottom = nullptr;     // those without such a child (not in d_large)
   uint32_t *d_large_cnt = nullptr;  // per-level counts, then the bottom count
+  // collisions (allocated by the first rb_collide): two code lists (the
+  // detected pairs, then the survivors of each resolution round), their
+  // counts, each particle's smallest pending queue key, R_max, resolved
+  uint64_t *d_cq[2] = {nullptr, nullptr};
+  uint64_t cq_cap = 0;
+  uint32_t *d_ccnt = nullptr;
+  unsigned long long *d_cbest = nullptr;
+  unsigned long long *d_cmax = nullptr;
+  unsigned long long *d_cres = nullptr;
   double *d_acc = nullptr;          // (n_img or 1) * 3 * cap
 
   // per-call dynamic region [ctr | StepConst | schedule], uploaded from a
@@ -149,6 +158,9 @@ struct rb_ctx {
 hipError_t launch_keys(rb_ctx *c, const double *x, const double *y, const double *z,
                        double s_unused);
 hipError_t launch_sort(rb_ctx *c);
+hipError_t launch_coll_detect(rb_ctx *c, const double *radius, double t);
+hipError_t launch_coll_round(rb_ctx *c, int a, const rb_particles *pp, double t, double eps,
+                             uint64_t seed, uint32_t count);
 hipError_t launch_bsort(rb_ctx *c);
 hipError_t launch_permute_state(rb_ctx *c, int src, int dst);
 hipError_t launch_permute_gravity(rb_ctx *c, const double *x, const double *y,

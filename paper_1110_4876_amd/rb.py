@@ -23,7 +23,7 @@ RB_FP64, RB_FP32_MIXED = 0, 1
 RB_DRIFT_LEAPFROG, RB_DRIFT_EPICYCLE = 0, 1
 
 PHASES = ["keys", "sort", "permute", "topology", "moments", "walk", "kick_drift", "direct",
-          "total"]
+          "collide", "total"]
 
 
 class rb_params(ctypes.Structure):
@@ -115,6 +115,11 @@ _SIGS = {
     "rb_state_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rb_particles),
                                      ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
                                      ctypes.c_char_p]),
+    "rb_collide": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rb_particles), ctypes.c_void_p,
+                                  ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_uint64, ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p,
+                                  ctypes.c_int64]),
     "rb_error_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rb_last_error": (ctypes.c_char_p, []),
 }
@@ -303,3 +308,19 @@ def rb_error_string(code: int) -> str:
 
 def rb_last_error() -> str:
     return lib().rb_last_error().decode()
+
+
+def rb_collide(ctx, parts, radius, n: int, t: float, epsilon: float, seed: int,
+               codes=None):
+    """Collisions at time t (rb.h); velocities of `parts` change in place.
+    radius: device tensor (caller order).  codes: optional numpy uint64 array
+    that receives the detected pair codes (unordered).  Returns
+    (pairs, resolved)."""
+    npairs, nres = ctypes.c_int64(0), ctypes.c_int64(0)
+    cptr, ccap = None, 0
+    if codes is not None:
+        cptr, ccap = codes.ctypes.data_as(ctypes.c_void_p), len(codes)
+    check(lib().rb_collide(ctx, ctypes.byref(parts), ctypes.c_void_p(_ptr(radius)), int(n),
+                           float(t), float(epsilon), ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF),
+                           ctypes.byref(npairs), ctypes.byref(nres), cptr, ccap), "rb_collide")
+    return int(npairs.value), int(nres.value)
