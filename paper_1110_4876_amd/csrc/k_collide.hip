@@ -4,13 +4,16 @@
 // with a normal coefficient of restitution, one collision after the other in
 // queue order.
 //
-// Detection: one thread per live particle i (Morton order) and ghost image
-// o_k walks the tree with the child / skip links of the topology; it descends
-// into a cell while the distance from x_i to the image-shifted cell centre is
-// below R_i + R_max + (sqrt 3 / 2) w (every particle of the cell that could
-// overlap i passes this test, so the search finds every overlap).  In a leaf,
-// j overlaps i when |x_j + o_k - x_i| < R_i + R_j; the pair is queued once,
-// from its lower caller index i, as the code i 2^35 + j 2^7 + k.
+// Detection: the criterion of Eq. (3) opens a cell for particle i while the
+// distance from x_i to the image-shifted cell centre is below R_i + R_max +
+// (sqrt 3 / 2) w; every particle of the cell that could overlap i passes it,
+// so the search finds every overlap.  One wave searches for the (up to 64)
+// Morton-consecutive particles of a work item at once: a cell is opened when
+// it is within R_g + R_max + (sqrt 3 / 2) w of the item's bounding box (R_g
+// the item's largest radius), which holds whenever it holds for any member.
+// Opened leaves go to an LDS list that every lane then tests against its own
+// particle: j overlaps i when |x_j + o_k - x_i| < R_i + R_j; the pair is
+// queued once, from its lower caller index i, as the code i 2^35 + j 2^7 + k.
 //
 // Order and resolution: the queue's order is ascending h = splitmix64(seed +
 // code) (a bijection, so the order is total).  Resolving collisions one after
@@ -70,98 +73,185 @@ __global__ __launch_bounds__(256) void k_coll_rmax(const double *__restrict__ R,
   if (rb_lane() == 0 && r > 0.0) atomicMax(rmax, (unsigned long long)__double_as_longlong(r));
 }
 
+// order a wave's LDS writes before its later reads (a wave runs in lockstep)
+__device__ __forceinline__ void coll_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+#define CG_SCAP 1024  // traversal stack entries per wave (node << 5 | image)
+#define CG_RESERVE (7 * RB_DEPTH + 8)
+#define CG_LL 128     // opened-leaf list capacity per wave (tested at >= 64)
+
+__device__ __forceinline__ double rb_wave_min_d(double v) {
+  for (int d = 32; d >= 1; d >>= 1) v = fmin(v, __shfl_xor(v, d, 64));
+  return v;
+}
+__device__ __forceinline__ double rb_wave_max_d(double v) {
+  for (int d = 32; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
+  return v;
+}
+
+// queue a pair from the lane's local list, writing the list out when full
+__device__ __forceinline__ void rb_coll_keep(uint64_t code, uint64_t (&mine)[RB_COLL_LOCAL],
+                                             uint32_t &nm, uint64_t *__restrict__ queue,
+                                             uint32_t qcap, uint32_t *__restrict__ qcnt,
+                                             uint32_t *__restrict__ err) {
+  if (nm == RB_COLL_LOCAL) {
+    const uint32_t at = atomicAdd(qcnt, (uint32_t)nm);
+    for (uint32_t q = 0; q < nm; ++q)
+      if (at + q < qcap) queue[at + q] = mine[q];
+    if (at + nm > qcap) atomicOr(err, RB_ERR_COLL);
+    nm = 0;
+  }
+  mine[nm++] = code;
+}
+
+// One wave per work item (consecutive sibling subtrees of at most
+// group_size particles), four waves per workgroup, items strided over the
+// grid.
 __global__ __launch_bounds__(256) void k_coll_detect(
-    const double *__restrict__ sx, const double *__restrict__ sy, const double *__restrict__ sz,
+    const WalkItem *__restrict__ items, const WalkItem *__restrict__ items_mid,
+    const uint32_t *__restrict__ gctr, uint64_t cap, const double *__restrict__ sx,
+    const double *__restrict__ sy, const double *__restrict__ sz,
     const uint32_t *__restrict__ orig, const double *__restrict__ R,
     const PatchInfo *__restrict__ patch, const uint32_t *__restrict__ starts,
     const uint32_t *__restrict__ nlive, const uint32_t *__restrict__ root,
     const uint32_t *__restrict__ nfirst, const uint32_t *__restrict__ nlast,
-    const uint32_t *__restrict__ nchild, const uint32_t *__restrict__ nskip,
-    const uint8_t *__restrict__ nlevel, const uint8_t *__restrict__ nleaf, uint32_t P,
-    uint32_t n, int ngx, int ngy, int boundary, double omega, double t,
-    const unsigned long long *__restrict__ rmax_bits, uint64_t *__restrict__ queue,
-    uint32_t qcap, uint32_t *__restrict__ qcnt, uint32_t *__restrict__ err) {
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  uint64_t mine[RB_COLL_LOCAL];
-  uint32_t nm = 0;
-  bool live = false;
-  if (s < n) {
-    const uint32_t p = (P == 1) ? 0u : rb_patch_of(starts, P, s);
-    live = s - starts[p] < nlive[p];
-    if (live) {
-      const PatchInfo pi = patch[p];
-      const double W = pi.W;
-      const double sh = (boundary == RB_SHEAR) ? remainder(1.5 * omega * W * t, W) : 0.0;
-      const double xi = sx[s], yi = sy[s], zi = sz[s];
-      const uint32_t oi = orig[s];
-      const double Ri = R[oi];
-      const double reach = Ri + __longlong_as_double((long long)rmax_bits[0]);
-      const double hd = 0.8660254037844386;  // half the diagonal of a unit cube
-      const int n_img = (boundary == RB_OPEN) ? 1 : (2 * ngx + 1) * (2 * ngy + 1);
-      for (int k = 0; k < n_img; ++k) {
-        double ox, oy, wy;
-        rb_coll_image(k, ngx, ngy, boundary, W, sh, omega, ox, oy, wy);
-        const bool self_img = ox == 0.0 && oy == 0.0;
-        uint32_t node = root[p];
-        while (node != RB_NONE) {
-          const int l = nlevel[node];
-          const double w = ldexp(W, -l);
-          // centre of the cell: the level-l cell of its first particle
-          const uint32_t f = nfirst[node];
-          uint32_t qx = 0, qy = 0, qz = 0;
-          (void)rb_quantise(sx[f], pi.x0[0], W, pi.S, qx);
-          (void)rb_quantise(sy[f], pi.x0[1], W, pi.S, qy);
-          (void)rb_quantise(sz[f], pi.x0[2], W, pi.S, qz);
-          const int sft = RB_DEPTH - l;
-          const double cx = pi.x0[0] + ((double)(qx >> sft) + 0.5) * w + ox;
-          const double cy = pi.x0[1] + ((double)(qy >> sft) + 0.5) * w + oy;
-          const double cz = pi.x0[2] + ((double)(qz >> sft) + 0.5) * w;
-          const double ex = cx - xi, ey = cy - yi, ez = cz - zi;
-          const double lim = (reach + hd * w) * (1.0 + 1e-9);
-          if (!(ex * ex + ey * ey + ez * ez < lim * lim)) {
-            node = nskip[node];
-            continue;
-          }
-          if (!nleaf[node]) {
-            node = nchild[node];
-            continue;
-          }
+    const uint32_t *__restrict__ nchild, const uint32_t *__restrict__ nlastchild,
+    const uint8_t *__restrict__ nlevel, const uint8_t *__restrict__ nleaf, int ngx, int ngy,
+    int boundary, double omega, double t, const unsigned long long *__restrict__ rmax_bits,
+    uint64_t *__restrict__ queue, uint32_t qcap, uint32_t *__restrict__ qcnt,
+    uint32_t *__restrict__ err) {
+  __shared__ uint32_t stk_all[4][CG_SCAP];
+  __shared__ uint32_t leaf_all[4][CG_LL];
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  uint32_t *stk = stk_all[wv];
+  uint32_t *lf = leaf_all[wv];
+  const uint32_t n_big = gctr[2], n_mid = gctr[3], n_items = n_big + n_mid + gctr[4];
+  for (uint32_t item = 4u * blockIdx.x + wv; item < n_items; item += 4u * gridDim.x) {
+    const WalkItem it = rb_walk_item(items, items_mid, item, n_big, n_mid, cap);
+    const uint32_t p = it.patch, st = starts[p];
+    const uint32_t s = it.start + lane;
+    const bool act = s < it.end && it.end - it.start <= 64u && s - st < nlive[p];
+    if (!__ballot(act)) continue;
+    const PatchInfo pi = patch[p];
+    const double W = pi.W;
+    const double sh = (boundary == RB_SHEAR) ? remainder(1.5 * omega * W * t, W) : 0.0;
+    const double xi = act ? sx[s] : 0.0, yi = act ? sy[s] : 0.0, zi = act ? sz[s] : 0.0;
+    const uint32_t oi = act ? orig[s] : 0u;
+    const double Ri = act ? R[oi] : 0.0;
+    const double lx = rb_wave_min_d(act ? xi : INFINITY);
+    const double hx = rb_wave_max_d(act ? xi : -INFINITY);
+    const double ly = rb_wave_min_d(act ? yi : INFINITY);
+    const double hy = rb_wave_max_d(act ? yi : -INFINITY);
+    const double lz = rb_wave_min_d(act ? zi : INFINITY);
+    const double hz = rb_wave_max_d(act ? zi : -INFINITY);
+    const double Rg = rb_wave_max_d(act ? Ri : 0.0);
+    const double reach = Rg + __longlong_as_double((long long)rmax_bits[0]);
+    const double hd = 0.8660254037844386;  // half the diagonal of a unit cube
+    const int n_img = (boundary == RB_OPEN) ? 1 : (2 * ngx + 1) * (2 * ngy + 1);
+    uint64_t mine[RB_COLL_LOCAL];
+    uint32_t nm = 0;
+    int sp = 0;
+    for (int k = lane; k < n_img; k += 64) stk[k] = (root[p] << 5) | (uint32_t)k;
+    sp = n_img;
+    int nl = 0;
+    coll_wave_sync();
+    for (;;) {
+      int T = sp < 64 ? sp : 64;
+      if (sp + 7 * T > CG_SCAP - CG_RESERVE) {
+        T = (CG_SCAP - CG_RESERVE - sp) / 7;
+        if (T < 1) T = (sp > 0) ? 1 : 0;
+      }
+      // test the opened leaves against the lanes' particles
+      if (nl >= 64 || (T == 0 && nl > 0)) {
+        for (int q = 0; q < nl; ++q) {
+          const uint32_t en = lf[q];
+          const uint32_t node = en >> 5;
+          const int k = (int)(en & 31u);
+          double ox, oy, wy;
+          rb_coll_image(k, ngx, ngy, boundary, W, sh, omega, ox, oy, wy);
+          const bool self_img = ox == 0.0 && oy == 0.0;
           const uint32_t jl = nlast[node];
-          for (uint32_t j = f; j <= jl; ++j) {
-            if (j == s && self_img) continue;
+          for (uint32_t j = nfirst[node]; j <= jl; ++j) {
             const uint32_t oj = orig[j];
-            if (oi >= oj) continue;  // queued from the lower caller index
+            if (!act || (j == s && self_img) || oi >= oj) continue;
             const double d0 = (sx[j] + ox) - xi;
             const double d1 = (sy[j] + oy) - yi;
             const double d2 = (sz[j] + 0.0) - zi;
             const double sum = Ri + R[oj];
-            if (d0 * d0 + d1 * d1 + d2 * d2 < sum * sum) {
-              const uint64_t code = ((uint64_t)oi << 35) | ((uint64_t)oj << 7) | (uint64_t)k;
-              if (nm == RB_COLL_LOCAL) {  // write out the full local list
-                const uint32_t at = atomicAdd(qcnt, (uint32_t)nm);
-                for (uint32_t q = 0; q < nm; ++q)
-                  if (at + q < qcap) queue[at + q] = mine[q];
-                if (at + nm > qcap) atomicOr(err, RB_ERR_COLL);
-                nm = 0;
-              }
-              mine[nm++] = code;
-            }
+            if (d0 * d0 + d1 * d1 + d2 * d2 < sum * sum)
+              rb_coll_keep(((uint64_t)oi << 35) | ((uint64_t)oj << 7) | (uint64_t)k, mine, nm,
+                           queue, qcap, qcnt, err);
           }
-          node = nskip[node];
+        }
+        nl = 0;
+      }
+      if (T == 0) break;  // uniform
+      const int base = sp - T;
+      const bool has = (int)lane < T;
+      const uint32_t e = has ? stk[base + (int)lane] : 0u;
+      coll_wave_sync();
+      sp = base;
+      bool open = false, leaf = false;
+      uint32_t c0 = 0, nc = 0;
+      if (has) {
+        const uint32_t node = e >> 5;
+        const int k = (int)(e & 31u);
+        double ox, oy, wy;
+        rb_coll_image(k, ngx, ngy, boundary, W, sh, omega, ox, oy, wy);
+        const int l = nlevel[node];
+        const double w = ldexp(W, -l);
+        const uint32_t f = nfirst[node];
+        uint32_t qx = 0, qy = 0, qz = 0;
+        (void)rb_quantise(sx[f], pi.x0[0], W, pi.S, qx);
+        (void)rb_quantise(sy[f], pi.x0[1], W, pi.S, qy);
+        (void)rb_quantise(sz[f], pi.x0[2], W, pi.S, qz);
+        const int sft = RB_DEPTH - l;
+        const double cx = pi.x0[0] + ((double)(qx >> sft) + 0.5) * w + ox;
+        const double cy = pi.x0[1] + ((double)(qy >> sft) + 0.5) * w + oy;
+        const double cz = pi.x0[2] + ((double)(qz >> sft) + 0.5) * w;
+        const double dx = fmax(fmax(lx - cx, cx - hx), 0.0);
+        const double dy = fmax(fmax(ly - cy, cy - hy), 0.0);
+        const double dz = fmax(fmax(lz - cz, cz - hz), 0.0);
+        const double lim = (reach + hd * w) * (1.0 + 1e-9);
+        open = dx * dx + dy * dy + dz * dz < lim * lim;
+        leaf = nleaf[node] != 0;
+        if (open && !leaf) {
+          c0 = nchild[node];
+          const uint32_t c1 = nlastchild[node];
+          nc = (c1 >= c0 && c1 - c0 < 8) ? c1 - c0 + 1 : 0;
+          if (c1 < c0 || c1 - c0 >= 8) atomicOr(err, RB_ERR_TREE);
         }
       }
+      // opened internal nodes push their children, opened leaves join the list
+      const uint32_t incl = rb_wave_incl_scan(nc);
+      const uint32_t tot = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl(incl, 63, 64));
+      if (sp + (int)tot > CG_SCAP) {  // cannot happen with the reserve above
+        if (lane == 0) atomicOr(err, RB_ERR_STACK);
+        break;
+      }
+      for (uint32_t q = 0; q < nc; ++q)
+        stk[sp + (int)(incl - nc + q)] = ((c0 + q) << 5) | (e & 31u);
+      sp += (int)tot;
+      const uint64_t lm = __ballot(open && leaf);
+      if (open && leaf) lf[nl + (int)rb_mbcnt(lm)] = e;
+      nl += __popcll(lm);
+      coll_wave_sync();
     }
+    // the rest: one atomic per wave
+    const uint32_t incl = rb_wave_incl_scan(nm);
+    const uint32_t tot = __shfl(incl, 63, 64);
+    uint32_t qbase = 0;
+    if (lane == 63 && tot) qbase = atomicAdd(qcnt, tot);
+    qbase = __shfl(qbase, 63, 64);
+    const uint32_t at = qbase + incl - nm;
+    for (uint32_t q = 0; q < nm; ++q)
+      if (at + q < qcap) queue[at + q] = mine[q];
+    if (nm && at + nm > qcap) atomicOr(err, RB_ERR_COLL);
   }
-  // the rest: one atomic per wave
-  const uint32_t incl = rb_wave_incl_scan(nm);
-  const uint32_t tot = __shfl(incl, 63, 64);
-  uint32_t base = 0;
-  if (rb_lane() == 63 && tot) base = atomicAdd(qcnt, tot);
-  base = __shfl(base, 63, 64);
-  const uint32_t at = base + incl - nm;
-  for (uint32_t q = 0; q < nm; ++q)
-    if (at + q < qcap) queue[at + q] = mine[q];
-  if (nm && at + nm > qcap) atomicOr(err, RB_ERR_COLL);
 }
 
 // round, step 1: every particle learns the smallest h among its unresolved
@@ -254,12 +344,17 @@ hipError_t launch_coll_detect(rb_ctx *c, const double *radius, double t) {
   const unsigned grid = rb_div_up(n, 256);
   hipLaunchKernelGGL(k_coll_rmax, dim3(grid), dim3(256), 0, c->stream, radius, c->d_orig[0],
                      c->d_starts, c->d_nlive, c->P, n, c->d_cmax);
-  hipLaunchKernelGGL(k_coll_detect, dim3(grid), dim3(256), 0, c->stream, c->d_px[0][0],
-                     c->d_px[0][1], c->d_px[0][2], c->d_orig[0], radius, c->d_patch,
-                     c->d_starts, c->d_nlive, c->d_root, c->d_nfirst, c->d_nlast, c->d_nchild,
-                     c->d_nskip, c->d_nlevel, c->d_nleaf, c->P, n, c->p.n_ghost[0],
-                     c->p.n_ghost[1], c->p.boundary, c->p.omega, t, c->d_cmax, c->d_cq[0],
-                     (uint32_t)c->cq_cap, c->d_ccnt, c->d_err);
+  hipError_t e = launch_groups(c);
+  if (e != hipSuccess) return e;
+  unsigned ggrid = rb_div_up(n, 64);
+  if (ggrid > 2048) ggrid = 2048;
+  hipLaunchKernelGGL(k_coll_detect, dim3(ggrid), dim3(256), 0, c->stream, c->d_witems,
+                     c->d_witems_mid, c->d_gctr, c->cap, c->d_px[0][0], c->d_px[0][1],
+                     c->d_px[0][2],
+                     c->d_orig[0], radius, c->d_patch, c->d_starts, c->d_nlive, c->d_root,
+                     c->d_nfirst, c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nlevel,
+                     c->d_nleaf, c->p.n_ghost[0], c->p.n_ghost[1], c->p.boundary, c->p.omega,
+                     t, c->d_cmax, c->d_cq[0], (uint32_t)c->cq_cap, c->d_ccnt, c->d_err);
   return hipGetLastError();
 }
 

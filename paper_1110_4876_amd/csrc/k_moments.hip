@@ -714,18 +714,25 @@ __global__ __launch_bounds__(256) void k_moments_large_level(
     rb_node_moments(large[base + i], l, clo, chi, RB_MOMENT_ARGS);
 }
 
+// the work items and large-node lists of the current tree (k_groups)
+hipError_t launch_groups(rb_ctx *c) {
+  unsigned grid = rb_div_up(c->node_cap, 256);
+  if (grid > 2048) grid = 2048;
+  hipLaunchKernelGGL(k_groups, dim3(grid), dim3(256), 0, c->stream, c->d_lev_off, c->d_nfirst,
+                     c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nleaf, c->d_nlevel,
+                     c->d_starts, c->P, (uint32_t)c->p.group_size, c->d_witems,
+                     c->d_witems_mid, (uint32_t)c->cap, c->d_gctr, c->d_large, c->d_bottom,
+                     c->d_large_cnt);
+  return hipGetLastError();
+}
+
 hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const double *sz) {
   const uint32_t n = (uint32_t)c->h_starts[c->P];
   if (n == 0) return hipSuccess;
   const uint32_t G = (uint32_t)c->p.group_size;
   // the grouped walk's node records are written only when it will run
   WNode *const wnode = c->p.precision == RB_FP32_MIXED ? c->d_wnode : nullptr;
-  unsigned grid = rb_div_up(c->node_cap, 256);
-  if (grid > 2048) grid = 2048;
-  hipLaunchKernelGGL(k_groups, dim3(grid), dim3(256), 0, c->stream, c->d_lev_off, c->d_nfirst,
-                     c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nleaf, c->d_nlevel,
-                     c->d_starts, c->P, G, c->d_witems, c->d_witems_mid, (uint32_t)c->cap,
-                     c->d_gctr, c->d_large, c->d_bottom, c->d_large_cnt);
+  (void)launch_groups(c);
 #define RB_MARGS                                                                          \
   c->d_nfirst, c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nskip, c->d_nleaf, sx, sy, sz, \
       c->d_msrc, c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, wnode,              \

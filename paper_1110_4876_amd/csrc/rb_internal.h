@@ -158,6 +158,7 @@ struct rb_ctx {
 hipError_t launch_keys(rb_ctx *c, const double *x, const double *y, const double *z,
                        double s_unused);
 hipError_t launch_sort(rb_ctx *c);
+hipError_t launch_groups(rb_ctx *c);
 hipError_t launch_coll_detect(rb_ctx *c, const double *radius, double t);
 hipError_t launch_coll_round(rb_ctx *c, int a, const rb_particles *pp, double t, double eps,
                              uint64_t seed, uint32_t count);

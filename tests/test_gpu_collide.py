@@ -147,3 +147,34 @@ def test_batch_patches_match_oracle(orc):
             assert abs(after - before) <= 1e-9 * (np.abs(pr.m * getattr(pr, k)).sum() + 1e-30)
         off += pr.n
     assert nres > 0
+
+
+def test_c1_full_size_after_steps(orc):
+    # the 50,000-particle sheet after 20 FP32-mixed steps on the GPU: the
+    # pair set, the resolved count and the velocities equal the oracle's on
+    # the same state (brute-force detection, one-by-one resolution)
+    from gpu_util import dev
+    from paper_1110_4876_amd import rb
+    from paper_1110_4876_amd.system import System
+    pr = inputs.sheet(50000, seed=0)
+    R = pr.extra["radius"]
+    sysm = System(pr)
+    ctx = sysm.create(rb.RB_FP32_MIXED, theta=0.42, group_size=64, walk_waves=4)
+    try:
+        X = sysm.clone()
+        sysm.step(ctx, X, 0.0, 20)
+        rb.rb_sync(ctx)
+        t = 20 * pr.dt
+        host = {k: X[k].cpu().numpy().copy() for k in ("x", "y", "z", "vx", "vy", "vz")}
+        codes = np.zeros(16 * pr.n, dtype=np.uint64)
+        npair, nres = rb.rb_collide(ctx, sysm.parts(X), dev(R), pr.n, t, 0.5, 2024, codes)
+        rb.rb_sync(ctx)
+        got = {k: X[k].cpu().numpy() for k in ("vx", "vy", "vz")}
+    finally:
+        rb.rb_destroy(ctx)
+    p = orc.make_params(**pr.params)
+    oc, onp, onr, ost = orc.collide(p, host, pr.m, R, t, 0.5, 2024)
+    assert npair == onp and nres == onr and npair > 1000
+    np.testing.assert_array_equal(np.sort(codes[:npair]), np.sort(oc))
+    for k in ("vx", "vy", "vz"):
+        assert np.abs(got[k] - ost[k]).max() <= 1e-13 * np.abs(ost[k]).max(), k
