@@ -185,6 +185,108 @@ def write_traffic(args):
     print(json.dumps(meta))
 
 
+def collide_run(args, sysm, wdesc):
+    """Collisional sheet: K steps, each one DKD step of FP32-mixed tree
+    gravity (rb_step) and then collisions at the end of the step
+    (rb_collide: tree build on the end-of-step positions, search of Eq. (3),
+    queue in random order, hard-sphere resolution with restitution), timed
+    after W such steps from the initial state, so that the initial overlaps
+    are gone; the search kernel is timed with HIP events on the context's
+    stream."""
+    import numpy as np
+    import torch
+    from paper_1110_4876_amd import autotune, rb
+    if sysm.batch or "radius" not in sysm.problems[0].extra:
+        raise SystemExit("--collide needs a single shearing-sheet workload with radii")
+    pr = sysm.problems[0]
+    n, dt = sysm.n, sysm.dt
+    if args.theta:
+        knobs = dict(theta=args.theta, leaf_size=args.leaf_size, group_size=args.group_size,
+                     split_images=args.split_images, walk_waves=args.walk_waves)
+    else:
+        t_kick = 0.5 * dt
+        tg = sysm.sample_targets(4096, 16, seed=0)
+        cfg = autotune.tune(sysm, sysm.direct(tg, t_kick), tg, t_kick,
+                            precision=rb.RB_FP32_MIXED, rms_target=RMS_TARGET, log=log)
+        knobs = {k: cfg[k] for k in KNOBS}
+    R = torch.as_tensor(pr.extra["radius"], dtype=torch.float64, device="cuda")
+    eps = args.epsilon
+    ctx = sysm.create(rb.RB_FP32_MIXED, profile=4, **knobs)
+    try:
+        X = sysm.clone()
+        for k in range(args.warmup):
+            sysm.step(ctx, X, k * dt, 1)
+            rb.rb_collide(ctx, sysm.parts(X), R, n, (k + 1) * dt, eps, 1000 + k)
+        rb.rb_sync(ctx)
+        rb.rb_stats(ctx)  # discard warm-up timers
+        pairs = resolved = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.warmup, args.warmup + args.steps):
+            sysm.step(ctx, X, k * dt, 1)
+            a, b = rb.rb_collide(ctx, sysm.parts(X), R, n, (k + 1) * dt, eps, 1000 + k)
+            pairs += a
+            resolved += b
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        s = rb.rb_stats(ctx)
+        n_nodes, n_live = rb.rb_tree_info(ctx)
+    finally:
+        rb.rb_destroy(ctx)
+    search_ms = s["ms"]["coll_search"] / max(1, s["calls"]["coll_search"])
+    walk_ms = s["ms"]["walk"] / max(1, s["calls"]["walk"])
+    # algorithmic bytes of one search: every live particle's position, radius
+    # and caller index read once (36 B), every cell record once (32 B), every
+    # found pair written once (8 B)
+    algo = 36 * n_live + 32 * n_nodes + 8 * pairs / args.steps
+    achieved = algo / (search_ms * 1e-3)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        op = oracle.make_params(**dict(pr.params, theta=knobs["theta"]))
+        st = pr.state()
+        radius = np.asarray(pr.extra["radius"], dtype=np.float64)
+        k, c0 = 0, time.perf_counter()
+        while True:
+            st = oracle.step(op, st, pr.m, k * dt, dt, 1, use_tree=True)
+            _, _, _, st = oracle.collide(op, st, pr.m, radius, (k + 1) * dt, eps, 1000 + k)
+            k += 1
+            if time.perf_counter() - c0 >= args.cpu_seconds:
+                break
+        cs = time.perf_counter() - c0
+        cpu = {"value": n * k / cs, "unit": "particle-steps/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"{k} collisional steps of the same {n}-particle sheet from the "
+                         f"initial state (oracle tree gravity at theta={knobs['theta']}, "
+                         f"brute-force overlap search, sequential queue)"}
+    out = {
+        "metric": "collisional-sheet particle-steps/s (FP32-mixed tree gravity DKD step + "
+                  "FP64 tree collision search and resolution)",
+        "value": n * args.steps / secs,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": wdesc + ", collisions at the end of every step, "
+                   f"epsilon={eps}", "n": n, "images": 9, **knobs},
+        "collisions": {"pairs_per_step": pairs / args.steps,
+                       "resolved_per_step": resolved / args.steps,
+                       "search_ms": search_ms, "walk_ms": walk_ms,
+                       "tree_nodes": n_nodes},
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": 8000.0,
+                     "unit": "GB/s", "frac": achieved / 8e12, "traffic": None,
+                     "kernel": "k_coll_detect"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +306,12 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the known-size "
                          "kernel that scales the HBM byte counters) and exit")
+    ap.add_argument("--collide", action="store_true",
+                    help="the collisional sheet instead: every step is a DKD step with "
+                         "FP32-mixed tree gravity followed by the tree collision search and "
+                         "hard-sphere resolution at the end of the step (own JSON line)")
+    ap.add_argument("--epsilon", type=float, default=0.5,
+                    help="coefficient of restitution of the collisional sheet")
     ap.add_argument("--write-traffic", nargs=4, default=None,
                     metavar=("COPY_FETCH", "COPY_WRITE", "WALK_FETCH", "WALK_WRITE"),
                     help="only turn four rocprofv3 --pmc output folders into the stored "
@@ -238,6 +346,9 @@ def main():
     prob, wdesc = workload(args.workload)
     sysm = System(prob)
     n = sysm.n
+    if args.collide:
+        collide_run(args, sysm, wdesc)
+        return
     t_kick = 0.5 * sysm.dt
     tg = sysm.sample_targets(4096, 16, seed=0)
     # reference: FP64 direct sum (Eq. 1 over all images) on the samples, for

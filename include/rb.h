@@ -82,7 +82,8 @@ typedef enum { RB_DRIFT_LEAPFROG = 0, RB_DRIFT_EPICYCLE = 1 } rb_drift;
  *  profile          bit 0: record per-phase times with HIP events on the
  *                   context's stream; bit 1: count walk interactions
  *                   (atomics in the walk); bit 2: time the walk kernel
- *                   only.  All are read by rb_stats.
+ *                   and the collision search kernel only.  All are read
+ *                   by rb_stats.
  *  use_graph        1: rb_step / rb_batch_step replay a captured HIP graph
  *                   of one step.
  *  walk_waves       FP32-mixed walk only: waves that share one group's
@@ -259,8 +260,10 @@ int rb_batch_gravity(rb_ctx *ctx, const rb_particles *p, double t, double *ax,
  *             particular order; NULL / 0 to skip).
  * For a batch context n is the total and pairs stay inside their patches.
  * Synchronises.  Errors: RB_EINVAL (null pointer, epsilon, n), RB_EUNSUPPORTED
- * (capacity >= 2^28), RB_ECAPACITY (more than 8 pairs per particle), and
- * the deferred errors of the tree build.
+ * (capacity >= 2^28, or node capacity >= 2^27), RB_ECAPACITY (more than 8
+ * pairs per particle), and the deferred errors of the tree build.  Phase
+ * times: "coll_search" is the search kernel, "collide" the rest (R_max, cell
+ * records, work items, resolution rounds).
  */
 int rb_collide(rb_ctx *ctx, rb_particles *p, const double *radius, int64_t n, double t,
                double epsilon, uint64_t seed, int64_t *n_pairs, int64_t *n_resolved,

@@ -53,24 +53,29 @@ __device__ __forceinline__ void rb_coll_image(int k, int ngx, int ngy, int bound
 }
 
 // largest radius of the live particles (as ordered bits of a non-negative
-// double)
+// double): slots strided over the grid, one atomic per workgroup
 __global__ __launch_bounds__(256) void k_coll_rmax(const double *__restrict__ R,
                                                    const uint32_t *__restrict__ orig,
                                                    const uint32_t *__restrict__ starts,
                                                    const uint32_t *__restrict__ nlive,
                                                    uint32_t P, uint32_t n,
                                                    unsigned long long *__restrict__ rmax) {
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double part[4];
   double r = 0.0;
-  if (s < n) {
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
     const uint32_t p = (P == 1) ? 0u : rb_patch_of(starts, P, s);
     if (s - starts[p] < nlive[p]) {
       const double v = R[orig[s]];
-      r = v > 0.0 ? v : 0.0;
+      r = v > r ? v : r;  // (a NaN radius is never larger)
     }
   }
   for (int d = 32; d >= 1; d >>= 1) r = fmax(r, __shfl_xor(r, d, 64));
-  if (rb_lane() == 0 && r > 0.0) atomicMax(rmax, (unsigned long long)__double_as_longlong(r));
+  if (rb_lane() == 0) part[threadIdx.x >> 6] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    r = fmax(fmax(part[0], part[1]), fmax(part[2], part[3]));
+    if (r > 0.0) atomicMax(rmax, (unsigned long long)__double_as_longlong(r));
+  }
 }
 
 // order a wave's LDS writes before its later reads (a wave runs in lockstep)
@@ -79,9 +84,12 @@ __device__ __forceinline__ void coll_wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-#define CG_SCAP 1024  // traversal stack entries per wave (node << 5 | image)
+#define CG_SCAP 768   // traversal stack entries per wave (node << 5 | image)
 #define CG_RESERVE (7 * RB_DEPTH + 8)
 #define CG_LL 128     // opened-leaf list capacity per wave (tested at >= 64)
+#ifndef CG_SUB
+#define CG_SUB 16     // particles one wave searches for (64 / CG_SUB lanes each)
+#endif
 
 __device__ __forceinline__ double rb_wave_min_d(double v) {
   for (int d = 32; d >= 1; d >>= 1) v = fmin(v, __shfl_xor(v, d, 64));
@@ -107,34 +115,97 @@ __device__ __forceinline__ void rb_coll_keep(uint64_t code, uint64_t (&mine)[RB_
   mine[nm++] = code;
 }
 
-// One wave per work item (consecutive sibling subtrees of at most
-// group_size particles), four waves per workgroup, items strided over the
-// grid.
-__global__ __launch_bounds__(256) void k_coll_detect(
+// The cell as the search reads it (one 32-byte record): the centre of the
+// cell in its own root box, a = first child (internal) or first slot (leaf),
+// b = leaf << 31 | level << 26 | (children - 1, or last slot - first slot).
+struct __align__(32) CollNode {
+  double cx, cy, cz;
+  uint32_t a, b;
+};
+
+// the cells' records, from the topology of the sorted particles
+__global__ __launch_bounds__(256) void k_coll_geom(
+    const double *__restrict__ sx, const double *__restrict__ sy, const double *__restrict__ sz,
+    const PatchInfo *__restrict__ patch, const uint32_t *__restrict__ starts, uint32_t P,
+    const uint32_t *__restrict__ lev_off, uint64_t node_cap,
+    const uint32_t *__restrict__ nfirst, const uint32_t *__restrict__ nlast,
+    const uint32_t *__restrict__ nchild, const uint32_t *__restrict__ nlastchild,
+    const uint8_t *__restrict__ nlevel, const uint8_t *__restrict__ nleaf,
+    CollNode *__restrict__ out, uint32_t *__restrict__ err) {
+  const uint32_t node = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t total = lev_off[RB_NLEV];
+  if (node >= total || node >= node_cap) return;
+  const uint32_t f = nfirst[node];
+  const uint32_t p = (P == 1) ? 0u : rb_patch_of(starts, P, f);
+  const PatchInfo pi = patch[p];
+  const int l = nlevel[node];
+  const double w = ldexp(pi.W, -l);
+  uint32_t qx = 0, qy = 0, qz = 0;
+  (void)rb_quantise(sx[f], pi.x0[0], pi.W, pi.S, qx);
+  (void)rb_quantise(sy[f], pi.x0[1], pi.W, pi.S, qy);
+  (void)rb_quantise(sz[f], pi.x0[2], pi.W, pi.S, qz);
+  const int sft = RB_DEPTH - l;
+  CollNode r;
+  r.cx = pi.x0[0] + ((double)(qx >> sft) + 0.5) * w;
+  r.cy = pi.x0[1] + ((double)(qy >> sft) + 0.5) * w;
+  r.cz = pi.x0[2] + ((double)(qz >> sft) + 0.5) * w;
+  if (nleaf[node]) {
+    const uint32_t span = nlast[node] - f;
+    if (nlast[node] < f || span >= (1u << 26)) atomicOr(err, RB_ERR_TREE);
+    r.a = f;
+    r.b = 0x80000000u | ((uint32_t)l << 26) | (span & ((1u << 26) - 1u));
+  } else {
+    const uint32_t c0 = nchild[node], c1 = nlastchild[node];
+    const bool ok = c1 >= c0 && c1 - c0 < 8;
+    if (!ok) atomicOr(err, RB_ERR_TREE);
+    r.a = c0;
+    // a broken range is treated as a childless cell (flagged above)
+    r.b = ((uint32_t)l << 26) | (ok ? c1 - c0 : 0u) | (ok ? 0u : 0x8u);
+  }
+  out[node] = r;
+}
+
+// One wave searches for CG_SUB particles of a work item (consecutive sibling
+// subtrees of at most group_size particles; an item is split into parts of
+// CG_SUB slots, one part per wave), 64 / CG_SUB lanes per particle.  Four
+// waves per workgroup, parts strided over the grid.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_coll_detect(
     const WalkItem *__restrict__ items, const WalkItem *__restrict__ items_mid,
     const uint32_t *__restrict__ gctr, uint64_t cap, const double *__restrict__ sx,
     const double *__restrict__ sy, const double *__restrict__ sz,
     const uint32_t *__restrict__ orig, const double *__restrict__ R,
     const PatchInfo *__restrict__ patch, const uint32_t *__restrict__ starts,
     const uint32_t *__restrict__ nlive, const uint32_t *__restrict__ root,
-    const uint32_t *__restrict__ nfirst, const uint32_t *__restrict__ nlast,
-    const uint32_t *__restrict__ nchild, const uint32_t *__restrict__ nlastchild,
-    const uint8_t *__restrict__ nlevel, const uint8_t *__restrict__ nleaf, int ngx, int ngy,
-    int boundary, double omega, double t, const unsigned long long *__restrict__ rmax_bits,
-    uint64_t *__restrict__ queue, uint32_t qcap, uint32_t *__restrict__ qcnt,
-    uint32_t *__restrict__ err) {
+    const CollNode *__restrict__ cells, int ngx, int ngy, int boundary, double omega, double t,
+    const unsigned long long *__restrict__ rmax_bits, uint64_t *__restrict__ queue,
+    uint32_t qcap, uint32_t *__restrict__ qcnt, uint32_t *__restrict__ err) {
+  constexpr uint32_t NS = 64 / CG_SUB;  // parts per item (items hold <= 64 slots)
   __shared__ uint32_t stk_all[4][CG_SCAP];
-  __shared__ uint32_t leaf_all[4][CG_LL];
+  __shared__ uint32_t lfa_all[4][CG_LL], lfb_all[4][CG_LL], lsc_all[4][64];
+  // staged candidates: image-shifted position, radius, caller index,
+  // slot << 1 | same-box flag, image
+  __shared__ double cx_all[4][64], cy_all[4][64], cz_all[4][64], cr_all[4][64];
+  __shared__ uint32_t co_all[4][64], cs_all[4][64];
+  __shared__ uint8_t ck_all[4][64];
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   uint32_t *stk = stk_all[wv];
-  uint32_t *lf = leaf_all[wv];
+  uint32_t *lfa = lfa_all[wv], *lfb = lfb_all[wv], *lsc = lsc_all[wv];
+  double *cx_ = cx_all[wv], *cy_ = cy_all[wv], *cz_ = cz_all[wv], *cr_ = cr_all[wv];
+  uint32_t *co_ = co_all[wv], *cs_ = cs_all[wv];
+  uint8_t *ck_ = ck_all[wv];
+  const uint32_t pidx = lane % CG_SUB, sub = lane / CG_SUB;
   const uint32_t n_big = gctr[2], n_mid = gctr[3], n_items = n_big + n_mid + gctr[4];
-  for (uint32_t item = 4u * blockIdx.x + wv; item < n_items; item += 4u * gridDim.x) {
-    const WalkItem it = rb_walk_item(items, items_mid, item, n_big, n_mid, cap);
+  const double rmax = __longlong_as_double((long long)rmax_bits[0]);
+  const double hd = 0.8660254037844386;  // half the diagonal of a unit cube
+  const int n_img = (boundary == RB_OPEN) ? 1 : (2 * ngx + 1) * (2 * ngy + 1);
+  for (uint32_t u = 4u * blockIdx.x + wv; u < n_items * NS; u += 4u * gridDim.x) {
+    const WalkItem it = rb_walk_item(items, items_mid, u / NS, n_big, n_mid, cap);
+    const uint32_t s0 = it.start + (u % NS) * CG_SUB;
+    if (s0 >= it.end || it.end - it.start > 64u) continue;  // uniform
     const uint32_t p = it.patch, st = starts[p];
-    const uint32_t s = it.start + lane;
-    const bool act = s < it.end && it.end - it.start <= 64u && s - st < nlive[p];
+    const uint32_t s = s0 + pidx;
+    const bool act = s < it.end && s - st < nlive[p];
     if (!__ballot(act)) continue;
     const PatchInfo pi = patch[p];
     const double W = pi.W;
@@ -148,15 +219,11 @@ __global__ __launch_bounds__(256) void k_coll_detect(
     const double hy = rb_wave_max_d(act ? yi : -INFINITY);
     const double lz = rb_wave_min_d(act ? zi : INFINITY);
     const double hz = rb_wave_max_d(act ? zi : -INFINITY);
-    const double Rg = rb_wave_max_d(act ? Ri : 0.0);
-    const double reach = Rg + __longlong_as_double((long long)rmax_bits[0]);
-    const double hd = 0.8660254037844386;  // half the diagonal of a unit cube
-    const int n_img = (boundary == RB_OPEN) ? 1 : (2 * ngx + 1) * (2 * ngy + 1);
+    const double reach = rb_wave_max_d(act ? Ri : 0.0) + rmax;
     uint64_t mine[RB_COLL_LOCAL];
     uint32_t nm = 0;
-    int sp = 0;
     for (int k = lane; k < n_img; k += 64) stk[k] = (root[p] << 5) | (uint32_t)k;
-    sp = n_img;
+    int sp = n_img;
     int nl = 0;
     coll_wave_sync();
     for (;;) {
@@ -165,26 +232,58 @@ __global__ __launch_bounds__(256) void k_coll_detect(
         T = (CG_SCAP - CG_RESERVE - sp) / 7;
         if (T < 1) T = (sp > 0) ? 1 : 0;
       }
-      // test the opened leaves against the lanes' particles
+      // test the opened leaves' particles against the lanes' particles: up
+      // to 64 leaves at a time, their particles staged in LDS 64 at a time
+      // (image-shifted, one load per lane), candidate q then tested by the
+      // lanes with sub = q mod (64 / CG_SUB)
       if (nl >= 64 || (T == 0 && nl > 0)) {
-        for (int q = 0; q < nl; ++q) {
-          const uint32_t en = lf[q];
-          const uint32_t node = en >> 5;
-          const int k = (int)(en & 31u);
-          double ox, oy, wy;
-          rb_coll_image(k, ngx, ngy, boundary, W, sh, omega, ox, oy, wy);
-          const bool self_img = ox == 0.0 && oy == 0.0;
-          const uint32_t jl = nlast[node];
-          for (uint32_t j = nfirst[node]; j <= jl; ++j) {
-            const uint32_t oj = orig[j];
-            if (!act || (j == s && self_img) || oi >= oj) continue;
-            const double d0 = (sx[j] + ox) - xi;
-            const double d1 = (sy[j] + oy) - yi;
-            const double d2 = (sz[j] + 0.0) - zi;
-            const double sum = Ri + R[oj];
-            if (d0 * d0 + d1 * d1 + d2 * d2 < sum * sum)
-              rb_coll_keep(((uint64_t)oi << 35) | ((uint64_t)oj << 7) | (uint64_t)k, mine, nm,
-                           queue, qcap, qcnt, err);
+        for (int lb = 0; lb < nl; lb += 64) {
+          const int L = min(64, nl - lb);
+          const uint32_t cntq = (int)lane < L ? (lfb[lb + (int)lane] >> 5) + 1u : 0u;
+          const uint32_t incl = rb_wave_incl_scan(cntq);
+          const uint32_t M =
+              (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl(incl, 63, 64));
+          lsc[lane] = incl;
+          coll_wave_sync();
+          for (uint32_t e0 = 0; e0 < M; e0 += 64) {
+            const uint32_t e = e0 + lane;
+            if (e < M) {
+              int lo = 0, hi = L - 1;  // first leaf whose inclusive count exceeds e
+              while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (lsc[mid] > e) hi = mid; else lo = mid + 1;
+              }
+              const uint32_t eb = lfb[lb + lo];
+              const uint32_t j = lfa[lb + lo] + (e - (lsc[lo] - ((eb >> 5) + 1u)));
+              const int k = (int)(eb & 31u);
+              double ox, oy, wy;
+              rb_coll_image(k, ngx, ngy, boundary, W, sh, omega, ox, oy, wy);
+              const uint32_t oj = orig[j];
+              cx_[lane] = sx[j] + ox;
+              cy_[lane] = sy[j] + oy;
+              cz_[lane] = sz[j] + 0.0;
+              cr_[lane] = R[oj];
+              co_[lane] = oj;
+              // the slot, flagged when the image is the box itself
+              cs_[lane] = (j << 1) | ((ox == 0.0 && oy == 0.0) ? 1u : 0u);
+              ck_[lane] = (uint8_t)k;
+            }
+            coll_wave_sync();
+            const int C = (int)min(64u, M - e0);
+            if (act) {
+              for (int q = (int)sub; q < C; q += (int)NS) {
+                const uint32_t oj = co_[q], sj = cs_[q];
+                if (((sj & 1u) && (sj >> 1) == s) || oi >= oj) continue;
+                const double d0 = cx_[q] - xi;
+                const double d1 = cy_[q] - yi;
+                const double d2 = cz_[q] - zi;
+                const double sum = Ri + cr_[q];
+                if (d0 * d0 + d1 * d1 + d2 * d2 < sum * sum)
+                  rb_coll_keep(((uint64_t)oi << 35) | ((uint64_t)oj << 7) | (uint64_t)ck_[q],
+                               mine, nm, queue, qcap, qcnt, err);
+              }
+            }
+            coll_wave_sync();
           }
         }
         nl = 0;
@@ -196,35 +295,25 @@ __global__ __launch_bounds__(256) void k_coll_detect(
       coll_wave_sync();
       sp = base;
       bool open = false, leaf = false;
-      uint32_t c0 = 0, nc = 0;
+      uint32_t c0 = 0, nc = 0, span = 0;
       if (has) {
-        const uint32_t node = e >> 5;
+        const CollNode cn = cells[e >> 5];
         const int k = (int)(e & 31u);
         double ox, oy, wy;
         rb_coll_image(k, ngx, ngy, boundary, W, sh, omega, ox, oy, wy);
-        const int l = nlevel[node];
+        const int l = (int)((cn.b >> 26) & 31u);
         const double w = ldexp(W, -l);
-        const uint32_t f = nfirst[node];
-        uint32_t qx = 0, qy = 0, qz = 0;
-        (void)rb_quantise(sx[f], pi.x0[0], W, pi.S, qx);
-        (void)rb_quantise(sy[f], pi.x0[1], W, pi.S, qy);
-        (void)rb_quantise(sz[f], pi.x0[2], W, pi.S, qz);
-        const int sft = RB_DEPTH - l;
-        const double cx = pi.x0[0] + ((double)(qx >> sft) + 0.5) * w + ox;
-        const double cy = pi.x0[1] + ((double)(qy >> sft) + 0.5) * w + oy;
-        const double cz = pi.x0[2] + ((double)(qz >> sft) + 0.5) * w;
+        const double cx = cn.cx + ox, cy = cn.cy + oy, cz = cn.cz;
         const double dx = fmax(fmax(lx - cx, cx - hx), 0.0);
         const double dy = fmax(fmax(ly - cy, cy - hy), 0.0);
         const double dz = fmax(fmax(lz - cz, cz - hz), 0.0);
         const double lim = (reach + hd * w) * (1.0 + 1e-9);
         open = dx * dx + dy * dy + dz * dz < lim * lim;
-        leaf = nleaf[node] != 0;
-        if (open && !leaf) {
-          c0 = nchild[node];
-          const uint32_t c1 = nlastchild[node];
-          nc = (c1 >= c0 && c1 - c0 < 8) ? c1 - c0 + 1 : 0;
-          if (c1 < c0 || c1 - c0 >= 8) atomicOr(err, RB_ERR_TREE);
-        }
+        leaf = (cn.b >> 31) != 0;
+        c0 = cn.a;
+        span = cn.b & ((1u << 26) - 1u);
+        // (a flagged broken child range has bit 3 set and opens nothing)
+        if (open && !leaf && span < 8u) nc = span + 1u;
       }
       // opened internal nodes push their children, opened leaves join the list
       const uint32_t incl = rb_wave_incl_scan(nc);
@@ -237,7 +326,11 @@ __global__ __launch_bounds__(256) void k_coll_detect(
         stk[sp + (int)(incl - nc + q)] = ((c0 + q) << 5) | (e & 31u);
       sp += (int)tot;
       const uint64_t lm = __ballot(open && leaf);
-      if (open && leaf) lf[nl + (int)rb_mbcnt(lm)] = e;
+      if (open && leaf) {
+        const int at = nl + (int)rb_mbcnt(lm);
+        lfa[at] = c0;
+        lfb[at] = (span << 5) | (e & 31u);
+      }
       nl += __popcll(lm);
       coll_wave_sync();
     }
@@ -254,24 +347,72 @@ __global__ __launch_bounds__(256) void k_coll_detect(
   }
 }
 
+// The rounds run on a fixed grid that strides over the list, whose length
+// each kernel reads on the device (at most the queue's capacity), so the host
+// launches them without knowing it.
+#define CR_GRID 256
+
 // round, step 1: every particle learns the smallest h among its unresolved
-// collisions
+// collisions; the next list's count is cleared (that list was the previous
+// round's input), and the first round saves the number of detected pairs
 __global__ __launch_bounds__(256) void k_coll_min(const uint64_t *__restrict__ list,
                                                   const uint32_t *__restrict__ cnt,
+                                                  uint32_t *__restrict__ next_cnt,
+                                                  uint32_t *__restrict__ save, uint32_t qcap,
                                                   uint64_t seed,
                                                   unsigned long long *__restrict__ best) {
-  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= cnt[0]) return;
-  const uint64_t c = list[q];
-  const unsigned long long h = rb_splitmix64(seed + c);
-  atomicMin(&best[c >> 35], h);
-  atomicMin(&best[(c >> 7) & ((1ull << 28) - 1ull)], h);
+  const uint32_t n = min(cnt[0], qcap);
+  const uint32_t q0 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q0 == 0) {
+    next_cnt[0] = 0;
+    if (save) save[0] = cnt[0];
+  }
+  for (uint32_t q = q0; q < n; q += gridDim.x * blockDim.x) {
+    const uint64_t c = list[q];
+    const unsigned long long h = rb_splitmix64(seed + c);
+    atomicMin(&best[c >> 35], h);
+    atomicMin(&best[(c >> 7) & ((1ull << 28) - 1ull)], h);
+  }
+}
+
+// Resolve the collision of code c if its particles approach (d . u < 0);
+// returns whether it did.  Each particle takes part in at most one
+// collision resolved in a round, so the updates of a round do not race.
+__device__ __forceinline__ bool rb_coll_apply(
+    uint64_t c, double *__restrict__ x, double *__restrict__ y, double *__restrict__ z,
+    double *__restrict__ vx, double *__restrict__ vy, double *__restrict__ vz,
+    const double *__restrict__ m, const PatchInfo *__restrict__ patch,
+    const uint32_t *__restrict__ starts, uint32_t P, int ngx, int ngy, int boundary,
+    double omega, double t, double eps) {
+  const uint32_t i = (uint32_t)(c >> 35), j = (uint32_t)((c >> 7) & ((1ull << 28) - 1ull));
+  const int k = (int)(c & 127ull);
+  const uint32_t p = (P == 1) ? 0u : rb_patch_of(starts, P, i);
+  const double W = patch[p].W;
+  const double sh = (boundary == RB_SHEAR) ? remainder(1.5 * omega * W * t, W) : 0.0;
+  double ox, oy, wy;
+  rb_coll_image(k, ngx, ngy, boundary, W, sh, omega, ox, oy, wy);
+  const double d0 = (x[j] + ox) - x[i];
+  const double d1 = (y[j] + oy) - y[i];
+  const double d2 = (z[j] + 0.0) - z[i];
+  const double u0 = vx[j] - vx[i];
+  const double u1 = (vy[j] + wy) - vy[i];
+  const double u2 = vz[j] - vz[i];
+  const double M = m[i] + m[j];
+  if (!(d0 * u0 + d1 * u1 + d2 * u2 < 0.0 && M > 0.0)) return false;
+  const double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  const double n0 = d0 / dist, n1 = d1 / dist, n2 = d2 / dist;
+  const double vn = n0 * u0 + n1 * u1 + n2 * u2;
+  const double f = (1.0 + eps) * vn;
+  const double fi = (m[j] / M) * f, fj = (m[i] / M) * f;
+  vx[i] = vx[i] + fi * n0; vy[i] = vy[i] + fi * n1; vz[i] = vz[i] + fi * n2;
+  vx[j] = vx[j] - fj * n0; vy[j] = vy[j] - fj * n1; vz[j] = vz[j] - fj * n2;
+  return true;
 }
 
 // round, step 2: collisions first in line for both particles are resolved;
 // the others go to the next round's list
 __global__ __launch_bounds__(256) void k_coll_resolve(
-    const uint64_t *__restrict__ list, const uint32_t *__restrict__ cnt,
+    const uint64_t *__restrict__ list, const uint32_t *__restrict__ cnt, uint32_t qcap,
     uint64_t *__restrict__ next, uint32_t *__restrict__ next_cnt, uint64_t seed,
     const unsigned long long *__restrict__ best, double *__restrict__ x,
     double *__restrict__ y, double *__restrict__ z, double *__restrict__ vx,
@@ -279,98 +420,192 @@ __global__ __launch_bounds__(256) void k_coll_resolve(
     const PatchInfo *__restrict__ patch, const uint32_t *__restrict__ starts, uint32_t P,
     int ngx, int ngy, int boundary, double omega, double t, double eps,
     unsigned long long *__restrict__ n_res) {
-  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool in = q < cnt[0];
-  uint64_t c = 0;
-  bool ready = false;
-  if (in) {
-    c = list[q];
-    const unsigned long long h = rb_splitmix64(seed + c);
-    ready = best[c >> 35] == h && best[(c >> 7) & ((1ull << 28) - 1ull)] == h;
-  }
-  bool resolved = false;
-  if (ready) {
-    const uint32_t i = (uint32_t)(c >> 35), j = (uint32_t)((c >> 7) & ((1ull << 28) - 1ull));
-    const int k = (int)(c & 127ull);
-    const uint32_t p = (P == 1) ? 0u : rb_patch_of(starts, P, i);
-    const double W = patch[p].W;
-    const double sh = (boundary == RB_SHEAR) ? remainder(1.5 * omega * W * t, W) : 0.0;
-    double ox, oy, wy;
-    rb_coll_image(k, ngx, ngy, boundary, W, sh, omega, ox, oy, wy);
-    const double d0 = (x[j] + ox) - x[i];
-    const double d1 = (y[j] + oy) - y[i];
-    const double d2 = (z[j] + 0.0) - z[i];
-    const double u0 = vx[j] - vx[i];
-    const double u1 = (vy[j] + wy) - vy[i];
-    const double u2 = vz[j] - vz[i];
-    const double M = m[i] + m[j];
-    if (d0 * u0 + d1 * u1 + d2 * u2 < 0.0 && M > 0.0) {
-      const double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-      const double n0 = d0 / dist, n1 = d1 / dist, n2 = d2 / dist;
-      const double vn = n0 * u0 + n1 * u1 + n2 * u2;
-      const double f = (1.0 + eps) * vn;
-      const double fi = (m[j] / M) * f, fj = (m[i] / M) * f;
-      vx[i] = vx[i] + fi * n0; vy[i] = vy[i] + fi * n1; vz[i] = vz[i] + fi * n2;
-      vx[j] = vx[j] - fj * n0; vy[j] = vy[j] - fj * n1; vz[j] = vz[j] - fj * n2;
-      resolved = true;
+  const uint32_t n = min(cnt[0], qcap);
+  // wave-uniform trip count: a wave covers 64 consecutive entries per pass
+  const uint32_t wbase = blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
+  for (uint32_t q0 = wbase; q0 < n; q0 += gridDim.x * blockDim.x) {
+    const uint32_t q = q0 + rb_lane();
+    const bool in = q < n;
+    uint64_t c = 0;
+    bool ready = false;
+    if (in) {
+      c = list[q];
+      const unsigned long long h = rb_splitmix64(seed + c);
+      ready = best[c >> 35] == h && best[(c >> 7) & ((1ull << 28) - 1ull)] == h;
     }
+    const bool resolved = ready && rb_coll_apply(c, x, y, z, vx, vy, vz, m, patch, starts, P,
+                                                 ngx, ngy, boundary, omega, t, eps);
+    const uint64_t rm = __ballot(resolved);
+    if (rb_lane() == 0 && rm) atomicAdd(n_res, (unsigned long long)__popcll(rm));
+    // survivors to the next list, one atomic per wave
+    const bool keep = in && !ready;
+    const uint64_t km = __ballot(keep);
+    uint32_t base = 0;
+    if (rb_lane() == 0 && km) base = atomicAdd(next_cnt, (uint32_t)__popcll(km));
+    base = __shfl(base, 0, 64);
+    if (keep) next[base + rb_mbcnt(km)] = c;
   }
-  const uint64_t rm = __ballot(resolved);
-  if (rb_lane() == 0 && rm) atomicAdd(n_res, (unsigned long long)__popcll(rm));
-  // survivors to the next list, one atomic per wave
-  const bool keep = in && !ready;
-  const uint64_t km = __ballot(keep);
-  uint32_t base = 0;
-  if (rb_lane() == 0 && km) base = atomicAdd(next_cnt, (uint32_t)__popcll(km));
-  base = __shfl(base, 0, 64);
-  if (keep) next[base + rb_mbcnt(km)] = c;
 }
 
 // round, step 3: the particles of this round's collisions forget their
 // minimum (ready for the next round)
 __global__ __launch_bounds__(256) void k_coll_reset(const uint64_t *__restrict__ list,
                                                     const uint32_t *__restrict__ cnt,
+                                                    uint32_t qcap,
                                                     unsigned long long *__restrict__ best) {
-  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= cnt[0]) return;
-  const uint64_t c = list[q];
-  best[c >> 35] = ~0ull;
-  best[(c >> 7) & ((1ull << 28) - 1ull)] = ~0ull;
+  const uint32_t n = min(cnt[0], qcap);
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += gridDim.x * blockDim.x) {
+    const uint64_t c = list[q];
+    best[c >> 35] = ~0ull;
+    best[(c >> 7) & ((1ull << 28) - 1ull)] = ~0ull;
+  }
+}
+
+// All remaining rounds in one workgroup, for short lists (at most CR_SMALL
+// entries; a longer list is left as it is, for the multi-workgroup rounds).
+// The lists ping-pong between l[a] and l[1 - a]; on completion both counts
+// are zero.  Being the last kernel before the host reads the counts, it
+// copies the error word next to them (cnt[3]).  best[] is read and cleared with device-scope atomics (its
+// minima are formed by atomics, which the L1 cache does not see); the
+// velocities are plain loads and stores ordered by the workgroup barriers.
+#define CR_SMALL 4096
+__global__ __launch_bounds__(1024) void k_coll_rounds1(
+    uint64_t *__restrict__ l0, uint64_t *__restrict__ l1, uint32_t *__restrict__ cnt, int a,
+    uint32_t *__restrict__ save, uint32_t qcap, uint64_t seed,
+    unsigned long long *__restrict__ best, double *__restrict__ x, double *__restrict__ y,
+    double *__restrict__ z, double *__restrict__ vx, double *__restrict__ vy,
+    double *__restrict__ vz, const double *__restrict__ m,
+    const PatchInfo *__restrict__ patch, const uint32_t *__restrict__ starts, uint32_t P,
+    int ngx, int ngy, int boundary, double omega, double t, double eps,
+    unsigned long long *__restrict__ n_res, const uint32_t *__restrict__ err) {
+  __shared__ uint32_t s_n, s_next;
+  __shared__ unsigned long long s_res;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t n0 = min(cnt[a], qcap);
+  if (tid == 0 && save) save[0] = cnt[a];
+  if (n0 > CR_SMALL) {  // uniform
+    if (tid == 0) cnt[3] = err[0];
+    return;
+  }
+  if (tid == 0) {
+    s_n = n0;
+    s_res = 0;
+  }
+  uint64_t *cur = a ? l1 : l0, *nxt = a ? l0 : l1;
+  __syncthreads();
+  for (;;) {
+    const uint32_t n = s_n;
+    if (n == 0) break;  // uniform
+    if (tid == 0) s_next = 0;
+    for (uint32_t q = tid; q < n; q += blockDim.x) {
+      const uint64_t c = cur[q];
+      const unsigned long long h = rb_splitmix64(seed + c);
+      atomicMin(&best[c >> 35], h);
+      atomicMin(&best[(c >> 7) & ((1ull << 28) - 1ull)], h);
+    }
+    __syncthreads();
+    for (uint32_t q0 = tid & ~63u; q0 < n; q0 += blockDim.x) {
+      const uint32_t q = q0 + rb_lane();
+      const bool in = q < n;
+      uint64_t c = 0;
+      bool ready = false;
+      if (in) {
+        c = cur[q];
+        const unsigned long long h = rb_splitmix64(seed + c);
+        ready = __hip_atomic_load(&best[c >> 35], __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT) == h &&
+                __hip_atomic_load(&best[(c >> 7) & ((1ull << 28) - 1ull)], __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT) == h;
+      }
+      const bool resolved = ready && rb_coll_apply(c, x, y, z, vx, vy, vz, m, patch, starts,
+                                                   P, ngx, ngy, boundary, omega, t, eps);
+      const uint64_t rm = __ballot(resolved);
+      if (rb_lane() == 0 && rm) atomicAdd(&s_res, (unsigned long long)__popcll(rm));
+      const bool keep = in && !ready;
+      const uint64_t km = __ballot(keep);
+      uint32_t base = 0;
+      if (rb_lane() == 0 && km) base = atomicAdd(&s_next, (uint32_t)__popcll(km));
+      base = __shfl(base, 0, 64);
+      if (keep) nxt[base + rb_mbcnt(km)] = c;
+    }
+    __syncthreads();
+    for (uint32_t q = tid; q < n; q += blockDim.x) {
+      const uint64_t c = cur[q];
+      __hip_atomic_store(&best[c >> 35], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&best[(c >> 7) & ((1ull << 28) - 1ull)], ~0ull, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    uint64_t *tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+    __syncthreads();
+    if (tid == 0) s_n = s_next;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    cnt[0] = 0;
+    cnt[1] = 0;
+    cnt[3] = err[0];
+    if (s_res) atomicAdd(n_res, s_res);
+  }
+}
+
+// R_max, the cells' records and the work items of the search
+hipError_t launch_coll_prep(rb_ctx *c, const double *radius) {
+  const uint32_t n = (uint32_t)c->h_starts[c->P];
+  if (n == 0) return hipSuccess;
+  const unsigned grid = std::min(rb_div_up(n, 1024), 128u);
+  hipLaunchKernelGGL(k_coll_rmax, dim3(grid), dim3(256), 0, c->stream, radius, c->d_orig[0],
+                     c->d_starts, c->d_nlive, c->P, n, c->d_cmax);
+  CollNode *cells = reinterpret_cast<CollNode *>(c->d_cgeo);
+  hipLaunchKernelGGL(k_coll_geom, dim3(rb_div_up(c->node_cap, 256)), dim3(256), 0, c->stream,
+                     c->d_px[0][0], c->d_px[0][1], c->d_px[0][2], c->d_patch, c->d_starts, c->P,
+                     c->d_lev_off, c->node_cap, c->d_nfirst, c->d_nlast, c->d_nchild,
+                     c->d_nlastchild, c->d_nlevel, c->d_nleaf, cells, c->d_err);
+  return launch_groups(c);
 }
 
 hipError_t launch_coll_detect(rb_ctx *c, const double *radius, double t) {
   const uint32_t n = (uint32_t)c->h_starts[c->P];
   if (n == 0) return hipSuccess;
-  const unsigned grid = rb_div_up(n, 256);
-  hipLaunchKernelGGL(k_coll_rmax, dim3(grid), dim3(256), 0, c->stream, radius, c->d_orig[0],
-                     c->d_starts, c->d_nlive, c->P, n, c->d_cmax);
-  hipError_t e = launch_groups(c);
-  if (e != hipSuccess) return e;
-  unsigned ggrid = rb_div_up(n, 64);
-  if (ggrid > 2048) ggrid = 2048;
+  CollNode *cells = reinterpret_cast<CollNode *>(c->d_cgeo);
+  // about one wave per non-empty item part (parts average over CG_SUB / 2
+  // particles); the loop strides over any others
+  unsigned ggrid = rb_div_up(n, 4 * CG_SUB / 2);
+  if (ggrid > 4096) ggrid = 4096;
   hipLaunchKernelGGL(k_coll_detect, dim3(ggrid), dim3(256), 0, c->stream, c->d_witems,
                      c->d_witems_mid, c->d_gctr, c->cap, c->d_px[0][0], c->d_px[0][1],
-                     c->d_px[0][2],
-                     c->d_orig[0], radius, c->d_patch, c->d_starts, c->d_nlive, c->d_root,
-                     c->d_nfirst, c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nlevel,
-                     c->d_nleaf, c->p.n_ghost[0], c->p.n_ghost[1], c->p.boundary, c->p.omega,
-                     t, c->d_cmax, c->d_cq[0], (uint32_t)c->cq_cap, c->d_ccnt, c->d_err);
+                     c->d_px[0][2], c->d_orig[0], radius, c->d_patch, c->d_starts, c->d_nlive,
+                     c->d_root, cells, c->p.n_ghost[0], c->p.n_ghost[1], c->p.boundary,
+                     c->p.omega, t, c->d_cmax, c->d_cq[0], (uint32_t)c->cq_cap, c->d_ccnt,
+                     c->d_err);
   return hipGetLastError();
 }
 
 // One round over list `a` (count d_ccnt[a]) into list 1 - a.
+hipError_t launch_coll_rounds1(rb_ctx *c, int a, const rb_particles *pp, double t, double eps,
+                               uint64_t seed, uint32_t *save) {
+  hipLaunchKernelGGL(k_coll_rounds1, dim3(1), dim3(1024), 0, c->stream, c->d_cq[0],
+                     c->d_cq[1], c->d_ccnt, a, save, (uint32_t)c->cq_cap, seed, c->d_cbest,
+                     pp->x, pp->y, pp->z, pp->vx, pp->vy, pp->vz, pp->m, c->d_patch,
+                     c->d_starts, c->P, c->p.n_ghost[0], c->p.n_ghost[1], c->p.boundary,
+                     c->p.omega, t, eps, c->d_cres, c->d_err);
+  return hipGetLastError();
+}
+
 hipError_t launch_coll_round(rb_ctx *c, int a, const rb_particles *pp, double t, double eps,
-                             uint64_t seed, uint32_t count) {
-  if (count == 0) return hipSuccess;
-  const unsigned grid = rb_div_up(count, 256);
+                             uint64_t seed, uint32_t *save) {
   uint32_t *cnt = c->d_ccnt + a, *next_cnt = c->d_ccnt + (1 - a);
-  hipLaunchKernelGGL(k_coll_min, dim3(grid), dim3(256), 0, c->stream, c->d_cq[a], cnt, seed,
-                     c->d_cbest);
-  hipLaunchKernelGGL(k_coll_resolve, dim3(grid), dim3(256), 0, c->stream, c->d_cq[a], cnt,
-                     c->d_cq[1 - a], next_cnt, seed, c->d_cbest, pp->x, pp->y, pp->z, pp->vx,
-                     pp->vy, pp->vz, pp->m, c->d_patch, c->d_starts, c->P, c->p.n_ghost[0],
-                     c->p.n_ghost[1], c->p.boundary, c->p.omega, t, eps, c->d_cres);
-  hipLaunchKernelGGL(k_coll_reset, dim3(grid), dim3(256), 0, c->stream, c->d_cq[a], cnt,
-                     c->d_cbest);
+  const uint32_t qcap = (uint32_t)c->cq_cap;
+  hipLaunchKernelGGL(k_coll_min, dim3(CR_GRID), dim3(256), 0, c->stream, c->d_cq[a], cnt,
+                     next_cnt, save, qcap, seed, c->d_cbest);
+  hipLaunchKernelGGL(k_coll_resolve, dim3(CR_GRID), dim3(256), 0, c->stream, c->d_cq[a], cnt,
+                     qcap, c->d_cq[1 - a], next_cnt, seed, c->d_cbest, pp->x, pp->y, pp->z,
+                     pp->vx, pp->vy, pp->vz, pp->m, c->d_patch, c->d_starts, c->P,
+                     c->p.n_ghost[0], c->p.n_ghost[1], c->p.boundary, c->p.omega, t, eps,
+                     c->d_cres);
+  hipLaunchKernelGGL(k_coll_reset, dim3(CR_GRID), dim3(256), 0, c->stream, c->d_cq[a], cnt,
+                     qcap, c->d_cbest);
   return hipGetLastError();
 }

@@ -337,6 +337,7 @@ int init_ctx(rb_ctx *c, const rb_params *p, uint32_t P, const int64_t *off, cons
 void free_ctx(rb_ctx *c) {
   if (!c) return;
   if (c->h_dyn) (void)hipHostFree(c->h_dyn);
+  if (c->h_cpin) (void)hipHostFree(c->h_cpin);
   if (c->dyn_ev) (void)hipEventDestroy(c->dyn_ev);
   for (int k = 0; k < 2; ++k) {
     if (c->graph_exec[k]) (void)hipGraphExecDestroy(c->graph_exec[k]);
@@ -447,8 +448,10 @@ hipEvent_t get_event(rb_ctx *c) {
 }
 
 int mark(rb_ctx *c, int phase, bool begin) {
-  // bit 0: every phase; bit 2: the walk only (lightest timing of a run)
-  if (!(c->p.profile & 1) && !((c->p.profile & 4) && phase == 5)) return RB_OK;
+  // bit 0: every phase; bit 2: the walk and the collision search only
+  // (lightest timing of a run)
+  if (!(c->p.profile & 1) && !((c->p.profile & 4) && (phase == 5 || phase == 10)))
+    return RB_OK;
   EvPool &pl = g_pools[c];
   hipEvent_t e = get_event(c);
   if (!e) return fail(RB_EHIP, "hipEventCreate failed");
@@ -499,9 +502,9 @@ void drop_pool(rb_ctx *c) {
 }
 
 enum { PH_KEYS = 0, PH_SORT, PH_PERMUTE, PH_TOPO, PH_MOMENTS, PH_WALK, PH_POST, PH_DIRECT,
-       PH_COLLIDE, PH_TOTAL, PH_COUNT };
+       PH_COLLIDE, PH_TOTAL, PH_CSEARCH, PH_COUNT };
 const char *g_phase_names[] = {"keys", "sort", "permute", "topology", "moments", "walk",
-                               "kick_drift", "direct", "collide", "total"};
+                               "kick_drift", "direct", "collide", "total", "coll_search"};
 
 #define RB_LAUNCH(expr)                                                              \
   do {                                                                               \
@@ -879,50 +882,68 @@ int rb_collide(rb_ctx *c, rb_particles *p, const double *radius, int64_t n, doub
     RB_TRY(set_single_n(c, n, n));
   }
   if (c->cap >= (1ull << 28)) return fail(RB_EUNSUPPORTED, "pair codes need n < 2^28");
+  if (c->node_cap >= (1ull << 27))
+    return fail(RB_EUNSUPPORTED, "the collision search needs fewer than 2^27 nodes");
   if (!c->d_cq[0]) {
     c->cq_cap = 8 * c->cap + 1024;
     RB_TRY(dalloc(c, &c->d_cq[0], c->cq_cap));
     RB_TRY(dalloc(c, &c->d_cq[1], c->cq_cap));
-    RB_TRY(dalloc(c, &c->d_ccnt, 4));
+    RB_TRY(dalloc(c, &c->d_ccnt, 8));
+    c->d_cmax = reinterpret_cast<unsigned long long *>(c->d_ccnt + 4);
+    c->d_cres = reinterpret_cast<unsigned long long *>(c->d_ccnt + 6);
+    RB_HIP(hipHostMalloc((void **)&c->h_cpin, 32, hipHostMallocDefault));
     RB_TRY(dalloc(c, &c->d_cbest, c->cap));
-    RB_TRY(dalloc(c, &c->d_cmax, 1));
-    RB_TRY(dalloc(c, &c->d_cres, 1));
+    RB_TRY(dalloc(c, &c->d_cgeo, 4 * c->node_cap));
     RB_HIP(hipMemsetAsync(c->d_cbest, 0xFF, 8 * c->cap, c->stream));
   }
-  RB_HIP(hipMemsetAsync(c->d_ccnt, 0, 16, c->stream));
-  RB_HIP(hipMemsetAsync(c->d_cmax, 0, 8, c->stream));
-  RB_HIP(hipMemsetAsync(c->d_cres, 0, 8, c->stream));
+  RB_HIP(hipMemsetAsync(c->d_ccnt, 0, 32, c->stream));
   RB_TRY(mark(c, PH_TOTAL, true));
   RB_PHASE(PH_KEYS, launch_keys(c, p->x, p->y, p->z, 0.0));
   RB_PHASE(PH_SORT, launch_sort(c));
   RB_PHASE(PH_PERMUTE, launch_permute_gravity(c, p->x, p->y, p->z, p->m, 0));
   RB_PHASE(PH_TOPO, launch_topology(c));
-  RB_PHASE(PH_COLLIDE, launch_coll_detect(c, radius, t));
-  uint32_t cnt = 0;
-  RB_HIP(hipMemcpyAsync(&cnt, c->d_ccnt, 4, hipMemcpyDeviceToHost, c->stream));
-  RB_HIP(hipStreamSynchronize(c->stream));
-  RB_TRY(report_device_errors(c));
-  const uint32_t pairs = cnt;
-  if (codes_cap > 0 && pairs > 0)
-    RB_HIP(hipMemcpy(codes, c->d_cq[0], 8 * (size_t)std::min<int64_t>(pairs, codes_cap),
-                     hipMemcpyDeviceToHost));
-  // rounds: each resolves at least the collision first in the whole queue
-  int a = 0;
-  for (uint32_t round = 0; cnt > 0; ++round) {
-    if (round > pairs) return fail(RB_EHIP, "collision rounds did not finish (internal error)");
-    RB_HIP(hipMemsetAsync(c->d_ccnt + (1 - a), 0, 4, c->stream));
-    RB_PHASE(PH_COLLIDE, launch_coll_round(c, a, p, t, epsilon, seed, cnt));
-    RB_HIP(hipMemcpyAsync(&cnt, c->d_ccnt + (1 - a), 4, hipMemcpyDeviceToHost, c->stream));
+  RB_PHASE(PH_COLLIDE, launch_coll_prep(c, radius));
+  RB_PHASE(PH_CSEARCH, launch_coll_detect(c, radius, t));
+  if (codes_cap > 0) {  // the detected pairs, before the rounds reuse their list
+    uint32_t cnt = 0;
+    RB_HIP(hipMemcpyAsync(&cnt, c->d_ccnt, 4, hipMemcpyDeviceToHost, c->stream));
     RB_HIP(hipStreamSynchronize(c->stream));
-    a = 1 - a;
+    RB_TRY(report_device_errors(c));
+    if (cnt > 0)
+      RB_HIP(hipMemcpy(codes, c->d_cq[0], 8 * (size_t)std::min<int64_t>(cnt, codes_cap),
+                       hipMemcpyDeviceToHost));
   }
-  unsigned long long res = 0;
-  RB_HIP(hipMemcpyAsync(&res, c->d_cres, 8, hipMemcpyDeviceToHost, c->stream));
+  // rounds: each resolves at least the collision first in the whole queue.
+  // A short queue is resolved entirely by one workgroup; a long one first
+  // goes through batches of multi-workgroup rounds (whose kernels read the
+  // list's length on the device) until it is short.  The first launch saves
+  // the number of detected pairs in the third count.
+  int a = 0;
+  uint64_t rounds = 0;
+  const uint32_t *h_cnt = c->h_cpin;
+  RB_PHASE(PH_COLLIDE, launch_coll_rounds1(c, a, p, t, epsilon, seed, c->d_ccnt + 2));
+  for (;;) {
+    RB_HIP(hipMemcpyAsync(c->h_cpin, c->d_ccnt, 32, hipMemcpyDeviceToHost, c->stream));
+    RB_HIP(hipStreamSynchronize(c->stream));
+    if (h_cnt[3]) return report_device_errors(c);  // (a full queue ends the call here)
+    if (h_cnt[a] == 0) break;
+    if (rounds > h_cnt[2])
+      return fail(RB_EHIP, "collision rounds did not finish (internal error)");
+    for (int r = 0; r < 4; ++r, ++rounds) {
+      RB_PHASE(PH_COLLIDE, launch_coll_round(c, a, p, t, epsilon, seed, nullptr));
+      a = 1 - a;
+    }
+    RB_PHASE(PH_COLLIDE, launch_coll_rounds1(c, a, p, t, epsilon, seed, nullptr));
+  }
   RB_TRY(mark(c, PH_TOTAL, false));
-  RB_HIP(hipStreamSynchronize(c->stream));
-  if (n_pairs) *n_pairs = (int64_t)pairs;
-  if (n_resolved) *n_resolved = (int64_t)res;
-  return report_device_errors(c);
+  if (n_pairs) *n_pairs = (int64_t)h_cnt[2];
+  if (n_resolved) {
+    unsigned long long res;
+    memcpy(&res, h_cnt + 6, 8);
+    *n_resolved = (int64_t)res;
+  }
+  // (with phase timing on, wait for the last event before reading the timers)
+  return (c->p.profile & 1) ? report_device_errors(c) : RB_OK;
 }
 
 int rb_sync(rb_ctx *c) {

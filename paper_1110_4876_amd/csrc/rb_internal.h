@@ -114,12 +114,18 @@ struct rb_ctx {
   // collisions (allocated by the first rb_collide): two code lists (the
   // detected pairs, then the survivors of each resolution round), their
   // counts, each particle's smallest pending queue key, R_max, resolved
+  // collisions, the cells' centres and links
   uint64_t *d_cq[2] = {nullptr, nullptr};
   uint64_t cq_cap = 0;
+  // one 32-byte block [list counts 0, 1 | detected pairs | copy of the
+  // error word | R_max bits (2 words) | resolved (2 words)], cleared by one
+  // memset per call and read back in one copy
   uint32_t *d_ccnt = nullptr;
   unsigned long long *d_cbest = nullptr;
-  unsigned long long *d_cmax = nullptr;
-  unsigned long long *d_cres = nullptr;
+  unsigned long long *d_cmax = nullptr;  // = d_ccnt + 4
+  unsigned long long *d_cres = nullptr;  // = d_ccnt + 6
+  uint32_t *h_cpin = nullptr;            // pinned host copy of the block (8 words)
+  double *d_cgeo = nullptr;         // 4 per node: the search's cell records
   double *d_acc = nullptr;          // (n_img or 1) * 3 * cap
 
   // per-call dynamic region [ctr | StepConst | schedule], uploaded from a
@@ -159,9 +165,12 @@ hipError_t launch_keys(rb_ctx *c, const double *x, const double *y, const double
                        double s_unused);
 hipError_t launch_sort(rb_ctx *c);
 hipError_t launch_groups(rb_ctx *c);
+hipError_t launch_coll_prep(rb_ctx *c, const double *radius);
 hipError_t launch_coll_detect(rb_ctx *c, const double *radius, double t);
+hipError_t launch_coll_rounds1(rb_ctx *c, int a, const rb_particles *pp, double t, double eps,
+                               uint64_t seed, uint32_t *save);
 hipError_t launch_coll_round(rb_ctx *c, int a, const rb_particles *pp, double t, double eps,
-                             uint64_t seed, uint32_t count);
+                             uint64_t seed, uint32_t *save);
 hipError_t launch_bsort(rb_ctx *c);
 hipError_t launch_permute_state(rb_ctx *c, int src, int dst);
 hipError_t launch_permute_gravity(rb_ctx *c, const double *x, const double *y,

@@ -23,7 +23,7 @@ RB_FP64, RB_FP32_MIXED = 0, 1
 RB_DRIFT_LEAPFROG, RB_DRIFT_EPICYCLE = 0, 1
 
 PHASES = ["keys", "sort", "permute", "topology", "moments", "walk", "kick_drift", "direct",
-          "collide", "total"]
+          "collide", "total", "coll_search"]
 
 
 class rb_params(ctypes.Structure):

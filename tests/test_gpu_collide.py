@@ -149,10 +149,13 @@ def test_batch_patches_match_oracle(orc):
     assert nres > 0
 
 
-def test_c1_full_size_after_steps(orc):
-    # the 50,000-particle sheet after 20 FP32-mixed steps on the GPU: the
-    # pair set, the resolved count and the velocities equal the oracle's on
-    # the same state (brute-force detection, one-by-one resolution)
+@pytest.mark.parametrize("steps", [0, 20])
+def test_c1_full_size_after_steps(orc, steps):
+    # the 50,000-particle sheet initially (about 28,000 pairs: multi-workgroup
+    # rounds first) and after 20 FP32-mixed steps on the GPU (a few thousand:
+    # one workgroup throughout): the pair set, the resolved count and the
+    # velocities equal the oracle's on the same state (brute-force detection,
+    # one-by-one resolution)
     from gpu_util import dev
     from paper_1110_4876_amd import rb
     from paper_1110_4876_amd.system import System
@@ -162,9 +165,10 @@ def test_c1_full_size_after_steps(orc):
     ctx = sysm.create(rb.RB_FP32_MIXED, theta=0.42, group_size=64, walk_waves=4)
     try:
         X = sysm.clone()
-        sysm.step(ctx, X, 0.0, 20)
-        rb.rb_sync(ctx)
-        t = 20 * pr.dt
+        if steps:
+            sysm.step(ctx, X, 0.0, steps)
+            rb.rb_sync(ctx)
+        t = steps * pr.dt
         host = {k: X[k].cpu().numpy().copy() for k in ("x", "y", "z", "vx", "vy", "vz")}
         codes = np.zeros(16 * pr.n, dtype=np.uint64)
         npair, nres = rb.rb_collide(ctx, sysm.parts(X), dev(R), pr.n, t, 0.5, 2024, codes)
