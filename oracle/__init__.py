@@ -103,6 +103,9 @@ def lib():
         L.orc_collide.argtypes = [P, i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_uint64, vp, i64, vp]
         L.orc_collide.restype = i64
+        L.orc_sweep.argtypes = [P, i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_uint64, vp, i64, vp]
+        L.orc_sweep.restype = i64
         _lib = L
         del dp
     return _lib
@@ -290,4 +293,24 @@ def collide(p: Params, state: dict, m, radius, t: float, eps: float, seed: int,
                             ("x", "y", "z", "vx", "vy", "vz")], _ptr(m), _ptr(radius),
                             float(s_off), float(eps), ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF),
                             _ptr(codes), cap, _ptr(nres))
+    return codes[:min(int(cnt), cap)].copy(), int(cnt), int(nres[0]), s
+
+
+def sweep(p: Params, state: dict, m, radius, t: float, dt: float, eps: float, seed: int,
+          cap: int = None):
+    """Collisions at time t as the plane sweep finds them (Sect. 5): pairs
+    whose straight trajectories over the past time-step dt come within
+    R_i + R_j; the same queue and resolution as collide().  Returns (codes in
+    queue order, number of pairs, number resolved, new state)."""
+    s = {k: _f64(state[k]).copy() for k in ("x", "y", "z", "vx", "vy", "vz")}
+    m, radius = _f64(m), _f64(radius)
+    n = len(m)
+    cap = 16 * n + 16 if cap is None else int(cap)
+    codes = np.zeros(max(cap, 1), dtype=np.uint64)
+    nres = np.zeros(1, dtype=np.int64)
+    s_off = shear_offset(p, t)
+    cnt = lib().orc_sweep(ctypes.byref(p), n, *[_ptr(s[k]) for k in
+                          ("x", "y", "z", "vx", "vy", "vz")], _ptr(m), _ptr(radius),
+                          float(s_off), float(dt), float(eps),
+                          ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), _ptr(codes), cap, _ptr(nres))
     return codes[:min(int(cnt), cap)].copy(), int(cnt), int(nres[0]), s

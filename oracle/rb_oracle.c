@@ -732,10 +732,33 @@ static int orc_coll_cmp(const void *a, const void *b) {
   return (x->h > y->h) - (x->h < y->h);
 }
 
-int64_t orc_collide(const orc_params *p, int64_t n, const double *x, const double *y,
-                    const double *z, double *vx, double *vy, double *vz, const double *m,
-                    const double *R, double s, double eps, uint64_t seed, uint64_t *codes,
-                    int64_t cap, int64_t *n_resolved) {
+/* Does particle i meet image k of particle j?  sweep = 0: they overlap now,
+ * |d| < R_i + R_j.  sweep = 1: their straight trajectories over the past
+ * time-step come that close: with d(sigma) = d + u sigma for sigma in
+ * [-dt, 0] (the line through the present positions with the present
+ * velocities), min |d(sigma)| < R_i + R_j.  The minimum over the segment is
+ * at sigma = 0 unless the pair is now separating (d . u > 0); then it is at
+ * -d.u / u.u, or at -dt if that lies further back. */
+static int orc_meets(int sweep, double d0, double d1, double d2, double u0, double u1,
+                     double u2, double sum, double dt) {
+  if (d0 * d0 + d1 * d1 + d2 * d2 < sum * sum) return 1;
+  if (!sweep) return 0;
+  const double du = d0 * u0 + d1 * u1 + d2 * u2;
+  const double uu = u0 * u0 + u1 * u1 + u2 * u2;
+  if (!(du > 0.0 && uu > 0.0)) return 0;
+  double sg = -du / uu;
+  if (sg < -dt) sg = -dt;
+  const double e0 = d0 + u0 * sg, e1 = d1 + u1 * sg, e2 = d2 + u2 * sg;
+  return e0 * e0 + e1 * e1 + e2 * e2 < sum * sum;
+}
+
+/* detection (brute force over all pairs and images; counted, then written,
+ * both passes parallel over i), the queue in random order, resolution */
+static int64_t orc_coll_run(const orc_params *p, int64_t n, const double *x, const double *y,
+                            const double *z, double *vx, double *vy, double *vz,
+                            const double *m, const double *R, double s, int sweep, double dt,
+                            double eps, uint64_t seed, uint64_t *codes, int64_t cap,
+                            int64_t *n_resolved) {
   double o[ORC_MAX_IMAGES][3];
   int zero = 0;
   const int ni = orc_images(p, s, o, &zero);
@@ -750,53 +773,46 @@ int64_t orc_collide(const orc_params *p, int64_t n, const double *x, const doubl
   }
   uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
   orc_keys(p, n, x, y, z, keys);
-  /* detection: all pairs, all images (brute force; counted, then written,
-   * both passes parallel over i) */
   int64_t *per = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
-#pragma omp parallel for schedule(dynamic, 64)
-  for (int64_t i = 0; i < n; ++i) {
-    if (keys[i] == UINT64_MAX) continue;
-    int64_t c = 0;
-    for (int64_t j = i + 1; j < n; ++j) {
-      if (keys[j] == UINT64_MAX) continue;
-      const double sum = R[i] + R[j];
-      for (int k = 0; k < ni; ++k) {
-        const double d0 = (x[j] + o[k][0]) - x[i];
-        const double d1 = (y[j] + o[k][1]) - y[i];
-        const double d2 = (z[j] + o[k][2]) - z[i];
-        if (d0 * d0 + d1 * d1 + d2 * d2 < sum * sum) ++c;
-      }
+  orc_coll *q = NULL;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+      for (int64_t i = 0; i < n; ++i) per[i + 1] += per[i];
+      q = (orc_coll *)malloc(sizeof(orc_coll) * (size_t)(per[n] > 0 ? per[n] : 1));
     }
-    per[i + 1] = c;
-  }
-  for (int64_t i = 0; i < n; ++i) per[i + 1] += per[i];
-  const int64_t count = per[n];
-  int64_t stored = 0;
-  orc_coll *q = (orc_coll *)malloc(sizeof(orc_coll) * (size_t)(count > 0 ? count : 1));
 #pragma omp parallel for schedule(dynamic, 64)
-  for (int64_t i = 0; i < n; ++i) {
-    if (keys[i] == UINT64_MAX) continue;
-    int64_t at = per[i];
-    for (int64_t j = i + 1; j < n; ++j) {
-      if (keys[j] == UINT64_MAX) continue;
-      const double sum = R[i] + R[j];
-      for (int k = 0; k < ni; ++k) {
-        const double d0 = (x[j] + o[k][0]) - x[i];
-        const double d1 = (y[j] + o[k][1]) - y[i];
-        const double d2 = (z[j] + o[k][2]) - z[i];
-        if (d0 * d0 + d1 * d1 + d2 * d2 < sum * sum) {
-          const uint64_t c = ((uint64_t)i << 35) | ((uint64_t)j << 7) | (uint64_t)k;
-          q[at].code = c;
-          q[at].h = orc_splitmix64(seed + c);
-          ++at;
+    for (int64_t i = 0; i < n; ++i) {
+      if (keys[i] == UINT64_MAX) continue;
+      int64_t c = 0, at = pass ? per[i] : 0;
+      for (int64_t j = i + 1; j < n; ++j) {
+        if (keys[j] == UINT64_MAX) continue;
+        const double sum = R[i] + R[j];
+        for (int k = 0; k < ni; ++k) {
+          const double d0 = (x[j] + o[k][0]) - x[i];
+          const double d1 = (y[j] + o[k][1]) - y[i];
+          const double d2 = (z[j] + o[k][2]) - z[i];
+          const double u0 = vx[j] - vx[i];
+          const double u1 = (vy[j] + w[k]) - vy[i];
+          const double u2 = vz[j] - vz[i];
+          if (!orc_meets(sweep, d0, d1, d2, u0, u1, u2, sum, dt)) continue;
+          if (pass == 0) {
+            ++c;
+          } else {
+            const uint64_t cd = ((uint64_t)i << 35) | ((uint64_t)j << 7) | (uint64_t)k;
+            q[at].code = cd;
+            q[at].h = orc_splitmix64(seed + cd);
+            ++at;
+          }
         }
       }
+      if (pass == 0) per[i + 1] = c;
     }
   }
+  const int64_t count = per[n];
   free(per);
   qsort(q, (size_t)count, sizeof(orc_coll), orc_coll_cmp);
   /* resolution in queue order */
-  int64_t res = 0;
+  int64_t res = 0, stored = 0;
   for (int64_t c = 0; c < count; ++c) {
     const int64_t i = (int64_t)(q[c].code >> 35);
     const int64_t j = (int64_t)((q[c].code >> 7) & ((1ull << 28) - 1ull));
@@ -824,4 +840,23 @@ int64_t orc_collide(const orc_params *p, int64_t n, const double *x, const doubl
   free(q);
   free(keys);
   return count;
+}
+
+int64_t orc_collide(const orc_params *p, int64_t n, const double *x, const double *y,
+                    const double *z, double *vx, double *vy, double *vz, const double *m,
+                    const double *R, double s, double eps, uint64_t seed, uint64_t *codes,
+                    int64_t cap, int64_t *n_resolved) {
+  return orc_coll_run(p, n, x, y, z, vx, vy, vz, m, R, s, 0, 0.0, eps, seed, codes, cap,
+                      n_resolved);
+}
+
+/* The plane-sweep modules (Sect. 5) find the pairs whose straight
+ * trajectories over the time-step come within R_i + R_j: the sweep along x
+ * only narrows the candidates, so its result is this set. */
+int64_t orc_sweep(const orc_params *p, int64_t n, const double *x, const double *y,
+                  const double *z, double *vx, double *vy, double *vz, const double *m,
+                  const double *R, double s, double dt, double eps, uint64_t seed,
+                  uint64_t *codes, int64_t cap, int64_t *n_resolved) {
+  return orc_coll_run(p, n, x, y, z, vx, vy, vz, m, R, s, 1, dt, eps, seed, codes, cap,
+                      n_resolved);
 }

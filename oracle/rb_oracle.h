@@ -103,6 +103,14 @@ int64_t orc_collide(const orc_params *p, int64_t n, const double *x, const doubl
                     const double *z, double *vx, double *vy, double *vz, const double *m,
                     const double *R, double s, double eps, uint64_t seed, uint64_t *codes,
                     int64_t cap, int64_t *n_resolved);
+/* The same with the pairs the plane sweep finds (Sect. 5): i and image k of
+ * j whose straight trajectories over the past time-step dt (through the
+ * present positions, with the present velocities, the image's shear
+ * velocity included) come closer than R_i + R_j.                          */
+int64_t orc_sweep(const orc_params *p, int64_t n, const double *x, const double *y,
+                  const double *z, double *vx, double *vy, double *vz, const double *m,
+                  const double *R, double s, double dt, double eps, uint64_t seed,
+                  uint64_t *codes, int64_t cap, int64_t *n_resolved);
 
 #ifdef __cplusplus
 }
