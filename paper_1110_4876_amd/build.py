@@ -24,7 +24,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result"]
 # host-side schedule arithmetic and the collision tests and updates must not
 # be contracted
-PER_FILE = {"rb_api.hip": ["-ffp-contract=off"], "k_collide.hip": ["-ffp-contract=off"]}
+PER_FILE = {"rb_api.hip": ["-ffp-contract=off"], "k_collide.hip": ["-ffp-contract=off"],
+            "k_sweep.hip": ["-ffp-contract=off"]}
 
 
 def hipcc() -> str:

@@ -28,28 +28,12 @@
 // updates round exactly as a plain evaluation of the same expressions.
 #include "rb_internal.h"
 
-#define RB_COLL_LOCAL 8  // pairs a thread keeps before it writes them out
 
 __device__ __forceinline__ uint64_t rb_splitmix64(uint64_t x) {
   uint64_t z = x + 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
-}
-
-// image k of the ghost boxes: ix outer and iy inner in [-ng, ng] (a single
-// image for open boundaries); position offset and y velocity offset
-__device__ __forceinline__ void rb_coll_image(int k, int ngx, int ngy, int boundary, double W,
-                                              double sh, double omega, double &ox, double &oy,
-                                              double &wy) {
-  if (boundary == RB_OPEN) { ox = oy = wy = 0.0; return; }
-  const int ny = 2 * ngy + 1;
-  const int ix = k / ny - ngx, iy = k % ny - ngy;
-  const double fx = (double)ix, fy = (double)iy;
-  const double s = (boundary == RB_SHEAR) ? sh : 0.0;
-  ox = fx * W;
-  oy = fy * W - fx * s;
-  wy = (boundary == RB_SHEAR) ? -1.5 * omega * W * fx : 0.0;
 }
 
 // largest radius of the live particles (as ordered bits of a non-negative
@@ -98,21 +82,6 @@ __device__ __forceinline__ double rb_wave_min_d(double v) {
 __device__ __forceinline__ double rb_wave_max_d(double v) {
   for (int d = 32; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
   return v;
-}
-
-// queue a pair from the lane's local list, writing the list out when full
-__device__ __forceinline__ void rb_coll_keep(uint64_t code, uint64_t (&mine)[RB_COLL_LOCAL],
-                                             uint32_t &nm, uint64_t *__restrict__ queue,
-                                             uint32_t qcap, uint32_t *__restrict__ qcnt,
-                                             uint32_t *__restrict__ err) {
-  if (nm == RB_COLL_LOCAL) {
-    const uint32_t at = atomicAdd(qcnt, (uint32_t)nm);
-    for (uint32_t q = 0; q < nm; ++q)
-      if (at + q < qcap) queue[at + q] = mine[q];
-    if (at + nm > qcap) atomicOr(err, RB_ERR_COLL);
-    nm = 0;
-  }
-  mine[nm++] = code;
 }
 
 // The cell as the search reads it (one 32-byte record): the centre of the

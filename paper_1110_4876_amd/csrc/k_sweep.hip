@@ -1,0 +1,284 @@
+// k_sweep.hip -- collision detection by a plane sweep along x (Sect. 5 of
+// the paper), for one system.
+//
+// Every particle's trajectory over the past time-step dt is taken as the
+// straight line through its present position with its present velocity,
+// x(sigma) = x + v sigma for sigma in [-dt, 0].  Particle i and image k of
+// particle j collide when those lines (the image moving with v_j + w_k, w_k
+// its shear velocity) come closer than R_i + R_j; the collisions then join
+// the same random-order queue and hard-sphere resolution as the tree search.
+//
+// The sweep: each trajectory's extent along x, widened by the radius, is an
+// interval [lo, hi].  Sorting the intervals by lo and stepping through them
+// in that order is the plane moving along x: the particles whose intervals
+// contain the plane's position are the active list of the paper, and a
+// particle entering it is checked against those already there.  Here every
+// interval in sorted order checks the ones after it that start before it
+// ends (on the GPU, one thread per interval: the active list is implicit),
+// so each pair of overlapping intervals is visited once.  With periodic or
+// shear boundaries, the copies of the box shifted by ix W (ix = +-1 .. +-ng)
+// are visited too: interval i looks up, in the same sorted list, the
+// intervals that overlap its own once shifted by ix W (they start after
+// lo_i - ix W - L, L the longest interval, and before hi_i - ix W) and keeps
+// the pairs with i the lower caller index, so each pair and image is found
+// once.  Ghost images along y are tested for every candidate pair.
+//
+// Sort keys are lo quantised on a 63-bit grid (monotone, clamped), so the
+// context's Morton-key sort orders them; a scan ends at the first interval
+// whose key exceeds the quantised end of its range, which visits every
+// interval that starts in the range.  The intervals carry a relative
+// widening of 1e-9 so that rounding never separates a pair that the exact
+// test below finds in contact.
+//
+// Compiled without FP contraction: the contact test rounds exactly as the
+// plain evaluation of the same expressions.
+#include "rb_internal.h"
+
+struct SweepGrid {
+  double base, scale;  // key = clamp(floor((lo - base) * scale), 0, RB_SW_KMAX)
+};
+#define RB_SW_KMAX 0x7FFFFFFFFFFFF000ull
+
+__device__ __forceinline__ uint64_t rb_sw_key(double v, SweepGrid g) {
+  const double f = floor((v - g.base) * g.scale);
+  if (!(f > 0.0)) return 0ull;  // (below the grid)
+  if (f >= (double)RB_SW_KMAX) return RB_SW_KMAX;
+  return (uint64_t)f;
+}
+
+// the trajectory's extent along x, widened by the radius and the margin
+__device__ __forceinline__ void rb_sw_extent(double x, double vx, double R, double dt, double W,
+                                             double &lo, double &hi) {
+  // position at the start of the step (a velocity that is not a number
+  // leaves only the present position, where the contact test can still hold)
+  const double mv = vx * dt;
+  const bool moves = !isnan(mv);
+  const double xs = moves ? x - mv : x;
+  const double r = fabs(R);
+  const double pad = 1e-9 * (W + r + (moves ? fabs(mv) : 0.0));
+  lo = fmin(x, xs) - r - pad;
+  hi = fmax(x, xs) + r + pad;
+}
+
+// keys of the caller's particles (live: inside the box, radius a number)
+__global__ __launch_bounds__(256) void k_sw_keys(
+    const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
+    const double *__restrict__ vx, const double *__restrict__ R,
+    const PatchInfo *__restrict__ patch, uint32_t n, int open_xy, double dt, SweepGrid g,
+    uint64_t *__restrict__ key, uint32_t *__restrict__ idx, uint32_t *__restrict__ err,
+    uint32_t *__restrict__ bcnt, uint32_t *__restrict__ bctl,
+    unsigned long long *__restrict__ lmax) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  double len = 0.0;
+  if (s < n) {
+    const PatchInfo pi = patch[0];
+    const double xs = x[s], ys = y[s], zs = z[s];
+    uint32_t q;
+    const bool okx = rb_quantise(xs, pi.x0[0], pi.W, pi.S, q);
+    const bool oky = rb_quantise(ys, pi.x0[1], pi.W, pi.S, q);
+    const bool okz = rb_quantise(zs, pi.x0[2], pi.W, pi.S, q);
+    uint64_t k = RB_KEY_DEAD;
+    if (okx && oky && okz) {
+      const double r = R[s];
+      if (!isnan(r)) {
+        double lo, hi;
+        rb_sw_extent(xs, vx[s], r, dt, pi.W, lo, hi);
+        k = (isnan(lo) || isnan(hi)) ? RB_KEY_DEAD : rb_sw_key(lo, g);
+        if (k != RB_KEY_DEAD) len = hi - lo;
+      }
+    } else if (!open_xy && !(isnan(xs) || isnan(ys) || isnan(zs)) && (!okx || !oky)) {
+      atomicOr(err, RB_ERR_OUTSIDE);  // a periodic axis must have been wrapped
+    }
+    key[s] = k;
+    idx[s] = s;
+    if (bcnt) {
+      if (s == 0) bctl[0] = 0;  // segments of the bucket sort, counted anew
+      rb_bucket_add(bcnt, 0, 1, k);
+    }
+  }
+  // the longest interval (ordered bits of a non-negative double)
+  for (int d = 32; d >= 1; d >>= 1) len = fmax(len, __shfl_xor(len, d, 64));
+  if (rb_lane() == 0 && len > 0.0)
+    atomicMax(lmax, (unsigned long long)__double_as_longlong(len));
+}
+
+// the particles in sorted order, each interval's end, the live count
+__global__ __launch_bounds__(256) void k_sw_gather(
+    const uint64_t *__restrict__ key, const uint32_t *__restrict__ idx,
+    const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
+    const double *__restrict__ vx, const double *__restrict__ vy,
+    const double *__restrict__ vz, const double *__restrict__ R,
+    const PatchInfo *__restrict__ patch, uint32_t n, double dt, double *__restrict__ sx,
+    double *__restrict__ sy, double *__restrict__ sz, double *__restrict__ svx,
+    double *__restrict__ svy, double *__restrict__ svz, double *__restrict__ sR,
+    double *__restrict__ shi, uint32_t *__restrict__ orig, uint32_t *__restrict__ nlive) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const uint64_t k = key[s];
+  const bool live = k != RB_KEY_DEAD;
+  const uint32_t j = idx[s];
+  orig[s] = j;
+  if (live) {
+    const double xj = x[j], vxj = vx[j], r = R[j];
+    double lo, hi;
+    rb_sw_extent(xj, vxj, r, dt, patch[0].W, lo, hi);
+    sx[s] = xj; sy[s] = y[j]; sz[s] = z[j];
+    svx[s] = vxj; svy[s] = vy[j]; svz[s] = vz[j];
+    sR[s] = r;
+    shi[s] = hi;
+  }
+  if (live && (s + 1 == n || key[s + 1] == RB_KEY_DEAD)) nlive[0] = s + 1;
+  if (!live && s == 0) nlive[0] = 0;
+}
+
+// The contact test along the two straight trajectories (d = x_j + o_k -
+// x_i, u = v_j + w_k - v_i): in contact now, or, when now separating, at
+// the closest approach within the step (the segment's far end if that
+// approach lies further back).
+__device__ __forceinline__ bool rb_sw_meets(double d0, double d1, double d2, double u0,
+                                            double u1, double u2, double sum, double dt) {
+  if (d0 * d0 + d1 * d1 + d2 * d2 < sum * sum) return true;
+  const double du = d0 * u0 + d1 * u1 + d2 * u2;
+  const double uu = u0 * u0 + u1 * u1 + u2 * u2;
+  if (!(du > 0.0 && uu > 0.0)) return false;
+  double sg = -du / uu;
+  if (sg < -dt) sg = -dt;
+  const double e0 = d0 + u0 * sg, e1 = d1 + u1 * sg, e2 = d2 + u2 * sg;
+  return e0 * e0 + e1 * e1 + e2 * e2 < sum * sum;
+}
+
+// first sorted position whose key is at least v (n if none)
+__device__ __forceinline__ uint32_t rb_sw_lower(const uint64_t *__restrict__ key, uint32_t n,
+                                                uint64_t v) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (key[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// one thread per sorted live interval e: the intervals after it that start
+// before it ends (image ix = 0), then for every ix != 0 the intervals that
+// overlap it once shifted by ix W, kept when e is the lower caller index
+__global__ __launch_bounds__(256) void k_sw_pairs(
+    const uint64_t *__restrict__ key, const uint32_t *__restrict__ orig,
+    const double *__restrict__ sx, const double *__restrict__ sy,
+    const double *__restrict__ sz, const double *__restrict__ svx,
+    const double *__restrict__ svy, const double *__restrict__ svz,
+    const double *__restrict__ sR, const double *__restrict__ shi,
+    const uint32_t *__restrict__ nlive, const PatchInfo *__restrict__ patch, int ngx, int ngy,
+    int boundary, double omega, double t, double dt, SweepGrid g,
+    const unsigned long long *__restrict__ lmax_bits, uint64_t *__restrict__ queue,
+    uint32_t qcap, uint32_t *__restrict__ qcnt, uint32_t *__restrict__ err) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t n = nlive[0];
+  const bool act = r < n;
+  const double W = patch[0].W;
+  const double sh = (boundary == RB_SHEAR) ? remainder(1.5 * omega * W * t, W) : 0.0;
+  const int ngs = (boundary == RB_OPEN) ? 0 : ngx;
+  const int ny = 2 * ngy + 1;
+  // the longest interval, widened against rounding in lo - ix W - L
+  const double L = __longlong_as_double((long long)lmax_bits[0]) * (1.0 + 1e-9) + 1e-9 * W;
+  uint64_t mine[RB_COLL_LOCAL];
+  uint32_t nm = 0;
+  if (act) {
+    const uint32_t pe = orig[r];
+    const double ex = sx[r], ey = sy[r], ez = sz[r];
+    const double evx = svx[r], evy = svy[r], evz = svz[r], eR = sR[r], ehi = shi[r];
+    // e's own start, recomputed as the keys were
+    double elo, ehi2;
+    rb_sw_extent(ex, evx, eR, dt, W, elo, ehi2);
+    for (int c = -ngs; c <= ngs; ++c) {
+      uint32_t f;
+      uint64_t qend;
+      if (c == 0) {
+        f = r + 1;
+        qend = rb_sw_key(ehi, g);
+      } else {
+        const double sft = (double)c * W;
+        qend = rb_sw_key(ehi - sft, g);
+        f = rb_sw_lower(key, n, rb_sw_key((elo - sft) - L, g));
+      }
+      for (; f < n && key[f] <= qend; ++f) {
+        const uint32_t pf = orig[f];
+        if (pf == pe || (c != 0 && pe > pf)) continue;
+        // the lower caller index is i; image ix of j relative to i
+        const bool e_is_i = pe < pf;
+        const uint32_t i = e_is_i ? pe : pf, j = e_is_i ? pf : pe;
+        const int ix = e_is_i ? c : -c;
+        const double fx = sx[f], fy = sy[f], fz = sz[f];
+        const double fvx = svx[f], fvy = svy[f], fvz = svz[f], fR = sR[f];
+        const double xi = e_is_i ? ex : fx, yi = e_is_i ? ey : fy, zi = e_is_i ? ez : fz;
+        const double xj = e_is_i ? fx : ex, yj = e_is_i ? fy : ey, zj = e_is_i ? fz : ez;
+        const double vxi = e_is_i ? evx : fvx, vyi = e_is_i ? evy : fvy;
+        const double vzi = e_is_i ? evz : fvz;
+        const double vxj = e_is_i ? fvx : evx, vyj = e_is_i ? fvy : evy;
+        const double vzj = e_is_i ? fvz : evz;
+        const double sum = (e_is_i ? eR : fR) + (e_is_i ? fR : eR);
+        for (int iy = -ngy; iy <= ngy; ++iy) {
+          const int k = (boundary == RB_OPEN) ? 0 : (ix + ngx) * ny + (iy + ngy);
+          double ox, oy, wy;
+          rb_coll_image(k, ngx, ngy, boundary, W, sh, omega, ox, oy, wy);
+          const double d0 = (xj + ox) - xi;
+          const double d1 = (yj + oy) - yi;
+          const double d2 = (zj + 0.0) - zi;
+          const double u0 = vxj - vxi;
+          const double u1 = (vyj + wy) - vyi;
+          const double u2 = vzj - vzi;
+          if (rb_sw_meets(d0, d1, d2, u0, u1, u2, sum, dt))
+            rb_coll_keep(((uint64_t)i << 35) | ((uint64_t)j << 7) | (uint64_t)k, mine, nm,
+                         queue, qcap, qcnt, err);
+          if (boundary == RB_OPEN) break;
+        }
+      }
+    }
+  }
+  // the rest: one atomic per wave
+  const uint32_t incl = rb_wave_incl_scan(nm);
+  const uint32_t tot = __shfl(incl, 63, 64);
+  uint32_t qbase = 0;
+  if (rb_lane() == 63 && tot) qbase = atomicAdd(qcnt, tot);
+  qbase = __shfl(qbase, 63, 64);
+  const uint32_t at = qbase + incl - nm;
+  for (uint32_t q = 0; q < nm; ++q)
+    if (at + q < qcap) queue[at + q] = mine[q];
+  if (nm && at + nm > qcap) atomicOr(err, RB_ERR_COLL);
+}
+
+static SweepGrid sweep_grid(const rb_ctx *c) {
+  // lo spans about [x0 - W/2, x0 + 3W/2): 2W over the 63-bit grid
+  const double W = c->h_patch[0].W;
+  SweepGrid g;
+  g.base = c->h_patch[0].x0[0] - 0.5 * W;
+  g.scale = 4.0e18 / (2.0 * W);
+  return g;
+}
+
+hipError_t launch_sweep_keys(rb_ctx *c, const double *x, const double *y, const double *z,
+                             const double *vx, const double *radius, double dt) {
+  const uint32_t n = (uint32_t)c->h_starts[1];
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sw_keys, dim3(rb_div_up(n, 256)), dim3(256), 0, c->stream, x, y, z, vx,
+                     radius, c->d_patch, n, c->p.boundary == RB_OPEN ? 1 : 0, dt,
+                     sweep_grid(c), c->d_key[0], c->d_idx[0], c->d_err,
+                     c->sort_small ? c->d_bcnt : nullptr, c->d_bctl, c->d_cmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_pairs(rb_ctx *c, const rb_particles *pp, const double *radius,
+                              double t, double dt) {
+  const uint32_t n = (uint32_t)c->h_starts[1];
+  if (n == 0) return hipSuccess;
+  double **s = c->d_px[0];
+  hipLaunchKernelGGL(k_sw_gather, dim3(rb_div_up(n, 256)), dim3(256), 0, c->stream,
+                     c->d_key[0], c->d_idx[0], pp->x, pp->y, pp->z, pp->vx, pp->vy, pp->vz,
+                     radius, c->d_patch, n, dt, s[0], s[1], s[2], s[3], s[4], s[5], c->d_swR,
+                     c->d_swhi, c->d_orig[0], c->d_nlive);
+  hipLaunchKernelGGL(k_sw_pairs, dim3(rb_div_up(n, 256)), dim3(256), 0, c->stream,
+                     c->d_key[0], c->d_orig[0], s[0], s[1], s[2], s[3], s[4], s[5], c->d_swR,
+                     c->d_swhi, c->d_nlive, c->d_patch, c->p.n_ghost[0], c->p.n_ghost[1],
+                     c->p.boundary, c->p.omega, t, dt, sweep_grid(c), c->d_cmax, c->d_cq[0],
+                     (uint32_t)c->cq_cap, c->d_ccnt, c->d_err);
+  return hipGetLastError();
+}

@@ -867,43 +867,42 @@ int rb_batch_step(rb_ctx *c, rb_particles *p, double t, double dt, int32_t nstep
   return run_step(c, p, t, dt, nsteps);
 }
 
-int rb_collide(rb_ctx *c, rb_particles *p, const double *radius, int64_t n, double t,
-               double epsilon, uint64_t seed, int64_t *n_pairs, int64_t *n_resolved,
-               uint64_t *codes, int64_t codes_cap) {
+// collision buffers, allocated by the first collision call of a context
+static int coll_alloc(rb_ctx *c) {
+  if (c->cap >= (1ull << 28)) return fail(RB_EUNSUPPORTED, "pair codes need n < 2^28");
+  if (c->d_cq[0]) return RB_OK;
+  c->cq_cap = 8 * c->cap + 1024;
+  RB_TRY(dalloc(c, &c->d_cq[0], c->cq_cap));
+  RB_TRY(dalloc(c, &c->d_cq[1], c->cq_cap));
+  RB_TRY(dalloc(c, &c->d_ccnt, 8));
+  c->d_cmax = reinterpret_cast<unsigned long long *>(c->d_ccnt + 4);
+  c->d_cres = reinterpret_cast<unsigned long long *>(c->d_ccnt + 6);
+  RB_HIP(hipHostMalloc((void **)&c->h_cpin, 32, hipHostMallocDefault));
+  RB_TRY(dalloc(c, &c->d_cbest, c->cap));
+  RB_HIP(hipMemsetAsync(c->d_cbest, 0xFF, 8 * c->cap, c->stream));
+  return RB_OK;
+}
+
+static int coll_check_args(rb_ctx *c, rb_particles *p, const double *radius, double t,
+                           double epsilon, uint64_t *codes, int64_t codes_cap) {
   if (!c) return fail(RB_EINVAL, "null context");
   RB_TRY(check_particles(p, true));
   if (!radius) return fail(RB_EINVAL, "null radius array");
   if (!isfinite(t)) return fail(RB_EINVAL, "t must be finite");
   if (!(epsilon >= 0.0 && epsilon <= 1.0)) return fail(RB_EINVAL, "epsilon outside [0, 1]");
   if (codes_cap < 0 || (codes_cap > 0 && !codes)) return fail(RB_EINVAL, "bad code buffer");
-  if (c->batch) {
-    if (n != (int64_t)c->h_starts[c->P]) return fail(RB_EINVAL, "n must be the batch total");
-  } else {
-    RB_TRY(set_single_n(c, n, n));
-  }
-  if (c->cap >= (1ull << 28)) return fail(RB_EUNSUPPORTED, "pair codes need n < 2^28");
-  if (c->node_cap >= (1ull << 27))
-    return fail(RB_EUNSUPPORTED, "the collision search needs fewer than 2^27 nodes");
-  if (!c->d_cq[0]) {
-    c->cq_cap = 8 * c->cap + 1024;
-    RB_TRY(dalloc(c, &c->d_cq[0], c->cq_cap));
-    RB_TRY(dalloc(c, &c->d_cq[1], c->cq_cap));
-    RB_TRY(dalloc(c, &c->d_ccnt, 8));
-    c->d_cmax = reinterpret_cast<unsigned long long *>(c->d_ccnt + 4);
-    c->d_cres = reinterpret_cast<unsigned long long *>(c->d_ccnt + 6);
-    RB_HIP(hipHostMalloc((void **)&c->h_cpin, 32, hipHostMallocDefault));
-    RB_TRY(dalloc(c, &c->d_cbest, c->cap));
-    RB_TRY(dalloc(c, &c->d_cgeo, 4 * c->node_cap));
-    RB_HIP(hipMemsetAsync(c->d_cbest, 0xFF, 8 * c->cap, c->stream));
-  }
-  RB_HIP(hipMemsetAsync(c->d_ccnt, 0, 32, c->stream));
-  RB_TRY(mark(c, PH_TOTAL, true));
-  RB_PHASE(PH_KEYS, launch_keys(c, p->x, p->y, p->z, 0.0));
-  RB_PHASE(PH_SORT, launch_sort(c));
-  RB_PHASE(PH_PERMUTE, launch_permute_gravity(c, p->x, p->y, p->z, p->m, 0));
-  RB_PHASE(PH_TOPO, launch_topology(c));
-  RB_PHASE(PH_COLLIDE, launch_coll_prep(c, radius));
-  RB_PHASE(PH_CSEARCH, launch_coll_detect(c, radius, t));
+  return RB_OK;
+}
+
+// The queue the search left in list 0: optional copy of the codes, then the
+// resolution rounds, each resolving at least the collision first in the
+// whole queue.  A short queue is resolved entirely by one workgroup; a long
+// one first goes through batches of multi-workgroup rounds (whose kernels
+// read the list's length on the device) until it is short.  The first launch
+// saves the number of detected pairs in the third count.
+static int coll_resolve(rb_ctx *c, rb_particles *p, double t, double epsilon, uint64_t seed,
+                        uint64_t *codes, int64_t codes_cap, int64_t *n_pairs,
+                        int64_t *n_resolved) {
   if (codes_cap > 0) {  // the detected pairs, before the rounds reuse their list
     uint32_t cnt = 0;
     RB_HIP(hipMemcpyAsync(&cnt, c->d_ccnt, 4, hipMemcpyDeviceToHost, c->stream));
@@ -913,11 +912,6 @@ int rb_collide(rb_ctx *c, rb_particles *p, const double *radius, int64_t n, doub
       RB_HIP(hipMemcpy(codes, c->d_cq[0], 8 * (size_t)std::min<int64_t>(cnt, codes_cap),
                        hipMemcpyDeviceToHost));
   }
-  // rounds: each resolves at least the collision first in the whole queue.
-  // A short queue is resolved entirely by one workgroup; a long one first
-  // goes through batches of multi-workgroup rounds (whose kernels read the
-  // list's length on the device) until it is short.  The first launch saves
-  // the number of detected pairs in the third count.
   int a = 0;
   uint64_t rounds = 0;
   const uint32_t *h_cnt = c->h_cpin;
@@ -944,6 +938,50 @@ int rb_collide(rb_ctx *c, rb_particles *p, const double *radius, int64_t n, doub
   }
   // (with phase timing on, wait for the last event before reading the timers)
   return (c->p.profile & 1) ? report_device_errors(c) : RB_OK;
+}
+
+int rb_collide(rb_ctx *c, rb_particles *p, const double *radius, int64_t n, double t,
+               double epsilon, uint64_t seed, int64_t *n_pairs, int64_t *n_resolved,
+               uint64_t *codes, int64_t codes_cap) {
+  RB_TRY(coll_check_args(c, p, radius, t, epsilon, codes, codes_cap));
+  if (c->batch) {
+    if (n != (int64_t)c->h_starts[c->P]) return fail(RB_EINVAL, "n must be the batch total");
+  } else {
+    RB_TRY(set_single_n(c, n, n));
+  }
+  if (c->node_cap >= (1ull << 27))
+    return fail(RB_EUNSUPPORTED, "the collision search needs fewer than 2^27 nodes");
+  RB_TRY(coll_alloc(c));
+  if (!c->d_cgeo) RB_TRY(dalloc(c, &c->d_cgeo, 4 * c->node_cap));
+  RB_HIP(hipMemsetAsync(c->d_ccnt, 0, 32, c->stream));
+  RB_TRY(mark(c, PH_TOTAL, true));
+  RB_PHASE(PH_KEYS, launch_keys(c, p->x, p->y, p->z, 0.0));
+  RB_PHASE(PH_SORT, launch_sort(c));
+  RB_PHASE(PH_PERMUTE, launch_permute_gravity(c, p->x, p->y, p->z, p->m, 0));
+  RB_PHASE(PH_TOPO, launch_topology(c));
+  RB_PHASE(PH_COLLIDE, launch_coll_prep(c, radius));
+  RB_PHASE(PH_CSEARCH, launch_coll_detect(c, radius, t));
+  return coll_resolve(c, p, t, epsilon, seed, codes, codes_cap, n_pairs, n_resolved);
+}
+
+int rb_sweep(rb_ctx *c, rb_particles *p, const double *radius, int64_t n, double t, double dt,
+             double epsilon, uint64_t seed, int64_t *n_pairs, int64_t *n_resolved,
+             uint64_t *codes, int64_t codes_cap) {
+  RB_TRY(coll_check_args(c, p, radius, t, epsilon, codes, codes_cap));
+  if (!(dt >= 0.0 && isfinite(dt))) return fail(RB_EINVAL, "dt must be finite and >= 0");
+  if (c->batch) return fail(RB_EUNSUPPORTED, "the plane sweep runs on a single system");
+  RB_TRY(set_single_n(c, n, n));
+  RB_TRY(coll_alloc(c));
+  if (!c->d_swR) {
+    RB_TRY(dalloc(c, &c->d_swR, c->cap));
+    RB_TRY(dalloc(c, &c->d_swhi, c->cap));
+  }
+  RB_HIP(hipMemsetAsync(c->d_ccnt, 0, 32, c->stream));
+  RB_TRY(mark(c, PH_TOTAL, true));
+  RB_PHASE(PH_KEYS, launch_sweep_keys(c, p->x, p->y, p->z, p->vx, radius, dt));
+  RB_PHASE(PH_SORT, launch_sort(c));
+  RB_PHASE(PH_CSEARCH, launch_sweep_pairs(c, p, radius, t, dt));
+  return coll_resolve(c, p, t, epsilon, seed, codes, codes_cap, n_pairs, n_resolved);
 }
 
 int rb_sync(rb_ctx *c) {

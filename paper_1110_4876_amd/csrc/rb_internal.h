@@ -126,6 +126,7 @@ struct rb_ctx {
   unsigned long long *d_cres = nullptr;  // = d_ccnt + 6
   uint32_t *h_cpin = nullptr;            // pinned host copy of the block (8 words)
   double *d_cgeo = nullptr;         // 4 per node: the search's cell records
+  double *d_swR = nullptr, *d_swhi = nullptr;  // plane sweep: sorted radii, interval ends
   double *d_acc = nullptr;          // (n_img or 1) * 3 * cap
 
   // per-call dynamic region [ctr | StepConst | schedule], uploaded from a
@@ -160,11 +161,48 @@ struct rb_ctx {
   std::vector<void *> allocs;
 };
 
+// ---- collisions: shared by the tree search and the plane sweep ----
+#define RB_COLL_LOCAL 8  // pairs a thread keeps before it writes them out
+
+// image k of the ghost boxes: ix outer and iy inner in [-ng, ng] (a single
+// image for open boundaries); position offset and y velocity offset
+__device__ __forceinline__ void rb_coll_image(int k, int ngx, int ngy, int boundary, double W,
+                                              double sh, double omega, double &ox, double &oy,
+                                              double &wy) {
+  if (boundary == RB_OPEN) { ox = oy = wy = 0.0; return; }
+  const int ny = 2 * ngy + 1;
+  const int ix = k / ny - ngx, iy = k % ny - ngy;
+  const double fx = (double)ix, fy = (double)iy;
+  const double s = (boundary == RB_SHEAR) ? sh : 0.0;
+  ox = fx * W;
+  oy = fy * W - fx * s;
+  wy = (boundary == RB_SHEAR) ? -1.5 * omega * W * fx : 0.0;
+}
+
+// queue a pair from the lane's local list, writing the list out when full
+__device__ __forceinline__ void rb_coll_keep(uint64_t code, uint64_t (&mine)[RB_COLL_LOCAL],
+                                             uint32_t &nm, uint64_t *__restrict__ queue,
+                                             uint32_t qcap, uint32_t *__restrict__ qcnt,
+                                             uint32_t *__restrict__ err) {
+  if (nm == RB_COLL_LOCAL) {
+    const uint32_t at = atomicAdd(qcnt, (uint32_t)nm);
+    for (uint32_t q = 0; q < nm; ++q)
+      if (at + q < qcap) queue[at + q] = mine[q];
+    if (at + nm > qcap) atomicOr(err, RB_ERR_COLL);
+    nm = 0;
+  }
+  mine[nm++] = code;
+}
+
 // ---- launchers (each returns hipSuccess or the launch error) ----
 hipError_t launch_keys(rb_ctx *c, const double *x, const double *y, const double *z,
                        double s_unused);
 hipError_t launch_sort(rb_ctx *c);
 hipError_t launch_groups(rb_ctx *c);
+hipError_t launch_sweep_keys(rb_ctx *c, const double *x, const double *y, const double *z,
+                             const double *vx, const double *radius, double dt);
+hipError_t launch_sweep_pairs(rb_ctx *c, const rb_particles *pp, const double *radius,
+                              double t, double dt);
 hipError_t launch_coll_prep(rb_ctx *c, const double *radius);
 hipError_t launch_coll_detect(rb_ctx *c, const double *radius, double t);
 hipError_t launch_coll_rounds1(rb_ctx *c, int a, const rb_particles *pp, double t, double eps,

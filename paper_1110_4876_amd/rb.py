@@ -120,6 +120,11 @@ _SIGS = {
                                   ctypes.c_uint64, ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p,
                                   ctypes.c_int64]),
+    "rb_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rb_particles), ctypes.c_void_p,
+                                ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p,
+                                ctypes.c_int64]),
     "rb_error_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rb_last_error": (ctypes.c_char_p, []),
 }
@@ -323,4 +328,20 @@ def rb_collide(ctx, parts, radius, n: int, t: float, epsilon: float, seed: int,
     check(lib().rb_collide(ctx, ctypes.byref(parts), ctypes.c_void_p(_ptr(radius)), int(n),
                            float(t), float(epsilon), ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF),
                            ctypes.byref(npairs), ctypes.byref(nres), cptr, ccap), "rb_collide")
+    return int(npairs.value), int(nres.value)
+
+
+def rb_sweep(ctx, parts, radius, n: int, t: float, dt: float, epsilon: float, seed: int,
+             codes=None):
+    """Collisions at time t found by the plane sweep along x over the past
+    time-step dt (rb.h); velocities of `parts` change in place.  Returns
+    (pairs, resolved)."""
+    npairs, nres = ctypes.c_int64(0), ctypes.c_int64(0)
+    cptr, ccap = None, 0
+    if codes is not None:
+        cptr, ccap = codes.ctypes.data_as(ctypes.c_void_p), len(codes)
+    check(lib().rb_sweep(ctx, ctypes.byref(parts), ctypes.c_void_p(_ptr(radius)), int(n),
+                         float(t), float(dt), float(epsilon),
+                         ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ctypes.byref(npairs),
+                         ctypes.byref(nres), cptr, ccap), "rb_sweep")
     return int(npairs.value), int(nres.value)

@@ -1,0 +1,168 @@
+"""GPU plane-sweep collisions (Sect. 5) against the oracle: the set of pairs
+whose straight trajectories over the step come within contact (bit-exact
+codes), the number resolved and the velocities after resolving the queue in
+its splitmix64 order, for the shearing sheet (pairs through the periodic x
+boundary, shear velocity of the images), long steps, an open box with
+removed particles, a periodic box, dt = 0 (the overlap set of rb_collide),
+the degenerate cases, and the 50,000-particle sheet."""
+import numpy as np
+import pytest
+
+from paper_1110_4876_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _run_gpu(pr, R, t, dt, eps, seed, fn="sweep"):
+    from gpu_util import Dev, dev, make_ctx
+    from paper_1110_4876_amd import rb
+    ctx = make_ctx(pr)
+    try:
+        d = Dev(pr)
+        r = dev(R)
+        codes = np.zeros(16 * pr.n + 16, dtype=np.uint64)
+        if fn == "sweep":
+            npair, nres = rb.rb_sweep(ctx, d.parts, r, pr.n, t, dt, eps, seed, codes)
+        else:
+            npair, nres = rb.rb_collide(ctx, d.parts, r, pr.n, t, eps, seed, codes)
+        rb.rb_sync(ctx)
+        st = d.state()
+    finally:
+        rb.rb_destroy(ctx)
+    return np.sort(codes[:npair]), npair, nres, st
+
+
+def _compare(orc, pr, R, t, dt, eps, seed, vtol=1e-13):
+    p = orc.make_params(**pr.params)
+    ocodes, onpair, onres, ost = orc.sweep(p, pr.state(), pr.m, R, t, dt, eps, seed)
+    gcodes, gnpair, gnres, gst = _run_gpu(pr, R, t, dt, eps, seed)
+    assert gnpair == onpair
+    np.testing.assert_array_equal(gcodes, np.sort(ocodes))
+    assert gnres == onres
+    for k in ("vx", "vy", "vz"):
+        scale = np.abs(ost[k]).max() + 1e-300
+        assert np.abs(gst[k] - ost[k]).max() <= vtol * scale, k
+    for k in ("x", "y", "z"):
+        np.testing.assert_array_equal(gst[k], pr.state()[k])
+    return onpair, onres, gcodes
+
+
+def _images_ix(codes, ng=1):
+    k = (codes & np.uint64(127)).astype(np.int64)
+    return k // (2 * ng + 1) - ng
+
+
+@pytest.mark.parametrize("n,seed,steps", [(3000, 1, 1), (7000, 2, 1), (4000, 3, 40)])
+def test_sheet_matches_oracle(orc, n, seed, steps):
+    # dt = one step, and forty steps (long trajectories: many pairs found
+    # only along them, and through the x boundary)
+    pr = inputs.sheet(n, seed=seed)
+    R = pr.extra["radius"]
+    npair, nres, codes = _compare(orc, pr, R, 0.37 * pr.dt, steps * pr.dt, 0.5, 1000 + seed)
+    assert npair > n // 4 and nres > 0
+    assert np.any(_images_ix(codes) != 0)
+
+
+def test_sheet_late_time_shear_offset(orc):
+    pr = inputs.sheet(4000, seed=5)
+    _compare(orc, pr, pr.extra["radius"], 731.0 * pr.dt, 3.0 * pr.dt, 1.0, 77)
+
+
+def test_open_box_and_removed_particles(orc):
+    pr = inputs.uniform_sphere(2500, seed=3)
+    rng = np.random.default_rng(4)
+    pr.vx[:] = rng.normal(size=pr.n); pr.vy[:] = rng.normal(size=pr.n)
+    pr.vz[:] = rng.normal(size=pr.n)
+    pr.x[5] = np.nan           # removed
+    pr.x[6] = 1e3              # outside the open box: removed
+    R = rng.uniform(0.01, 0.06, pr.n)
+    npair, nres, _ = _compare(orc, pr, R, 0.0, 0.05, 0.3, 5)
+    assert npair > 100 and nres > 0
+
+
+def test_periodic_box(orc):
+    rng = np.random.default_rng(8)
+    n = 3000
+    W = 10.0
+    x = rng.uniform(-W / 2, W / 2, (n, 3))
+    v = rng.normal(size=(n, 3))
+    m = rng.uniform(0.5, 2.0, n)
+    params = inputs.base_params(G=1.0, b=0.0, W=W, x0=(-W / 2, -W / 2, -W / 2),
+                                boundary=inputs.PERIODIC, ng=(1, 1))
+    pr = inputs.Problem(x[:, 0].copy(), x[:, 1].copy(), x[:, 2].copy(), v[:, 0].copy(),
+                        v[:, 1].copy(), v[:, 2].copy(), m, params, n, 0.1)
+    R = rng.uniform(0.05, 0.25, n)
+    npair, _, codes = _compare(orc, pr, R, 0.0, 0.2, 0.8, 11)
+    assert npair > 100 and np.any(_images_ix(codes) != 0)
+
+
+def test_zero_step_is_the_overlap_set(orc):
+    pr = inputs.sheet(5000, seed=9)
+    R = pr.extra["radius"]
+    a = _run_gpu(pr, R, 0.5 * pr.dt, 0.0, 0.5, 31, fn="sweep")
+    b = _run_gpu(pr, R, 0.5 * pr.dt, 0.0, 0.5, 31, fn="collide")
+    assert a[1] == b[1] and a[2] == b[2] and a[1] > 0
+    np.testing.assert_array_equal(a[0], b[0])
+    for k in ("vx", "vy", "vz"):
+        np.testing.assert_array_equal(a[3][k], b[3][k])
+
+
+def test_degenerate_cases(orc):
+    for n in (1, 2):
+        pr = inputs.sheet(n, seed=3)
+        _compare(orc, pr, np.full(n, 0.5), 0.0, pr.dt, 0.5, 1)
+    # open box: a pair that crossed half a step ago is found, not resolved
+    pr = inputs.uniform_sphere(2, seed=0)
+    pr.x[:] = [-0.15, 0.15]; pr.y[:] = 0.0; pr.z[:] = 0.0
+    pr.vx[:] = [-3.0, 3.0]; pr.vy[:] = 0.0; pr.vz[:] = 0.0
+    codes, npair, nres, st = _run_gpu(pr, np.array([0.1, 0.1]), 0.0, 0.1, 0.5, 3)
+    assert npair == 1 and nres == 0 and int(codes[0]) == (0 << 35) | (1 << 7) | 0
+    np.testing.assert_array_equal(st["vx"], pr.vx)
+    _, npair, _, _ = _run_gpu(pr, np.array([0.1, 0.1]), 0.0, 0.015, 0.5, 3)
+    assert npair == 0
+
+
+def test_batch_context_is_refused():
+    from gpu_util import dev
+    from paper_1110_4876_amd import rb
+    from paper_1110_4876_amd.system import System
+    probs = [inputs.sheet(n, seed=40 + k) for k, n in enumerate((500, 700))]
+    sysm = System(probs)
+    R = np.concatenate([pr.extra["radius"] for pr in probs])
+    ctx = sysm.create(rb.RB_FP64)
+    try:
+        X = sysm.clone()
+        with pytest.raises(rb.RBError):
+            rb.rb_sweep(ctx, sysm.parts(X), dev(R), sysm.n, 0.0, 1.0, 0.5, 1)
+    finally:
+        rb.rb_destroy(ctx)
+
+
+def test_c1_full_size_after_steps(orc):
+    # the 50,000-particle sheet after 20 FP32-mixed steps on the GPU, swept
+    # over the last step
+    from gpu_util import dev
+    from paper_1110_4876_amd import rb
+    from paper_1110_4876_amd.system import System
+    pr = inputs.sheet(50000, seed=0)
+    R = pr.extra["radius"]
+    sysm = System(pr)
+    ctx = sysm.create(rb.RB_FP32_MIXED, theta=0.42, group_size=64, walk_waves=4)
+    try:
+        X = sysm.clone()
+        sysm.step(ctx, X, 0.0, 20)
+        rb.rb_sync(ctx)
+        t = 20 * pr.dt
+        host = {k: X[k].cpu().numpy().copy() for k in ("x", "y", "z", "vx", "vy", "vz")}
+        codes = np.zeros(16 * pr.n, dtype=np.uint64)
+        npair, nres = rb.rb_sweep(ctx, sysm.parts(X), dev(R), pr.n, t, pr.dt, 0.5, 2024, codes)
+        rb.rb_sync(ctx)
+        got = {k: X[k].cpu().numpy() for k in ("vx", "vy", "vz")}
+    finally:
+        rb.rb_destroy(ctx)
+    p = orc.make_params(**pr.params)
+    oc, onp, onr, ost = orc.sweep(p, host, pr.m, R, t, pr.dt, 0.5, 2024)
+    assert npair == onp and nres == onr and npair > 1000
+    np.testing.assert_array_equal(np.sort(codes[:npair]), np.sort(oc))
+    for k in ("vx", "vy", "vz"):
+        assert np.abs(got[k] - ost[k]).max() <= 1e-13 * np.abs(ost[k]).max(), k
