@@ -214,9 +214,15 @@ def collide_run(args, sysm, wdesc):
     ctx = sysm.create(rb.RB_FP32_MIXED, profile=4, **knobs)
     try:
         X = sysm.clone()
+        sweep = args.detector == "sweep"
+
+        def collide(k):
+            if sweep:
+                return rb.rb_sweep(ctx, sysm.parts(X), R, n, (k + 1) * dt, dt, eps, 1000 + k)
+            return rb.rb_collide(ctx, sysm.parts(X), R, n, (k + 1) * dt, eps, 1000 + k)
         for k in range(args.warmup):
             sysm.step(ctx, X, k * dt, 1)
-            rb.rb_collide(ctx, sysm.parts(X), R, n, (k + 1) * dt, eps, 1000 + k)
+            collide(k)
         rb.rb_sync(ctx)
         rb.rb_stats(ctx)  # discard warm-up timers
         pairs = resolved = 0
@@ -224,21 +230,26 @@ def collide_run(args, sysm, wdesc):
         t0 = time.perf_counter()
         for k in range(args.warmup, args.warmup + args.steps):
             sysm.step(ctx, X, k * dt, 1)
-            a, b = rb.rb_collide(ctx, sysm.parts(X), R, n, (k + 1) * dt, eps, 1000 + k)
+            a, b = collide(k)
             pairs += a
             resolved += b
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         s = rb.rb_stats(ctx)
-        n_nodes, n_live = rb.rb_tree_info(ctx)
+        n_nodes, n_live = (0, n) if sweep else rb.rb_tree_info(ctx)
     finally:
         rb.rb_destroy(ctx)
     search_ms = s["ms"]["coll_search"] / max(1, s["calls"]["coll_search"])
     walk_ms = s["ms"]["walk"] / max(1, s["calls"]["walk"])
-    # algorithmic bytes of one search: every live particle's position, radius
-    # and caller index read once (36 B), every cell record once (32 B), every
-    # found pair written once (8 B)
-    algo = 36 * n_live + 32 * n_nodes + 8 * pairs / args.steps
+    # algorithmic bytes of one search.  Tree: every live particle's position,
+    # radius and caller index read once (36 B), every cell record once
+    # (32 B), every found pair written once (8 B).  Sweep: every particle's
+    # sorted record read once (position, velocity, radius, interval end,
+    # key, caller index: 76 B), every found pair written once (8 B).
+    if sweep:
+        algo = 76 * n_live + 8 * pairs / args.steps
+    else:
+        algo = 36 * n_live + 32 * n_nodes + 8 * pairs / args.steps
     achieved = algo / (search_ms * 1e-3)
     cpu = None
     if not args.no_cpu_baseline:
@@ -249,7 +260,11 @@ def collide_run(args, sysm, wdesc):
         k, c0 = 0, time.perf_counter()
         while True:
             st = oracle.step(op, st, pr.m, k * dt, dt, 1, use_tree=True)
-            _, _, _, st = oracle.collide(op, st, pr.m, radius, (k + 1) * dt, eps, 1000 + k)
+            if sweep:
+                _, _, _, st = oracle.sweep(op, st, pr.m, radius, (k + 1) * dt, dt, eps,
+                                           1000 + k)
+            else:
+                _, _, _, st = oracle.collide(op, st, pr.m, radius, (k + 1) * dt, eps, 1000 + k)
             k += 1
             if time.perf_counter() - c0 >= args.cpu_seconds:
                 break
@@ -258,10 +273,11 @@ def collide_run(args, sysm, wdesc):
                "kind": "oracle",
                "sample": f"{k} collisional steps of the same {n}-particle sheet from the "
                          f"initial state (oracle tree gravity at theta={knobs['theta']}, "
-                         f"brute-force overlap search, sequential queue)"}
+                         f"brute-force {'trajectory' if sweep else 'overlap'} search, "
+                         f"sequential queue)"}
     out = {
         "metric": "collisional-sheet particle-steps/s (FP32-mixed tree gravity DKD step + "
-                  "FP64 tree collision search and resolution)",
+                  f"FP64 {'plane-sweep' if sweep else 'tree'} collision search and resolution)",
         "value": n * args.steps / secs,
         "unit": "particle-steps/s",
         "n_gpus": 1,
@@ -274,14 +290,14 @@ def collide_run(args, sysm, wdesc):
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": wdesc + ", collisions at the end of every step, "
-                   f"epsilon={eps}", "n": n, "images": 9, **knobs},
+                   f"epsilon={eps}", "n": n, "images": 9, "detector": args.detector, **knobs},
         "collisions": {"pairs_per_step": pairs / args.steps,
                        "resolved_per_step": resolved / args.steps,
                        "search_ms": search_ms, "walk_ms": walk_ms,
-                       "tree_nodes": n_nodes},
+                       "tree_nodes": n_nodes if not sweep else None},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": 8000.0,
                      "unit": "GB/s", "frac": achieved / 8e12, "traffic": None,
-                     "kernel": "k_coll_detect"},
+                     "kernel": "k_sw_gather + k_sw_pairs" if sweep else "k_coll_detect"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -312,6 +328,10 @@ def main():
                          "hard-sphere resolution at the end of the step (own JSON line)")
     ap.add_argument("--epsilon", type=float, default=0.5,
                     help="coefficient of restitution of the collisional sheet")
+    ap.add_argument("--detector", default="tree", choices=["tree", "sweep"],
+                    help="collision detection of the collisional sheet: the octree search "
+                         "(overlaps at the end of the step) or the plane sweep along x "
+                         "(trajectories over the step)")
     ap.add_argument("--write-traffic", nargs=4, default=None,
                     metavar=("COPY_FETCH", "COPY_WRITE", "WALK_FETCH", "WALK_WRITE"),
                     help="only turn four rocprofv3 --pmc output folders into the stored "

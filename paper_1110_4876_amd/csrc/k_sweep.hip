@@ -158,10 +158,66 @@ __device__ __forceinline__ uint32_t rb_sw_lower(const uint64_t *__restrict__ key
   return lo;
 }
 
-// one thread per sorted live interval e: the intervals after it that start
-// before it ends (image ix = 0), then for every ix != 0 the intervals that
-// overlap it once shifted by ix W, kept when e is the lower caller index
-__global__ __launch_bounds__(256) void k_sw_pairs(
+// A particle record as the pair test reads it.
+struct SwRec {
+  double x, y, z, vx, vy, vz, R;
+  uint32_t p;
+};
+
+// Test interval e (record E) against interval f (record F), F's copy
+// shifted by c W along x; queue the pairs in contact.  The lower caller
+// index is i, and ix is j's image relative to i.  Before the exact test an
+// image iy is skipped when the pair's y separation over the step stays
+// beyond R_i + R_j; that check uses approximate offsets and a margin of
+// 1e-9 (R_i + R_j + W + |u_y dt|), far above their rounding.
+__device__ __forceinline__ void rb_sw_test(const SwRec &E, const SwRec &F, int c, int ngx,
+                                           int ngy, int boundary, double W, double sh,
+                                           double omega, double dt,
+                                           uint64_t (&mine)[RB_COLL_LOCAL], uint32_t &nm,
+                                           uint64_t *__restrict__ queue, uint32_t qcap,
+                                           uint32_t *__restrict__ qcnt,
+                                           uint32_t *__restrict__ err) {
+  const bool e_is_i = E.p < F.p;
+  const SwRec &I = e_is_i ? E : F;
+  const SwRec &J = e_is_i ? F : E;
+  const int ix = e_is_i ? c : -c;
+  const double sum = I.R + J.R;
+  const bool shear = boundary == RB_SHEAR;
+  const double fx = (double)ix;
+  const double dy0 = (J.y - I.y) - (shear ? fx * sh : 0.0);
+  const double uy = (J.vy - I.vy) + (shear ? -1.5 * omega * W * fx : 0.0);
+  const double lim = fabs(sum) + 1e-9 * (fabs(sum) + W + fabs(uy * dt));
+  const int ny = (boundary == RB_OPEN) ? 0 : ngy;
+  for (int iy = -ny; iy <= ny; ++iy) {
+    const double a = dy0 + (double)iy * W;  // y separation now
+    const double b = a - uy * dt;           // and at the start of the step
+    if (fmin(a, b) > lim || fmax(a, b) < -lim) continue;
+    double ox, oy, wy;
+    rb_coll_image_xy(ix, iy, boundary, W, sh, omega, ox, oy, wy);
+    const double d0 = (J.x + ox) - I.x;
+    const double d1 = (J.y + oy) - I.y;
+    const double d2 = (J.z + 0.0) - I.z;
+    const double u0 = J.vx - I.vx;
+    const double u1 = (J.vy + wy) - I.vy;
+    const double u2 = J.vz - I.vz;
+    if (rb_sw_meets(d0, d1, d2, u0, u1, u2, sum, dt)) {
+      const int k = (boundary == RB_OPEN) ? 0 : (ix + ngx) * (2 * ngy + 1) + (iy + ngy);
+      rb_coll_keep(((uint64_t)I.p << 35) | ((uint64_t)J.p << 7) | (uint64_t)k, mine, nm,
+                   queue, qcap, qcnt, err);
+    }
+  }
+}
+
+#define SW_SUB 16                // lanes per interval
+#define SW_EPB (64 / SW_SUB)     // intervals per workgroup (one wave)
+
+// One wave per SW_EPB consecutive sorted live intervals, SW_SUB lanes per
+// interval (lane sub takes every SW_SUB-th candidate).  Image ix = 0: the
+// intervals after e that start before it ends, read from chunks of 64
+// staged in LDS.  Then for every ix != 0 the intervals that overlap e once
+// shifted by ix W, read directly (they exist only near the x boundaries),
+// kept when e is the lower caller index.
+__global__ __launch_bounds__(64) void k_sw_pairs(
     const uint64_t *__restrict__ key, const uint32_t *__restrict__ orig,
     const double *__restrict__ sx, const double *__restrict__ sy,
     const double *__restrict__ sz, const double *__restrict__ svx,
@@ -171,66 +227,84 @@ __global__ __launch_bounds__(256) void k_sw_pairs(
     int boundary, double omega, double t, double dt, SweepGrid g,
     const unsigned long long *__restrict__ lmax_bits, uint64_t *__restrict__ queue,
     uint32_t qcap, uint32_t *__restrict__ qcnt, uint32_t *__restrict__ err) {
-  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ uint64_t c_key[64];
+  __shared__ double c_x[64], c_y[64], c_z[64], c_vx[64], c_vy[64], c_vz[64], c_R[64];
+  __shared__ uint32_t c_p[64];
+  const uint32_t lane = threadIdx.x;
+  const uint32_t sub = lane % SW_SUB;
+  const uint32_t r0 = blockIdx.x * SW_EPB;
+  const uint32_t r = r0 + lane / SW_SUB;
   const uint32_t n = nlive[0];
+  if (r0 >= n) return;  // uniform over the wave
   const bool act = r < n;
   const double W = patch[0].W;
   const double sh = (boundary == RB_SHEAR) ? remainder(1.5 * omega * W * t, W) : 0.0;
   const int ngs = (boundary == RB_OPEN) ? 0 : ngx;
-  const int ny = 2 * ngy + 1;
-  // the longest interval, widened against rounding in lo - ix W - L
-  const double L = __longlong_as_double((long long)lmax_bits[0]) * (1.0 + 1e-9) + 1e-9 * W;
   uint64_t mine[RB_COLL_LOCAL];
   uint32_t nm = 0;
+  SwRec E;
+  double ehi = 0.0;
   if (act) {
-    const uint32_t pe = orig[r];
-    const double ex = sx[r], ey = sy[r], ez = sz[r];
-    const double evx = svx[r], evy = svy[r], evz = svz[r], eR = sR[r], ehi = shi[r];
-    // e's own start, recomputed as the keys were
-    double elo, ehi2;
-    rb_sw_extent(ex, evx, eR, dt, W, elo, ehi2);
-    for (int c = -ngs; c <= ngs; ++c) {
-      uint32_t f;
-      uint64_t qend;
-      if (c == 0) {
-        f = r + 1;
-        qend = rb_sw_key(ehi, g);
-      } else {
-        const double sft = (double)c * W;
-        qend = rb_sw_key(ehi - sft, g);
-        f = rb_sw_lower(key, n, rb_sw_key((elo - sft) - L, g));
+    E.x = sx[r]; E.y = sy[r]; E.z = sz[r];
+    E.vx = svx[r]; E.vy = svy[r]; E.vz = svz[r];
+    E.R = sR[r]; E.p = orig[r];
+    ehi = shi[r];
+  }
+  // image ix = 0, chunks staged in LDS
+  {
+    const uint64_t qend = act ? rb_sw_key(ehi, g) : 0ull;
+    bool going = act;
+    for (uint32_t base = r0 + 1; base < n; base += 64) {
+      const uint32_t f = base + lane;
+      if (f < n) {
+        c_key[lane] = key[f];
+        c_x[lane] = sx[f]; c_y[lane] = sy[f]; c_z[lane] = sz[f];
+        c_vx[lane] = svx[f]; c_vy[lane] = svy[f]; c_vz[lane] = svz[f];
+        c_R[lane] = sR[f];
+        c_p[lane] = orig[f];
       }
-      for (; f < n && key[f] <= qend; ++f) {
-        const uint32_t pf = orig[f];
-        if (pf == pe || (c != 0 && pe > pf)) continue;
-        // the lower caller index is i; image ix of j relative to i
-        const bool e_is_i = pe < pf;
-        const uint32_t i = e_is_i ? pe : pf, j = e_is_i ? pf : pe;
-        const int ix = e_is_i ? c : -c;
-        const double fx = sx[f], fy = sy[f], fz = sz[f];
-        const double fvx = svx[f], fvy = svy[f], fvz = svz[f], fR = sR[f];
-        const double xi = e_is_i ? ex : fx, yi = e_is_i ? ey : fy, zi = e_is_i ? ez : fz;
-        const double xj = e_is_i ? fx : ex, yj = e_is_i ? fy : ey, zj = e_is_i ? fz : ez;
-        const double vxi = e_is_i ? evx : fvx, vyi = e_is_i ? evy : fvy;
-        const double vzi = e_is_i ? evz : fvz;
-        const double vxj = e_is_i ? fvx : evx, vyj = e_is_i ? fvy : evy;
-        const double vzj = e_is_i ? fvz : evz;
-        const double sum = (e_is_i ? eR : fR) + (e_is_i ? fR : eR);
-        for (int iy = -ngy; iy <= ngy; ++iy) {
-          const int k = (boundary == RB_OPEN) ? 0 : (ix + ngx) * ny + (iy + ngy);
-          double ox, oy, wy;
-          rb_coll_image(k, ngx, ngy, boundary, W, sh, omega, ox, oy, wy);
-          const double d0 = (xj + ox) - xi;
-          const double d1 = (yj + oy) - yi;
-          const double d2 = (zj + 0.0) - zi;
-          const double u0 = vxj - vxi;
-          const double u1 = (vyj + wy) - vyi;
-          const double u2 = vzj - vzi;
-          if (rb_sw_meets(d0, d1, d2, u0, u1, u2, sum, dt))
-            rb_coll_keep(((uint64_t)i << 35) | ((uint64_t)j << 7) | (uint64_t)k, mine, nm,
-                         queue, qcap, qcnt, err);
-          if (boundary == RB_OPEN) break;
+      __syncthreads();
+      if (going) {
+        const uint32_t hi = min(64u, n - base);
+        for (uint32_t q = ((r + 1 > base) ? r + 1 - base : 0u) + sub; q < hi; q += SW_SUB) {
+          if (c_key[q] > qend) {
+            going = false;
+            break;
+          }
+          SwRec F;
+          F.x = c_x[q]; F.y = c_y[q]; F.z = c_z[q];
+          F.vx = c_vx[q]; F.vy = c_vy[q]; F.vz = c_vz[q];
+          F.R = c_R[q]; F.p = c_p[q];
+          if (F.p != E.p)
+            rb_sw_test(E, F, 0, ngx, ngy, boundary, W, sh, omega, dt, mine, nm, queue, qcap,
+                       qcnt, err);
         }
+      }
+      // (every lane reaches this barrier: the loop bounds are uniform)
+      if (!__syncthreads_or(going)) break;
+    }
+  }
+  // images ix != 0 (both ends of the sorted list, near the x boundaries)
+  if (act && ngs > 0) {
+    // the longest interval, widened against rounding in lo - ix W - L
+    const double L =
+        __longlong_as_double((long long)lmax_bits[0]) * (1.0 + 1e-9) + 1e-9 * W;
+    double elo, ehi2;
+    rb_sw_extent(E.x, E.vx, E.R, dt, W, elo, ehi2);
+    for (int c = -ngs; c <= ngs; ++c) {
+      if (c == 0) continue;
+      const double sft = (double)c * W;
+      const uint64_t qend = rb_sw_key(ehi - sft, g);
+      for (uint32_t f = rb_sw_lower(key, n, rb_sw_key((elo - sft) - L, g)) + sub;
+           f < n && key[f] <= qend; f += SW_SUB) {
+        const uint32_t pf = orig[f];
+        if (pf <= E.p) continue;  // kept from the lower caller index only
+        SwRec F;
+        F.x = sx[f]; F.y = sy[f]; F.z = sz[f];
+        F.vx = svx[f]; F.vy = svy[f]; F.vz = svz[f];
+        F.R = sR[f]; F.p = pf;
+        rb_sw_test(E, F, c, ngx, ngy, boundary, W, sh, omega, dt, mine, nm, queue, qcap,
+                   qcnt, err);
       }
     }
   }
@@ -275,7 +349,7 @@ hipError_t launch_sweep_pairs(rb_ctx *c, const rb_particles *pp, const double *r
                      c->d_key[0], c->d_idx[0], pp->x, pp->y, pp->z, pp->vx, pp->vy, pp->vz,
                      radius, c->d_patch, n, dt, s[0], s[1], s[2], s[3], s[4], s[5], c->d_swR,
                      c->d_swhi, c->d_orig[0], c->d_nlive);
-  hipLaunchKernelGGL(k_sw_pairs, dim3(rb_div_up(n, 256)), dim3(256), 0, c->stream,
+  hipLaunchKernelGGL(k_sw_pairs, dim3(rb_div_up(n, SW_EPB)), dim3(64), 0, c->stream,
                      c->d_key[0], c->d_orig[0], s[0], s[1], s[2], s[3], s[4], s[5], c->d_swR,
                      c->d_swhi, c->d_nlive, c->d_patch, c->p.n_ghost[0], c->p.n_ghost[1],
                      c->p.boundary, c->p.omega, t, dt, sweep_grid(c), c->d_cmax, c->d_cq[0],

@@ -166,17 +166,21 @@ struct rb_ctx {
 
 // image k of the ghost boxes: ix outer and iy inner in [-ng, ng] (a single
 // image for open boundaries); position offset and y velocity offset
-__device__ __forceinline__ void rb_coll_image(int k, int ngx, int ngy, int boundary, double W,
-                                              double sh, double omega, double &ox, double &oy,
-                                              double &wy) {
+__device__ __forceinline__ void rb_coll_image_xy(int ix, int iy, int boundary, double W,
+                                                 double sh, double omega, double &ox,
+                                                 double &oy, double &wy) {
   if (boundary == RB_OPEN) { ox = oy = wy = 0.0; return; }
-  const int ny = 2 * ngy + 1;
-  const int ix = k / ny - ngx, iy = k % ny - ngy;
   const double fx = (double)ix, fy = (double)iy;
   const double s = (boundary == RB_SHEAR) ? sh : 0.0;
   ox = fx * W;
   oy = fy * W - fx * s;
   wy = (boundary == RB_SHEAR) ? -1.5 * omega * W * fx : 0.0;
+}
+__device__ __forceinline__ void rb_coll_image(int k, int ngx, int ngy, int boundary, double W,
+                                              double sh, double omega, double &ox, double &oy,
+                                              double &wy) {
+  const int ny = 2 * ngy + 1;
+  rb_coll_image_xy(k / ny - ngx, k % ny - ngy, boundary, W, sh, omega, ox, oy, wy);
 }
 
 // queue a pair from the lane's local list, writing the list out when full
