@@ -269,9 +269,14 @@ int rb_collide(rb_ctx *ctx, rb_particles *p, const double *radius, int64_t n, do
                double epsilon, uint64_t seed, int64_t *n_pairs, int64_t *n_resolved,
                uint64_t *codes, int64_t codes_cap);
 
+/* rb_sweep's axis: along x, or along the azimuth around the z axis */
+enum { RB_SWEEP_X = 0, RB_SWEEP_PHI = 1 };
+
 /*
- * Collisions found by the plane sweep along x (Sect. 5 of the paper), for a
- * single system (not a batch context), at time t after a time-step dt >= 0.
+ * Collisions found by the plane sweep (Sect. 5 of the paper), along x or
+ * along the azimuthal angle phi = atan2(y, x) measured around the z axis
+ * through the origin, for a single system (not a batch context), at time t
+ * after a time-step dt >= 0.
  * Each particle's trajectory over the step is the straight line through its
  * present position with its present velocity, x + v sigma for sigma in
  * [-dt, 0].  Live particles i < j (caller indices) and ghost image k of j
@@ -279,8 +284,9 @@ int rb_collide(rb_ctx *ctx, rb_particles *p, const double *radius, int64_t n, do
  * -3/2 omega W ix) collide when those lines come closer than R_i + R_j: in
  * contact now, or, for a pair now separating, at their closest approach
  * within the step.  The intervals that the trajectories (widened by the
- * radii) cover along x are sorted, and each is checked against the ones
- * it overlaps, also across the periodic x boundary.  The collisions form
+ * radii) cover along the axis are sorted, and each is checked against the
+ * ones it overlaps, also across the periodic x boundary, or across phi =
+ * +-pi.  The found set does not depend on the axis.  The collisions form
  * the same queue (ascending splitmix64(seed + code)) and are resolved as
  * by rb_collide: only pairs approaching now are resolved, so a pair that
  * met during the step and is now separating is found but left as it is.
@@ -288,15 +294,18 @@ int rb_collide(rb_ctx *ctx, rb_particles *p, const double *radius, int64_t n, do
  *             rb_collide.
  *  dt         the time-step the trajectories span; 0 finds exactly the
  *             pairs that rb_collide finds.
- * Synchronises.  Errors: RB_EINVAL (null pointer, epsilon, dt, n),
- * RB_EUNSUPPORTED (batch context, capacity >= 2^28), RB_ECAPACITY (more
+ *  axis       RB_SWEEP_X (any boundary) or RB_SWEEP_PHI (open box only:
+ *             narrow rings in global simulations).
+ * Synchronises.  Errors: RB_EINVAL (null pointer, epsilon, dt, n, axis),
+ * RB_EUNSUPPORTED (batch context, phi without an open box, capacity >=
+ * 2^28), RB_ECAPACITY (more
  * than 8 pairs per particle), RB_EOUTSIDE (a particle outside a periodic or
  * shear axis).  The context's tree is not kept (the sort reuses its
  * buffers).  Phase times: "coll_search" is the sweep, "collide" the
  * resolution rounds.
  */
 int rb_sweep(rb_ctx *ctx, rb_particles *p, const double *radius, int64_t n, double t,
-             double dt, double epsilon, uint64_t seed, int64_t *n_pairs,
+             double dt, int32_t axis, double epsilon, uint64_t seed, int64_t *n_pairs,
              int64_t *n_resolved, uint64_t *codes, int64_t codes_cap);
 
 /* Synchronise the context's stream and return any deferred device error. */

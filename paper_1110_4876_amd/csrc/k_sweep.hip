@@ -60,14 +60,53 @@ __device__ __forceinline__ void rb_sw_extent(double x, double vx, double R, doub
   hi = fmax(x, xs) + r + pad;
 }
 
+// The azimuthal sweep (global simulations, open box): the trajectory's
+// extent in phi = atan2(y, x) around the z axis, widened by the angle the
+// radius subtends at the segment's closest approach to the axis (a sphere
+// of radius R whose centre is at least rho from the axis lies within
+// asin(R / rho) of its centre's angle); a segment that passes within R of
+// the axis covers every angle.  lo is brought into [-pi, pi); hi = lo + len.
+#define RB_PI 3.141592653589793
+__device__ __forceinline__ void rb_sw_phi_extent(double x, double y, double vx, double vy,
+                                                 double R, double dt, double &lo,
+                                                 double &hi) {
+  double mx = vx * dt, my = vy * dt;
+  if (isnan(mx) || isnan(my)) mx = my = 0.0;  // only the present position counts
+  const double x0 = x - mx, y0 = y - my;    // start of the step
+  const double p1 = atan2(y, x), p0 = atan2(y0, x0);
+  double dp = p1 - p0;
+  if (dp > RB_PI) dp -= 2.0 * RB_PI;
+  if (dp < -RB_PI) dp += 2.0 * RB_PI;
+  // closest approach of the segment to the axis
+  const double dd = mx * mx + my * my;
+  double u = dd > 0.0 ? -(x0 * mx + y0 * my) / dd : 0.0;
+  u = fmin(fmax(u, 0.0), 1.0);
+  const double qx = x0 + u * mx, qy = y0 + u * my;
+  const double rho = sqrt(qx * qx + qy * qy);
+  const double r = fabs(R);
+  double a = -RB_PI, len = 2.0 * RB_PI;
+  if (rho > r * (1.0 + 1e-6) + 1e-300) {
+    const double half = asin(r / rho) * (1.0 + 1e-9) + 1e-12;
+    const double l = fabs(dp) + 2.0 * half + 1e-9 * (1.0 + fabs(dp));
+    if (l < 2.0 * RB_PI) {
+      len = l;
+      a = fmin(p0, p0 + dp) - half - 0.5e-9 * (1.0 + fabs(dp));
+      if (a < -RB_PI) a += 2.0 * RB_PI;
+      if (a >= RB_PI) a -= 2.0 * RB_PI;
+    }
+  }
+  lo = a;
+  hi = a + len;
+}
+
 // keys of the caller's particles (live: inside the box, radius a number)
 __global__ __launch_bounds__(256) void k_sw_keys(
     const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
-    const double *__restrict__ vx, const double *__restrict__ R,
-    const PatchInfo *__restrict__ patch, uint32_t n, int open_xy, double dt, SweepGrid g,
-    uint64_t *__restrict__ key, uint32_t *__restrict__ idx, uint32_t *__restrict__ err,
-    uint32_t *__restrict__ bcnt, uint32_t *__restrict__ bctl,
-    unsigned long long *__restrict__ lmax) {
+    const double *__restrict__ vx, const double *__restrict__ vy,
+    const double *__restrict__ R, const PatchInfo *__restrict__ patch, uint32_t n,
+    int open_xy, int phi, double dt, SweepGrid g, uint64_t *__restrict__ key,
+    uint32_t *__restrict__ idx, uint32_t *__restrict__ err, uint32_t *__restrict__ bcnt,
+    uint32_t *__restrict__ bctl, unsigned long long *__restrict__ lmax) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   double len = 0.0;
   if (s < n) {
@@ -82,7 +121,10 @@ __global__ __launch_bounds__(256) void k_sw_keys(
       const double r = R[s];
       if (!isnan(r)) {
         double lo, hi;
-        rb_sw_extent(xs, vx[s], r, dt, pi.W, lo, hi);
+        if (phi)
+          rb_sw_phi_extent(xs, ys, vx[s], vy[s], r, dt, lo, hi);
+        else
+          rb_sw_extent(xs, vx[s], r, dt, pi.W, lo, hi);
         k = (isnan(lo) || isnan(hi)) ? RB_KEY_DEAD : rb_sw_key(lo, g);
         if (k != RB_KEY_DEAD) len = hi - lo;
       }
@@ -108,7 +150,8 @@ __global__ __launch_bounds__(256) void k_sw_gather(
     const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
     const double *__restrict__ vx, const double *__restrict__ vy,
     const double *__restrict__ vz, const double *__restrict__ R,
-    const PatchInfo *__restrict__ patch, uint32_t n, double dt, double *__restrict__ sx,
+    const PatchInfo *__restrict__ patch, uint32_t n, int phi, double dt,
+    double *__restrict__ sx,
     double *__restrict__ sy, double *__restrict__ sz, double *__restrict__ svx,
     double *__restrict__ svy, double *__restrict__ svz, double *__restrict__ sR,
     double *__restrict__ shi, uint32_t *__restrict__ orig, uint32_t *__restrict__ nlive) {
@@ -119,11 +162,14 @@ __global__ __launch_bounds__(256) void k_sw_gather(
   const uint32_t j = idx[s];
   orig[s] = j;
   if (live) {
-    const double xj = x[j], vxj = vx[j], r = R[j];
+    const double xj = x[j], yj = y[j], vxj = vx[j], vyj = vy[j], r = R[j];
     double lo, hi;
-    rb_sw_extent(xj, vxj, r, dt, patch[0].W, lo, hi);
-    sx[s] = xj; sy[s] = y[j]; sz[s] = z[j];
-    svx[s] = vxj; svy[s] = vy[j]; svz[s] = vz[j];
+    if (phi)
+      rb_sw_phi_extent(xj, yj, vxj, vyj, r, dt, lo, hi);
+    else
+      rb_sw_extent(xj, vxj, r, dt, patch[0].W, lo, hi);
+    sx[s] = xj; sy[s] = yj; sz[s] = z[j];
+    svx[s] = vxj; svy[s] = vyj; svz[s] = vz[j];
     sR[s] = r;
     shi[s] = hi;
   }
@@ -320,39 +366,117 @@ __global__ __launch_bounds__(64) void k_sw_pairs(
   if (nm && at + nm > qcap) atomicOr(err, RB_ERR_COLL);
 }
 
-static SweepGrid sweep_grid(const rb_ctx *c) {
-  // lo spans about [x0 - W/2, x0 + 3W/2): 2W over the 63-bit grid
-  const double W = c->h_patch[0].W;
+// The azimuthal sweep: one wave per SW_EPB consecutive sorted intervals,
+// SW_SUB lanes per interval.  The angle is periodic, so interval e checks
+// the intervals that overlap it directly (c = 0) or through a turn
+// (c = +-1: its own interval shifted by -c 2 pi): for each c the sorted
+// intervals starting after lo_e - c 2 pi - L and before hi_e - c 2 pi.  A
+// pair is a single pair whatever c (there are no images), so it is kept
+// from its lower caller index, and only for the first c whose range holds
+// it.
+__global__ __launch_bounds__(64) void k_sw_pairs_phi(
+    const uint64_t *__restrict__ key, const uint32_t *__restrict__ orig,
+    const double *__restrict__ sx, const double *__restrict__ sy,
+    const double *__restrict__ sz, const double *__restrict__ svx,
+    const double *__restrict__ svy, const double *__restrict__ svz,
+    const double *__restrict__ sR, const uint32_t *__restrict__ nlive,
+    const PatchInfo *__restrict__ patch, double dt, SweepGrid g,
+    const unsigned long long *__restrict__ lmax_bits, uint64_t *__restrict__ queue,
+    uint32_t qcap, uint32_t *__restrict__ qcnt, uint32_t *__restrict__ err) {
+  const uint32_t lane = threadIdx.x;
+  const uint32_t sub = lane % SW_SUB;
+  const uint32_t r = blockIdx.x * SW_EPB + lane / SW_SUB;
+  const uint32_t n = nlive[0];
+  const bool act = r < n;
+  const double W = patch[0].W;
+  uint64_t mine[RB_COLL_LOCAL];
+  uint32_t nm = 0;
+  if (act) {
+    SwRec E;
+    E.x = sx[r]; E.y = sy[r]; E.z = sz[r];
+    E.vx = svx[r]; E.vy = svy[r]; E.vz = svz[r];
+    E.R = sR[r]; E.p = orig[r];
+    double elo, ehi;
+    rb_sw_phi_extent(E.x, E.y, E.vx, E.vy, E.R, dt, elo, ehi);
+    const double L = __longlong_as_double((long long)lmax_bits[0]) * (1.0 + 1e-9) + 1e-9;
+    uint64_t qs[3], qe[3];
+    for (int c = -1; c <= 1; ++c) {
+      const double sft = (double)c * 2.0 * RB_PI;
+      qs[c + 1] = rb_sw_key((elo - sft) - L, g);
+      qe[c + 1] = rb_sw_key(ehi - sft, g);
+    }
+    for (int c = -1; c <= 1; ++c) {
+      for (uint32_t f = rb_sw_lower(key, n, qs[c + 1]) + sub; f < n && key[f] <= qe[c + 1];
+           f += SW_SUB) {
+        const uint32_t pf = orig[f];
+        if (pf <= E.p) continue;  // kept from the lower caller index only
+        const uint64_t kf = key[f];
+        bool seen = false;
+        for (int c2 = -1; c2 < c; ++c2) seen |= kf >= qs[c2 + 1] && kf <= qe[c2 + 1];
+        if (seen) continue;
+        SwRec F;
+        F.x = sx[f]; F.y = sy[f]; F.z = sz[f];
+        F.vx = svx[f]; F.vy = svy[f]; F.vz = svz[f];
+        F.R = sR[f]; F.p = pf;
+        rb_sw_test(E, F, 0, 0, 0, RB_OPEN, W, 0.0, 0.0, dt, mine, nm, queue, qcap, qcnt, err);
+      }
+    }
+  }
+  // the rest: one atomic per wave
+  const uint32_t incl = rb_wave_incl_scan(nm);
+  const uint32_t tot = __shfl(incl, 63, 64);
+  uint32_t qbase = 0;
+  if (rb_lane() == 63 && tot) qbase = atomicAdd(qcnt, tot);
+  qbase = __shfl(qbase, 63, 64);
+  const uint32_t at = qbase + incl - nm;
+  for (uint32_t q = 0; q < nm; ++q)
+    if (at + q < qcap) queue[at + q] = mine[q];
+  if (nm && at + nm > qcap) atomicOr(err, RB_ERR_COLL);
+}
+
+static SweepGrid sweep_grid(const rb_ctx *c, int phi) {
+  // lo spans about [x0 - W/2, x0 + 3W/2): 2W over the 63-bit grid (phi:
+  // x0 = -pi, W = 2 pi)
+  const double W = phi ? 2.0 * RB_PI : c->h_patch[0].W;
+  const double x0 = phi ? -RB_PI : c->h_patch[0].x0[0];
   SweepGrid g;
-  g.base = c->h_patch[0].x0[0] - 0.5 * W;
+  g.base = x0 - 0.5 * W;
   g.scale = 4.0e18 / (2.0 * W);
   return g;
 }
 
-hipError_t launch_sweep_keys(rb_ctx *c, const double *x, const double *y, const double *z,
-                             const double *vx, const double *radius, double dt) {
+hipError_t launch_sweep_keys(rb_ctx *c, const rb_particles *pp, const double *radius,
+                             double dt, int phi) {
   const uint32_t n = (uint32_t)c->h_starts[1];
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sw_keys, dim3(rb_div_up(n, 256)), dim3(256), 0, c->stream, x, y, z, vx,
-                     radius, c->d_patch, n, c->p.boundary == RB_OPEN ? 1 : 0, dt,
-                     sweep_grid(c), c->d_key[0], c->d_idx[0], c->d_err,
-                     c->sort_small ? c->d_bcnt : nullptr, c->d_bctl, c->d_cmax);
+  hipLaunchKernelGGL(k_sw_keys, dim3(rb_div_up(n, 256)), dim3(256), 0, c->stream, pp->x,
+                     pp->y, pp->z, pp->vx, pp->vy, radius, c->d_patch, n,
+                     c->p.boundary == RB_OPEN ? 1 : 0, phi, dt, sweep_grid(c, phi), c->d_key[0],
+                     c->d_idx[0], c->d_err, c->sort_small ? c->d_bcnt : nullptr, c->d_bctl,
+                     c->d_cmax);
   return hipGetLastError();
 }
 
 hipError_t launch_sweep_pairs(rb_ctx *c, const rb_particles *pp, const double *radius,
-                              double t, double dt) {
+                              double t, double dt, int phi) {
   const uint32_t n = (uint32_t)c->h_starts[1];
   if (n == 0) return hipSuccess;
   double **s = c->d_px[0];
   hipLaunchKernelGGL(k_sw_gather, dim3(rb_div_up(n, 256)), dim3(256), 0, c->stream,
                      c->d_key[0], c->d_idx[0], pp->x, pp->y, pp->z, pp->vx, pp->vy, pp->vz,
-                     radius, c->d_patch, n, dt, s[0], s[1], s[2], s[3], s[4], s[5], c->d_swR,
-                     c->d_swhi, c->d_orig[0], c->d_nlive);
+                     radius, c->d_patch, n, phi, dt, s[0], s[1], s[2], s[3], s[4], s[5],
+                     c->d_swR, c->d_swhi, c->d_orig[0], c->d_nlive);
+  if (phi) {
+    hipLaunchKernelGGL(k_sw_pairs_phi, dim3(rb_div_up(n, SW_EPB)), dim3(64), 0, c->stream,
+                       c->d_key[0], c->d_orig[0], s[0], s[1], s[2], s[3], s[4], s[5],
+                       c->d_swR, c->d_nlive, c->d_patch, dt, sweep_grid(c, 1), c->d_cmax,
+                       c->d_cq[0], (uint32_t)c->cq_cap, c->d_ccnt, c->d_err);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_sw_pairs, dim3(rb_div_up(n, SW_EPB)), dim3(64), 0, c->stream,
                      c->d_key[0], c->d_orig[0], s[0], s[1], s[2], s[3], s[4], s[5], c->d_swR,
                      c->d_swhi, c->d_nlive, c->d_patch, c->p.n_ghost[0], c->p.n_ghost[1],
-                     c->p.boundary, c->p.omega, t, dt, sweep_grid(c), c->d_cmax, c->d_cq[0],
+                     c->p.boundary, c->p.omega, t, dt, sweep_grid(c, 0), c->d_cmax, c->d_cq[0],
                      (uint32_t)c->cq_cap, c->d_ccnt, c->d_err);
   return hipGetLastError();
 }

@@ -965,11 +965,15 @@ int rb_collide(rb_ctx *c, rb_particles *p, const double *radius, int64_t n, doub
 }
 
 int rb_sweep(rb_ctx *c, rb_particles *p, const double *radius, int64_t n, double t, double dt,
-             double epsilon, uint64_t seed, int64_t *n_pairs, int64_t *n_resolved,
-             uint64_t *codes, int64_t codes_cap) {
+             int32_t axis, double epsilon, uint64_t seed, int64_t *n_pairs,
+             int64_t *n_resolved, uint64_t *codes, int64_t codes_cap) {
   RB_TRY(coll_check_args(c, p, radius, t, epsilon, codes, codes_cap));
   if (!(dt >= 0.0 && isfinite(dt))) return fail(RB_EINVAL, "dt must be finite and >= 0");
+  if (axis != RB_SWEEP_X && axis != RB_SWEEP_PHI) return fail(RB_EINVAL, "axis must be 0 or 1");
   if (c->batch) return fail(RB_EUNSUPPORTED, "the plane sweep runs on a single system");
+  if (axis == RB_SWEEP_PHI && c->p.boundary != RB_OPEN)
+    return fail(RB_EUNSUPPORTED, "the azimuthal sweep needs an open box");
+  const int phi = axis == RB_SWEEP_PHI ? 1 : 0;
   RB_TRY(set_single_n(c, n, n));
   RB_TRY(coll_alloc(c));
   if (!c->d_swR) {
@@ -978,9 +982,9 @@ int rb_sweep(rb_ctx *c, rb_particles *p, const double *radius, int64_t n, double
   }
   RB_HIP(hipMemsetAsync(c->d_ccnt, 0, 32, c->stream));
   RB_TRY(mark(c, PH_TOTAL, true));
-  RB_PHASE(PH_KEYS, launch_sweep_keys(c, p->x, p->y, p->z, p->vx, radius, dt));
+  RB_PHASE(PH_KEYS, launch_sweep_keys(c, p, radius, dt, phi));
   RB_PHASE(PH_SORT, launch_sort(c));
-  RB_PHASE(PH_CSEARCH, launch_sweep_pairs(c, p, radius, t, dt));
+  RB_PHASE(PH_CSEARCH, launch_sweep_pairs(c, p, radius, t, dt, phi));
   return coll_resolve(c, p, t, epsilon, seed, codes, codes_cap, n_pairs, n_resolved);
 }
 

@@ -203,10 +203,10 @@ hipError_t launch_keys(rb_ctx *c, const double *x, const double *y, const double
                        double s_unused);
 hipError_t launch_sort(rb_ctx *c);
 hipError_t launch_groups(rb_ctx *c);
-hipError_t launch_sweep_keys(rb_ctx *c, const double *x, const double *y, const double *z,
-                             const double *vx, const double *radius, double dt);
+hipError_t launch_sweep_keys(rb_ctx *c, const rb_particles *pp, const double *radius,
+                             double dt, int phi);
 hipError_t launch_sweep_pairs(rb_ctx *c, const rb_particles *pp, const double *radius,
-                              double t, double dt);
+                              double t, double dt, int phi);
 hipError_t launch_coll_prep(rb_ctx *c, const double *radius);
 hipError_t launch_coll_detect(rb_ctx *c, const double *radius, double t);
 hipError_t launch_coll_rounds1(rb_ctx *c, int a, const rb_particles *pp, double t, double eps,

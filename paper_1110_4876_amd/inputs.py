@@ -17,6 +17,9 @@ patches, Sect. 6.1 and Sect. 7; no dataset is involved):
 * ``e1_box``    -- the force-accuracy set-up of Sect. 6.1: random particles
                    of different masses in a box.
 * ``batch``     -- many independent sheet patches of uneven size.
+* ``ring``      -- a narrow ring of colliding particles on circular orbits
+                   around the origin, in an open box (a global simulation,
+                   for the azimuthal plane sweep of Sect. 5).
 """
 from __future__ import annotations
 
@@ -148,6 +151,45 @@ def sheet_from_rng(rng, n: int, tau: float = 0.5, omega: float = 1.95e-4,
 
 def sheet(n: int, seed: int = 0, **kw) -> Problem:
     return sheet_from_rng(np.random.default_rng(seed), n, **kw)
+
+
+def ring(n: int, seed: int = 0, r0: float = 1.0, width: float = 0.01, tau: float = 0.5,
+         GM: float = 1.0, sigma_rel: float = 2.0) -> Problem:
+    """Narrow ring around a central mass GM at the origin (the central body
+    itself is not a particle), open box.
+
+    Draw order: radii by inverse CDF of dN/dR ~ R^-3 on [1, 4] (n uniforms,
+    scaled below), orbital radius r ~ U(r0 - width/2, r0 + width/2) (n),
+    azimuth ~ U(-pi, pi) (n), z ~ N(0, R_i) (n), velocity dispersions
+    N(0, sigma) for the three components (n each), sigma = sigma_rel times
+    the mean radius times the orbital frequency at r0.  The radii are scaled
+    so that the ring's optical depth sum(pi R^2) / (2 pi r0 width) is tau.
+    Velocities: circular Keplerian speed sqrt(GM / r) along the azimuth plus
+    the dispersion.  Density 1 (masses 4/3 pi R^3).  dt is 1e-3 of the
+    orbital period at r0.
+    """
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(0.0, 1.0, n)
+    Rt = (1.0 - u * (1.0 - 4.0 ** -2)) ** -0.5
+    scale = math.sqrt(tau * 2.0 * math.pi * r0 * width / float(np.sum(math.pi * Rt * Rt)))
+    R = Rt * scale
+    r = rng.uniform(r0 - width / 2, r0 + width / 2, n)
+    ph = rng.uniform(-math.pi, math.pi, n)
+    z = rng.normal(0.0, 1.0, n) * R
+    om = math.sqrt(GM / r0 ** 3)
+    sig = sigma_rel * float(np.mean(R)) * om
+    dv = rng.normal(0.0, sig, (3, n))
+    vk = np.sqrt(GM / r)
+    x, y = r * np.cos(ph), r * np.sin(ph)
+    vx = -vk * np.sin(ph) + dv[0]
+    vy = vk * np.cos(ph) + dv[1]
+    vz = dv[2]
+    m = 4.0 / 3.0 * math.pi * R ** 3
+    W = 2.2 * (r0 + width)
+    params = base_params(G=1.0, b=0.0, W=W, x0=(-W / 2, -W / 2, -W / 2), boundary=OPEN)
+    dt = 1e-3 * 2.0 * math.pi / om
+    return Problem(x, y, z, vx, vy, vz, m, params, n, dt, 0.0, f"ring{n}",
+                   dict(radius=R, tau=tau))
 
 
 def e1_box(n: int = 1000, seed: int = 0, theta: float = 0.5,

@@ -20,6 +20,7 @@ RB_OK, RB_EINVAL, RB_ENOMEM, RB_EHIP, RB_ECAPACITY, RB_EOUTSIDE, RB_EUNSUPPORTED
     0, -1, -2, -3, -4, -5, -6, -7)
 RB_OPEN, RB_PERIODIC, RB_SHEAR = 0, 1, 2
 RB_FP64, RB_FP32_MIXED = 0, 1
+RB_SWEEP_X, RB_SWEEP_PHI = 0, 1
 RB_DRIFT_LEAPFROG, RB_DRIFT_EPICYCLE = 0, 1
 
 PHASES = ["keys", "sort", "permute", "topology", "moments", "walk", "kick_drift", "direct",
@@ -122,7 +123,8 @@ _SIGS = {
                                   ctypes.c_int64]),
     "rb_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rb_particles), ctypes.c_void_p,
                                 ctypes.c_int64, ctypes.c_double, ctypes.c_double,
-                                ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int64),
+                                ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
+                                ctypes.POINTER(ctypes.c_int64),
                                 ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p,
                                 ctypes.c_int64]),
     "rb_error_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -332,16 +334,16 @@ def rb_collide(ctx, parts, radius, n: int, t: float, epsilon: float, seed: int,
 
 
 def rb_sweep(ctx, parts, radius, n: int, t: float, dt: float, epsilon: float, seed: int,
-             codes=None):
-    """Collisions at time t found by the plane sweep along x over the past
-    time-step dt (rb.h); velocities of `parts` change in place.  Returns
-    (pairs, resolved)."""
+             codes=None, axis: int = 0):
+    """Collisions at time t found by the plane sweep over the past time-step
+    dt (rb.h), along x (axis RB_SWEEP_X) or the azimuth (RB_SWEEP_PHI);
+    velocities of `parts` change in place.  Returns (pairs, resolved)."""
     npairs, nres = ctypes.c_int64(0), ctypes.c_int64(0)
     cptr, ccap = None, 0
     if codes is not None:
         cptr, ccap = codes.ctypes.data_as(ctypes.c_void_p), len(codes)
     check(lib().rb_sweep(ctx, ctypes.byref(parts), ctypes.c_void_p(_ptr(radius)), int(n),
-                         float(t), float(dt), float(epsilon),
+                         float(t), float(dt), int(axis), float(epsilon),
                          ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ctypes.byref(npairs),
                          ctypes.byref(nres), cptr, ccap), "rb_sweep")
     return int(npairs.value), int(nres.value)

@@ -4,7 +4,8 @@ codes), the number resolved and the velocities after resolving the queue in
 its splitmix64 order, for the shearing sheet (pairs through the periodic x
 boundary, shear velocity of the images), long steps, an open box with
 removed particles, a periodic box, dt = 0 (the overlap set of rb_collide),
-the degenerate cases, and the 50,000-particle sheet."""
+the degenerate cases, and the 50,000-particle sheet; the azimuthal sweep
+for narrow rings and an open sphere (particles near the axis)."""
 import numpy as np
 import pytest
 
@@ -13,7 +14,7 @@ from paper_1110_4876_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-def _run_gpu(pr, R, t, dt, eps, seed, fn="sweep"):
+def _run_gpu(pr, R, t, dt, eps, seed, fn="sweep", axis=0):
     from gpu_util import Dev, dev, make_ctx
     from paper_1110_4876_amd import rb
     ctx = make_ctx(pr)
@@ -22,7 +23,8 @@ def _run_gpu(pr, R, t, dt, eps, seed, fn="sweep"):
         r = dev(R)
         codes = np.zeros(16 * pr.n + 16, dtype=np.uint64)
         if fn == "sweep":
-            npair, nres = rb.rb_sweep(ctx, d.parts, r, pr.n, t, dt, eps, seed, codes)
+            npair, nres = rb.rb_sweep(ctx, d.parts, r, pr.n, t, dt, eps, seed, codes,
+                                      axis=axis)
         else:
             npair, nres = rb.rb_collide(ctx, d.parts, r, pr.n, t, eps, seed, codes)
         rb.rb_sync(ctx)
@@ -32,10 +34,10 @@ def _run_gpu(pr, R, t, dt, eps, seed, fn="sweep"):
     return np.sort(codes[:npair]), npair, nres, st
 
 
-def _compare(orc, pr, R, t, dt, eps, seed, vtol=1e-13):
+def _compare(orc, pr, R, t, dt, eps, seed, vtol=1e-13, axis=0):
     p = orc.make_params(**pr.params)
     ocodes, onpair, onres, ost = orc.sweep(p, pr.state(), pr.m, R, t, dt, eps, seed)
-    gcodes, gnpair, gnres, gst = _run_gpu(pr, R, t, dt, eps, seed)
+    gcodes, gnpair, gnres, gst = _run_gpu(pr, R, t, dt, eps, seed, axis=axis)
     assert gnpair == onpair
     np.testing.assert_array_equal(gcodes, np.sort(ocodes))
     assert gnres == onres
@@ -166,3 +168,46 @@ def test_c1_full_size_after_steps(orc):
     np.testing.assert_array_equal(np.sort(codes[:npair]), np.sort(oc))
     for k in ("vx", "vy", "vz"):
         assert np.abs(got[k] - ost[k]).max() <= 1e-13 * np.abs(ost[k]).max(), k
+
+
+@pytest.mark.parametrize("n,steps", [(5000, 1), (20000, 1), (20000, 6)])
+def test_phi_ring_matches_oracle(orc, n, steps):
+    # a narrow ring around the origin: pairs through phi = +-pi included
+    pr = inputs.ring(n, seed=n + steps)
+    R = pr.extra["radius"]
+    # particles 0 and 1 overlap across the cut at phi = +-pi
+    for k, ph in ((0, np.pi - 1e-4), (1, -np.pi + 1e-4)):
+        pr.x[k], pr.y[k] = np.cos(ph), np.sin(ph)
+        pr.vx[k], pr.vy[k] = -np.sin(ph), np.cos(ph)
+    npair, nres, codes = _compare(orc, pr, R, 0.0, steps * pr.dt, 0.5, 17, axis=1)
+    assert npair > n // 50 and nres > 0
+    assert (0 << 35) | (1 << 7) in set(int(c) for c in codes)
+
+
+def test_phi_and_x_agree_on_open_sphere(orc):
+    # particles near the z axis cover every angle; both axes give the
+    # oracle's set
+    pr = inputs.uniform_sphere(3000, seed=12)
+    rng = np.random.default_rng(13)
+    pr.vx[:] = rng.normal(size=pr.n); pr.vy[:] = rng.normal(size=pr.n)
+    pr.vz[:] = rng.normal(size=pr.n)
+    pr.x[:10] *= 1e-3; pr.y[:10] *= 1e-3   # on the axis
+    R = rng.uniform(0.01, 0.05, pr.n)
+    a = _compare(orc, pr, R, 0.0, 0.04, 0.4, 21, axis=1)
+    b = _compare(orc, pr, R, 0.0, 0.04, 0.4, 21, axis=0)
+    np.testing.assert_array_equal(a[2], b[2])
+    assert a[0] > 100
+
+
+def test_phi_needs_an_open_box():
+    from gpu_util import Dev, dev, make_ctx
+    from paper_1110_4876_amd import rb
+    pr = inputs.sheet(500, seed=1)
+    ctx = make_ctx(pr)
+    try:
+        d = Dev(pr)
+        with pytest.raises(rb.RBError):
+            rb.rb_sweep(ctx, d.parts, dev(pr.extra["radius"]), pr.n, 0.0, pr.dt, 0.5, 1,
+                        axis=1)
+    finally:
+        rb.rb_destroy(ctx)
