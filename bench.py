@@ -303,6 +303,98 @@ def collide_run(args, sysm, wdesc):
     print(json.dumps(out), flush=True)
 
 
+def sweep_ring_run(args):
+    """A narrow ring of 50,000 colliding particles around the origin (optical
+    depth 0.5, width 0.01 of the radius, open box): K calls of rb_sweep along
+    the azimuth over one time-step (detection and resolution), after W
+    untimed calls; the x sweep and the tree search (rb_collide) timed the
+    same way on the same state."""
+    import numpy as np
+    import torch
+    from paper_1110_4876_amd import inputs, rb
+    from paper_1110_4876_amd.system import System
+    pr = inputs.ring(50000, seed=0)
+    sysm = System(pr)
+    n, dt = pr.n, pr.dt
+    R = torch.as_tensor(pr.extra["radius"], dtype=torch.float64, device="cuda")
+    steps = args.steps
+    warm = args.warmup
+
+    def run(kind):
+        ctx = sysm.create(rb.RB_FP64, profile=4)
+        try:
+            X = sysm.clone()
+
+            def call(k):
+                if kind == "tree":
+                    return rb.rb_collide(ctx, sysm.parts(X), R, n, 0.0, 0.5, 1000 + k)
+                axis = rb.RB_SWEEP_PHI if kind == "phi" else rb.RB_SWEEP_X
+                return rb.rb_sweep(ctx, sysm.parts(X), R, n, 0.0, dt, 0.5, 1000 + k,
+                                   axis=axis)
+            for k in range(warm):
+                call(k)
+            rb.rb_sync(ctx)
+            rb.rb_stats(ctx)
+            pairs = 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(warm, warm + steps):
+                pairs += call(k)[0]
+            torch.cuda.synchronize()
+            secs = time.perf_counter() - t0
+            s = rb.rb_stats(ctx)
+        finally:
+            rb.rb_destroy(ctx)
+        return (secs, pairs / steps,
+                s["ms"]["coll_search"] / max(1, s["calls"]["coll_search"]))
+    res = {k: run(k) for k in ("phi", "x", "tree")}
+    secs, pairs, search_ms = res["phi"]
+    algo = 76 * n + 8 * pairs
+    achieved = algo / (search_ms * 1e-3)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        op = oracle.make_params(**pr.params)
+        radius = np.asarray(pr.extra["radius"], dtype=np.float64)
+        k, c0 = 0, time.perf_counter()
+        while True:
+            oracle.sweep(op, pr.state(), pr.m, radius, 0.0, dt, 0.5, 1000 + k)
+            k += 1
+            if time.perf_counter() - c0 >= args.cpu_seconds:
+                break
+        cs = time.perf_counter() - c0
+        cpu = {"value": n * k / cs, "unit": "particles/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"{k} calls of the oracle's trajectory collision search "
+                         f"(brute force over all pairs) with resolution on the same ring"}
+    out = {
+        "metric": "ring collision-search particles/s (azimuthal plane sweep over one "
+                  "time-step, FP64, with resolution)",
+        "value": n * steps / secs,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": secs * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "ring50k: narrow ring N=50000 around the origin, tau=0.5, "
+                               "width 0.01 r0, open box, dt = 1e-3 orbital period",
+                   "n": n},
+        "pairs_per_call": pairs,
+        "compare_ms_per_call": {k: v[0] * 1e3 / steps for k, v in res.items()},
+        "search_ms": {k: v[2] for k, v in res.items()},
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": 8000.0,
+                     "unit": "GB/s", "frac": achieved / 8e12, "traffic": None,
+                     "kernel": "k_sw_gather + k_sw_pairs_phi"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,6 +424,11 @@ def main():
                     help="collision detection of the collisional sheet: the octree search "
                          "(overlaps at the end of the step) or the plane sweep along x "
                          "(trajectories over the step)")
+    ap.add_argument("--sweep-ring", action="store_true",
+                    help="collision search on a narrow ring around the origin (50,000 "
+                         "particles, open box): the azimuthal plane sweep, timed per call, "
+                         "with the x sweep and the tree search on the same state beside it "
+                         "(own JSON line)")
     ap.add_argument("--write-traffic", nargs=4, default=None,
                     metavar=("COPY_FETCH", "COPY_WRITE", "WALK_FETCH", "WALK_WRITE"),
                     help="only turn four rocprofv3 --pmc output folders into the stored "
@@ -362,6 +459,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_read_bytes": nbytes, "copy_write_bytes": nbytes, "launches": 5}))
+        return
+    if args.sweep_ring:
+        sweep_ring_run(args)
         return
     prob, wdesc = workload(args.workload)
     sysm = System(prob)
