@@ -185,6 +185,67 @@ def write_traffic(args):
     print(json.dumps(meta))
 
 
+def build_traffic(args):
+    """Turn rocprofv3 --pmc runs over every kernel of a bench run (FETCH_SIZE
+    and WRITE_SIZE, plus the copy calibration runs) into HBM bytes per step
+    of the build kernels: the dispatches between the fourth and the last
+    walk launch (the timed steps) grouped by kernel, each kernel's mean
+    scaled by the copy's true bytes / counter reading and multiplied by its
+    dispatches per step.  Prints one JSON object."""
+    import csv
+    import glob
+    cf, cw, af, aw = args.build_traffic
+    copy_bytes = (args.calibrate_copy or 512) << 20
+
+    def rows(d, counter):
+        out = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if r["Counter_Name"] == counter:
+                        out.append((int(r["Dispatch_Id"]), r["Kernel_Name"].split("(")[0]
+                                    .replace("void ", ""), float(r["Counter_Value"])))
+        return sorted(out)
+
+    mean = lambda v: sum(v) / len(v)
+    scale = {}
+    for c, d in (("FETCH_SIZE", cf), ("WRITE_SIZE", cw)):
+        v = [x for _, k, x in rows(d, c) if "copyBuffer" in k]
+        scale[c] = copy_bytes / 1024 / mean(v)
+    per_kernel = {}
+    steps = None
+    for c, d in (("FETCH_SIZE", af), ("WRITE_SIZE", aw)):
+        rs = rows(d, c)
+        walks = [i for i, (_, k, _) in enumerate(rs) if k.startswith("k_walk32")]
+        lo, hi = walks[3], walks[-1]
+        window = rs[lo:hi]
+        steps = sum(1 for _, k, _ in window if k.startswith("k_walk32"))
+        for _, k, x in window:
+            if k.startswith("k_walk") or "copyBuffer" in k or "fillBuffer" in k:
+                continue
+            e = per_kernel.setdefault(k, {"FETCH_SIZE": [], "WRITE_SIZE": []})
+            e[c].append(x * 1024 * scale[c])
+    out = {"steps": steps, "kernels": {}}
+    tot = 0.0
+    for k, e in sorted(per_kernel.items()):
+        f = sum(e["FETCH_SIZE"]) / steps
+        w = sum(e["WRITE_SIZE"]) / steps
+        out["kernels"][k] = {"fetch_bytes_per_step": f, "write_bytes_per_step": w,
+                             "dispatches_per_step": len(e["FETCH_SIZE"]) / steps}
+        tot += f + w
+    out["build_bytes_per_step"] = tot
+    out["copy_scale"] = scale
+    print(json.dumps(out))
+
+
+def build_bytes(n, n_nodes, small_sort):
+    """Algorithmic HBM bytes of one step's build (keys, sort, permute,
+    topology, moments, kick and drift): per particle keys 36, sort 48 (bucket
+    sort) or 192 (eight radix passes), permute 128, topology 30, drift and
+    kick 96; moments 1.5 x 120 per node."""
+    return n * (36 + (48 if small_sort else 192) + 128 + 30 + 96) + 180.0 * n_nodes
+
+
 def collide_run(args, sysm, wdesc):
     """Collisional sheet: K steps, each one DKD step of FP32-mixed tree
     gravity (rb_step) and then collisions at the end of the step
@@ -429,6 +490,11 @@ def main():
                          "particles, open box): the azimuthal plane sweep, timed per call, "
                          "with the x sweep and the tree search on the same state beside it "
                          "(own JSON line)")
+    ap.add_argument("--build-traffic", nargs=4, default=None,
+                    metavar=("COPY_FETCH", "COPY_WRITE", "ALL_FETCH", "ALL_WRITE"),
+                    help="only turn rocprofv3 --pmc folders of the copy calibration and of "
+                         "a bench run over every kernel into the build's HBM bytes per step "
+                         "(runs without a GPU) and exit")
     ap.add_argument("--write-traffic", nargs=4, default=None,
                     metavar=("COPY_FETCH", "COPY_WRITE", "WALK_FETCH", "WALK_WRITE"),
                     help="only turn four rocprofv3 --pmc output folders into the stored "
@@ -436,6 +502,9 @@ def main():
     args = ap.parse_args()
     if args.write_traffic:
         write_traffic(args)
+        return
+    if args.build_traffic:
+        build_traffic(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
@@ -493,6 +562,7 @@ def main():
         try:
             sysm.gravity(ctx, t_kick)
             s = rb.rb_stats(ctx)
+            s["n_nodes"] = rb.rb_tree_info(ctx)[0]
         finally:
             rb.rb_destroy(ctx)
         flops = (FLOP_OPEN * s["open_tests"] + FLOP_MONO * s["pp"] +
@@ -578,6 +648,13 @@ def main():
                                                pp=st["pp"]),
                              algorithmic_flops_per_walk=flops,
                              interactions_per_s=(st["cells"] + st["pp"]) / (walk_ms * 1e-3))
+        # the build (everything but the walk) against HBM: algorithmic bytes
+        # over the step time the walk leaves
+        b_ms = ms_step - walk_ms
+        b_bytes = build_bytes(n, st["n_nodes"], n <= (1 << 18))
+        results[path]["build"] = dict(ms_per_step=b_ms, algorithmic_bytes=b_bytes,
+                                      achieved_GBps=b_bytes / (b_ms * 1e-3) / 1e9,
+                                      frac_of_hbm=b_bytes / (b_ms * 1e-3) / 8e12)
         log(f"[{path}] {ms_step:.3f} ms/step, walk {walk_ms:.3f} ms, "
             f"{results[path]['particle_steps_per_s']:.3e} particle-steps/s, "
             f"end-of-run rms {err_end['rms']:.3e}")
@@ -626,6 +703,7 @@ def main():
                    "hip_graph": bool(r["use_graph"])},
         "paths": results,
         "roofline": roofline,
+        "build": r["build"],
         "cpu_baseline": cpu,
     }
     if "fp64" in results and "fp32" in results:
