@@ -490,6 +490,9 @@ def main():
                          "particles, open box): the azimuthal plane sweep, timed per call, "
                          "with the x sweep and the tree search on the same state beside it "
                          "(own JSON line)")
+    ap.add_argument("--peaks", action="store_true",
+                    help="only measure this GPU's FP32 (unpacked) and FP64 FMA rates and "
+                         "its streaming-copy HBM rate, print them as JSON and exit")
     ap.add_argument("--build-traffic", nargs=4, default=None,
                     metavar=("COPY_FETCH", "COPY_WRITE", "ALL_FETCH", "ALL_WRITE"),
                     help="only turn rocprofv3 --pmc folders of the copy calibration and of "
@@ -520,6 +523,13 @@ def main():
     from paper_1110_4876_amd.system import System
 
     torch.cuda.set_device(0)
+    if args.peaks:
+        f32, f64, hbm = (rb.rb_peak_probe(k) for k in (0, 1, 2))
+        print(json.dumps({"fp32_unpacked_tflops": f32 / 1e12, "fp64_tflops": f64 / 1e12,
+                          "hbm_copy_tbps": hbm / 1e12,
+                          "published": {"fp32_packed_tflops": PEAK_F32 / 1e12,
+                                        "fp64_tflops": PEAK_F64 / 1e12, "hbm_tbps": 8.0}}))
+        return
     if args.calibrate_copy:
         nbytes = args.calibrate_copy << 20
         a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")

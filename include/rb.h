@@ -308,6 +308,17 @@ int rb_sweep(rb_ctx *ctx, rb_particles *p, const double *radius, int64_t n, doub
              double dt, int32_t axis, double epsilon, uint64_t seed, int64_t *n_pairs,
              int64_t *n_resolved, uint64_t *codes, int64_t codes_cap);
 
+/*
+ * Measured ceilings of the current GPU, for the rooflines (diagnostics, not
+ * part of any step): kind 0 = FP32 vector FMA rate as this library compiles
+ * FP32 (unpacked), 1 = FP64 vector FMA rate (flop/s, an FMA counting 2),
+ * 2 = HBM rate of a 2 GiB streaming copy (bytes read + written per s).
+ * Best of four timed launches on the null stream; allocates and frees its
+ * own buffers (4 GiB for kind 2).  Synchronises.  Errors: RB_EINVAL (kind,
+ * null value), RB_EHIP.
+ */
+int rb_peak_probe(int32_t kind, double *value);
+
 /* Synchronise the context's stream and return any deferred device error. */
 int rb_sync(rb_ctx *ctx);
 

@@ -127,6 +127,7 @@ _SIGS = {
                                 ctypes.POINTER(ctypes.c_int64),
                                 ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p,
                                 ctypes.c_int64]),
+    "rb_peak_probe": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "rb_error_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rb_last_error": (ctypes.c_char_p, []),
 }
@@ -347,3 +348,11 @@ def rb_sweep(ctx, parts, radius, n: int, t: float, dt: float, epsilon: float, se
                          ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ctypes.byref(npairs),
                          ctypes.byref(nres), cptr, ccap), "rb_sweep")
     return int(npairs.value), int(nres.value)
+
+
+def rb_peak_probe(kind: int) -> float:
+    """Measured GPU ceiling (rb.h): 0 FP32 FMA flop/s (unpacked), 1 FP64 FMA
+    flop/s, 2 HBM bytes/s of a streaming copy."""
+    v = ctypes.c_double(0.0)
+    check(lib().rb_peak_probe(int(kind), ctypes.byref(v)), "rb_peak_probe")
+    return float(v.value)
