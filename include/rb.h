@@ -199,7 +199,10 @@ int rb_tree_build(rb_ctx *ctx, const rb_particles *p, int64_t n, int64_t n_activ
 int rb_tree_info(rb_ctx *ctx, int64_t *n_nodes, int64_t *n_live);
 
 /* Synchronise and copy the last tree to host buffers (single system or
- * patch `patch` of a batch; node indices are patch-local). */
+ * patch `patch` of a batch; node indices are patch-local).  The last tree
+ * must come from rb_tree_build, rb_gravity or an FP64 step: an FP32-mixed
+ * step keeps FP64 moments only where its build needs them, and rb_collide /
+ * rb_sweep reuse the tree's buffers; then RB_EUNSUPPORTED. */
 int rb_tree_export(rb_ctx *ctx, int32_t patch, rb_tree_host *out);
 
 /*

@@ -99,17 +99,22 @@ __device__ __forceinline__ void mom_child_q(Mom &a, double M, double x, double y
   a.Q5 += q[5] + M * (3.0 * d2 * d2 - dd);
 }
 
+// fp64: write the FP64 records (links, centre of mass and mass, S, Q); the
+// FP32 walk's record is written whenever wn is given
 __device__ __forceinline__ void mom_store(uint32_t id, const Mom &a, NodeLink lk,
                                           NodeLink *__restrict__ link,
                                           double4 *__restrict__ mcom, double *__restrict__ Sarr,
-                                          double *__restrict__ Qarr, WNode *__restrict__ wn) {
-  link[id] = lk;
-  mcom[id] = make_double4(a.c0, a.c1, a.c2, a.M);
-  Sarr[3 * (size_t)id + 0] = a.S0;
-  Sarr[3 * (size_t)id + 1] = a.S1;
-  Sarr[3 * (size_t)id + 2] = a.S2;
-  double *q = Qarr + 6 * (size_t)id;
-  q[0] = a.Q0; q[1] = a.Q1; q[2] = a.Q2; q[3] = a.Q3; q[4] = a.Q4; q[5] = a.Q5;
+                                          double *__restrict__ Qarr, WNode *__restrict__ wn,
+                                          bool fp64 = true) {
+  if (fp64) {
+    link[id] = lk;
+    mcom[id] = make_double4(a.c0, a.c1, a.c2, a.M);
+    Sarr[3 * (size_t)id + 0] = a.S0;
+    Sarr[3 * (size_t)id + 1] = a.S1;
+    Sarr[3 * (size_t)id + 2] = a.S2;
+    double *q = Qarr + 6 * (size_t)id;
+    q[0] = a.Q0; q[1] = a.Q1; q[2] = a.Q2; q[3] = a.Q3; q[4] = a.Q4; q[5] = a.Q5;
+  }
   if (wn) {
     WNode r;
     r.cx = a.c0; r.cy = a.c1; r.cz = a.c2; r.M = a.M;
@@ -393,7 +398,9 @@ __device__ __forceinline__ void rb_wave_sync() {
 // node list.  Levels are then done bottom-up with the particles and the
 // previous level's node values in LDS; a node's leader lane (the lane of its
 // first slot) sums its children or particles in order, exactly as
-// rb_node_moments does.
+// rb_node_moments does.  With roots_only (FP32-mixed steps, where only the
+// walk's node records are read), the FP64 records are written for the run's
+// subtree roots alone: the large nodes above them read those.
 __global__ __launch_bounds__(128) void k_moments_group(
     const WalkItem *__restrict__ items, const WalkItem *__restrict__ items_mid, uint64_t wcap,
     const uint32_t *__restrict__ gctr, const uint64_t *__restrict__ key, const uint32_t *__restrict__ starts,
@@ -403,7 +410,7 @@ __global__ __launch_bounds__(128) void k_moments_group(
     const double *__restrict__ sy, const double *__restrict__ sz,
     const double *__restrict__ msrc, int L, int quad, NodeLink *__restrict__ link,
     double4 *__restrict__ mcom, double *__restrict__ Sarr, double *__restrict__ Qarr,
-    WNode *__restrict__ wn, uint32_t *__restrict__ err) {
+    WNode *__restrict__ wn, int roots_only, uint32_t *__restrict__ err) {
   // two independent waves per workgroup (fewer workgroups to dispatch),
   // each with its own LDS slice; within a wave LDS accesses stay in order,
   // so a wave-level fence orders its writes and reads
@@ -529,7 +536,7 @@ __global__ __launch_bounds__(128) void k_moments_group(
           lk.skip = skip;
           lk.count = end - lane;
           lk.lvl = (uint32_t)l | (is_leaf ? 256u : 0u) | ((uint32_t)__popcll(kids) << 9);
-          mom_store(id, a, lk, link, mcom, Sarr, Qarr, wn);
+          mom_store(id, a, lk, link, mcom, Sarr, Qarr, wn, !roots_only || l == l0);
         } else {
           atomicOr(err, RB_ERR_TREE);
         }
@@ -726,7 +733,8 @@ hipError_t launch_groups(rb_ctx *c) {
   return hipGetLastError();
 }
 
-hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const double *sz) {
+hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const double *sz,
+                          bool roots_only) {
   const uint32_t n = (uint32_t)c->h_starts[c->P];
   if (n == 0) return hipSuccess;
   const uint32_t G = (uint32_t)c->p.group_size;
@@ -743,7 +751,7 @@ hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const d
                      c->d_witems_mid, c->cap, c->d_gctr, c->d_key[0], c->d_starts, c->d_csr, c->d_start_ids, c->d_nskip,
                      c->d_nlevel, c->d_lev_off, sx, sy, sz, c->d_msrc, c->p.leaf_size,
                      c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, wnode,
-                     c->d_err);
+                     (wnode && roots_only) ? 1 : 0, c->d_err);
   // bottom large nodes are disjoint subtrees of more than G particles each
   unsigned bgrid = rb_div_up(n / (G + 1) + 1, 64);
   if (bgrid > 2048) bgrid = 2048;

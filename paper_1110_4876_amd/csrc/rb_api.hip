@@ -526,6 +526,7 @@ int build_tree(rb_ctx *c, const rb_particles *p) {
   RB_PHASE(PH_PERMUTE, launch_permute_gravity(c, p->x, p->y, p->z, p->m, 0));
   RB_PHASE(PH_TOPO, launch_topology(c));
   RB_PHASE(PH_MOMENTS, launch_moments(c, c->d_px[0][0], c->d_px[0][1], c->d_px[0][2]));
+  c->fp64_partial = false;
   return RB_OK;
 }
 
@@ -568,7 +569,9 @@ int step_kernels(rb_ctx *c, int src) {
   RB_PHASE(PH_SORT, launch_sort(c));
   RB_PHASE(PH_PERMUTE, launch_permute_state(c, src, dst));
   RB_PHASE(PH_TOPO, launch_topology(c));
-  RB_PHASE(PH_MOMENTS, launch_moments(c, c->d_px[dst][0], c->d_px[dst][1], c->d_px[dst][2]));
+  RB_PHASE(PH_MOMENTS, launch_moments(c, c->d_px[dst][0], c->d_px[dst][1], c->d_px[dst][2],
+                                      c->p.precision == RB_FP32_MIXED));
+  c->fp64_partial = c->p.precision == RB_FP32_MIXED;
   RB_TRY(walk(c, dst, src));
   RB_PHASE(PH_POST, launch_post(c, dst, src));
   return RB_OK;
@@ -760,6 +763,10 @@ int rb_tree_info(rb_ctx *c, int64_t *n_nodes, int64_t *n_live) {
 int rb_tree_export(rb_ctx *c, int32_t patch, rb_tree_host *o) {
   if (!c || !o) return fail(RB_EINVAL, "null argument");
   if (patch < 0 || (uint32_t)patch >= c->P) return fail(RB_EINVAL, "patch out of range");
+  if (c->fp64_partial)
+    return fail(RB_EUNSUPPORTED,
+                "the last tree has no complete FP64 moments (an FP32-mixed step or a "
+                "collision search built it): call rb_tree_build first");
   RB_TRY(report_device_errors(c));
   uint32_t off[RB_NLEV + 1];
   RB_HIP(hipMemcpy(off, c->d_lev_off, sizeof(off), hipMemcpyDeviceToHost));
@@ -959,6 +966,7 @@ int rb_collide(rb_ctx *c, rb_particles *p, const double *radius, int64_t n, doub
   RB_PHASE(PH_SORT, launch_sort(c));
   RB_PHASE(PH_PERMUTE, launch_permute_gravity(c, p->x, p->y, p->z, p->m, 0));
   RB_PHASE(PH_TOPO, launch_topology(c));
+  c->fp64_partial = true;  // a topology without moments
   RB_PHASE(PH_COLLIDE, launch_coll_prep(c, radius));
   RB_PHASE(PH_CSEARCH, launch_coll_detect(c, radius, t));
   return coll_resolve(c, p, t, epsilon, seed, codes, codes_cap, n_pairs, n_resolved);
@@ -982,6 +990,7 @@ int rb_sweep(rb_ctx *c, rb_particles *p, const double *radius, int64_t n, double
   }
   RB_HIP(hipMemsetAsync(c->d_ccnt, 0, 32, c->stream));
   RB_TRY(mark(c, PH_TOTAL, true));
+  c->fp64_partial = true;  // the sort buffers now hold the sweep's order
   RB_PHASE(PH_KEYS, launch_sweep_keys(c, p, radius, dt, phi));
   RB_PHASE(PH_SORT, launch_sort(c));
   RB_PHASE(PH_CSEARCH, launch_sweep_pairs(c, p, radius, t, dt, phi));

@@ -101,6 +101,7 @@ struct rb_ctx {
   double *d_S = nullptr;      // 3 per node
   double *d_Q = nullptr;      // 6 per node
   WNode *d_wnode = nullptr;   // the grouped walk's node records (FP32-mixed only)
+  bool fp64_partial = false;  // the last tree (an FP32-mixed step) lacks FP64 records
 
   // walk
   std::vector<WalkItem> h_items64;  // FP64 walk: 64 Morton-consecutive slots
@@ -218,7 +219,10 @@ hipError_t launch_permute_state(rb_ctx *c, int src, int dst);
 hipError_t launch_permute_gravity(rb_ctx *c, const double *x, const double *y,
                                   const double *z, const double *m, uint32_t n_active_single);
 hipError_t launch_topology(rb_ctx *c);
-hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const double *sz);
+// roots_only: an FP32-mixed step, whose walk reads only the FP32 node
+// records; the FP64 records below the walk items' subtree roots are skipped
+hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const double *sz,
+                          bool roots_only = false);
 hipError_t launch_rowscan_levels(rb_ctx *c);
 hipError_t launch_walk64(rb_ctx *c, const double *sx, const double *sy, const double *sz,
                          int slot);

@@ -181,3 +181,30 @@ def test_multi_wave_theta_zero_precision(orc):
         rb.rb_destroy(c64)
         rb.rb_destroy(c32)
     assert rms_rel(a, ref) <= 1e-5, rms_rel(a, ref)
+
+
+def test_export_after_fp32_step_is_refused():
+    # an FP32-mixed step keeps FP64 moments only where its build needs them:
+    # exporting that tree is refused; after rb_tree_build it is complete
+    from gpu_util import Dev, export, make_ctx
+    from paper_1110_4876_amd import rb
+    pr = inputs.sheet(3000, seed=4)
+    ctx = make_ctx(pr, precision=rb.RB_FP32_MIXED)
+    try:
+        d = Dev(pr)
+        rb.rb_step(ctx, d.parts, pr.n, pr.n, 0.0, pr.dt, 2)
+        rb.rb_sync(ctx)
+        with pytest.raises(rb.RBError):
+            export(ctx)
+        rb.rb_tree_build(ctx, d.parts, pr.n, pr.n)
+        got = export(ctx)
+    finally:
+        rb.rb_destroy(ctx)
+    c64 = make_ctx(pr)
+    try:
+        rb.rb_tree_build(c64, d.parts, pr.n, pr.n)  # the same stepped state
+        ref = export(c64)
+    finally:
+        rb.rb_destroy(c64)
+    for k in ref:
+        np.testing.assert_array_equal(got[k], ref[k])
