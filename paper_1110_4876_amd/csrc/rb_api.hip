@@ -155,12 +155,16 @@ int build_layout(rb_ctx *c) {
   }
   c->h_patch_tile0[P] = (uint32_t)c->h_tile_start.size();
   c->n_tiles = (uint32_t)c->h_tile_start.size();
-  // small systems use the bucket sort; larger ones the look-back radix
-  // sort, tiles of 256 x R slots per 256-thread block, R growing with the
-  // system so that large sorts use fewer, fuller tiles
+  // systems (or batches) whose patches all hold at most 2^18 slots use the
+  // bucket sort; larger ones the look-back radix sort, tiles of 256 x R
+  // slots per 256-thread block, R growing with the system so that large
+  // sorts use fewer, fuller tiles
   {
     const uint64_t n = c->h_starts[P];
-    c->sort_small = n <= c->small_sort_max;
+    uint64_t largest = 0;
+    for (uint32_t p = 0; p < P; ++p)
+      largest = std::max<uint64_t>(largest, c->h_starts[p + 1] - c->h_starts[p]);
+    c->sort_small = largest <= c->small_sort_max;
     c->sort_rows = n < (1u << 18) ? 1 : n < (1u << 19) ? 2 : n < (1u << 20) ? 4 : 8;
     const uint32_t st = c->sort_small ? 256u : 256u * (uint32_t)c->sort_rows;
     c->stile = st;
@@ -274,11 +278,12 @@ int init_ctx(rb_ctx *c, const rb_params *p, uint32_t P, const int64_t *off, cons
   RB_HIP(hipMemsetAsync(c->d_stot, 0, 4 * 2 * 2048 * (size_t)P, c->stream));
   RB_HIP(hipMemsetAsync(c->d_sdesc, 0, 8 * 256 * max_stiles, c->stream));
   RB_HIP(hipMemsetAsync(c->d_sctl, 0, 16, c->stream));
-  // small-system bucket sort: up to 2^18 slots
+  // bucket sort: patches of up to 2^18 slots (segments: at most one per
+  // slot, plus one per patch)
   c->small_sort_max = std::min<uint64_t>(cap, 1u << 18);
   RB_TRY(dalloc(c, &c->d_bcnt, (uint64_t)BS_NB * P));
   RB_TRY(dalloc(c, &c->d_bcur, (uint64_t)BS_NB * P));
-  RB_TRY(dalloc(c, &c->d_bseg, c->small_sort_max + P + 1));
+  RB_TRY(dalloc(c, &c->d_bseg, cap + P + 1));
   RB_TRY(dalloc(c, &c->d_bctl, 4));
   RB_HIP(hipMemsetAsync(c->d_bcnt, 0, 4 * (size_t)BS_NB * P, c->stream));
   RB_HIP(hipMemsetAsync(c->d_bctl, 0, 16, c->stream));

@@ -72,7 +72,7 @@ struct rb_ctx {
   uint32_t *d_sctl = nullptr;          // [sort number, tile counter A, B, pad]
   // small systems: bucket sort (k_bsort.hip)
   bool sort_small = false;
-  uint64_t small_sort_max = 0;  // slots the small-sort buffers cover
+  uint64_t small_sort_max = 0;  // largest patch the bucket sort takes
   uint32_t *d_bcnt = nullptr;   // P x 4097 bucket counts (zero between sorts)
   uint32_t *d_bcur = nullptr;   // P x 4097 scatter cursors
   uint2 *d_bseg = nullptr;      // segments (first slot, patch)
