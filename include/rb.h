@@ -272,6 +272,28 @@ int rb_collide(rb_ctx *ctx, rb_particles *p, const double *radius, int64_t n, do
                double epsilon, uint64_t seed, int64_t *n_pairs, int64_t *n_resolved,
                uint64_t *codes, int64_t codes_cap);
 
+/*
+ * Collisions inside rb_step / rb_batch_step (Sect. 5): with enable != 0,
+ * every step ends with the collision search of rb_collide on the step's own
+ * tree (the one built for its kick, searched with every cell's reach
+ * widened by the largest displacement since the build, across the periodic
+ * wraps of the second drift) and the resolution of its queue, before the
+ * next step's first drift.  The pairs, their queue order and the velocity
+ * changes are those rb_collide finds and makes on the end-of-step state.
+ * The k-th step run since this call uses the seed seed + k.
+ *  radius     device FP64, caller order; kept by reference: the caller keeps
+ *             it alive and unchanged while collisions are on.
+ *  epsilon    coefficient of restitution in [0, 1].
+ * enable = 0 turns them off.  Captured step graphs are captured again.
+ * Errors: RB_EINVAL, RB_EUNSUPPORTED (2^27 nodes or more), RB_EHIP.
+ */
+int rb_set_collisions(rb_ctx *ctx, const double *radius, double epsilon, uint64_t seed,
+                      int32_t enable);
+
+/* Synchronise; the pairs found and the collisions resolved by the steps
+ * since the last call (or since rb_set_collisions), then reset them. */
+int rb_collision_counts(rb_ctx *ctx, int64_t *n_pairs, int64_t *n_resolved);
+
 /* rb_sweep's axis: along x, or along the azimuth around the z axis */
 enum { RB_SWEEP_X = 0, RB_SWEEP_PHI = 1 };
 

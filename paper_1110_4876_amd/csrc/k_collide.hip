@@ -43,10 +43,12 @@ __global__ __launch_bounds__(256) void k_coll_rmax(const double *__restrict__ R,
                                                    const uint32_t *__restrict__ starts,
                                                    const uint32_t *__restrict__ nlive,
                                                    uint32_t P, uint32_t n,
-                                                   unsigned long long *__restrict__ rmax) {
+                                                   unsigned long long *__restrict__ rmax,
+                                                   uint32_t *__restrict__ inv) {
   __shared__ double part[4];
   double r = 0.0;
   for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
+    if (inv) inv[orig[s]] = s;  // (collisions inside a step: caller index -> slot)
     const uint32_t p = (P == 1) ? 0u : rb_patch_of(starts, P, s);
     if (s - starts[p] < nlive[p]) {
       const double v = R[orig[s]];
@@ -100,8 +102,10 @@ __global__ __launch_bounds__(256) void k_coll_geom(
     const uint32_t *__restrict__ nfirst, const uint32_t *__restrict__ nlast,
     const uint32_t *__restrict__ nchild, const uint32_t *__restrict__ nlastchild,
     const uint8_t *__restrict__ nlevel, const uint8_t *__restrict__ nleaf,
-    CollNode *__restrict__ out, uint32_t *__restrict__ err) {
+    CollNode *__restrict__ out, uint32_t *__restrict__ err, uint32_t *__restrict__ clear) {
   const uint32_t node = blockIdx.x * blockDim.x + threadIdx.x;
+  // (collisions inside a step: the counters of this step start at zero)
+  if (clear && node < 10) clear[node] = 0u;
   const uint64_t total = lev_off[RB_NLEV];
   if (node >= total || node >= node_cap) return;
   const uint32_t f = nfirst[node];
@@ -138,6 +142,15 @@ __global__ __launch_bounds__(256) void k_coll_geom(
 // subtrees of at most group_size particles; an item is split into parts of
 // CG_SUB slots, one part per wave), 64 / CG_SUB lanes per particle.  Four
 // waves per workgroup, parts strided over the grid.
+//
+// STEP: the search at the end of a step, on the tree built mid-step.  The
+// particles have moved by at most D (the largest displacement) since, and
+// some have been wrapped into the box: the search runs on their unwrapped
+// positions x^u = x + o(w) (w the image the wrap moved them out of) with
+// every cell's reach widened by D, and a pair found through image k' of the
+// unwrapped positions is the pair through image k' + w_j - w_i of the
+// wrapped ones, where the contact test is evaluated.
+template <bool STEP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_coll_detect(
     const WalkItem *__restrict__ items, const WalkItem *__restrict__ items_mid,
     const uint32_t *__restrict__ gctr, uint64_t cap, const double *__restrict__ sx,
@@ -147,48 +160,67 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     const uint32_t *__restrict__ nlive, const uint32_t *__restrict__ root,
     const CollNode *__restrict__ cells, int ngx, int ngy, int boundary, double omega, double t,
     const unsigned long long *__restrict__ rmax_bits, uint64_t *__restrict__ queue,
-    uint32_t qcap, uint32_t *__restrict__ qcnt, uint32_t *__restrict__ err) {
+    uint32_t qcap, uint32_t *__restrict__ qcnt, uint32_t *__restrict__ err,
+    const uint16_t *__restrict__ wrap, const unsigned long long *__restrict__ disp_bits,
+    const double *__restrict__ sched, const uint32_t *__restrict__ ctr, int slot,
+    uint32_t P) {
   constexpr uint32_t NS = 64 / CG_SUB;  // parts per item (items hold <= 64 slots)
   __shared__ uint32_t stk_all[4][CG_SCAP];
   __shared__ uint32_t lfa_all[4][CG_LL], lfb_all[4][CG_LL], lsc_all[4][64];
-  // staged candidates: image-shifted position, radius, caller index,
-  // slot << 1 | same-box flag, image
+  // staged candidates: position, radius, caller index, image (ix + 8) |
+  // (iy + 8) << 4 of the unwrapped search plus the candidate's own wrap
   __shared__ double cx_all[4][64], cy_all[4][64], cz_all[4][64], cr_all[4][64];
-  __shared__ uint32_t co_all[4][64], cs_all[4][64];
+  __shared__ uint32_t co_all[4][64];
   __shared__ uint8_t ck_all[4][64];
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   uint32_t *stk = stk_all[wv];
   uint32_t *lfa = lfa_all[wv], *lfb = lfb_all[wv], *lsc = lsc_all[wv];
   double *cx_ = cx_all[wv], *cy_ = cy_all[wv], *cz_ = cz_all[wv], *cr_ = cr_all[wv];
-  uint32_t *co_ = co_all[wv], *cs_ = cs_all[wv];
+  uint32_t *co_ = co_all[wv];
   uint8_t *ck_ = ck_all[wv];
   const uint32_t pidx = lane % CG_SUB, sub = lane / CG_SUB;
   const uint32_t n_big = gctr[2], n_mid = gctr[3], n_items = n_big + n_mid + gctr[4];
   const double rmax = __longlong_as_double((long long)rmax_bits[0]);
+  const double slack = STEP ? __longlong_as_double((long long)disp_bits[0]) : 0.0;
   const double hd = 0.8660254037844386;  // half the diagonal of a unit cube
   const int n_img = (boundary == RB_OPEN) ? 1 : (2 * ngx + 1) * (2 * ngy + 1);
+  const int ny = 2 * ngy + 1;
+  const double *s_end = STEP ? sched + (size_t)ctr[slot] * 2 * P + P : nullptr;
   for (uint32_t u = 4u * blockIdx.x + wv; u < n_items * NS; u += 4u * gridDim.x) {
     const WalkItem it = rb_walk_item(items, items_mid, u / NS, n_big, n_mid, cap);
     const uint32_t s0 = it.start + (u % NS) * CG_SUB;
     if (s0 >= it.end || it.end - it.start > 64u) continue;  // uniform
     const uint32_t p = it.patch, st = starts[p];
     const uint32_t s = s0 + pidx;
-    const bool act = s < it.end && s - st < nlive[p];
+    bool act = s < it.end && s - st < nlive[p];
+    if (STEP && act) act = !isnan(sx[s]);  // (left an open box this step)
     if (!__ballot(act)) continue;
     const PatchInfo pi = patch[p];
     const double W = pi.W;
-    const double sh = (boundary == RB_SHEAR) ? remainder(1.5 * omega * W * t, W) : 0.0;
+    const double sh = (boundary != RB_SHEAR) ? 0.0
+                      : STEP ? s_end[p] : remainder(1.5 * omega * W * t, W);
     const double xi = act ? sx[s] : 0.0, yi = act ? sy[s] : 0.0, zi = act ? sz[s] : 0.0;
     const uint32_t oi = act ? orig[s] : 0u;
     const double Ri = act ? R[oi] : 0.0;
-    const double lx = rb_wave_min_d(act ? xi : INFINITY);
-    const double hx = rb_wave_max_d(act ? xi : -INFINITY);
-    const double ly = rb_wave_min_d(act ? yi : INFINITY);
-    const double hy = rb_wave_max_d(act ? yi : -INFINITY);
+    int wxi = 0, wyi = 0;  // the lane's own wrap
+    double qx = xi, qy = yi;
+    if (STEP && act) {
+      const uint32_t wb = wrap[s];
+      wxi = (int)(wb & 15u) - 2;
+      wyi = (int)(wb >> 4) - 2;
+      double ox, oy, wy;
+      rb_coll_image_xy(wxi, wyi, boundary, W, sh, omega, ox, oy, wy);
+      qx = xi + ox;
+      qy = yi + oy;
+    }
+    const double lx = rb_wave_min_d(act ? qx : INFINITY);
+    const double hx = rb_wave_max_d(act ? qx : -INFINITY);
+    const double ly = rb_wave_min_d(act ? qy : INFINITY);
+    const double hy = rb_wave_max_d(act ? qy : -INFINITY);
     const double lz = rb_wave_min_d(act ? zi : INFINITY);
     const double hz = rb_wave_max_d(act ? zi : -INFINITY);
-    const double reach = rb_wave_max_d(act ? Ri : 0.0) + rmax;
+    const double reach = rb_wave_max_d(act ? Ri : 0.0) + rmax + slack;
     uint64_t mine[RB_COLL_LOCAL];
     uint32_t nm = 0;
     for (int k = lane; k < n_img; k += 64) stk[k] = (root[p] << 5) | (uint32_t)k;
@@ -225,31 +257,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
               const uint32_t eb = lfb[lb + lo];
               const uint32_t j = lfa[lb + lo] + (e - (lsc[lo] - ((eb >> 5) + 1u)));
               const int k = (int)(eb & 31u);
-              double ox, oy, wy;
-              rb_coll_image(k, ngx, ngy, boundary, W, sh, omega, ox, oy, wy);
+              int kx = (boundary == RB_OPEN) ? 0 : k / ny - ngx;
+              int ky = (boundary == RB_OPEN) ? 0 : k % ny - ngy;
+              if (STEP) {
+                const uint32_t wb = wrap[j];
+                kx += (int)(wb & 15u) - 2;
+                ky += (int)(wb >> 4) - 2;
+              }
               const uint32_t oj = orig[j];
-              cx_[lane] = sx[j] + ox;
-              cy_[lane] = sy[j] + oy;
-              cz_[lane] = sz[j] + 0.0;
+              cx_[lane] = sx[j];
+              cy_[lane] = sy[j];
+              cz_[lane] = sz[j];
               cr_[lane] = R[oj];
               co_[lane] = oj;
-              // the slot, flagged when the image is the box itself
-              cs_[lane] = (j << 1) | ((ox == 0.0 && oy == 0.0) ? 1u : 0u);
-              ck_[lane] = (uint8_t)k;
+              ck_[lane] = (uint8_t)((kx + 8) | ((ky + 8) << 4));
             }
             coll_wave_sync();
             const int C = (int)min(64u, M - e0);
             if (act) {
               for (int q = (int)sub; q < C; q += (int)NS) {
-                const uint32_t oj = co_[q], sj = cs_[q];
-                if (((sj & 1u) && (sj >> 1) == s) || oi >= oj) continue;
-                const double d0 = cx_[q] - xi;
-                const double d1 = cy_[q] - yi;
-                const double d2 = cz_[q] - zi;
+                const uint32_t oj = co_[q];
+                if (oi >= oj) continue;  // each pair once, from its lower caller index
+                // the image of j relative to i in the (wrapped) box
+                const uint32_t kb = ck_[q];
+                const int ix = (int)(kb & 15u) - 8 - wxi, iy = (int)(kb >> 4) - 8 - wyi;
+                if (ix < -ngx || ix > ngx || iy < -ngy || iy > ngy) continue;
+                double ox, oy, wy;
+                rb_coll_image_xy(ix, iy, boundary, W, sh, omega, ox, oy, wy);
+                const double d0 = (cx_[q] + ox) - xi;
+                const double d1 = (cy_[q] + oy) - yi;
+                const double d2 = (cz_[q] + 0.0) - zi;
                 const double sum = Ri + cr_[q];
-                if (d0 * d0 + d1 * d1 + d2 * d2 < sum * sum)
-                  rb_coll_keep(((uint64_t)oi << 35) | ((uint64_t)oj << 7) | (uint64_t)ck_[q],
+                if (d0 * d0 + d1 * d1 + d2 * d2 < sum * sum) {
+                  const uint32_t kc =
+                      (boundary == RB_OPEN) ? 0u : (uint32_t)((ix + ngx) * ny + (iy + ngy));
+                  rb_coll_keep(((uint64_t)oi << 35) | ((uint64_t)oj << 7) | (uint64_t)kc,
                                mine, nm, queue, qcap, qcnt, err);
+                }
               }
             }
             coll_wave_sync();
@@ -347,17 +391,24 @@ __global__ __launch_bounds__(256) void k_coll_min(const uint64_t *__restrict__ l
 // Resolve the collision of code c if its particles approach (d . u < 0);
 // returns whether it did.  Each particle takes part in at most one
 // collision resolved in a round, so the updates of a round do not race.
+// The arrays are in caller order, or (inv given: collisions inside a step)
+// in the step's sorted order, inv mapping caller indices to slots; the
+// shear offset is taken from the step's schedule row when s_end is given.
 __device__ __forceinline__ bool rb_coll_apply(
     uint64_t c, double *__restrict__ x, double *__restrict__ y, double *__restrict__ z,
     double *__restrict__ vx, double *__restrict__ vy, double *__restrict__ vz,
     const double *__restrict__ m, const PatchInfo *__restrict__ patch,
     const uint32_t *__restrict__ starts, uint32_t P, int ngx, int ngy, int boundary,
-    double omega, double t, double eps) {
-  const uint32_t i = (uint32_t)(c >> 35), j = (uint32_t)((c >> 7) & ((1ull << 28) - 1ull));
+    double omega, double t, double eps, const uint32_t *__restrict__ inv = nullptr,
+    const double *__restrict__ s_end = nullptr) {
+  const uint32_t ci = (uint32_t)(c >> 35), cj = (uint32_t)((c >> 7) & ((1ull << 28) - 1ull));
   const int k = (int)(c & 127ull);
-  const uint32_t p = (P == 1) ? 0u : rb_patch_of(starts, P, i);
+  // (patches hold the same ranges in caller and sorted order)
+  const uint32_t p = (P == 1) ? 0u : rb_patch_of(starts, P, ci);
+  const uint32_t i = inv ? inv[ci] : ci, j = inv ? inv[cj] : cj;
   const double W = patch[p].W;
-  const double sh = (boundary == RB_SHEAR) ? remainder(1.5 * omega * W * t, W) : 0.0;
+  const double sh = (boundary != RB_SHEAR) ? 0.0
+                    : s_end ? s_end[p] : remainder(1.5 * omega * W * t, W);
   double ox, oy, wy;
   rb_coll_image(k, ngx, ngy, boundary, W, sh, omega, ox, oy, wy);
   const double d0 = (x[j] + ox) - x[i];
@@ -439,6 +490,11 @@ __global__ __launch_bounds__(256) void k_coll_reset(const uint64_t *__restrict__
 // minima are formed by atomics, which the L1 cache does not see); the
 // velocities are plain loads and stores ordered by the workgroup barriers.
 #define CR_SMALL 4096
+//
+// Inside a step (inv given) every queue is resolved here, however long; the
+// seed is the step's (seedp[0] + the step index), the shear offset the
+// step's end-time offset, and the pairs and resolutions are added to the
+// running totals in cum.
 __global__ __launch_bounds__(1024) void k_coll_rounds1(
     uint64_t *__restrict__ l0, uint64_t *__restrict__ l1, uint32_t *__restrict__ cnt, int a,
     uint32_t *__restrict__ save, uint32_t qcap, uint64_t seed,
@@ -447,13 +503,18 @@ __global__ __launch_bounds__(1024) void k_coll_rounds1(
     double *__restrict__ vz, const double *__restrict__ m,
     const PatchInfo *__restrict__ patch, const uint32_t *__restrict__ starts, uint32_t P,
     int ngx, int ngy, int boundary, double omega, double t, double eps,
-    unsigned long long *__restrict__ n_res, const uint32_t *__restrict__ err) {
+    unsigned long long *__restrict__ n_res, const uint32_t *__restrict__ err,
+    const uint32_t *__restrict__ inv, const uint64_t *__restrict__ seedp,
+    const double *__restrict__ sched, const uint32_t *__restrict__ ctr, int slot,
+    unsigned long long *__restrict__ cum) {
   __shared__ uint32_t s_n, s_next;
   __shared__ unsigned long long s_res;
   const uint32_t tid = threadIdx.x;
   const uint32_t n0 = min(cnt[a], qcap);
   if (tid == 0 && save) save[0] = cnt[a];
-  if (n0 > CR_SMALL) {  // uniform
+  const double *s_end = inv ? sched + (size_t)ctr[slot] * 2 * P + P : nullptr;
+  if (inv) seed = seedp[0] + ctr[slot];
+  if (!inv && n0 > CR_SMALL) {  // uniform
     if (tid == 0) cnt[3] = err[0];
     return;
   }
@@ -488,7 +549,8 @@ __global__ __launch_bounds__(1024) void k_coll_rounds1(
                                   __HIP_MEMORY_SCOPE_AGENT) == h;
       }
       const bool resolved = ready && rb_coll_apply(c, x, y, z, vx, vy, vz, m, patch, starts,
-                                                   P, ngx, ngy, boundary, omega, t, eps);
+                                                   P, ngx, ngy, boundary, omega, t, eps, inv,
+                                                   s_end);
       const uint64_t rm = __ballot(resolved);
       if (rb_lane() == 0 && rm) atomicAdd(&s_res, (unsigned long long)__popcll(rm));
       const bool keep = in && !ready;
@@ -517,6 +579,10 @@ __global__ __launch_bounds__(1024) void k_coll_rounds1(
     cnt[1] = 0;
     cnt[3] = err[0];
     if (s_res) atomicAdd(n_res, s_res);
+    if (cum) {
+      cum[0] += (unsigned long long)n0;
+      cum[1] += s_res;
+    }
   }
 }
 
@@ -526,12 +592,12 @@ hipError_t launch_coll_prep(rb_ctx *c, const double *radius) {
   if (n == 0) return hipSuccess;
   const unsigned grid = std::min(rb_div_up(n, 1024), 128u);
   hipLaunchKernelGGL(k_coll_rmax, dim3(grid), dim3(256), 0, c->stream, radius, c->d_orig[0],
-                     c->d_starts, c->d_nlive, c->P, n, c->d_cmax);
+                     c->d_starts, c->d_nlive, c->P, n, c->d_cmax, nullptr);
   CollNode *cells = reinterpret_cast<CollNode *>(c->d_cgeo);
   hipLaunchKernelGGL(k_coll_geom, dim3(rb_div_up(c->node_cap, 256)), dim3(256), 0, c->stream,
                      c->d_px[0][0], c->d_px[0][1], c->d_px[0][2], c->d_patch, c->d_starts, c->P,
                      c->d_lev_off, c->node_cap, c->d_nfirst, c->d_nlast, c->d_nchild,
-                     c->d_nlastchild, c->d_nlevel, c->d_nleaf, cells, c->d_err);
+                     c->d_nlastchild, c->d_nlevel, c->d_nleaf, cells, c->d_err, nullptr);
   return launch_groups(c);
 }
 
@@ -543,12 +609,12 @@ hipError_t launch_coll_detect(rb_ctx *c, const double *radius, double t) {
   // particles); the loop strides over any others
   unsigned ggrid = rb_div_up(n, 4 * CG_SUB / 2);
   if (ggrid > 4096) ggrid = 4096;
-  hipLaunchKernelGGL(k_coll_detect, dim3(ggrid), dim3(256), 0, c->stream, c->d_witems,
+  hipLaunchKernelGGL(k_coll_detect<false>, dim3(ggrid), dim3(256), 0, c->stream, c->d_witems,
                      c->d_witems_mid, c->d_gctr, c->cap, c->d_px[0][0], c->d_px[0][1],
                      c->d_px[0][2], c->d_orig[0], radius, c->d_patch, c->d_starts, c->d_nlive,
                      c->d_root, cells, c->p.n_ghost[0], c->p.n_ghost[1], c->p.boundary,
                      c->p.omega, t, c->d_cmax, c->d_cq[0], (uint32_t)c->cq_cap, c->d_ccnt,
-                     c->d_err);
+                     c->d_err, nullptr, nullptr, nullptr, nullptr, 0, c->P);
   return hipGetLastError();
 }
 
@@ -559,7 +625,8 @@ hipError_t launch_coll_rounds1(rb_ctx *c, int a, const rb_particles *pp, double 
                      c->d_cq[1], c->d_ccnt, a, save, (uint32_t)c->cq_cap, seed, c->d_cbest,
                      pp->x, pp->y, pp->z, pp->vx, pp->vy, pp->vz, pp->m, c->d_patch,
                      c->d_starts, c->P, c->p.n_ghost[0], c->p.n_ghost[1], c->p.boundary,
-                     c->p.omega, t, eps, c->d_cres, c->d_err);
+                     c->p.omega, t, eps, c->d_cres, c->d_err, nullptr, nullptr, nullptr,
+                     nullptr, 0, nullptr);
   return hipGetLastError();
 }
 
@@ -576,5 +643,56 @@ hipError_t launch_coll_round(rb_ctx *c, int a, const rb_particles *pp, double t,
                      c->d_cres);
   hipLaunchKernelGGL(k_coll_reset, dim3(CR_GRID), dim3(256), 0, c->stream, c->d_cq[a], cnt,
                      qcap, c->d_cbest);
+  return hipGetLastError();
+}
+
+// ---- collisions inside a step (the tree of the step, in its sorted order)
+
+// before the kick: the cells' records from the build's (mid-step)
+// positions in buffer buf, the step's counters cleared, R_max and the
+// caller-to-slot map
+hipError_t launch_coll_step_prep(rb_ctx *c, int buf) {
+  const uint32_t n = (uint32_t)c->h_starts[c->P];
+  if (n == 0) return hipSuccess;
+  CollNode *cells = reinterpret_cast<CollNode *>(c->d_cgeo);
+  hipLaunchKernelGGL(k_coll_geom, dim3(rb_div_up(c->node_cap, 256)), dim3(256), 0, c->stream,
+                     c->d_px[buf][0], c->d_px[buf][1], c->d_px[buf][2], c->d_patch,
+                     c->d_starts, c->P, c->d_lev_off, c->node_cap, c->d_nfirst, c->d_nlast,
+                     c->d_nchild, c->d_nlastchild, c->d_nlevel, c->d_nleaf, cells, c->d_err,
+                     c->d_ccnt);
+  const unsigned grid = std::min(rb_div_up(n, 1024), 128u);
+  hipLaunchKernelGGL(k_coll_rmax, dim3(grid), dim3(256), 0, c->stream, c->coll_R,
+                     c->d_orig[buf], c->d_starts, c->d_nlive, c->P, n, c->d_cmax, c->d_cinv);
+  return hipGetLastError();
+}
+
+// after the second drift (the end-of-step state in buffer buf): the search
+hipError_t launch_coll_step_search(rb_ctx *c, int buf, int slot) {
+  const uint32_t n = (uint32_t)c->h_starts[c->P];
+  if (n == 0) return hipSuccess;
+  CollNode *cells = reinterpret_cast<CollNode *>(c->d_cgeo);
+  unsigned ggrid = rb_div_up(n, 4 * CG_SUB / 2);
+  if (ggrid > 4096) ggrid = 4096;
+  hipLaunchKernelGGL(k_coll_detect<true>, dim3(ggrid), dim3(256), 0, c->stream, c->d_witems,
+                     c->d_witems_mid, c->d_gctr, c->cap, c->d_px[buf][0], c->d_px[buf][1],
+                     c->d_px[buf][2], c->d_orig[buf], c->coll_R, c->d_patch, c->d_starts,
+                     c->d_nlive, c->d_root, cells, c->p.n_ghost[0], c->p.n_ghost[1],
+                     c->p.boundary, c->p.omega, 0.0, c->d_cmax, c->d_cq[0],
+                     (uint32_t)c->cq_cap, c->d_ccnt, c->d_err, c->d_cwrap,
+                     reinterpret_cast<const unsigned long long *>(c->d_ccnt + 8), c->d_sched,
+                     c->d_ctr, slot, c->P);
+  return hipGetLastError();
+}
+
+// then every round of the queue, on the sorted state
+hipError_t launch_coll_step_rounds(rb_ctx *c, int buf, int slot) {
+  double *const *b = c->d_px[buf];
+  hipLaunchKernelGGL(k_coll_rounds1, dim3(1), dim3(1024), 0, c->stream, c->d_cq[0],
+                     c->d_cq[1], c->d_ccnt, 0, c->d_ccnt + 2, (uint32_t)c->cq_cap, 0ull,
+                     c->d_cbest, b[0], b[1], b[2], b[3], b[4], b[5], b[6], c->d_patch,
+                     c->d_starts, c->P, c->p.n_ghost[0], c->p.n_ghost[1], c->p.boundary,
+                     c->p.omega, 0.0, c->coll_eps, c->d_cres, c->d_err, c->d_cinv,
+                     reinterpret_cast<const uint64_t *>(c->d_ctr + 4), c->d_sched, c->d_ctr,
+                     slot, reinterpret_cast<unsigned long long *>(c->d_ccnt + 10));
   return hipGetLastError();
 }

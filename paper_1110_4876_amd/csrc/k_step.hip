@@ -129,7 +129,12 @@ hipError_t launch_prologue(rb_ctx *c, const rb_particles *cp) {
 
 // Kick with the walk's accelerations (images summed in order), second drift
 // and boundary; then, unless this is the last step, the next step's first
-// drift, boundary and keys.  Works in place on the sorted buffer.
+// drift, boundary and keys.  Works in place on the sorted buffer.  With
+// collisions at the end of the step the work is split around them: mode 1
+// stops after the second drift and records, per slot, the periodic wrap it
+// applied (the image (wx, wy) the unwrapped position lies in) and the
+// largest displacement since the tree was built; mode 2 then does the next
+// step's first drift and keys.  Mode 0 does both at once.
 __global__ __launch_bounds__(256) void k_post(
     double *__restrict__ bx, double *__restrict__ by, double *__restrict__ bz,
     double *__restrict__ bvx, double *__restrict__ bvy, double *__restrict__ bvz,
@@ -139,32 +144,53 @@ __global__ __launch_bounds__(256) void k_post(
     const StepConst *__restrict__ scp, const double *__restrict__ sched,
     uint32_t *__restrict__ ctr, int slot, uint64_t *__restrict__ key,
     uint32_t *__restrict__ idx, uint32_t *__restrict__ err, uint32_t *__restrict__ bcnt,
-    uint32_t *__restrict__ bctl) {
+    uint32_t *__restrict__ bctl, int mode, uint16_t *__restrict__ wrap,
+    unsigned long long *__restrict__ disp) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t k = ctr[slot], nsteps = ctr[2];
   // the next step reads its index from the other slot
-  if (s == 0) ctr[1 - slot] = k + 1;
-  if (s >= n) return;
+  if (s == 0 && mode != 2) ctr[1 - slot] = k + 1;
+  double moved = 0.0;
+  if (s < n) {
   const uint32_t p = (P == 1) ? 0 : rb_patch_of(starts, P, s);
   const PatchInfo pi = patch[p];
   const StepConst sc = *scp;
-  const bool has_next = k + 1 < nsteps;
+  const bool has_next = k + 1 < nsteps && mode != 1;
   PState q{bx[s], by[s], bz[s], bvx[s], bvy[s], bvz[s]};
   const bool live = (s - pi.start) < nlive[p];
   if (live) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int im = 0; im < n_acc; ++im) {
-      const double *a = acc + (size_t)im * 3 * cap;
-      a0 += a[s]; a1 += a[cap + s]; a2 += a[2 * cap + s];
-    }
-    {
+    if (mode != 2) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+      for (int im = 0; im < n_acc; ++im) {
+        const double *a = acc + (size_t)im * 3 * cap;
+        a0 += a[s]; a1 += a[cap + s]; a2 += a[2 * cap + s];
+      }
+      {
 #pragma clang fp contract(off)
-      q.vx = q.vx + a0 * sc.dt;
-      q.vy = q.vy + a1 * sc.dt;
-      q.vz = q.vz + a2 * sc.dt;
+        q.vx = q.vx + a0 * sc.dt;
+        q.vy = q.vy + a1 * sc.dt;
+        q.vz = q.vz + a2 * sc.dt;
+      }
+      const double mx = q.x, my = q.y, mz = q.z;  // where the tree put the particle
+      rb_apply_drift(q, drift, sc);
+      const double ux = q.x, uy = q.y, uz = q.z;  // before any wrap
+      const double s_end = sched[(size_t)k * 2 * P + P + p];
+      rb_apply_boundary(q, boundary, pi, sc.omega, s_end);
+      if (mode == 1) {
+        uint16_t wv = (2u << 4) | 2u;  // (wx + 2) | (wy + 2) << 4; 0, 0 when nothing moved
+        if (!(isnan(q.x) || isnan(q.y) || isnan(q.z))) {
+          const double dx = ux - mx, dy = uy - my, dz = uz - mz;
+          moved = sqrt(dx * dx + dy * dy + dz * dz);
+          if (boundary != RB_OPEN) {
+            const double fx = rint((ux - q.x) / pi.W);
+            const double sx = (boundary == RB_SHEAR) ? fx * s_end : 0.0;
+            const double fy = rint(((uy - q.y) + sx) / pi.W);
+            wv = (uint16_t)(((int)fx + 2) | (((int)fy + 2) << 4));
+          }
+        }
+        wrap[s] = wv;
+      }
     }
-    rb_apply_drift(q, drift, sc);
-    rb_apply_boundary(q, boundary, pi, sc.omega, sched[(size_t)k * 2 * P + P + p]);
     if (has_next) {
       const bool alive = !(isnan(q.x) || isnan(q.y) || isnan(q.z));
       if (alive) {
@@ -174,6 +200,8 @@ __global__ __launch_bounds__(256) void k_post(
     }
     bx[s] = q.x; by[s] = q.y; bz[s] = q.z;
     bvx[s] = q.vx; bvy[s] = q.vy; bvz[s] = q.vz;
+  } else if (mode == 1) {
+    wrap[s] = (2u << 4) | 2u;
   }
   if (has_next) {
     const uint64_t k2 = live ? rb_state_key(q, pi, boundary, err) : RB_KEY_DEAD;
@@ -184,9 +212,15 @@ __global__ __launch_bounds__(256) void k_post(
       rb_bucket_add(bcnt, p, P, k2);
     }
   }
+  }
+  if (mode == 1) {  // the largest displacement (ordered bits of a non-negative double)
+    for (int d = 32; d >= 1; d >>= 1) moved = fmax(moved, __shfl_xor(moved, d, 64));
+    if (rb_lane() == 0 && moved > 0.0)
+      atomicMax(disp, (unsigned long long)__double_as_longlong(moved));
+  }
 }
 
-hipError_t launch_post(rb_ctx *c, int buf, int slot) {
+hipError_t launch_post(rb_ctx *c, int buf, int slot, int mode) {
   const uint32_t n = (uint32_t)c->h_starts[c->P];
   if (n == 0) return hipSuccess;
   double *const *b = c->d_px[buf];
@@ -195,7 +229,9 @@ hipError_t launch_post(rb_ctx *c, int buf, int slot) {
                      b[2], b[3], b[4], b[5], c->d_acc, c->cap, n_acc, c->d_patch, c->d_starts,
                      c->d_nlive, c->P, n, c->p.boundary, c->p.drift, c->d_sc, c->d_sched,
                      c->d_ctr, slot, c->d_key[0], c->d_idx[0], c->d_err,
-                     c->sort_small ? c->d_bcnt : nullptr, c->d_bctl);
+                     c->sort_small ? c->d_bcnt : nullptr, c->d_bctl, mode, c->d_cwrap,
+                     c->d_ccnt ? reinterpret_cast<unsigned long long *>(c->d_ccnt + 8)
+                               : nullptr);
   return hipGetLastError();
 }
 

@@ -393,6 +393,8 @@ int upload_schedule(rb_ctx *c, double t, double dt, int32_t nsteps) {
   RB_HIP(hipEventSynchronize(c->dyn_ev));
   uint32_t *ctr = (uint32_t *)c->h_dyn;
   ctr[0] = 0u; ctr[1] = 0u; ctr[2] = rows; ctr[3] = 0u;
+  // words 4-5: the collision seed of the schedule's first step
+  memcpy(c->h_dyn + 16, &c->chunk_seed, 8);
   StepConst *sc = (StepConst *)(c->h_dyn + 64);
   double *sched = (double *)(c->h_dyn + 256);
   const double half = 0.5 * dt;
@@ -577,8 +579,18 @@ int step_kernels(rb_ctx *c, int src) {
   RB_PHASE(PH_MOMENTS, launch_moments(c, c->d_px[dst][0], c->d_px[dst][1], c->d_px[dst][2],
                                       c->p.precision == RB_FP32_MIXED));
   c->fp64_partial = c->p.precision == RB_FP32_MIXED;
+  if (c->coll_on) RB_PHASE(PH_COLLIDE, launch_coll_step_prep(c, dst));
   RB_TRY(walk(c, dst, src));
-  RB_PHASE(PH_POST, launch_post(c, dst, src));
+  if (c->coll_on) {
+    // collisions at the end of the step, between the second drift and the
+    // next step's first drift
+    RB_PHASE(PH_POST, launch_post(c, dst, src, 1));
+    RB_PHASE(PH_CSEARCH, launch_coll_step_search(c, dst, src));
+    RB_PHASE(PH_COLLIDE, launch_coll_step_rounds(c, dst, src));
+    RB_PHASE(PH_POST, launch_post(c, dst, src, 2));
+  } else {
+    RB_PHASE(PH_POST, launch_post(c, dst, src));
+  }
   return RB_OK;
 }
 
@@ -634,7 +646,9 @@ int run_step(rb_ctx *c, rb_particles *p, double t, double dt, int32_t nsteps) {
   while (done < nsteps) {
     const int32_t chunk = std::min<int32_t>(nsteps - done, (int32_t)c->sched_cap);
     const double t0 = t + (double)done * dt;
+    c->chunk_seed = c->coll_seed + c->coll_steps;
     RB_TRY(upload_schedule(c, t0, dt, chunk));
+    if (c->coll_on) c->coll_steps += (uint64_t)chunk;
     RB_TRY(mark(c, PH_TOTAL, true));
     RB_PHASE(PH_KEYS, launch_prologue(c, p));
     int src = 0;
@@ -886,10 +900,11 @@ static int coll_alloc(rb_ctx *c) {
   c->cq_cap = 8 * c->cap + 1024;
   RB_TRY(dalloc(c, &c->d_cq[0], c->cq_cap));
   RB_TRY(dalloc(c, &c->d_cq[1], c->cq_cap));
-  RB_TRY(dalloc(c, &c->d_ccnt, 8));
+  RB_TRY(dalloc(c, &c->d_ccnt, 16));
   c->d_cmax = reinterpret_cast<unsigned long long *>(c->d_ccnt + 4);
   c->d_cres = reinterpret_cast<unsigned long long *>(c->d_ccnt + 6);
-  RB_HIP(hipHostMalloc((void **)&c->h_cpin, 32, hipHostMallocDefault));
+  RB_HIP(hipHostMalloc((void **)&c->h_cpin, 64, hipHostMallocDefault));
+  RB_HIP(hipMemsetAsync(c->d_ccnt, 0, 64, c->stream));
   RB_TRY(dalloc(c, &c->d_cbest, c->cap));
   RB_HIP(hipMemsetAsync(c->d_cbest, 0xFF, 8 * c->cap, c->stream));
   return RB_OK;
@@ -965,7 +980,7 @@ int rb_collide(rb_ctx *c, rb_particles *p, const double *radius, int64_t n, doub
     return fail(RB_EUNSUPPORTED, "the collision search needs fewer than 2^27 nodes");
   RB_TRY(coll_alloc(c));
   if (!c->d_cgeo) RB_TRY(dalloc(c, &c->d_cgeo, 4 * c->node_cap));
-  RB_HIP(hipMemsetAsync(c->d_ccnt, 0, 32, c->stream));
+  RB_HIP(hipMemsetAsync(c->d_ccnt, 0, 40, c->stream));
   RB_TRY(mark(c, PH_TOTAL, true));
   RB_PHASE(PH_KEYS, launch_keys(c, p->x, p->y, p->z, 0.0));
   RB_PHASE(PH_SORT, launch_sort(c));
@@ -975,6 +990,44 @@ int rb_collide(rb_ctx *c, rb_particles *p, const double *radius, int64_t n, doub
   RB_PHASE(PH_COLLIDE, launch_coll_prep(c, radius));
   RB_PHASE(PH_CSEARCH, launch_coll_detect(c, radius, t));
   return coll_resolve(c, p, t, epsilon, seed, codes, codes_cap, n_pairs, n_resolved);
+}
+
+int rb_set_collisions(rb_ctx *c, const double *radius, double epsilon, uint64_t seed,
+                      int32_t enable) {
+  if (!c) return fail(RB_EINVAL, "null context");
+  if (enable) {
+    if (!radius) return fail(RB_EINVAL, "null radius array");
+    if (!(epsilon >= 0.0 && epsilon <= 1.0)) return fail(RB_EINVAL, "epsilon outside [0, 1]");
+    if (c->node_cap >= (1ull << 27))
+      return fail(RB_EUNSUPPORTED, "the collision search needs fewer than 2^27 nodes");
+    RB_TRY(coll_alloc(c));
+    if (!c->d_cgeo) RB_TRY(dalloc(c, &c->d_cgeo, 4 * c->node_cap));
+    if (!c->d_cwrap) RB_TRY(dalloc(c, &c->d_cwrap, c->cap));
+    if (!c->d_cinv) RB_TRY(dalloc(c, &c->d_cinv, c->cap));
+    // the running totals start at zero
+    RB_HIP(hipMemsetAsync(c->d_ccnt + 10, 0, 16, c->stream));
+  }
+  c->coll_on = enable != 0;
+  c->coll_R = enable ? radius : nullptr;
+  c->coll_eps = epsilon;
+  c->coll_seed = seed;
+  c->coll_steps = 0;
+  c->graph_key = -1;  // the step's kernels change: capture again
+  return RB_OK;
+}
+
+int rb_collision_counts(rb_ctx *c, int64_t *n_pairs, int64_t *n_resolved) {
+  if (!c) return fail(RB_EINVAL, "null context");
+  RB_TRY(report_device_errors(c));
+  unsigned long long v[2] = {0ull, 0ull};
+  if (c->d_ccnt) {
+    RB_HIP(hipMemcpy(v, c->d_ccnt + 10, 16, hipMemcpyDeviceToHost));
+    RB_HIP(hipMemsetAsync(c->d_ccnt + 10, 0, 16, c->stream));
+    RB_HIP(hipStreamSynchronize(c->stream));
+  }
+  if (n_pairs) *n_pairs = (int64_t)v[0];
+  if (n_resolved) *n_resolved = (int64_t)v[1];
+  return RB_OK;
 }
 
 int rb_sweep(rb_ctx *c, rb_particles *p, const double *radius, int64_t n, double t, double dt,
@@ -993,7 +1046,7 @@ int rb_sweep(rb_ctx *c, rb_particles *p, const double *radius, int64_t n, double
     RB_TRY(dalloc(c, &c->d_swR, c->cap));
     RB_TRY(dalloc(c, &c->d_swhi, c->cap));
   }
-  RB_HIP(hipMemsetAsync(c->d_ccnt, 0, 32, c->stream));
+  RB_HIP(hipMemsetAsync(c->d_ccnt, 0, 40, c->stream));
   RB_TRY(mark(c, PH_TOTAL, true));
   c->fp64_partial = true;  // the sort buffers now hold the sweep's order
   RB_PHASE(PH_KEYS, launch_sweep_keys(c, p, radius, dt, phi));

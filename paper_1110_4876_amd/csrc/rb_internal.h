@@ -118,14 +118,27 @@ struct rb_ctx {
   // collisions, the cells' centres and links
   uint64_t *d_cq[2] = {nullptr, nullptr};
   uint64_t cq_cap = 0;
-  // one 32-byte block [list counts 0, 1 | detected pairs | copy of the
-  // error word | R_max bits (2 words) | resolved (2 words)], cleared by one
-  // memset per call and read back in one copy
+  // one 64-byte block [list counts 0, 1 | detected pairs | copy of the
+  // error word | R_max bits (2 words) | resolved (2 words) | largest
+  // displacement bits (2 words) | collisions of rb_step since they were
+  // last read: pairs (2 words), resolved (2 words) | -], its first 40 bytes
+  // cleared once per call or step and read back in one copy
   uint32_t *d_ccnt = nullptr;
   unsigned long long *d_cbest = nullptr;
   unsigned long long *d_cmax = nullptr;  // = d_ccnt + 4
   unsigned long long *d_cres = nullptr;  // = d_ccnt + 6
-  uint32_t *h_cpin = nullptr;            // pinned host copy of the block (8 words)
+  uint32_t *h_cpin = nullptr;            // pinned host copy of the block (16 words)
+  // collisions inside rb_step (rb_set_collisions): radius (caller order,
+  // the caller's device array), restitution, seed of the next step, the
+  // per-slot wrap of the second drift and the caller-to-slot map
+  bool coll_on = false;
+  const double *coll_R = nullptr;
+  double coll_eps = 0.0;
+  uint64_t coll_seed = 0;
+  uint16_t *d_cwrap = nullptr;
+  uint32_t *d_cinv = nullptr;
+  uint64_t coll_steps = 0;  // steps run with collisions since they were set
+  uint64_t chunk_seed = 0;  // seed of the first step of the uploaded schedule
   double *d_cgeo = nullptr;         // 4 per node: the search's cell records
   double *d_swR = nullptr, *d_swhi = nullptr;  // plane sweep: sorted radii, interval ends
   double *d_acc = nullptr;          // (n_img or 1) * 3 * cap
@@ -209,6 +222,9 @@ hipError_t launch_sweep_keys(rb_ctx *c, const rb_particles *pp, const double *ra
 hipError_t launch_sweep_pairs(rb_ctx *c, const rb_particles *pp, const double *radius,
                               double t, double dt, int phi);
 hipError_t launch_coll_prep(rb_ctx *c, const double *radius);
+hipError_t launch_coll_step_prep(rb_ctx *c, int buf);
+hipError_t launch_coll_step_search(rb_ctx *c, int buf, int slot);
+hipError_t launch_coll_step_rounds(rb_ctx *c, int buf, int slot);
 hipError_t launch_coll_detect(rb_ctx *c, const double *radius, double t);
 hipError_t launch_coll_rounds1(rb_ctx *c, int a, const rb_particles *pp, double t, double eps,
                                uint64_t seed, uint32_t *save);
@@ -230,7 +246,10 @@ hipError_t launch_walk32(rb_ctx *c, const double *sx, const double *sy, const do
                          int slot);
 hipError_t launch_scatter_acc(rb_ctx *c, double *ax, double *ay, double *az);
 hipError_t launch_prologue(rb_ctx *c, const rb_particles *cp);
-hipError_t launch_post(rb_ctx *c, int buf, int slot);
+// mode 0: kick, second drift, next first drift and keys; 1: up to the
+// second drift (records wraps and the largest displacement for the
+// collisions at the end of the step); 2: the next first drift and keys
+hipError_t launch_post(rb_ctx *c, int buf, int slot, int mode = 0);
 hipError_t launch_epilogue(rb_ctx *c, rb_particles *cp, int buf);
 hipError_t launch_direct(rb_ctx *c, const rb_particles *cp, uint32_t n, uint32_t n_active,
                          const double *s_img, const int64_t *targets, uint32_t nt,

@@ -128,6 +128,10 @@ _SIGS = {
                                 ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p,
                                 ctypes.c_int64]),
     "rb_peak_probe": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "rb_set_collisions": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                         ctypes.c_uint64, ctypes.c_int32]),
+    "rb_collision_counts": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.POINTER(ctypes.c_int64)]),
     "rb_error_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rb_last_error": (ctypes.c_char_p, []),
 }
@@ -356,3 +360,19 @@ def rb_peak_probe(kind: int) -> float:
     v = ctypes.c_double(0.0)
     check(lib().rb_peak_probe(int(kind), ctypes.byref(v)), "rb_peak_probe")
     return float(v.value)
+
+
+def rb_set_collisions(ctx, radius, epsilon: float, seed: int, enable: bool = True) -> None:
+    """Collisions at the end of every rb_step / rb_batch_step step (rb.h).
+    radius: device tensor (caller order), kept alive by the caller."""
+    check(lib().rb_set_collisions(ctx, ctypes.c_void_p(_ptr(radius) if enable else 0),
+                                  float(epsilon), ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF),
+                                  int(bool(enable))), "rb_set_collisions")
+
+
+def rb_collision_counts(ctx):
+    """(pairs, resolved) of the steps since the last call (rb.h)."""
+    a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+    check(lib().rb_collision_counts(ctx, ctypes.byref(a), ctypes.byref(b)),
+          "rb_collision_counts")
+    return int(a.value), int(b.value)

@@ -1,0 +1,131 @@
+"""Collisions inside rb_step (rb_set_collisions): the search on the step's
+own tree (reach widened by the displacement since the build, across the
+periodic wraps of the second drift) must find and resolve exactly what
+rb_collide finds and resolves on the same end-of-step state, which the
+oracle pins (tests/test_gpu_collide.py).  Also: several steps in one call,
+graph replay against eager launches, and the oracle's step + collide."""
+import numpy as np
+import pytest
+
+from paper_1110_4876_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _state(d):
+    return {k: getattr(d, k).cpu().numpy().copy() for k in ("x", "y", "z", "vx", "vy", "vz")}
+
+
+def _steps_with_collisions(pr, R, nsteps, seed, eps=0.5, **kw):
+    from gpu_util import Dev, dev, make_ctx
+    from paper_1110_4876_amd import rb
+    ctx = make_ctx(pr, **kw)
+    try:
+        d = Dev(pr)
+        r = dev(R)
+        rb.rb_set_collisions(ctx, r, eps, seed)
+        rb.rb_step(ctx, d.parts, pr.n, pr.n, 0.0, pr.dt, nsteps)
+        pairs, res = rb.rb_collision_counts(ctx)
+        st = _state(d)
+    finally:
+        rb.rb_destroy(ctx)
+    return st, pairs, res
+
+
+def _steps_then_collide(pr, R, nsteps, seed, eps=0.5, **kw):
+    # one step per call, then rb_collide on the end-of-step state
+    from gpu_util import Dev, dev, make_ctx
+    from paper_1110_4876_amd import rb
+    ctx = make_ctx(pr, **kw)
+    pairs = res = 0
+    try:
+        d = Dev(pr)
+        r = dev(R)
+        for k in range(nsteps):
+            rb.rb_step(ctx, d.parts, pr.n, pr.n, k * pr.dt, pr.dt, 1)
+            a, b = rb.rb_collide(ctx, d.parts, r, pr.n, (k + 1) * pr.dt, eps, seed + k)
+            pairs += a
+            res += b
+        rb.rb_sync(ctx)
+        st = _state(d)
+    finally:
+        rb.rb_destroy(ctx)
+    return st, pairs, res
+
+
+@pytest.mark.parametrize("n,seed", [(5000, 3), (12000, 4)])
+def test_one_step_equals_rb_collide(n, seed):
+    # the sheet starts with many overlaps, some through the x boundary
+    pr = inputs.sheet(n, seed=seed)
+    R = pr.extra["radius"]
+    a, pa, ra = _steps_with_collisions(pr, R, 1, 77)
+    b, pb, rb_ = _steps_then_collide(pr, R, 1, 77)
+    assert pa == pb and ra == rb_ and pa > n // 10 and ra > 0
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+def test_several_steps_periodic_box():
+    # no shear: the step times do not enter, so several steps in one call
+    # match one step per call followed by rb_collide
+    rng = np.random.default_rng(8)
+    n, W = 4000, 10.0
+    x = rng.uniform(-W / 2, W / 2, (n, 3))
+    v = rng.normal(size=(n, 3)) * 2.0
+    m = rng.uniform(0.5, 2.0, n) * 1e-6
+    params = inputs.base_params(G=1.0, b=0.01, W=W, x0=(-W / 2, -W / 2, -W / 2),
+                                boundary=inputs.PERIODIC, ng=(1, 1), theta=0.5)
+    pr = inputs.Problem(x[:, 0].copy(), x[:, 1].copy(), x[:, 2].copy(), v[:, 0].copy(),
+                        v[:, 1].copy(), v[:, 2].copy(), m, params, n, 0.02)
+    R = rng.uniform(0.05, 0.15, n)
+    a, pa, ra = _steps_with_collisions(pr, R, 4, 1234, eps=0.8)
+    b, pb, rb_ = _steps_then_collide(pr, R, 4, 1234, eps=0.8)
+    assert pa == pb and ra == rb_ and ra > 0
+    for k in a:  # (particles leaving through z, which is not periodic, are NaN in both)
+        np.testing.assert_array_equal(np.isnan(a[k]), np.isnan(b[k]))
+        scale = np.nanmax(np.abs(b[k]))
+        assert np.nanmax(np.abs(a[k] - b[k])) <= 1e-12 * scale, k
+
+
+def test_graph_replay_equals_eager():
+    from paper_1110_4876_amd import rb
+    pr = inputs.sheet(20000, seed=6)
+    R = pr.extra["radius"]
+    kw = dict(precision=rb.RB_FP32_MIXED, theta=0.42, group_size=64, walk_waves=4)
+    a, pa, ra = _steps_with_collisions(pr, R, 3, 9, use_graph=0, **kw)
+    b, pb, rb_ = _steps_with_collisions(pr, R, 3, 9, use_graph=1, **kw)
+    assert pa == pb and ra == rb_ and ra > 0
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+def test_matches_oracle_step_and_collide(orc):
+    pr = inputs.sheet(3000, seed=2)
+    R = pr.extra["radius"]
+    a, pa, ra = _steps_with_collisions(pr, R, 1, 55)
+    p = orc.make_params(**pr.params)
+    st = orc.step(p, pr.state(), pr.m, 0.0, pr.dt, 1, use_tree=True)
+    _, onp, onr, ost = orc.collide(p, st, pr.m, R, pr.dt, 0.5, 55)
+    assert pa == onp and ra == onr and pa > 100
+    for k in ("vx", "vy", "vz"):
+        scale = np.abs(ost[k]).max()
+        assert np.abs(a[k] - ost[k]).max() <= 1e-9 * scale, k
+
+
+def test_counts_reset_and_switch_off():
+    from gpu_util import Dev, dev, make_ctx
+    from paper_1110_4876_amd import rb
+    pr = inputs.sheet(3000, seed=7)
+    ctx = make_ctx(pr)
+    try:
+        d = Dev(pr)
+        rb.rb_set_collisions(ctx, dev(pr.extra["radius"]), 0.5, 1)
+        rb.rb_step(ctx, d.parts, pr.n, pr.n, 0.0, pr.dt, 2)
+        p1, r1 = rb.rb_collision_counts(ctx)
+        assert p1 > 0 and r1 > 0
+        assert rb.rb_collision_counts(ctx) == (0, 0)
+        rb.rb_set_collisions(ctx, None, 0.5, 1, enable=False)
+        rb.rb_step(ctx, d.parts, pr.n, pr.n, 2 * pr.dt, pr.dt, 2)
+        assert rb.rb_collision_counts(ctx) == (0, 0)
+    finally:
+        rb.rb_destroy(ctx)
