@@ -248,12 +248,14 @@ def build_bytes(n, n_nodes, small_sort):
 
 def collide_run(args, sysm, wdesc):
     """Collisional sheet: K steps, each one DKD step of FP32-mixed tree
-    gravity (rb_step) and then collisions at the end of the step
-    (rb_collide: tree build on the end-of-step positions, search of Eq. (3),
+    gravity and then collisions at the end of the step (search of Eq. (3),
     queue in random order, hard-sphere resolution with restitution), timed
     after W such steps from the initial state, so that the initial overlaps
-    are gone; the search kernel is timed with HIP events on the context's
-    stream."""
+    are gone.  Detector "tree": inside rb_step (rb_set_collisions), on the
+    step's own tree, all K steps in one call; "tree-call": rb_collide after
+    every one-step rb_step call (its own tree on the end-of-step positions);
+    "sweep": rb_sweep likewise.  The search kernel is timed with HIP events
+    on the context's stream."""
     import numpy as np
     import torch
     from paper_1110_4876_amd import autotune, rb
@@ -273,31 +275,49 @@ def collide_run(args, sysm, wdesc):
     R = torch.as_tensor(pr.extra["radius"], dtype=torch.float64, device="cuda")
     eps = args.epsilon
     ctx = sysm.create(rb.RB_FP32_MIXED, profile=4, **knobs)
+    sweep = args.detector == "sweep"
+    in_step = args.detector == "tree"
     try:
         X = sysm.clone()
-        sweep = args.detector == "sweep"
-
-        def collide(k):
-            if sweep:
-                return rb.rb_sweep(ctx, sysm.parts(X), R, n, (k + 1) * dt, dt, eps, 1000 + k)
-            return rb.rb_collide(ctx, sysm.parts(X), R, n, (k + 1) * dt, eps, 1000 + k)
-        for k in range(args.warmup):
-            sysm.step(ctx, X, k * dt, 1)
-            collide(k)
-        rb.rb_sync(ctx)
-        rb.rb_stats(ctx)  # discard warm-up timers
-        pairs = resolved = 0
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(args.warmup, args.warmup + args.steps):
-            sysm.step(ctx, X, k * dt, 1)
-            a, b = collide(k)
-            pairs += a
-            resolved += b
-        torch.cuda.synchronize()
-        secs = time.perf_counter() - t0
+        if in_step:
+            rb.rb_set_collisions(ctx, R, eps, 1000)
+            sysm.step(ctx, X, 0.0, args.warmup)
+            rb.rb_sync(ctx)
+            rb.rb_collision_counts(ctx)
+            rb.rb_stats(ctx)  # discard warm-up timers
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sysm.step(ctx, X, args.warmup * dt, args.steps)
+            torch.cuda.synchronize()
+            secs = time.perf_counter() - t0
+            pairs, resolved = rb.rb_collision_counts(ctx)
+        else:
+            def collide(k):
+                if sweep:
+                    return rb.rb_sweep(ctx, sysm.parts(X), R, n, (k + 1) * dt, dt, eps,
+                                       1000 + k)
+                return rb.rb_collide(ctx, sysm.parts(X), R, n, (k + 1) * dt, eps, 1000 + k)
+            for k in range(args.warmup):
+                sysm.step(ctx, X, k * dt, 1)
+                collide(k)
+            rb.rb_sync(ctx)
+            rb.rb_stats(ctx)  # discard warm-up timers
+            pairs = resolved = 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(args.warmup, args.warmup + args.steps):
+                sysm.step(ctx, X, k * dt, 1)
+                a, b = collide(k)
+                pairs += a
+                resolved += b
+            torch.cuda.synchronize()
+            secs = time.perf_counter() - t0
         s = rb.rb_stats(ctx)
-        n_nodes, n_live = (0, n) if sweep else rb.rb_tree_info(ctx)
+        if sweep:
+            n_nodes, n_live = 0, n
+        else:
+            rb.rb_tree_build(ctx, sysm.parts(X), n, n)  # (the node count of the end state)
+            n_nodes, n_live = rb.rb_tree_info(ctx)
     finally:
         rb.rb_destroy(ctx)
     search_ms = s["ms"]["coll_search"] / max(1, s["calls"]["coll_search"])
@@ -339,6 +359,9 @@ def collide_run(args, sysm, wdesc):
     out = {
         "metric": "collisional-sheet particle-steps/s (FP32-mixed tree gravity DKD step + "
                   f"FP64 {'plane-sweep' if sweep else 'tree'} collision search and resolution)",
+        "collision_path": {"tree": "inside rb_step, on the step's own tree",
+                           "tree-call": "rb_collide after every step, own tree",
+                           "sweep": "rb_sweep after every step"}[args.detector],
         "value": n * args.steps / secs,
         "unit": "particle-steps/s",
         "n_gpus": 1,
@@ -481,10 +504,11 @@ def main():
                          "hard-sphere resolution at the end of the step (own JSON line)")
     ap.add_argument("--epsilon", type=float, default=0.5,
                     help="coefficient of restitution of the collisional sheet")
-    ap.add_argument("--detector", default="tree", choices=["tree", "sweep"],
+    ap.add_argument("--detector", default="tree", choices=["tree", "tree-call", "sweep"],
                     help="collision detection of the collisional sheet: the octree search "
-                         "(overlaps at the end of the step) or the plane sweep along x "
-                         "(trajectories over the step)")
+                         "inside rb_step on the step's own tree (tree), the same search as a "
+                         "call after every step that builds its own tree (tree-call), or the "
+                         "plane sweep along x over the step's trajectories (sweep)")
     ap.add_argument("--sweep-ring", action="store_true",
                     help="collision search on a narrow ring around the origin (50,000 "
                          "particles, open box): the azimuthal plane sweep, timed per call, "
