@@ -180,9 +180,21 @@ def write_traffic(args):
     }
     meta["bytes_per_launch"] = meta["fetch_bytes_per_launch"] + meta["write_bytes_per_launch"]
     out = os.path.join(ROOT, "profiles", f"walk_{path}_{args.workload}_traffic.json")
+    # one entry per operating point: a new measurement replaces the entry of
+    # the same knobs
+    entries = traffic_entries(out)
+    entries = [e for e in entries if e.get("knobs") != meta["knobs"]] + [meta]
     with open(out, "w") as fh:
-        json.dump(meta, fh, indent=1)
+        json.dump({"entries": entries}, fh, indent=1)
     print(json.dumps(meta))
+
+
+def traffic_entries(path):
+    """The stored walk traffic measurements of a file (none if absent)."""
+    if not os.path.exists(path):
+        return []
+    d = json.load(open(path))
+    return d["entries"] if "entries" in d else [d]
 
 
 def build_traffic(args):
@@ -701,10 +713,9 @@ def main():
     achieved = r["algorithmic_flops_per_walk"] / (r["walk_ms"] * 1e-3)
     traffic = None
     tf = os.path.join(ROOT, "profiles", f"walk_{main_path}_{args.workload}_traffic.json")
-    if os.path.exists(tf):
-        # only for the same kernel sources at the same operating point
-        meta = json.load(open(tf))
-        knobs = {k: r[k] for k in KNOBS}
+    # only for the same kernel sources at the same operating point
+    knobs = {k: r[k] for k in KNOBS}
+    for meta in traffic_entries(tf):
         if (meta.get("source_sha256") == walk_source_sha(main_path) and
                 meta.get("knobs") == knobs):
             traffic = meta.get("bytes_per_launch")
