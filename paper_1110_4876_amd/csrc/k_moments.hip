@@ -740,7 +740,8 @@ hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const d
   const uint32_t G = (uint32_t)c->p.group_size;
   // the grouped walk's node records are written only when it will run
   WNode *const wnode = c->p.precision == RB_FP32_MIXED ? c->d_wnode : nullptr;
-  (void)launch_groups(c);
+  const hipError_t ge = launch_groups(c);
+  if (ge != hipSuccess) return ge;
 #define RB_MARGS                                                                          \
   c->d_nfirst, c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nskip, c->d_nleaf, sx, sy, sz, \
       c->d_msrc, c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, wnode,              \
