@@ -135,6 +135,7 @@ hipError_t launch_prologue(rb_ctx *c, const rb_particles *cp) {
 // applied (the image (wx, wy) the unwrapped position lies in) and the
 // largest displacement since the tree was built; mode 2 then does the next
 // step's first drift and keys.  Mode 0 does both at once.
+template <int mode>
 __global__ __launch_bounds__(256) void k_post(
     double *__restrict__ bx, double *__restrict__ by, double *__restrict__ bz,
     double *__restrict__ bvx, double *__restrict__ bvy, double *__restrict__ bvz,
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(256) void k_post(
     const StepConst *__restrict__ scp, const double *__restrict__ sched,
     uint32_t *__restrict__ ctr, int slot, uint64_t *__restrict__ key,
     uint32_t *__restrict__ idx, uint32_t *__restrict__ err, uint32_t *__restrict__ bcnt,
-    uint32_t *__restrict__ bctl, int mode, uint16_t *__restrict__ wrap,
+    uint32_t *__restrict__ bctl, uint16_t *__restrict__ wrap,
     unsigned long long *__restrict__ disp) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t k = ctr[slot], nsteps = ctr[2];
@@ -225,13 +226,17 @@ hipError_t launch_post(rb_ctx *c, int buf, int slot, int mode) {
   if (n == 0) return hipSuccess;
   double *const *b = c->d_px[buf];
   const int n_acc = c->img_split ? c->n_img : 1;
-  hipLaunchKernelGGL(k_post, dim3(rb_div_up(n, 256)), dim3(256), 0, c->stream, b[0], b[1],
-                     b[2], b[3], b[4], b[5], c->d_acc, c->cap, n_acc, c->d_patch, c->d_starts,
-                     c->d_nlive, c->P, n, c->p.boundary, c->p.drift, c->d_sc, c->d_sched,
-                     c->d_ctr, slot, c->d_key[0], c->d_idx[0], c->d_err,
-                     c->sort_small ? c->d_bcnt : nullptr, c->d_bctl, mode, c->d_cwrap,
-                     c->d_ccnt ? reinterpret_cast<unsigned long long *>(c->d_ccnt + 8)
-                               : nullptr);
+#define RB_POST_ARGS                                                                      \
+  b[0], b[1], b[2], b[3], b[4], b[5], c->d_acc, c->cap, n_acc, c->d_patch, c->d_starts,    \
+      c->d_nlive, c->P, n, c->p.boundary, c->p.drift, c->d_sc, c->d_sched, c->d_ctr, slot, \
+      c->d_key[0], c->d_idx[0], c->d_err, c->sort_small ? c->d_bcnt : nullptr, c->d_bctl,  \
+      c->d_cwrap,                                                                          \
+      c->d_ccnt ? reinterpret_cast<unsigned long long *>(c->d_ccnt + 8) : nullptr
+  const dim3 g(rb_div_up(n, 256)), bl(256);
+  if (mode == 1) hipLaunchKernelGGL(k_post<1>, g, bl, 0, c->stream, RB_POST_ARGS);
+  else if (mode == 2) hipLaunchKernelGGL(k_post<2>, g, bl, 0, c->stream, RB_POST_ARGS);
+  else hipLaunchKernelGGL(k_post<0>, g, bl, 0, c->stream, RB_POST_ARGS);
+#undef RB_POST_ARGS
   return hipGetLastError();
 }
 
