@@ -129,3 +129,34 @@ def test_counts_reset_and_switch_off():
         assert rb.rb_collision_counts(ctx) == (0, 0)
     finally:
         rb.rb_destroy(ctx)
+
+
+def test_batch_step_equals_rb_collide():
+    # rb_batch_step with collisions: pairs stay inside their patches, and the
+    # result is rb_collide's on the batch's end-of-step state
+    from gpu_util import dev
+    from paper_1110_4876_amd import rb
+    from paper_1110_4876_amd.system import System
+    probs = [inputs.sheet(n, seed=40 + k) for k, n in enumerate((1500, 2600, 900))]
+    sysm = System(probs)
+    R = dev(np.concatenate([pr.extra["radius"] for pr in probs]))
+    out = []
+    for mode in ("step", "call"):
+        ctx = sysm.create(rb.RB_FP64)
+        try:
+            X = sysm.clone()
+            if mode == "step":
+                rb.rb_set_collisions(ctx, R, 0.5, 5)
+                sysm.step(ctx, X, 0.0, 1)
+                counts = rb.rb_collision_counts(ctx)
+            else:
+                sysm.step(ctx, X, 0.0, 1)
+                counts = rb.rb_collide(ctx, sysm.parts(X), R, sysm.n, sysm.dt, 0.5, 5)
+            rb.rb_sync(ctx)
+            out.append((counts, {k: X[k].cpu().numpy() for k in ("x", "y", "z", "vx", "vy", "vz")}))
+        finally:
+            rb.rb_destroy(ctx)
+    (ca, a), (cb, b) = out
+    assert ca == cb and ca[1] > 0
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
