@@ -208,3 +208,14 @@ def test_export_after_fp32_step_is_refused():
         rb.rb_destroy(c64)
     for k in ref:
         np.testing.assert_array_equal(got[k], ref[k])
+
+
+def test_peak_probe_values():
+    # measured ceilings: positive, FP64 FMA not faster than FP32, a copy
+    # well below the published 8 TB/s but above 1 TB/s
+    from paper_1110_4876_amd import rb
+    f32, f64, hbm = (rb.rb_peak_probe(k) for k in (0, 1, 2))
+    assert 1e13 < f32 < 2e14 and 1e13 < f64 <= 1.05 * f32
+    assert 1e12 < hbm < 8.5e12
+    with pytest.raises(rb.RBError):
+        rb.rb_peak_probe(3)
