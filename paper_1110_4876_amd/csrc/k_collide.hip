@@ -43,12 +43,10 @@ __global__ __launch_bounds__(256) void k_coll_rmax(const double *__restrict__ R,
                                                    const uint32_t *__restrict__ starts,
                                                    const uint32_t *__restrict__ nlive,
                                                    uint32_t P, uint32_t n,
-                                                   unsigned long long *__restrict__ rmax,
-                                                   uint32_t *__restrict__ inv) {
+                                                   unsigned long long *__restrict__ rmax) {
   __shared__ double part[4];
   double r = 0.0;
   for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
-    if (inv) inv[orig[s]] = s;  // (collisions inside a step: caller index -> slot)
     const uint32_t p = (P == 1) ? 0u : rb_patch_of(starts, P, s);
     if (s - starts[p] < nlive[p]) {
       const double v = R[orig[s]];
@@ -592,7 +590,7 @@ hipError_t launch_coll_prep(rb_ctx *c, const double *radius) {
   if (n == 0) return hipSuccess;
   const unsigned grid = std::min(rb_div_up(n, 1024), 128u);
   hipLaunchKernelGGL(k_coll_rmax, dim3(grid), dim3(256), 0, c->stream, radius, c->d_orig[0],
-                     c->d_starts, c->d_nlive, c->P, n, c->d_cmax, nullptr);
+                     c->d_starts, c->d_nlive, c->P, n, c->d_cmax);
   CollNode *cells = reinterpret_cast<CollNode *>(c->d_cgeo);
   hipLaunchKernelGGL(k_coll_geom, dim3(rb_div_up(c->node_cap, 256)), dim3(256), 0, c->stream,
                      c->d_px[0][0], c->d_px[0][1], c->d_px[0][2], c->d_patch, c->d_starts, c->P,
@@ -649,8 +647,8 @@ hipError_t launch_coll_round(rb_ctx *c, int a, const rb_particles *pp, double t,
 // ---- collisions inside a step (the tree of the step, in its sorted order)
 
 // before the kick: the cells' records from the build's (mid-step)
-// positions in buffer buf, the step's counters cleared, R_max and the
-// caller-to-slot map
+// positions in buffer buf and the step's counters cleared (R_max and the
+// caller-to-slot map come from the first post kernel, k_post<1>)
 hipError_t launch_coll_step_prep(rb_ctx *c, int buf) {
   const uint32_t n = (uint32_t)c->h_starts[c->P];
   if (n == 0) return hipSuccess;
@@ -660,9 +658,6 @@ hipError_t launch_coll_step_prep(rb_ctx *c, int buf) {
                      c->d_starts, c->P, c->d_lev_off, c->node_cap, c->d_nfirst, c->d_nlast,
                      c->d_nchild, c->d_nlastchild, c->d_nlevel, c->d_nleaf, cells, c->d_err,
                      c->d_ccnt);
-  const unsigned grid = std::min(rb_div_up(n, 1024), 128u);
-  hipLaunchKernelGGL(k_coll_rmax, dim3(grid), dim3(256), 0, c->stream, c->coll_R,
-                     c->d_orig[buf], c->d_starts, c->d_nlive, c->P, n, c->d_cmax, c->d_cinv);
   return hipGetLastError();
 }
 

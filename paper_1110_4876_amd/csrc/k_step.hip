@@ -146,12 +146,14 @@ __global__ __launch_bounds__(256) void k_post(
     uint32_t *__restrict__ ctr, int slot, uint64_t *__restrict__ key,
     uint32_t *__restrict__ idx, uint32_t *__restrict__ err, uint32_t *__restrict__ bcnt,
     uint32_t *__restrict__ bctl, uint16_t *__restrict__ wrap,
-    unsigned long long *__restrict__ disp) {
+    unsigned long long *__restrict__ disp, const uint32_t *__restrict__ orig,
+    const double *__restrict__ radius, uint32_t *__restrict__ inv,
+    unsigned long long *__restrict__ rmax) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t k = ctr[slot], nsteps = ctr[2];
   // the next step reads its index from the other slot
   if (s == 0 && mode != 2) ctr[1 - slot] = k + 1;
-  double moved = 0.0;
+  double moved = 0.0, rad = 0.0;
   if (s < n) {
   const uint32_t p = (P == 1) ? 0 : rb_patch_of(starts, P, s);
   const PatchInfo pi = patch[p];
@@ -159,6 +161,14 @@ __global__ __launch_bounds__(256) void k_post(
   const bool has_next = k + 1 < nsteps && mode != 1;
   PState q{bx[s], by[s], bz[s], bvx[s], bvy[s], bvz[s]};
   const bool live = (s - pi.start) < nlive[p];
+  if (mode == 1) {  // for the search and the rounds: caller index -> slot, R_max
+    const uint32_t o = orig[s];
+    inv[o] = s;
+    if (live) {
+      const double v = radius[o];
+      rad = v > 0.0 ? v : 0.0;  // (a NaN radius is never larger)
+    }
+  }
   if (live) {
     if (mode != 2) {
       double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -214,10 +224,25 @@ __global__ __launch_bounds__(256) void k_post(
     }
   }
   }
-  if (mode == 1) {  // the largest displacement (ordered bits of a non-negative double)
-    for (int d = 32; d >= 1; d >>= 1) moved = fmax(moved, __shfl_xor(moved, d, 64));
-    if (rb_lane() == 0 && moved > 0.0)
-      atomicMax(disp, (unsigned long long)__double_as_longlong(moved));
+  if (mode == 1) {
+    // the largest displacement and radius (ordered bits of non-negative
+    // doubles), one atomic each per workgroup: both words share a cache line
+    __shared__ double part[2][4];
+    for (int d = 32; d >= 1; d >>= 1) {
+      moved = fmax(moved, __shfl_xor(moved, d, 64));
+      rad = fmax(rad, __shfl_xor(rad, d, 64));
+    }
+    if (rb_lane() == 0) {
+      part[0][threadIdx.x >> 6] = moved;
+      part[1][threadIdx.x >> 6] = rad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      moved = fmax(fmax(part[0][0], part[0][1]), fmax(part[0][2], part[0][3]));
+      rad = fmax(fmax(part[1][0], part[1][1]), fmax(part[1][2], part[1][3]));
+      if (moved > 0.0) atomicMax(disp, (unsigned long long)__double_as_longlong(moved));
+      if (rad > 0.0) atomicMax(rmax, (unsigned long long)__double_as_longlong(rad));
+    }
   }
 }
 
@@ -231,7 +256,8 @@ hipError_t launch_post(rb_ctx *c, int buf, int slot, int mode) {
       c->d_nlive, c->P, n, c->p.boundary, c->p.drift, c->d_sc, c->d_sched, c->d_ctr, slot, \
       c->d_key[0], c->d_idx[0], c->d_err, c->sort_small ? c->d_bcnt : nullptr, c->d_bctl,  \
       c->d_cwrap,                                                                          \
-      c->d_ccnt ? reinterpret_cast<unsigned long long *>(c->d_ccnt + 8) : nullptr
+      c->d_ccnt ? reinterpret_cast<unsigned long long *>(c->d_ccnt + 8) : nullptr,         \
+      c->d_orig[buf], c->coll_R, c->d_cinv, c->d_cmax
   const dim3 g(rb_div_up(n, 256)), bl(256);
   if (mode == 1) hipLaunchKernelGGL(k_post<1>, g, bl, 0, c->stream, RB_POST_ARGS);
   else if (mode == 2) hipLaunchKernelGGL(k_post<2>, g, bl, 0, c->stream, RB_POST_ARGS);
