@@ -255,20 +255,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
               const uint32_t eb = lfb[lb + lo];
               const uint32_t j = lfa[lb + lo] + (e - (lsc[lo] - ((eb >> 5) + 1u)));
               const int k = (int)(eb & 31u);
-              int kx = (boundary == RB_OPEN) ? 0 : k / ny - ngx;
-              int ky = (boundary == RB_OPEN) ? 0 : k % ny - ngy;
-              if (STEP) {
-                const uint32_t wb = wrap[j];
-                kx += (int)(wb & 15u) - 2;
-                ky += (int)(wb >> 4) - 2;
-              }
               const uint32_t oj = orig[j];
-              cx_[lane] = sx[j];
-              cy_[lane] = sy[j];
+              if (STEP) {
+                // raw position and the image relative to the box both wraps
+                // are counted from (the lane's own wrap is taken off later)
+                const uint32_t wb = wrap[j];
+                const int kx = ((boundary == RB_OPEN) ? 0 : k / ny - ngx) + (int)(wb & 15u) - 2;
+                const int ky = ((boundary == RB_OPEN) ? 0 : k % ny - ngy) + (int)(wb >> 4) - 2;
+                cx_[lane] = sx[j];
+                cy_[lane] = sy[j];
+                ck_[lane] = (uint8_t)((kx + 8) | ((ky + 8) << 4));
+              } else {
+                // the image-shifted position (the lanes' particles are in the box)
+                double ox, oy, wy;
+                rb_coll_image(k, ngx, ngy, boundary, W, sh, omega, ox, oy, wy);
+                cx_[lane] = sx[j] + ox;
+                cy_[lane] = sy[j] + oy;
+                ck_[lane] = (uint8_t)k;
+              }
               cz_[lane] = sz[j];
               cr_[lane] = R[oj];
               co_[lane] = oj;
-              ck_[lane] = (uint8_t)((kx + 8) | ((ky + 8) << 4));
             }
             coll_wave_sync();
             const int C = (int)min(64u, M - e0);
@@ -276,22 +283,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
               for (int q = (int)sub; q < C; q += (int)NS) {
                 const uint32_t oj = co_[q];
                 if (oi >= oj) continue;  // each pair once, from its lower caller index
-                // the image of j relative to i in the (wrapped) box
                 const uint32_t kb = ck_[q];
-                const int ix = (int)(kb & 15u) - 8 - wxi, iy = (int)(kb >> 4) - 8 - wyi;
-                if (ix < -ngx || ix > ngx || iy < -ngy || iy > ngy) continue;
-                double ox, oy, wy;
-                rb_coll_image_xy(ix, iy, boundary, W, sh, omega, ox, oy, wy);
-                const double d0 = (cx_[q] + ox) - xi;
-                const double d1 = (cy_[q] + oy) - yi;
-                const double d2 = (cz_[q] + 0.0) - zi;
+                double d0, d1;
+                uint32_t kc;
+                if (STEP) {
+                  // the image of j relative to i in the (wrapped) box
+                  const int ix = (int)(kb & 15u) - 8 - wxi, iy = (int)(kb >> 4) - 8 - wyi;
+                  if (ix < -ngx || ix > ngx || iy < -ngy || iy > ngy) continue;
+                  double ox, oy, wy;
+                  rb_coll_image_xy(ix, iy, boundary, W, sh, omega, ox, oy, wy);
+                  d0 = (cx_[q] + ox) - xi;
+                  d1 = (cy_[q] + oy) - yi;
+                  kc = (boundary == RB_OPEN) ? 0u : (uint32_t)((ix + ngx) * ny + (iy + ngy));
+                } else {
+                  d0 = cx_[q] - xi;
+                  d1 = cy_[q] - yi;
+                  kc = (boundary == RB_OPEN) ? 0u : kb;
+                }
+                const double d2 = cz_[q] - zi;
                 const double sum = Ri + cr_[q];
-                if (d0 * d0 + d1 * d1 + d2 * d2 < sum * sum) {
-                  const uint32_t kc =
-                      (boundary == RB_OPEN) ? 0u : (uint32_t)((ix + ngx) * ny + (iy + ngy));
+                if (d0 * d0 + d1 * d1 + d2 * d2 < sum * sum)
                   rb_coll_keep(((uint64_t)oi << 35) | ((uint64_t)oj << 7) | (uint64_t)kc,
                                mine, nm, queue, qcap, qcnt, err);
-                }
               }
             }
             coll_wave_sync();

@@ -255,6 +255,7 @@ __global__ __launch_bounds__(256) void k_groups(
     uint32_t *__restrict__ large_cnt) {
   const uint32_t n_nodes = lev_off[RB_NLEV];
   const uint32_t lane = rb_lane();
+  __shared__ uint32_t s_tot[3][4], s_base[3];
   for (uint32_t base = blockIdx.x * blockDim.x; base < n_nodes; base += gridDim.x * blockDim.x) {
     const uint32_t id = base + threadIdx.x;
     const bool in = id < n_nodes;
@@ -308,20 +309,31 @@ __global__ __launch_bounds__(256) void k_groups(
       }
       if (run) wi_tally(half, quarter, n_big, n_mid, n_small, run);
     }
-    // table slots: one atomic per wave and table
+    // table slots: one atomic per workgroup and table (atomics on one
+    // address serialise), the waves in order after the workgroup's base
     const uint32_t bincl = rb_wave_incl_scan(n_big);
-    const uint32_t btotal = __shfl(bincl, 63, 64);
     const uint32_t mincl = rb_wave_incl_scan(n_mid);
-    const uint32_t mtotal = __shfl(mincl, 63, 64);
     const uint32_t sincl = rb_wave_incl_scan(n_small);
-    const uint32_t stotal = __shfl(sincl, 63, 64);
-    uint32_t bbase = 0, mbase = 0, sbase = 0;
-    if (lane == 63 && btotal) bbase = atomicAdd(&gctr[2], btotal);
-    if (lane == 63 && mtotal) mbase = atomicAdd(&gctr[3], mtotal);
-    if (lane == 63 && stotal) sbase = atomicAdd(&gctr[4], stotal);
-    bbase = __shfl(bbase, 63, 64);
-    mbase = __shfl(mbase, 63, 64);
-    sbase = __shfl(sbase, 63, 64);
+    const uint32_t w = threadIdx.x >> 6;
+    if (lane == 63) {
+      s_tot[0][w] = bincl;
+      s_tot[1][w] = mincl;
+      s_tot[2][w] = sincl;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      const uint32_t t = threadIdx.x;
+      const uint32_t sum = s_tot[t][0] + s_tot[t][1] + s_tot[t][2] + s_tot[t][3];
+      s_base[t] = sum ? atomicAdd(&gctr[2 + t], sum) : 0u;
+    }
+    __syncthreads();
+    uint32_t bbase = s_base[0], mbase = s_base[1], sbase = s_base[2];
+    for (uint32_t v = 0; v < w; ++v) {
+      bbase += s_tot[0][v];
+      mbase += s_tot[1][v];
+      sbase += s_tot[2][v];
+    }
+    __syncthreads();  // (the next round rewrites s_tot and s_base)
     uint32_t bpos = bbase + bincl - n_big, mpos = mbase + mincl - n_mid;
     uint32_t spos = sbase + sincl - n_small;
     if (n_big + n_mid + n_small) {

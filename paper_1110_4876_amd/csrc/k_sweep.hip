@@ -138,10 +138,16 @@ __global__ __launch_bounds__(256) void k_sw_keys(
       rb_bucket_add(bcnt, 0, 1, k);
     }
   }
-  // the longest interval (ordered bits of a non-negative double)
+  // the longest interval (ordered bits of a non-negative double), one
+  // atomic per workgroup: same-address atomics serialise
+  __shared__ double part[4];
   for (int d = 32; d >= 1; d >>= 1) len = fmax(len, __shfl_xor(len, d, 64));
-  if (rb_lane() == 0 && len > 0.0)
-    atomicMax(lmax, (unsigned long long)__double_as_longlong(len));
+  if (rb_lane() == 0) part[threadIdx.x >> 6] = len;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    len = fmax(fmax(part[0], part[1]), fmax(part[2], part[3]));
+    if (len > 0.0) atomicMax(lmax, (unsigned long long)__double_as_longlong(len));
+  }
 }
 
 // the particles in sorted order, each interval's end, the live count
