@@ -469,11 +469,28 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W32M_WA
   const double theta2d = theta2;
   const uint32_t step = ctr[slot];
   unsigned long long n_cell = 0, n_pp = 0;
-  // the first item of every workgroup is fixed by its position in the
-  // grid, the others come from the queue
+  // The first item of every workgroup is fixed by its position in the
+  // grid, the others come from the queue.  Workgroups are dispatched to the
+  // eight XCDs in turn (workgroup b on XCD b mod 8, each XCD with its own
+  // L2).  When every item has a workgroup of its own, XCD x takes the x-th
+  // eighth of each size class: its items are neighbours in the tables
+  // (which follow the tree's slot order within a level), so its L2 holds
+  // their part of the tree, and every XCD gets the same mix of sizes.
+  uint32_t item0 = blockIdx.x;
+  if (!img_split && (gridDim.x & 7u) == 0 && n_items + 24u <= gridDim.x) {
+    const uint32_t x = blockIdx.x & 7u, j = blockIdx.x >> 3;
+    const uint32_t n_small = n_groups - n_big - n_mid;
+    const uint32_t b0 = n_big * x / 8u, nb = n_big * (x + 1u) / 8u - b0;
+    const uint32_t m0 = n_mid * x / 8u, nm = n_mid * (x + 1u) / 8u - m0;
+    const uint32_t q0 = n_small * x / 8u, nq = n_small * (x + 1u) / 8u - q0;
+    if (j < nb) item0 = b0 + j;
+    else if (j < nb + nm) item0 = n_big + m0 + (j - nb);
+    else if (j < nb + nm + nq) item0 = n_big + n_mid + q0 + (j - nb - nm);
+    else item0 = n_items;  // no item for this workgroup
+  }
   bool first = true;
   for (;;) {
-    if (threadIdx.x == 0) s_item = first ? blockIdx.x : gridDim.x + atomicAdd(&gctr[1], 1u);
+    if (threadIdx.x == 0) s_item = first ? item0 : gridDim.x + atomicAdd(&gctr[1], 1u);
     first = false;
     __syncthreads();
     const uint32_t item = (uint32_t)w32_uniform((int)s_item);
