@@ -166,6 +166,31 @@ def test_multi_wave_walk_matches_single_wave(orc, waves):
         assert rms_rel(am, a1) <= 1e-6, rms_rel(am, a1)
 
 
+@pytest.mark.parametrize("n", [30000, 60000, 90000, 150000])
+def test_multi_wave_takes_every_item(n):
+    # Four-wave workgroups take their first items by XCD while every item has
+    # a workgroup of its own (at most 1512 items, for the grid of 1536
+    # four-wave workgroups), and from the queue otherwise: 30,000 particles
+    # give fewer items than 50,000 (which fit), 150,000 at least 2344 (an
+    # item holds at most 64 particles).  An item
+    # taken twice or never would show against the single-wave walk, whose
+    # items all come in grid order.
+    from gpu_util import Dev, gravity, make_ctx, rms_rel
+    from paper_1110_4876_amd import rb
+    pr = inputs.sheet(n, seed=11).with_params(theta=0.42)
+    d = Dev(pr, with_v=False)
+    c1 = make_ctx(pr, precision=rb.RB_FP32_MIXED, group_size=64)
+    c4 = make_ctx(pr, precision=rb.RB_FP32_MIXED, group_size=64, walk_waves=4)
+    try:
+        a1 = gravity(c1, d, pr.n, 0.0)
+        a4 = gravity(c4, d, pr.n, 0.0)
+    finally:
+        rb.rb_destroy(c1)
+        rb.rb_destroy(c4)
+    assert np.all(np.isfinite(a4)) and np.all(np.linalg.norm(a4, axis=1) > 0)
+    assert rms_rel(a4, a1) <= 1e-6, rms_rel(a4, a1)
+
+
 def test_multi_wave_theta_zero_precision(orc):
     # theta = 0 with four waves: every term direct, FP32 rounding only
     from gpu_util import Dev, gravity, make_ctx, rms_rel
