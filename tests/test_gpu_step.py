@@ -171,3 +171,19 @@ def test_phase_timers_across_calls():
             assert s["ms"]["total"] >= s["ms"]["walk"] > 0
     finally:
         rb.rb_destroy(ctx)
+
+
+def test_periodic_wrap_across_steps(orc):
+    # plain periodic boundaries: particles pushed across the x and y faces
+    # during the step re-enter through the opposite face, as in the oracle
+    pr = inputs.sheet(3000, seed=9).with_params(boundary=inputs.PERIODIC)
+    W = pr.params["W"]
+    pr.vx[:150] = np.sign(pr.x[:150]) * 0.5 * W / pr.dt
+    pr.vy[150:300] = np.sign(pr.y[150:300]) * 0.5 * W / pr.dt
+    p = orc.make_params(**pr.params)
+    ref = orc.step(p, pr.state(), pr.m, 0.0, pr.dt, 2, use_tree=True)
+    got = _run_gpu(pr, 0.0, pr.dt, 2)
+    for k in ("x", "y", "z"):
+        np.testing.assert_allclose(got[k], ref[k], rtol=0, atol=1e-9 * W, err_msg=k)
+    for k in ("vx", "vy", "vz"):
+        np.testing.assert_allclose(got[k], ref[k], rtol=1e-9, atol=1e-12, err_msg=k)

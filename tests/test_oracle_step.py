@@ -141,3 +141,98 @@ def test_energy_closed_forms(orc):
     ek = 0.5 * 2.0 * (1.0 + 0.25) + 0.5 * 3.0 * 4.0 + 0.5 * 4.0 * 0.09
     ep = -G * 2.0 * 3.0 / math.sqrt(r2 + b * b)
     assert abs(e - (ek + ep)) <= 1e-14 * abs(ek)
+
+
+def test_periodic_wrap(orc):
+    # plain periodic boundaries (Sect. 2.3): a particle leaving through an x
+    # or y face re-enters through the opposite one, x -> x -+ W, with y (for
+    # an x crossing), z and the velocity unchanged; z stays open
+    W = 10.0
+    p = orc.make_params(W=W, x0=(-5.0, -5.0, -5.0), boundary=orc.PERIODIC, ng=(1, 1),
+                        omega=0.7)
+    st = dict(x=np.array([5.0, 5.75, -5.25, 1.0, 2.0, 0.5]),
+              y=np.array([1.0, -2.0, 3.0, 5.5, -5.125, 0.0]),
+              z=np.array([0.5, 0.0, -1.0, 0.0, 0.0, 5.0]),
+              vx=np.array([0.1, 0.2, 0.3, 0.4, 0.5, 0.6]),
+              vy=np.array([-0.1, -0.2, -0.3, -0.4, -0.5, -0.6]),
+              vz=np.array([1.0, 2.0, 3.0, 4.0, 5.0, 6.0]))
+    out = orc.boundary(p, st, 1.234)  # the shear offset is ignored here
+    np.testing.assert_array_equal(out["x"][:5], [-5.0, -4.25, 4.75, 1.0, 2.0])
+    np.testing.assert_array_equal(out["y"][:5], [1.0, -2.0, 3.0, -4.5, 4.875])
+    np.testing.assert_array_equal(out["z"][:5], st["z"][:5])
+    for k in ("vx", "vy", "vz"):
+        np.testing.assert_array_equal(out[k][:5], st[k][:5])
+    # the last one left through the open z face: removed
+    assert np.isnan(out["x"][5]) and out["vz"][5] == 0.0
+
+
+def _sheet_params(orc, W=1000.0, omega=2e-4):
+    return orc.make_params(G=1.0, b=0.0, W=W, x0=(-0.5 * W, -0.5 * W, -0.5 * W),
+                           boundary=orc.SHEAR, ng=(1, 1), drift=orc.EPICYCLE, omega=omega)
+
+
+def test_shear_ghost_image_is_the_unwrapped_neighbour(orc):
+    # Geometry of the shear-periodic ghost boxes at a time with s != 0: a
+    # source just outside the +x face, and a massless target d = 1 W/1000
+    # away just inside it.  The boundary wraps the source to the -x side
+    # (shifted in y by s); its ghost image in the box at +W must then sit
+    # where the source was, so the target feels the same nearby source
+    # before and after the wrap.  The image sets differ only by far images
+    # (relative size (d/W)^2).  A flipped sign of the wrap's y shift, or of
+    # the image offset, moves the nearby image by 2s and fails.
+    W = 1000.0
+    p = _sheet_params(orc, W)
+    for s in (0.31 * W, -0.44 * W, 0.49 * W):
+        for ys in (12.0, 0.5 * W - 0.4):  # the second one also wraps in y
+            src = dict(x=np.array([0.5 * W + 0.3]), y=np.array([ys]), z=np.array([0.0]),
+                       vx=np.zeros(1), vy=np.zeros(1), vz=np.zeros(1))
+            wr = orc.boundary(p, src, s)
+            assert wr["x"][0] < 0  # it was wrapped
+            tx, ty = 0.5 * W - 0.7, ys - 0.2  # target 1.02 m from the source
+            m = np.array([1.0, 0.0])
+            before = orc.direct(p, [src["x"][0], tx], [src["y"][0], ty], [0.0, 0.0], m,
+                                n_active=1, s=s, targets=[1])[0]
+            after = orc.direct(p, [wr["x"][0], tx], [wr["y"][0], ty], [0.0, 0.0], m,
+                               n_active=1, s=s, targets=[1])[0]
+            near = np.array([0.5 * W + 0.3 - tx, ys - ty, 0.0])
+            a_near = near / np.linalg.norm(near) ** 3
+            assert np.linalg.norm(after - before) <= 1e-4 * np.linalg.norm(a_near)
+            assert np.linalg.norm(after - a_near) <= 1e-4 * np.linalg.norm(a_near)
+
+
+def test_shear_image_follows_the_drifted_particle(orc):
+    # Hill's equations are invariant under the shear boost x -> x - W,
+    # y -> y + (3/2) Omega W t + c, vy -> vy + (3/2) Omega W.  So a particle
+    # wrapped across the +x face at t1 and then drifted with the epicycle
+    # map must keep its ghost image in the box at +W on the track of the
+    # same particle drifted without the wrap, at every later time t2 -- with
+    # the images' shear offset s(t2).  This pins the direction of the shear
+    # offset (relative to the mean flow vy = -(3/2) Omega x of the drift),
+    # the wrap's y and vy shifts and the image offset together: flipping any
+    # of them moves the image by 2 s(t1) ~ 0.6 W or by twice the slide.
+    W, om = 1000.0, 2e-4
+    p = _sheet_params(orc, W, om)
+    t1 = 0.37 * 2 * math.pi / om
+    # drift times over which the boxes slide by 20, 60 and 150 m against
+    # each other: far more than d, while the particle stays near the box
+    for slide in (20.0, 60.0, 150.0):
+        tau = slide / (1.5 * om * W)
+        x1 = 0.5 * W + 0.25
+        src = dict(x=np.array([x1]), y=np.array([-100.0]), z=np.array([0.5]),
+                   vx=np.array([0.02]), vy=np.array([-1.5 * om * x1 + 0.01]),
+                   vz=np.array([0.0]))
+        wr = orc.boundary(p, src, orc.shear_offset(p, t1))
+        assert wr["x"][0] < 0
+        free = orc.drift(p, src, tau)   # the unwrapped particle
+        moved = orc.drift(p, wr, tau)   # the wrapped one
+        t2 = t1 + tau
+        s2 = orc.shear_offset(p, t2)
+        # a massless target 0.8 m from the unwrapped particle's position:
+        # the nearby source must be the wrapped particle's ghost image
+        tx, ty, tz = free["x"][0] + 0.8, free["y"][0], free["z"][0]
+        m = np.array([1.0, 0.0])
+        a = orc.direct(p, [moved["x"][0], tx], [moved["y"][0], ty], [moved["z"][0], tz], m,
+                       n_active=1, s=s2, targets=[1])[0]
+        near = np.array([-0.8, 0.0, 0.0])
+        a_near = near / 0.8 ** 3
+        assert np.linalg.norm(a - a_near) <= 1e-4 * np.linalg.norm(a_near), (tau, a, a_near)
