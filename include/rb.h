@@ -90,6 +90,12 @@ typedef enum { RB_DRIFT_LEAPFROG = 0, RB_DRIFT_EPICYCLE = 1 } rb_drift;
  *                   traversal (1, 2 or 4; 0 selects 1).  More waves shorten
  *                   each group's chain of dependent steps when there are few
  *                   groups for the chip.
+ *  moments_level_log2  the moments of the nodes above the walk's work items
+ *                   (bottom-up, Sect. 4.2) run in one workgroup for systems
+ *                   of up to 2^k slots and level by level over the whole chip
+ *                   above; k = 0 selects 22.  6..31.  Both orders add the
+ *                   same children in the same order, so the moments are
+ *                   identical; only the speed differs.
  */
 typedef struct {
   double G;
@@ -111,7 +117,8 @@ typedef struct {
   int32_t profile;
   int32_t use_graph;
   int32_t walk_waves;
-  int32_t reserved[4];
+  int32_t moments_level_log2;
+  int32_t reserved[3];
 } rb_params;
 
 /* Device SoA of the particles, caller order, all FP64. */

@@ -184,3 +184,15 @@ def tune(system, ref, targets, t_kick, precision=rb.RB_FP32_MIXED, rms_target=1e
         with open(cache, "w") as f:
             json.dump(data, f, indent=1)
     return best
+
+
+OP_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "operating_points.json")
+KNOBS = ("theta", "leaf_size", "group_size", "split_images", "walk_waves")
+
+
+def operating_point(workload: str, path: str) -> dict:
+    """The fixed operating point of a benchmark workload ("batch256",
+    "sheet50k", "sheet1m", "plummer8m") for one path ("fp32" or "fp64"):
+    theta, leaf_size, group_size, split_images, walk_waves, use_graph."""
+    with open(OP_FILE) as f:
+        return dict(json.load(f)[workload][path])

@@ -770,7 +770,8 @@ hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const d
   if (bgrid > 2048) bgrid = 2048;
   hipLaunchKernelGGL(k_moments_bottom, dim3(bgrid), dim3(64), 0, c->stream, c->d_bottom,
                      c->d_large_cnt, c->d_lev_off, c->d_nlevel, RB_MARGS);
-  if (n <= (1u << 22)) {
+  const int lv = c->p.moments_level_log2 > 0 ? c->p.moments_level_log2 : 22;
+  if ((uint64_t)n <= (1ull << lv)) {
     hipLaunchKernelGGL(k_moments_large, dim3(1), dim3(512), 0, c->stream, c->d_large,
                        c->d_large_cnt, c->d_lev_off, RB_MARGS);
   } else {

@@ -99,6 +99,8 @@ int validate(const rb_params *p) {
     return fail(RB_EINVAL, "node_factor must be 0 or >= 1.5");
   if (p->walk_waves != 0 && p->walk_waves != 1 && p->walk_waves != 2 && p->walk_waves != 4)
     return fail(RB_EINVAL, "walk_waves must be 0, 1, 2 or 4");
+  if (p->moments_level_log2 != 0 && (p->moments_level_log2 < 6 || p->moments_level_log2 > 31))
+    return fail(RB_EINVAL, "moments_level_log2 must be 0 or 6..31");
   return RB_OK;
 }
 

@@ -48,7 +48,8 @@ class rb_params(ctypes.Structure):
         ("profile", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
         ("walk_waves", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("moments_level_log2", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 

@@ -40,11 +40,13 @@ def _sampled_direct(orc, pr, t, k, seed=0):
 _C1_REF = {}
 
 
-@pytest.mark.parametrize("group,theta,split", [(64, 0.4, 0), (32, 0.4, 0), (32, 0.4, 1),
-                                               (16, 0.35, 0)])
-def test_c1_operating_point_meets_gate(orc, group, theta, split):
+@pytest.mark.parametrize("group,theta,split,waves", [
+    (64, 0.4, 0, 1), (32, 0.4, 0, 1), (32, 0.4, 1, 1), (16, 0.35, 0, 1),
+    (32, 0.4, 0, 2), (64, 0.42, 0, 2), (64, 0.42, 0, 4), (32, 0.4, 1, 4), (16, 0.35, 0, 4)])
+def test_c1_operating_point_meets_gate(orc, group, theta, split, waves):
     # the 50,000-particle ring patch in the launch shapes the benchmark's
-    # autotuner picks from: FP32-mixed at these (group, theta, image split)
+    # autotuner picks from: FP32-mixed at these (group, theta, image split,
+    # waves per work item: one wave, or 2 and 4 waves sharing a traversal)
     # meets rms <= 1e-4 against the FP64 direct sum (Eq. 1 over the images)
     # on the benchmark's 4096 sampled targets
     from gpu_util import Dev, gravity, make_ctx
@@ -55,7 +57,8 @@ def test_c1_operating_point_meets_gate(orc, group, theta, split):
     if not _C1_REF:
         _C1_REF["tg"], _C1_REF["ref"] = _sampled_direct(orc, pr, t, 4096)
     tg, ref = _C1_REF["tg"], _C1_REF["ref"]
-    ctx = make_ctx(pr, precision=rb.RB_FP32_MIXED, group_size=group, split_images=split)
+    ctx = make_ctx(pr, precision=rb.RB_FP32_MIXED, group_size=group, split_images=split,
+                   walk_waves=waves)
     try:
         a = gravity(ctx, Dev(pr, with_v=False), pr.n, t)
     finally:

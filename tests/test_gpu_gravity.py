@@ -179,3 +179,61 @@ def test_c1_full_size_sampled(orc, theta, split):
     finally:
         rb.rb_destroy(ctx)
     assert rms_rel(a[tg], ref) <= TOL_BH
+
+
+@pytest.mark.parametrize("theta", [0.26, 0.5])
+def test_c1_interaction_counts_equal_oracle(orc, theta):
+    # the per-particle FP64 walk makes exactly the oracle walk's decisions, so
+    # its counts (opening tests, accepted cells, particle terms) -- the
+    # algorithmic work behind every roofline figure -- equal the oracle's
+    import torch
+    from gpu_util import Dev, make_ctx
+    from paper_1110_4876_amd import rb
+    pr = inputs.sheet(50000, seed=0).with_params(theta=theta)
+    t = 0.5 * pr.dt
+    p = orc.make_params(**pr.params)
+    T = orc.Tree(p, pr.x, pr.y, pr.z, pr.m)
+    T.walk(s=orc.shear_offset(p, t))
+    for split in (0, 1):
+        ctx = make_ctx(pr, profile=2, split_images=split)
+        try:
+            d = Dev(pr, with_v=False)
+            ax = torch.empty(pr.n, dtype=torch.float64, device="cuda")
+            ay, az = torch.empty_like(ax), torch.empty_like(ax)
+            rb.rb_gravity(ctx, d.parts, pr.n, pr.n, t, ax, ay, az)
+            s = rb.rb_stats(ctx)
+        finally:
+            rb.rb_destroy(ctx)
+        for k in ("open_tests", "cells", "pp"):
+            assert s[k] == T.stats[k], (split, k, s[k], T.stats[k])
+
+
+def test_c1_snapshots_along_a_run(orc):
+    # C1 (plain FP64, theta 0.5, quadrupoles) run for 100 steps on the GPU;
+    # from the snapshots at steps 0, 10, 50 and 100 the GPU walk and the
+    # oracle's walk get identical inputs and must agree (rms <= 1e-12 on the
+    # 4096 sampled targets, every target within 1e-10)
+    from gpu_util import Dev, gravity, make_ctx, rms_rel
+    from paper_1110_4876_amd import rb
+    pr = inputs.sheet(50000, seed=0).with_params(theta=0.5)
+    p = orc.make_params(**pr.params)
+    tg = inputs.sample_targets(pr.n, 4096, seed=0)
+    ctx = make_ctx(pr)
+    try:
+        d = Dev(pr)
+        done = 0
+        for upto in (0, 10, 50, 100):
+            if upto > done:
+                rb.rb_step(ctx, d.parts, d.n, d.n, done * pr.dt, pr.dt, upto - done)
+                rb.rb_sync(ctx)
+                done = upto
+            st = d.state()
+            t = (done + 0.5) * pr.dt
+            a = gravity(ctx, d, pr.n, t)  # reads the positions only
+            ref = orc.Tree(p, st["x"], st["y"], st["z"], pr.m).walk(
+                s=orc.shear_offset(p, t), targets=tg)
+            assert rms_rel(a[tg], ref) <= TOL_BH, (upto, rms_rel(a[tg], ref))
+            err = np.linalg.norm(a[tg] - ref, axis=1) / np.linalg.norm(ref, axis=1)
+            assert err.max() <= 1e-10, (upto, err.max())
+    finally:
+        rb.rb_destroy(ctx)
