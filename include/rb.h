@@ -96,6 +96,11 @@ typedef enum { RB_DRIFT_LEAPFROG = 0, RB_DRIFT_EPICYCLE = 1 } rb_drift;
  *                   above; k = 0 selects 22.  6..31.  Both orders add the
  *                   same children in the same order, so the moments are
  *                   identical; only the speed differs.
+ *  walk64_schedule  FP64 walk: 0 chooses by size, 1 every lane walks for its
+ *                   own particle, 2 a wave walks once for its 64 particles
+ *                   (each lane keeping its own decisions).  Both visit, per
+ *                   particle, the same nodes in the same order; only the
+ *                   speed differs.
  */
 typedef struct {
   double G;
@@ -118,7 +123,8 @@ typedef struct {
   int32_t use_graph;
   int32_t walk_waves;
   int32_t moments_level_log2;
-  int32_t reserved[3];
+  int32_t walk64_schedule;
+  int32_t reserved[2];
 } rb_params;
 
 /* Device SoA of the particles, caller order, all FP64. */

@@ -1,13 +1,35 @@
 // k_walk64.hip -- per-particle FP64 tree walk (Sect. 4.2 of the paper).
 //
-// One wave handles 64 Morton-consecutive particles; every lane walks the tree
-// for its own particle with its own opening decisions, so the result is the
-// plain per-particle Barnes-Hut sum.  The walk is stackless: nodes are
-// visited in depth-first octant order by following `child` when a node is
-// opened and `skip` (the next node after its subtree) otherwise.  Opening
-// test, image shifts and the centre-of-mass arithmetic round exactly as in a
-// plain sequential FP64 walk, so the decisions are reproducible bit for bit.
+// The result is the plain per-particle Barnes-Hut sum: every particle makes
+// its own opening decisions, w^2 < theta^2 R^2 with R measured from its own
+// position to the cell's centre of mass, and visits the nodes it needs in
+// depth-first octant order.  The opening test, the image shifts and the
+// term arithmetic round exactly as a plain sequential FP64 walk does, so the
+// decisions are reproducible bit for bit.
+//
+// Two schedules give the same sums.  k_walk64 (systems with many work
+// units): one wave takes 64 Morton-consecutive particles (one per lane)
+// and walks the tree once for all of them.  The node in hand is the same
+// for the whole wave, so its record is read with scalar loads; each lane
+// tests it against its own particle.  A lane takes part in a node only if
+// it opened every ancestor of that node: the lanes that opened a node at
+// level l are kept as a 64-bit mask for level l + 1 (lane k of a vector
+// register holds the mask of level k), and a node at level l is worked on
+// by the lanes of mask l.  Lanes that accept a cell add its monopole (and
+// quadrupole) term; the wave descends to the children when any lane opened
+// it and moves on to the next node after the subtree otherwise.  Every lane
+// thus sees exactly the nodes, in exactly the order, that its own
+// stackless walk (child link when opening, skip link otherwise) would.
+// k_walk64_lane (few work units, where the wave's single chain of dependent
+// node loads would leave the chip waiting): every lane follows that
+// stackless walk on its own, with its own loads.
 #include "rb_internal.h"
+
+// work units (64 particles and one image, or all images) from which the
+// wave-shared walk is used: below, the waves are too few to hide the
+// latency of its one chain of node loads per wave, and per-lane walks do
+// better (measured: 7,000 units per-lane faster, 16,000 wave-shared faster)
+#define RB_WALK64_SHARED_MIN 12288u
 
 // 1 / sqrt(x): hardware estimate (relative error ~2^-23) refined by two
 // Newton steps y <- y (3 - x y^2) / 2 to FP64 accuracy.
@@ -35,8 +57,207 @@ __device__ __forceinline__ void rb_image(int im, int ngx, int ngy, int boundary,
   self = (ix == 0 && iy == 0);
 }
 
+// Node records read through the constant address space: the node index is
+// uniform over the wave, so these become scalar loads.
+typedef __attribute__((address_space(4))) const uint32_t *w64_u32_p;
+typedef __attribute__((address_space(4))) const double *w64_dbl_p;
+
+__device__ __forceinline__ uint64_t w64_readlane(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// a node's walk record, in scalar registers
+struct W64Rec {
+  uint32_t child, skip, count, lvl;
+  double cx, cy, cz, m;
+};
+
+__device__ __forceinline__ void w64_fetch(w64_u32_p link, w64_dbl_p mcom, uint32_t v,
+                                          W64Rec &r) {
+  const w64_u32_p lp = link + 4 * (size_t)v;
+  r.child = lp[0]; r.skip = lp[1]; r.count = lp[2]; r.lvl = lp[3];
+  const w64_dbl_p mp = mcom + 4 * (size_t)v;
+  r.cx = mp[0]; r.cy = mp[1]; r.cz = mp[2]; r.m = mp[3];
+}
+
+__device__ __forceinline__ uint32_t w64_uniform(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
 template <bool QUAD, bool STATS>
-__global__ __launch_bounds__(64) void k_walk64(
+__global__ __launch_bounds__(256) void k_walk64(
+    const WalkItem *__restrict__ items, uint32_t n_items, int img_split, int n_img, int ngx,
+    int ngy, int boundary, const PatchInfo *__restrict__ patch,
+    const uint32_t *__restrict__ nlive, const uint32_t *__restrict__ root,
+    const NodeLink *__restrict__ link_g, const double4 *__restrict__ mcom_g,
+    const double *__restrict__ Q_g, const double *__restrict__ sx_g,
+    const double *__restrict__ sy_g, const double *__restrict__ sz_g,
+    const double *__restrict__ msrc_g, const double *__restrict__ sched,
+    const uint32_t *__restrict__ ctr, uint32_t P, double G, double b2, double theta2,
+    double *__restrict__ acc, uint64_t cap, unsigned long long *__restrict__ stats,
+    const uint32_t *__restrict__ lev_off, uint32_t *__restrict__ err, int slot) {
+  const w64_u32_p link = (w64_u32_p)link_g;
+  const w64_dbl_p mcom = (w64_dbl_p)mcom_g;
+  const w64_dbl_p Qarr = (w64_dbl_p)Q_g;
+  const w64_dbl_p msrc = (w64_dbl_p)msrc_g;
+  const w64_dbl_p sxc = (w64_dbl_p)sx_g, syc = (w64_dbl_p)sy_g, szc = (w64_dbl_p)sz_g;
+  // Workgroups are dealt to the eight XCDs in turn; block b is given work
+  // unit (b mod 8)-th eighth of the units, so each XCD's L2 holds the nodes
+  // of one Morton-contiguous eighth of the particles.
+  const uint32_t nb = gridDim.x, b = blockIdx.x;
+  const uint32_t q = nb >> 3, r = nb & 7u, x = b & 7u;
+  const uint32_t vb = x * q + (x < r ? x : r) + (b >> 3);
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t unit = vb * 4u + (threadIdx.x >> 6);  // one unit per wave
+  const uint32_t n_units = img_split ? n_items * (uint32_t)n_img : n_items;
+  if (unit >= n_units) return;  // whole waves
+  // a depth-first walk visits every node at most once per image: more
+  // visits, or an index past the node count, mean inconsistent links
+  const uint32_t n_nodes = lev_off[RB_NLEV];
+  const uint32_t item = img_split ? unit / (uint32_t)n_img : unit;
+  const int im0 = img_split ? (int)(unit % (uint32_t)n_img) : 0;
+  const int im1 = img_split ? im0 + 1 : n_img;
+  const WalkItem it = items[item];
+  const uint32_t p = it.patch;
+  const double W = patch[p].W;
+  // (W 2^-l)^2 = fl(W W) 2^-2l exactly: scaling by a power of two is exact
+  const double W2 = W * W;
+  const uint32_t st = patch[p].start, nl = nlive[p];
+  const uint32_t s = it.start + lane;
+  const bool valid = s < it.end && (s - st) < nl;
+  const double shear = sched[(size_t)ctr[slot] * 2 * P + p];
+  double px = 0.0, py = 0.0, pz = 0.0;
+  if (valid) { px = sx_g[s]; py = sy_g[s]; pz = sz_g[s]; }
+  const uint64_t live = __ballot(valid);
+  const uint32_t r0 = live ? w64_uniform(root[p]) : RB_NONE;
+  uint32_t n_open = 0, n_cell = 0, n_pp = 0;
+  double tx = 0.0, ty = 0.0, tz = 0.0;
+  for (int im = im0; im < im1; ++im) {
+    double ox, oy;
+    bool self;
+    rb_image(im, ngx, ngy, boundary, W, shear, ox, oy, self);
+    const double y0 = px - ox, y1 = py - oy, y2 = pz;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    // lane k holds the mask of the lanes working on nodes of level k
+    uint64_t lvm = (lane == 0) ? live : 0ull;
+    uint32_t cur = r0, visits = 0;
+    // the node in hand: NodeLink {child_or_first, skip, count, lvl} and
+    // double4 {com, M}; the records of both nodes that can come next (the
+    // first child and the next node after the subtree) are requested before
+    // this one is worked on, so their loads overlap its arithmetic
+    while (cur != RB_NONE) {
+      if (cur >= n_nodes || ++visits > n_nodes) {
+        if (lane == 0) atomicOr(err, RB_ERR_TREE);
+        break;
+      }
+      W64Rec rc;
+      w64_fetch(link, mcom, cur, rc);
+      const uint32_t l_child = rc.child, l_skip = rc.skip, l_count = rc.count, l_lvl = rc.lvl;
+      const double cx = rc.cx, cy = rc.cy, cz = rc.cz, cm = rc.m;
+      const bool internal = (l_lvl & 256u) == 0;
+      double q00 = 0.0, q01 = 0.0, q02 = 0.0, q11 = 0.0, q12 = 0.0, q22 = 0.0;
+      if (QUAD && !(l_count == 1 && !internal)) {
+        const w64_dbl_p qn = Qarr + 6 * (size_t)cur;
+        q00 = qn[0]; q01 = qn[1]; q02 = qn[2]; q11 = qn[3]; q12 = qn[4]; q22 = qn[5];
+      }
+      uint32_t next = l_skip;
+      const int l = (int)(l_lvl & 255u);
+      if (cm != 0.0 && l <= RB_DEPTH) {
+        const uint64_t act = w64_readlane(lvm, l);
+        const bool me = ((act >> lane) & 1ull) != 0;
+        const bool leaf = (l_lvl & 256u) != 0;
+        if (leaf && l_count == 1) {
+          if (me && !(self && l_child == s)) {
+            const double d0 = cx - y0, d1 = cy - y1, d2 = cz - y2;
+            const double r2 = d0 * d0 + d1 * d1 + d2 * d2 + b2;
+            const double ri = rb_rsqrt64(r2);
+            const double f = G * cm * (ri * ri * ri);
+            ax += f * d0; ay += f * d1; az += f * d2;
+            if (STATS) ++n_pp;
+          }
+        } else {
+          const double d0 = cx - y0, d1 = cy - y1, d2 = cz - y2;
+          const double R2 = __builtin_fma(d2, d2, __builtin_fma(d1, d1, d0 * d0));
+          const bool take = me && (ldexp(W2, -2 * l) < theta2 * R2);
+          const uint64_t opened = act & ~__ballot(take);
+          if (STATS && me) ++n_open;
+          if (take) {
+            const double ri = rb_rsqrt64(R2 + b2);
+            const double ri2 = ri * ri;
+            const double ri3 = ri * ri2;
+            const double f = G * cm * ri3;
+            ax += f * d0; ay += f * d1; az += f * d2;
+            if (QUAD) {
+              const double e0 = q00 * d0 + q01 * d1 + q02 * d2;
+              const double e1 = q01 * d0 + q11 * d1 + q12 * d2;
+              const double e2 = q02 * d0 + q12 * d1 + q22 * d2;
+              const double dqd = d0 * e0 + d1 * e1 + d2 * e2;
+              const double ri5 = ri3 * ri2;
+              const double g5 = G * ri5;
+              const double g7 = 2.5 * G * dqd * (ri5 * ri2);
+              ax += g7 * d0 - g5 * e0;
+              ay += g7 * d1 - g5 * e1;
+              az += g7 * d2 - g5 * e2;
+            }
+            if (STATS) ++n_cell;
+          }
+          if (opened != 0ull) {
+            if (leaf) {
+              // a bucket leaf that failed the test: its members one by one
+              const bool mine = ((opened >> lane) & 1ull) != 0;
+              const uint32_t j0 = l_child, j1 = j0 + l_count;
+              for (uint32_t j = j0; j < j1; ++j) {
+                const double mj = msrc[j];
+                if (mj == 0.0) continue;
+                if (mine && !(self && j == s)) {
+                  const double e0 = sxc[j] - y0, e1 = syc[j] - y1, e2 = szc[j] - y2;
+                  const double r2 = e0 * e0 + e1 * e1 + e2 * e2 + b2;
+                  const double ri = rb_rsqrt64(r2);
+                  const double f = G * mj * (ri * ri * ri);
+                  ax += f * e0; ay += f * e1; az += f * e2;
+                  if (STATS) ++n_pp;
+                }
+              }
+            } else if (l < RB_DEPTH) {
+              if (lane == (uint32_t)(l + 1)) lvm = opened;
+              next = l_child;
+            }
+          }
+        }
+      }
+      cur = w64_uniform(next);
+    }
+    if (img_split) {
+      if (s < it.end) {
+        double *a = acc + (size_t)im * 3 * cap;
+        a[s] = ax; a[cap + s] = ay; a[2 * cap + s] = az;
+      }
+    } else {
+      tx += ax; ty += ay; tz += az;
+    }
+  }
+  if (!img_split && s < it.end) {
+    acc[s] = tx; acc[cap + s] = ty; acc[2 * cap + s] = tz;
+  }
+  if (STATS) {
+    unsigned long long o = n_open, c = n_cell, q2 = n_pp;
+    for (int d = 32; d >= 1; d >>= 1) {
+      o += __shfl_xor(o, d, 64);
+      c += __shfl_xor(c, d, 64);
+      q2 += __shfl_xor(q2, d, 64);
+    }
+    if (lane == 0) {
+      atomicAdd(&stats[0], o);
+      atomicAdd(&stats[1], c);
+      atomicAdd(&stats[2], q2);
+    }
+  }
+}
+
+template <bool QUAD, bool STATS>
+__global__ __launch_bounds__(64) void k_walk64_lane(
     const WalkItem *__restrict__ items, int img_split, int n_img, int ngx, int ngy,
     int boundary, const PatchInfo *__restrict__ patch, const uint32_t *__restrict__ nlive,
     const uint32_t *__restrict__ root, const NodeLink *__restrict__ link,
@@ -169,23 +390,43 @@ hipError_t launch_walk64(rb_ctx *c, const double *sx, const double *sy, const do
   const uint32_t n_items = (uint32_t)c->h_items64.size();
   if (n_items == 0) return hipSuccess;
   const int split = c->img_split;
-  const unsigned grid = split ? n_items * (unsigned)c->n_img : n_items;
+  const uint32_t units = split ? n_items * (uint32_t)c->n_img : n_items;
   const double b2 = c->p.softening * c->p.softening;
   const double th2 = c->p.theta * c->p.theta;
   const bool quad = c->p.quadrupole != 0, stats = (c->p.profile & 2) != 0;
-#define RB_WALK64_ARGS                                                                   \
+  const int sched_mode = c->p.walk64_schedule;
+  if (sched_mode == 2 || (sched_mode == 0 && units >= RB_WALK64_SHARED_MIN)) {
+    const unsigned grid = (units + 3u) / 4u;  // four waves (units) per workgroup
+#define RB_WALK64_ARGS                                                                     \
+  c->d_items64, n_items, split, c->n_img, c->p.n_ghost[0], c->p.n_ghost[1], c->p.boundary, \
+      c->d_patch, c->d_nlive, c->d_root, c->d_link, c->d_mcom, c->d_Q, sx, sy, sz,         \
+      c->d_msrc, c->d_sched, c->d_ctr, c->P, c->p.G, b2, th2, c->d_acc, c->cap,           \
+      c->d_stats, c->d_lev_off, c->d_err, slot
+    if (quad && stats)
+      hipLaunchKernelGGL((k_walk64<true, true>), dim3(grid), dim3(256), 0, c->stream, RB_WALK64_ARGS);
+    else if (quad)
+      hipLaunchKernelGGL((k_walk64<true, false>), dim3(grid), dim3(256), 0, c->stream, RB_WALK64_ARGS);
+    else if (stats)
+      hipLaunchKernelGGL((k_walk64<false, true>), dim3(grid), dim3(256), 0, c->stream, RB_WALK64_ARGS);
+    else
+      hipLaunchKernelGGL((k_walk64<false, false>), dim3(grid), dim3(256), 0, c->stream, RB_WALK64_ARGS);
+#undef RB_WALK64_ARGS
+    return hipGetLastError();
+  }
+  const unsigned grid = units;
+#define RB_WALK64_LANE_ARGS                                                              \
   c->d_items64, split, c->n_img, c->p.n_ghost[0], c->p.n_ghost[1], c->p.boundary,        \
       c->d_patch, c->d_nlive, c->d_root, c->d_link, c->d_mcom, c->d_Q, sx, sy, sz,       \
       c->d_msrc, c->d_sched, c->d_ctr, c->P, c->p.G, b2, th2, c->d_acc, c->cap, c->d_stats, \
       c->d_lev_off, c->d_err, slot
   if (quad && stats)
-    hipLaunchKernelGGL((k_walk64<true, true>), dim3(grid), dim3(64), 0, c->stream, RB_WALK64_ARGS);
+    hipLaunchKernelGGL((k_walk64_lane<true, true>), dim3(grid), dim3(64), 0, c->stream, RB_WALK64_LANE_ARGS);
   else if (quad)
-    hipLaunchKernelGGL((k_walk64<true, false>), dim3(grid), dim3(64), 0, c->stream, RB_WALK64_ARGS);
+    hipLaunchKernelGGL((k_walk64_lane<true, false>), dim3(grid), dim3(64), 0, c->stream, RB_WALK64_LANE_ARGS);
   else if (stats)
-    hipLaunchKernelGGL((k_walk64<false, true>), dim3(grid), dim3(64), 0, c->stream, RB_WALK64_ARGS);
+    hipLaunchKernelGGL((k_walk64_lane<false, true>), dim3(grid), dim3(64), 0, c->stream, RB_WALK64_LANE_ARGS);
   else
-    hipLaunchKernelGGL((k_walk64<false, false>), dim3(grid), dim3(64), 0, c->stream, RB_WALK64_ARGS);
-#undef RB_WALK64_ARGS
+    hipLaunchKernelGGL((k_walk64_lane<false, false>), dim3(grid), dim3(64), 0, c->stream, RB_WALK64_LANE_ARGS);
+#undef RB_WALK64_LANE_ARGS
   return hipGetLastError();
 }

@@ -101,6 +101,8 @@ int validate(const rb_params *p) {
     return fail(RB_EINVAL, "walk_waves must be 0, 1, 2 or 4");
   if (p->moments_level_log2 != 0 && (p->moments_level_log2 < 6 || p->moments_level_log2 > 31))
     return fail(RB_EINVAL, "moments_level_log2 must be 0 or 6..31");
+  if (p->walk64_schedule < 0 || p->walk64_schedule > 2)
+    return fail(RB_EINVAL, "walk64_schedule must be 0, 1 or 2");
   return RB_OK;
 }
 

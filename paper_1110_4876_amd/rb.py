@@ -49,7 +49,8 @@ class rb_params(ctypes.Structure):
         ("use_graph", ctypes.c_int32),
         ("walk_waves", ctypes.c_int32),
         ("moments_level_log2", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("walk64_schedule", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 

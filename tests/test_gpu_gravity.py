@@ -39,12 +39,13 @@ def test_fp64_walk_matches_oracle(orc, name, maker, leaf, n_active, t):
     s = orc.shear_offset(p, t)
     ref = orc.bh(p, pr.x, pr.y, pr.z, pr.m, n_active=na, s=s)
     for split in (0, 1):
-        ctx = make_ctx(pr, leaf_size=leaf, split_images=split)
-        try:
-            a = gravity(ctx, Dev(pr, with_v=False), na, t)
-        finally:
-            rb.rb_destroy(ctx)
-        assert rms_rel(a, ref) <= TOL_BH, (split, rms_rel(a, ref))
+        for sched in (1, 2):  # per-lane walks, one wave-shared walk
+            ctx = make_ctx(pr, leaf_size=leaf, split_images=split, walk64_schedule=sched)
+            try:
+                a = gravity(ctx, Dev(pr, with_v=False), na, t)
+            finally:
+                rb.rb_destroy(ctx)
+            assert rms_rel(a, ref) <= TOL_BH, (split, sched, rms_rel(a, ref))
 
 
 def test_periodic_images(orc):
@@ -53,12 +54,13 @@ def test_periodic_images(orc):
     pr = _periodic(inputs.sheet(4000, seed=6))
     p = orc.make_params(**pr.params)
     ref = orc.bh(p, pr.x, pr.y, pr.z, pr.m)
-    ctx = make_ctx(pr)
-    try:
-        a = gravity(ctx, Dev(pr, with_v=False), pr.n)
-    finally:
-        rb.rb_destroy(ctx)
-    assert rms_rel(a, ref) <= TOL_BH
+    for sched in (1, 2):
+        ctx = make_ctx(pr, walk64_schedule=sched)
+        try:
+            a = gravity(ctx, Dev(pr, with_v=False), pr.n)
+        finally:
+            rb.rb_destroy(ctx)
+        assert rms_rel(a, ref) <= TOL_BH, sched
 
 
 def test_two_ghost_rings(orc):
@@ -68,12 +70,13 @@ def test_two_ghost_rings(orc):
     p = orc.make_params(**pr.params)
     s = orc.shear_offset(p, 300.0)
     ref = orc.bh(p, pr.x, pr.y, pr.z, pr.m, s=s)
-    ctx = make_ctx(pr)
-    try:
-        a = gravity(ctx, Dev(pr, with_v=False), pr.n, 300.0)
-    finally:
-        rb.rb_destroy(ctx)
-    assert rms_rel(a, ref) <= TOL_BH
+    for sched in (1, 2):
+        ctx = make_ctx(pr, walk64_schedule=sched)
+        try:
+            a = gravity(ctx, Dev(pr, with_v=False), pr.n, 300.0)
+        finally:
+            rb.rb_destroy(ctx)
+        assert rms_rel(a, ref) <= TOL_BH, sched
 
 
 def test_direct_matches_oracle(orc):
@@ -119,14 +122,15 @@ def test_removed_and_outside_particles_get_no_force(orc):
     pr.y[6] = 1e3
     p = orc.make_params(**pr.params)
     ref = orc.bh(p, pr.x, pr.y, pr.z, pr.m)
-    ctx = make_ctx(pr)
-    try:
-        a = gravity(ctx, Dev(pr, with_v=False), pr.n)
-    finally:
-        rb.rb_destroy(ctx)
-    assert np.all(a[5] == 0) and np.all(a[6] == 0)
-    keep = np.ones(pr.n, bool); keep[[5, 6]] = False
-    assert rms_rel(a[keep], ref[keep]) <= TOL_BH
+    for sched in (1, 2):
+        ctx = make_ctx(pr, walk64_schedule=sched)
+        try:
+            a = gravity(ctx, Dev(pr, with_v=False), pr.n)
+        finally:
+            rb.rb_destroy(ctx)
+        assert np.all(a[5] == 0) and np.all(a[6] == 0)
+        keep = np.ones(pr.n, bool); keep[[5, 6]] = False
+        assert rms_rel(a[keep], ref[keep]) <= TOL_BH, sched
 
 
 def test_empty_and_single_particle():
@@ -173,12 +177,13 @@ def test_c1_full_size_sampled(orc, theta, split):
     p = orc.make_params(**pr.params)
     tg = inputs.sample_targets(pr.n, 4096, seed=0)
     ref = orc.bh(p, pr.x, pr.y, pr.z, pr.m, s=orc.shear_offset(p, t), targets=tg)
-    ctx = make_ctx(pr, split_images=split)
-    try:
-        a = gravity(ctx, Dev(pr, with_v=False), pr.n, t)
-    finally:
-        rb.rb_destroy(ctx)
-    assert rms_rel(a[tg], ref) <= TOL_BH
+    for sched in (0, 1, 2):
+        ctx = make_ctx(pr, split_images=split, walk64_schedule=sched)
+        try:
+            a = gravity(ctx, Dev(pr, with_v=False), pr.n, t)
+        finally:
+            rb.rb_destroy(ctx)
+        assert rms_rel(a[tg], ref) <= TOL_BH, sched
 
 
 @pytest.mark.parametrize("theta", [0.26, 0.5])
@@ -194,8 +199,8 @@ def test_c1_interaction_counts_equal_oracle(orc, theta):
     p = orc.make_params(**pr.params)
     T = orc.Tree(p, pr.x, pr.y, pr.z, pr.m)
     T.walk(s=orc.shear_offset(p, t))
-    for split in (0, 1):
-        ctx = make_ctx(pr, profile=2, split_images=split)
+    for split, sched in ((0, 1), (1, 1), (0, 2), (1, 2)):
+        ctx = make_ctx(pr, profile=2, split_images=split, walk64_schedule=sched)
         try:
             d = Dev(pr, with_v=False)
             ax = torch.empty(pr.n, dtype=torch.float64, device="cuda")
@@ -205,7 +210,7 @@ def test_c1_interaction_counts_equal_oracle(orc, theta):
         finally:
             rb.rb_destroy(ctx)
         for k in ("open_tests", "cells", "pp"):
-            assert s[k] == T.stats[k], (split, k, s[k], T.stats[k])
+            assert s[k] == T.stats[k], (split, sched, k, s[k], T.stats[k])
 
 
 def test_c1_snapshots_along_a_run(orc):
