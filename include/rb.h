@@ -239,6 +239,28 @@ int rb_direct(rb_ctx *ctx, const rb_particles *p, int64_t n, int64_t n_active,
               double *ay, double *az);
 
 /*
+ * rb_direct without a context, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same sum, with the same kernels, for a single
+ * system described by p (box, boundary, ghost rings, omega, G, softening;
+ * theta and the tree fields are ignored), issued on hip_stream (a
+ * hipStream_t; NULL = the null stream).  It calls no hipMalloc, hipFree or
+ * allocating library routine: the per-chunk partial sums live in a fixed
+ * array of 8 MiB per GPU (2^20 doubles, 3 per target and source chunk),
+ * which the library holds on every GPU it runs on until the process ends.
+ * Every call on one GPU shares that array, so calls that overlap on one GPU
+ * (other streams, other threads) race; calls issued one after another on
+ * one stream do not.  Asynchronous; nothing is synchronised and no device
+ * error word exists: a target index outside [0, n) gets zero acceleration.
+ * Errors (host-side, nothing launched): RB_EINVAL for invalid parameters,
+ * null arrays, n outside [0, 2^31 - 1], n_targets outside [0, n] or above
+ * 349,525 (what the fixed array holds for one source chunk), RB_EHIP.
+ */
+int rb_direct_noalloc(const rb_params *p, const rb_particles *parts, int64_t n,
+                      int64_t n_active, double t, const int64_t *targets, int64_t n_targets,
+                      double *ax, double *ay, double *az, void *hip_stream);
+
+/*
  * nsteps drift-kick-drift steps of Sect. 3 from time t with step dt: drift
  * dt/2 (leap-frog or epicycle), boundaries, tree gravity at t + dt/2, kick
  * v += a dt, drift dt/2, boundaries.  Updates x, y, z, vx, vy, vz in place,

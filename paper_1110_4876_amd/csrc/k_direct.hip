@@ -5,7 +5,19 @@
 // at a time in LDS; every lane reads the same entry (broadcast) and adds its
 // term.  Per-chunk partial sums are reduced in chunk order afterwards, so
 // the result does not depend on scheduling.
+//
+// Two entry points share these kernels: rb_direct keeps the partial sums in
+// its context's accumulator buffer; rb_direct_noalloc, for callers that
+// cannot allocate, keeps them in the fixed array below.
+#include <mutex>
+
 #include "rb_internal.h"
+
+// Partial sums of rb_direct_noalloc: one array per GPU, held until the
+// process ends.  Every call on a GPU uses the same array, so calls that
+// overlap on one GPU race.  Host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[RB_DIRECT_SCRATCH_DOUBLES];
 
 __device__ __forceinline__ double rb_rsqrt64_d(double x) {
   double y = __builtin_amdgcn_rsq(x);
@@ -19,16 +31,15 @@ __global__ __launch_bounds__(64) void k_direct(
     const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
     const double *__restrict__ m, uint32_t n, uint32_t n_active,
     const int64_t *__restrict__ targets, uint32_t nt, uint32_t chunk, int n_img, int ngx,
-    int ngy, int boundary, double W, const double *__restrict__ sched,
-    const uint32_t *__restrict__ ctr, double G, double b2, double *__restrict__ part,
-    uint32_t *__restrict__ err) {
+    int ngy, int boundary, double W, double s, double G, double b2,
+    double *__restrict__ part, uint32_t *__restrict__ err) {
   __shared__ double4 src[64];
   const uint32_t t = blockIdx.x * 64 + threadIdx.x;
   const uint32_t c = blockIdx.y;
   const bool valid = t < nt;
   const int64_t ti = valid ? targets[t] : 0;
   const bool in_range = ti >= 0 && ti < (int64_t)n;
-  if (valid && !in_range && c == 0) atomicOr(err, RB_ERR_INDEX);
+  if (valid && !in_range && c == 0 && err) atomicOr(err, RB_ERR_INDEX);
   const uint32_t i = in_range ? (uint32_t)ti : 0u;
   double px = 0.0, py = 0.0, pz = 0.0;
   bool alive = false;
@@ -36,7 +47,6 @@ __global__ __launch_bounds__(64) void k_direct(
     px = x[i]; py = y[i]; pz = z[i];
     alive = !(isnan(px) || isnan(py) || isnan(pz));
   }
-  const double s = sched[(size_t)ctr[0] * 2];  // single system: patch 0
   const uint32_t nsrc = n_active < n ? n_active : n;
   const uint32_t j0 = c * chunk, j1 = (j0 + chunk < nsrc) ? j0 + chunk : nsrc;
   double ax = 0.0, ay = 0.0, az = 0.0;
@@ -98,28 +108,79 @@ __global__ __launch_bounds__(256) void k_direct_reduce(const double *__restrict_
   ax[t] = a0; ay[t] = a1; az[t] = a2;
 }
 
+// Chunking of the sources: enough (target group, chunk) blocks to fill the
+// chip, chunks of at least 1024 sources (a multiple of 64), at most
+// max_part partial doubles (3 per target and chunk).
+static void direct_chunks(uint32_t nsrc, uint32_t nt, uint64_t max_part, uint32_t &n_chunks,
+                          uint32_t &chunk) {
+  const uint32_t groups = rb_div_up(nt, 64);
+  n_chunks = (8192 + groups - 1) / groups;
+  const uint32_t max_by_src = rb_div_up(nsrc > 0 ? nsrc : 1, 1024);
+  if (n_chunks > max_by_src) n_chunks = max_by_src;
+  if ((uint64_t)n_chunks * 3 * nt > max_part) n_chunks = (uint32_t)(max_part / (3ull * nt));
+  if (n_chunks < 1) n_chunks = 1;
+  chunk = ((rb_div_up(nsrc > 0 ? nsrc : 1, n_chunks) + 63) / 64) * 64;
+  n_chunks = rb_div_up(nsrc > 0 ? nsrc : 1, chunk);
+}
+
+static void direct_kernels(const rb_particles *cp, uint32_t n, uint32_t n_active,
+                           const int64_t *targets, uint32_t nt, int n_img, int ngx, int ngy,
+                           int boundary, double W, double s, double G, double b2,
+                           double *part, uint64_t max_part, uint32_t *err, double *ax,
+                           double *ay, double *az, hipStream_t stream) {
+  const uint32_t nsrc = n_active < n ? n_active : n;
+  uint32_t n_chunks, chunk;
+  direct_chunks(nsrc, nt, max_part, n_chunks, chunk);
+  hipLaunchKernelGGL(k_direct, dim3(rb_div_up(nt, 64), n_chunks), dim3(64), 0, stream, cp->x,
+                     cp->y, cp->z, cp->m, n, n_active, targets, nt, chunk, n_img, ngx, ngy,
+                     boundary, W, s, G, b2, part, err);
+  hipLaunchKernelGGL(k_direct_reduce, dim3(rb_div_up(nt, 256)), dim3(256), 0, stream, part, nt,
+                     n_chunks, ax, ay, az);
+}
+
 hipError_t launch_direct(rb_ctx *c, const rb_particles *cp, uint32_t n, uint32_t n_active,
-                         const double *, const int64_t *targets, uint32_t nt, double *ax,
+                         double s, const int64_t *targets, uint32_t nt, double *ax,
                          double *ay, double *az) {
   if (nt == 0) return hipSuccess;
-  const uint32_t nsrc = n_active < n ? n_active : n;
-  // enough (target group, chunk) blocks to fill the chip, chunks of >= 1024
-  // sources, partials bounded by the accumulator buffer
+  // the partial sums live in the accumulator buffer
   const uint64_t acc_doubles = (uint64_t)(c->img_split ? c->n_img : 1) * 3 * c->cap;
-  uint32_t groups = rb_div_up(nt, 64);
-  uint32_t n_chunks = (8192 + groups - 1) / groups;
-  uint32_t max_by_src = rb_div_up(nsrc > 0 ? nsrc : 1, 1024);
-  if (n_chunks > max_by_src) n_chunks = max_by_src;
-  if ((uint64_t)n_chunks * 3 * nt > acc_doubles) n_chunks = (uint32_t)(acc_doubles / (3ull * nt));
-  if (n_chunks < 1) n_chunks = 1;
-  const uint32_t chunk = ((rb_div_up(nsrc > 0 ? nsrc : 1, n_chunks) + 63) / 64) * 64;
-  n_chunks = rb_div_up(nsrc > 0 ? nsrc : 1, chunk);
-  const double b2 = c->p.softening * c->p.softening;
-  hipLaunchKernelGGL(k_direct, dim3(groups, n_chunks), dim3(64), 0, c->stream, cp->x, cp->y,
-                     cp->z, cp->m, n, n_active, targets, nt, chunk, c->n_img,
-                     c->p.n_ghost[0], c->p.n_ghost[1], c->p.boundary, c->h_patch[0].W,
-                     c->d_sched, c->d_ctr, c->p.G, b2, c->d_acc, c->d_err);
-  hipLaunchKernelGGL(k_direct_reduce, dim3(rb_div_up(nt, 256)), dim3(256), 0, c->stream,
-                     c->d_acc, nt, n_chunks, ax, ay, az);
+  direct_kernels(cp, n, n_active, targets, nt, c->n_img, c->p.n_ghost[0], c->p.n_ghost[1],
+                 c->p.boundary, c->h_patch[0].W, s, c->p.G,
+                 c->p.softening * c->p.softening, c->d_acc, acc_doubles, c->d_err, ax, ay, az,
+                 c->stream);
+  return hipGetLastError();
+}
+
+// The device address of the current GPU's scratch array, looked up once per
+// device (with that device current) and kept.
+static hipError_t direct_scratch(double **out) {
+  static std::mutex mu;
+  static double *addr[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = (double *)p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_direct_noalloc(const rb_params *p, const rb_particles *cp, uint32_t n,
+                                 uint32_t n_active, double s, const int64_t *targets,
+                                 uint32_t nt, int n_img, double *ax, double *ay, double *az,
+                                 hipStream_t stream) {
+  if (nt == 0) return hipSuccess;
+  double *part = nullptr;
+  const hipError_t e = direct_scratch(&part);
+  if (e != hipSuccess) return e;
+  direct_kernels(cp, n, n_active, targets, nt, n_img, p->n_ghost[0], p->n_ghost[1],
+                 p->boundary, p->box_size, s, p->G, p->softening * p->softening, part,
+                 RB_DIRECT_SCRATCH_DOUBLES, nullptr, ax, ay, az, stream);
   return hipGetLastError();
 }

@@ -876,9 +876,33 @@ int rb_direct(rb_ctx *c, const rb_particles *p, int64_t n, int64_t n_active, dou
   if (n < 0 || (uint64_t)n > c->cap) return fail(RB_EINVAL, "n outside [0, capacity]");
   if (n_targets < 0 || n_targets > n) return fail(RB_EINVAL, "n_targets outside [0, n]");
   if (n_active < 0) return fail(RB_EINVAL, "n_active must be >= 0");
-  RB_TRY(upload_schedule(c, t, 0.0, 0));
-  RB_PHASE(PH_DIRECT, launch_direct(c, p, (uint32_t)n, (uint32_t)std::min(n_active, n), nullptr,
+  if (!isfinite(t)) return fail(RB_EINVAL, "t must be finite");
+  const double s = shear_offset(c->p, c->h_patch[0].W, t);
+  RB_PHASE(PH_DIRECT, launch_direct(c, p, (uint32_t)n, (uint32_t)std::min(n_active, n), s,
                                     targets, (uint32_t)n_targets, ax, ay, az));
+  return RB_OK;
+}
+
+int rb_direct_noalloc(const rb_params *p, const rb_particles *parts, int64_t n,
+                      int64_t n_active, double t, const int64_t *targets, int64_t n_targets,
+                      double *ax, double *ay, double *az, void *hip_stream) {
+  RB_TRY(validate(p));
+  RB_TRY(validate_box(p, p->box_size, p->box_min));
+  RB_TRY(check_particles(parts, false));
+  if (!targets || !ax || !ay || !az) return fail(RB_EINVAL, "null target or output array");
+  if (n < 0 || n > 0x7FFFFFFFll) return fail(RB_EINVAL, "n outside [0, 2^31 - 1]");
+  if (n_targets < 0 || n_targets > n) return fail(RB_EINVAL, "n_targets outside [0, n]");
+  if (n_targets > (int64_t)RB_DIRECT_SCRATCH_DOUBLES / 3)
+    return fail(RB_EINVAL, "n_targets = %lld is above the %u targets the fixed scratch array "
+                "holds", (long long)n_targets, RB_DIRECT_SCRATCH_DOUBLES / 3);
+  if (n_active < 0) return fail(RB_EINVAL, "n_active must be >= 0");
+  if (!isfinite(t)) return fail(RB_EINVAL, "t must be finite");
+  const double s = shear_offset(*p, p->box_size, t);
+  const hipError_t e = launch_direct_noalloc(p, parts, (uint32_t)n,
+                                             (uint32_t)std::min(n_active, n), s, targets,
+                                             (uint32_t)n_targets, n_images(*p), ax, ay, az,
+                                             (hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(RB_EHIP, "rb_direct_noalloc: %s", hipGetErrorString(e));
   return RB_OK;
 }
 

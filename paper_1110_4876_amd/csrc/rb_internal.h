@@ -252,5 +252,12 @@ hipError_t launch_prologue(rb_ctx *c, const rb_particles *cp);
 hipError_t launch_post(rb_ctx *c, int buf, int slot, int mode = 0);
 hipError_t launch_epilogue(rb_ctx *c, rb_particles *cp, int buf);
 hipError_t launch_direct(rb_ctx *c, const rb_particles *cp, uint32_t n, uint32_t n_active,
-                         const double *s_img, const int64_t *targets, uint32_t nt,
+                         double s, const int64_t *targets, uint32_t nt,
                          double *ax, double *ay, double *az);
+// the same without a context: partial sums in a fixed per-GPU array of
+// RB_DIRECT_SCRATCH_DOUBLES doubles (3 per target and source chunk)
+#define RB_DIRECT_SCRATCH_DOUBLES (1u << 20)
+hipError_t launch_direct_noalloc(const rb_params *p, const rb_particles *cp, uint32_t n,
+                                 uint32_t n_active, double s, const int64_t *targets,
+                                 uint32_t nt, int n_img, double *ax, double *ay, double *az,
+                                 hipStream_t stream);

@@ -102,6 +102,10 @@ _SIGS = {
                                  ctypes.c_int64, ctypes.c_double, ctypes.c_void_p,
                                  ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_void_p]),
+    "rb_direct_noalloc": (ctypes.c_int, [ctypes.POINTER(rb_params), ctypes.POINTER(rb_particles),
+                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                                         ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rb_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rb_particles), ctypes.c_int64,
                                ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                ctypes.c_int32]),
@@ -277,6 +281,14 @@ def rb_direct(ctx, parts: rb_particles, n: int, n_active: int, t: float, targets
     check(lib().rb_direct(ctx, ctypes.byref(parts), int(n), int(n_active), float(t),
                           _ptr(targets), int(targets.numel()), _ptr(ax), _ptr(ay), _ptr(az)),
           "rb_direct")
+
+
+def rb_direct_noalloc(p: rb_params, parts: rb_particles, n: int, n_active: int, t: float,
+                      targets, ax, ay, az) -> None:
+    """rb_direct without a context (rb.h), on the current torch stream."""
+    check(lib().rb_direct_noalloc(ctypes.byref(p), ctypes.byref(parts), int(n), int(n_active),
+                                  float(t), _ptr(targets), int(targets.numel()), _ptr(ax),
+                                  _ptr(ay), _ptr(az), _stream_handle()), "rb_direct_noalloc")
 
 
 def rb_step(ctx, parts: rb_particles, n: int, n_active: int, t: float, dt: float,
