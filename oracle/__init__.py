@@ -11,7 +11,9 @@ What each function follows in the paper (Rein & Liu 2012, REBOUND):
     boxes of Sect. 2.3;
   * ``tree`` / ``bh`` -- the octree of Sect. 4.2: insertion build, bottom-up
     mass, centre of mass and quadrupole (Hernquist 1987), walk with opening
-    angle theta = w / R;
+    angle theta = w / R; one tree per cubic root box (``n_root`` boxes per
+    axis, Sect. 2.3); ``Tree.update`` is the reconstruction after the
+    particles moved (Sect. 4.2);
   * ``step`` -- the drift-kick-drift step of Sect. 3 with the leap-frog
     (Sect. 3.1) or exact epicycle (Sect. 3.3) drift and the boundaries of
     Sect. 2.3;
@@ -60,6 +62,7 @@ class Params(ctypes.Structure):
         ("drift", ctypes.c_int32),
         ("omega", ctypes.c_double),
         ("omega_z", ctypes.c_double),
+        ("n_root", ctypes.c_int32 * 3),
     ]
 
 
@@ -79,6 +82,8 @@ def lib():
         L.orc_keys.argtypes = [P, i64, vp, vp, vp, vp]
         L.orc_tree_build.argtypes = [P, i64, i64, vp, vp, vp, vp]
         L.orc_tree_build.restype = vp
+        L.orc_tree_update.argtypes = [vp, vp, vp, vp]
+        L.orc_tree_update.restype = i64
         L.orc_tree_free.argtypes = [vp]
         L.orc_tree_n_nodes.argtypes = [vp]
         L.orc_tree_n_nodes.restype = i64
@@ -113,7 +118,7 @@ def lib():
 
 def make_params(G=1.0, b=0.0, theta=0.5, quadrupole=False, n_leaf=1, W=1.0,
                 x0=(0.0, 0.0, 0.0), boundary=OPEN, ng=(0, 0), drift=LEAPFROG,
-                omega=0.0, omega_z=None, **_ignored) -> Params:
+                omega=0.0, omega_z=None, n_root=(1, 1, 1), **_ignored) -> Params:
     p = Params()
     p.G, p.b, p.theta = float(G), float(b), float(theta)
     p.quadrupole = int(bool(quadrupole))
@@ -126,6 +131,8 @@ def make_params(G=1.0, b=0.0, theta=0.5, quadrupole=False, n_leaf=1, W=1.0,
     p.drift = int(drift)
     p.omega = float(omega)
     p.omega_z = float(omega if omega_z is None else omega_z)
+    for a in range(3):
+        p.n_root[a] = int(n_root[a])
     return p
 
 
@@ -163,6 +170,12 @@ class Tree:
         self.n_active = n if n_active is None else int(n_active)
         self.h = lib().orc_tree_build(ctypes.byref(p), n, self.n_active, _ptr(self.x),
                                       _ptr(self.y), _ptr(self.z), _ptr(self.m))
+
+    def update(self, x, y, z) -> int:
+        """Reconstruction after the particles moved (Sect. 4.2): returns the
+        number of particles taken out and inserted again."""
+        self.x, self.y, self.z = _f64(x), _f64(y), _f64(z)
+        return int(lib().orc_tree_update(self.h, _ptr(self.x), _ptr(self.y), _ptr(self.z)))
 
     def __del__(self):
         h = getattr(self, "h", None)

@@ -46,16 +46,45 @@ int orc_num_threads(void) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Domain (Sect. 2.3): n_root[a] cubic root boxes of side W along axis a,
+ * from the corner x0.  A single box when every n_root is 0 or 1.           */
+
+static int orc_nr(const orc_params *p, int a) {
+  return p->n_root[a] > 1 ? p->n_root[a] : 1;
+}
+
+/* domain extent along axis a */
+static double orc_L(const orc_params *p, int a) { return (double)orc_nr(p, a) * p->W; }
+
+/* root boxes per axis in powers of two: 2^D >= every n_root */
+static int orc_D(const orc_params *p) {
+  int m = orc_nr(p, 0);
+  if (orc_nr(p, 1) > m) m = orc_nr(p, 1);
+  if (orc_nr(p, 2) > m) m = orc_nr(p, 2);
+  int D = 0;
+  while ((1 << D) < m) ++D;
+  return D;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Keys.  Sect. 4.2: every cell splits into eight cubic sub-cells of half the
- * width.  The octant at level l is read from bit (21 - l) of the quantised
- * coordinates q = floor((x - x0) * 2^21 / W), x bit weighing 4, y 2, z 1.    */
+ * width.  The domain is quantised once, 2^(21-D) steps per root box per
+ * axis: q = floor((x - x0) * 2^(21-D) / W).  The root box of a particle is
+ * the integer part q >> (21-D) and its cell inside that box the low bits;
+ * both are read from the bits of q, never by comparing x with a floating-
+ * point boundary.  The key interleaves the 21 bits of q per axis (x bit
+ * weighing 4, y 2, z 1, most significant level first): its first D digits
+ * name the root box, the rest the cells of the root box's own tree at
+ * levels D+1..21 (level D is the root box itself).  With one root box
+ * (D = 0) this is q = floor((x - x0) 2^21 / W).                             */
 
 static int orc_quantise(const orc_params *p, double S, double xa, int a,
                         uint32_t *q) {
   double u = xa - p->x0[a];
-  if (!(u >= 0.0 && u < p->W)) return 0; /* outside, or NaN */
+  if (!(u >= 0.0 && u < orc_L(p, a))) return 0; /* outside, or NaN */
   double f = floor(u * S);
-  if (f >= 2097151.0) f = 2097151.0;     /* u*S may round up to 2^21 */
+  double top = (double)orc_nr(p, a) * ldexp(1.0, ORC_DEPTH - orc_D(p)) - 1.0;
+  if (f >= top) f = top; /* u*S may round up to the domain's end */
   *q = (uint32_t)f;
   return 1;
 }
@@ -77,7 +106,9 @@ static uint64_t orc_key_of(const orc_params *p, double S, double x, double y,
   return key;
 }
 
-static double orc_S(const orc_params *p) { return 2097152.0 / p->W; }
+static double orc_S(const orc_params *p) {
+  return (double)(1u << (ORC_DEPTH - orc_D(p))) / p->W;
+}
 
 void orc_keys(const orc_params *p, int64_t n, const double *x, const double *y,
               const double *z, uint64_t *keys) {
@@ -90,7 +121,10 @@ static int orc_digit(uint64_t key, int level) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Octree built by inserting particles one at a time (Sect. 4.2).           */
+/* One octree per root box (Sect. 2.3), each built by inserting particles
+ * one at a time (Sect. 4.2).  Node levels are counted from the domain: the
+ * tree of a root box has its root at level D, and a node at level l is a
+ * cube of side W 2^(D-l).                                                   */
 
 typedef struct {
   uint64_t prefix;
@@ -104,10 +138,14 @@ typedef struct {
 
 struct orc_tree {
   orc_params p;
+  int D;             /* levels above the root boxes */
   int64_t n, n_active, n_live;
   onode *nodes;
   int64_t n_nodes, cap;
+  int64_t *roots;    /* node of every occupied root box, by root prefix */
+  int64_t n_roots;
   int64_t *next;     /* member list links */
+  int64_t *leaf_of;  /* leaf node holding each particle, -1 if none */
   uint64_t *keys;
   int64_t *perm;     /* Morton rank -> particle index */
   double *x, *y, *z, *msrc; /* own copies; msrc = 0 for test particles */
@@ -136,6 +174,7 @@ static void orc_append(orc_tree *t, int64_t node, int64_t j) {
   if (nd->tail == ORC_NONE) nd->head = j; else t->next[nd->tail] = j;
   nd->tail = j;
   nd->nmem++;
+  t->leaf_of[j] = node;
 }
 
 static void orc_add(orc_tree *t, int64_t node, int64_t j);
@@ -172,8 +211,27 @@ static void orc_add(orc_tree *t, int64_t node, int64_t j) {
   orc_add_child(t, node, j);
 }
 
-/* Morton ranks by depth-first traversal in octant order.  Leaf members are
- * ranked by (key, index), i.e. the stable sort of the keys.                */
+/* the tree of particle j's root box (created with its first particle) */
+static int64_t orc_root_of(orc_tree *t, int64_t j) {
+  uint64_t pre = t->keys[j] >> (3 * (ORC_DEPTH - t->D));
+  int64_t lo = 0, hi = t->n_roots;
+  while (lo < hi) { /* first root with prefix >= pre */
+    int64_t mid = (lo + hi) / 2;
+    if (t->nodes[t->roots[mid]].prefix < pre) lo = mid + 1; else hi = mid;
+  }
+  if (lo < t->n_roots && t->nodes[t->roots[lo]].prefix == pre) return t->roots[lo];
+  int64_t r = orc_new_node(t, t->D, pre);
+  memmove(t->roots + lo + 1, t->roots + lo, (size_t)(t->n_roots - lo) * sizeof(int64_t));
+  t->roots[lo] = r;
+  t->n_roots++;
+  return r;
+}
+
+static void orc_insert(orc_tree *t, int64_t j) { orc_add(t, orc_root_of(t, j), j); }
+
+/* Morton ranks by depth-first traversal in octant order, root boxes in the
+ * order of their prefixes.  Leaf members are ranked by (key, index), i.e.
+ * the stable sort of the keys.                                              */
 static int64_t orc_rank(orc_tree *t, int64_t node, int64_t r) {
   onode *nd = &t->nodes[node];
   nd->first = r;
@@ -283,44 +341,190 @@ static void orc_moments(orc_tree *t, int64_t node) {
   for (int a = 0; a < 6; ++a) nd->Q[a] = Q[a];
 }
 
+/* Morton ranks and moments of every root box's tree */
+static void orc_finish(orc_tree *t) {
+  int64_t r = 0;
+  for (int64_t k = 0; k < t->n_roots; ++k) r = orc_rank(t, t->roots[k], r);
+  for (int64_t k = 0; k < t->n_roots; ++k) orc_moments(t, t->roots[k]);
+}
+
+static void orc_set_positions(orc_tree *t, const double *x, const double *y,
+                              const double *z) {
+  for (int64_t j = 0; j < t->n; ++j) { t->x[j] = x[j]; t->y[j] = y[j]; t->z[j] = z[j]; }
+  orc_keys(&t->p, t->n, x, y, z, t->keys);
+  t->n_live = 0;
+  for (int64_t j = 0; j < t->n; ++j) t->n_live += (t->keys[j] != UINT64_MAX);
+}
+
 orc_tree *orc_tree_build(const orc_params *p, int64_t n, int64_t n_active,
                          const double *x, const double *y, const double *z,
                          const double *m) {
   orc_tree *t = (orc_tree *)calloc(1, sizeof(orc_tree));
   t->p = *p;
+  t->D = orc_D(p);
   t->n = n;
   t->n_active = n_active;
-  size_t nb = (size_t)(n > 0 ? n : 1) * sizeof(double);
-  t->x = (double *)malloc(nb); t->y = (double *)malloc(nb);
-  t->z = (double *)malloc(nb); t->msrc = (double *)malloc(nb);
-  for (int64_t j = 0; j < n; ++j) {
-    t->x[j] = x[j]; t->y[j] = y[j]; t->z[j] = z[j];
-    t->msrc[j] = (j < n_active) ? m[j] : 0.0;
-  }
-  t->keys = (uint64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint64_t));
-  t->next = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
-  t->perm = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
-  orc_keys(p, n, x, y, z, t->keys);
+  size_t n1 = (size_t)(n > 0 ? n : 1);
+  t->x = (double *)malloc(n1 * sizeof(double)); t->y = (double *)malloc(n1 * sizeof(double));
+  t->z = (double *)malloc(n1 * sizeof(double)); t->msrc = (double *)malloc(n1 * sizeof(double));
+  for (int64_t j = 0; j < n; ++j) t->msrc[j] = (j < n_active) ? m[j] : 0.0;
+  t->keys = (uint64_t *)malloc(n1 * sizeof(uint64_t));
+  t->next = (int64_t *)malloc(n1 * sizeof(int64_t));
+  t->leaf_of = (int64_t *)malloc(n1 * sizeof(int64_t));
+  t->perm = (int64_t *)malloc(n1 * sizeof(int64_t));
+  size_t nr = (size_t)orc_nr(p, 0) * (size_t)orc_nr(p, 1) * (size_t)orc_nr(p, 2);
+  t->roots = (int64_t *)malloc(nr * sizeof(int64_t));
+  for (int64_t j = 0; j < n; ++j) t->leaf_of[j] = ORC_NONE;
+  orc_set_positions(t, x, y, z);
   for (int l = 0; l <= ORC_DEPTH; ++l) {
-    double w = ldexp(p->W, -l);
+    double w = ldexp(p->W, t->D - l);
     t->w2[l] = w * w;
   }
-  t->n_live = 0;
-  for (int64_t j = 0; j < n; ++j) t->n_live += (t->keys[j] != UINT64_MAX);
-  if (t->n_live > 0) {
-    orc_new_node(t, 0, 0);
-    for (int64_t j = 0; j < n; ++j)
-      if (t->keys[j] != UINT64_MAX) orc_add(t, 0, j);
-    orc_rank(t, 0, 0);
-    orc_moments(t, 0);
-  }
+  for (int64_t j = 0; j < n; ++j)
+    if (t->keys[j] != UINT64_MAX) orc_insert(t, j);
+  orc_finish(t);
   t->ok = 1;
   return t;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Reconstruction (Sect. 4.2).  A particle still inside the cell of its leaf
+ * stays.  Any other one is taken out of its leaf; a leaf left empty is
+ * destroyed, and so is every cell above it that holds nothing else; a cell
+ * left with at most n_leaf particles becomes a leaf holding them (the tree
+ * an insertion of the same particles would give, so that reconstruction
+ * and a fresh build agree).  The particles taken out are then inserted
+ * again from their root box, and the moments are recomputed bottom-up.     */
+
+static void orc_unlink(orc_tree *t, int64_t leaf, int64_t j) {
+  onode *nd = &t->nodes[leaf];
+  int64_t prev = ORC_NONE;
+  for (int64_t k = nd->head; k != ORC_NONE; prev = k, k = t->next[k]) {
+    if (k != j) continue;
+    if (prev == ORC_NONE) nd->head = t->next[k]; else t->next[prev] = t->next[k];
+    if (nd->tail == k) nd->tail = prev;
+    nd->nmem--;
+    break;
+  }
+  t->leaf_of[j] = ORC_NONE;
+}
+
+/* particles in a subtree (leaf member counts summed) */
+static int64_t orc_held(const orc_tree *t, int64_t node) {
+  const onode *nd = &t->nodes[node];
+  if (nd->leaf) return nd->nmem;
+  int64_t c = 0;
+  for (int o = 0; o < 8; ++o)
+    if (nd->child[o] != ORC_NONE) c += orc_held(t, nd->child[o]);
+  return c;
+}
+
+/* move every particle below `node` into `dst`'s member list */
+static void orc_gather(orc_tree *t, int64_t node, int64_t dst) {
+  onode *nd = &t->nodes[node];
+  if (nd->leaf) {
+    int64_t k = nd->head;
+    while (k != ORC_NONE) {
+      int64_t nxt = t->next[k];
+      if (node != dst) orc_append(t, dst, k);
+      k = nxt;
+    }
+    return;
+  }
+  for (int o = 0; o < 8; ++o)
+    if (t->nodes[node].child[o] != ORC_NONE) orc_gather(t, t->nodes[node].child[o], dst);
+}
+
+/* after removals: returns 0 when the subtree is left empty (to be destroyed) */
+static int orc_prune(orc_tree *t, int64_t node) {
+  onode *nd = &t->nodes[node];
+  if (nd->leaf) return nd->nmem > 0;
+  int64_t held = orc_held(t, node);
+  if (held == 0) return 0;
+  if (held <= t->p.n_leaf) {
+    /* collapse: the cell becomes a leaf with the particles below it */
+    int32_t ch[8];
+    for (int o = 0; o < 8; ++o) ch[o] = nd->child[o];
+    nd->leaf = 1;
+    nd->head = nd->tail = ORC_NONE;
+    nd->nmem = 0;
+    for (int o = 0; o < 8; ++o) t->nodes[node].child[o] = ORC_NONE;
+    for (int o = 0; o < 8; ++o)
+      if (ch[o] != ORC_NONE) orc_gather(t, ch[o], node);
+    return 1;
+  }
+  for (int o = 0; o < 8; ++o) {
+    int32_t c = t->nodes[node].child[o];
+    if (c != ORC_NONE && !orc_prune(t, c)) t->nodes[node].child[o] = ORC_NONE;
+  }
+  return 1;
+}
+
+/* drop nodes no longer reachable from a root box; indices are renumbered */
+static void orc_compact(orc_tree *t) {
+  int64_t *map = (int64_t *)malloc((size_t)(t->n_nodes > 0 ? t->n_nodes : 1) * sizeof(int64_t));
+  for (int64_t v = 0; v < t->n_nodes; ++v) map[v] = ORC_NONE;
+  int64_t *stack = (int64_t *)malloc((size_t)(t->n_nodes > 0 ? t->n_nodes : 1) * sizeof(int64_t));
+  int64_t live = 0;
+  for (int64_t k = 0; k < t->n_roots; ++k) {
+    int64_t sp = 0;
+    stack[sp++] = t->roots[k];
+    while (sp > 0) {
+      int64_t v = stack[--sp];
+      map[v] = live++;
+      for (int o = 0; o < 8; ++o)
+        if (t->nodes[v].child[o] != ORC_NONE) stack[sp++] = t->nodes[v].child[o];
+    }
+  }
+  onode *nn = (onode *)malloc((size_t)(live > 0 ? live : 1) * sizeof(onode));
+  for (int64_t v = 0; v < t->n_nodes; ++v) {
+    if (map[v] == ORC_NONE) continue;
+    onode c = t->nodes[v];
+    for (int o = 0; o < 8; ++o)
+      if (c.child[o] != ORC_NONE) c.child[o] = (int32_t)map[c.child[o]];
+    nn[map[v]] = c;
+  }
+  for (int64_t k = 0; k < t->n_roots; ++k) t->roots[k] = map[t->roots[k]];
+  for (int64_t j = 0; j < t->n; ++j)
+    if (t->leaf_of[j] != ORC_NONE) t->leaf_of[j] = map[t->leaf_of[j]];
+  free(t->nodes);
+  t->nodes = nn;
+  t->n_nodes = live;
+  t->cap = live > 0 ? live : 1;
+  free(map);
+  free(stack);
+}
+
+int64_t orc_tree_update(orc_tree *t, const double *x, const double *y, const double *z) {
+  orc_set_positions(t, x, y, z);
+  int64_t *moved = (int64_t *)malloc((size_t)(t->n > 0 ? t->n : 1) * sizeof(int64_t));
+  int64_t n_moved = 0;
+  for (int64_t j = 0; j < t->n; ++j) {
+    int64_t lf = t->leaf_of[j];
+    if (lf == ORC_NONE) continue; /* was outside: removed particles stay removed */
+    const onode *nd = &t->nodes[lf];
+    int stays = t->keys[j] != UINT64_MAX &&
+                (t->keys[j] >> (3 * (ORC_DEPTH - nd->level))) == nd->prefix;
+    if (stays) continue;
+    orc_unlink(t, lf, j);
+    if (t->keys[j] != UINT64_MAX) moved[n_moved++] = j;
+  }
+  /* destroy emptied cells, collapse cells left with few particles */
+  int64_t kept = 0;
+  for (int64_t k = 0; k < t->n_roots; ++k)
+    if (orc_prune(t, t->roots[k])) t->roots[kept++] = t->roots[k];
+  t->n_roots = kept;
+  orc_compact(t);
+  for (int64_t k = 0; k < n_moved; ++k) orc_insert(t, moved[k]);
+  orc_finish(t);
+  free(moved);
+  return n_moved;
+}
+
 void orc_tree_free(orc_tree *t) {
   if (!t) return;
-  free(t->nodes); free(t->next); free(t->keys); free(t->perm);
+  free(t->nodes); free(t->next); free(t->leaf_of); free(t->keys); free(t->perm);
+  free(t->roots);
   free(t->x); free(t->y); free(t->z); free(t->msrc);
   free(t);
 }
@@ -337,6 +541,18 @@ int orc_tree_selfcheck(const orc_tree *t) {
   return 1;
 }
 
+static const orc_tree *g_sort_tree; /* for the export's qsort */
+
+static int orc_node_cmp(const void *a, const void *b) {
+  const onode *na = &g_sort_tree->nodes[*(const int64_t *)a];
+  const onode *nb = &g_sort_tree->nodes[*(const int64_t *)b];
+  if (na->level != nb->level) return na->level < nb->level ? -1 : 1;
+  if (na->prefix != nb->prefix) return na->prefix < nb->prefix ? -1 : 1;
+  return 0;
+}
+
+/* canonical export: every root box's nodes together, level by level and by
+ * prefix inside a level (so siblings are consecutive) */
 void orc_tree_export(const orc_tree *t, int8_t *level, uint64_t *prefix,
                      int64_t *first, int64_t *count, int8_t *is_leaf,
                      int32_t *n_child, int64_t *first_child, double *M,
@@ -344,17 +560,11 @@ void orc_tree_export(const orc_tree *t, int8_t *level, uint64_t *prefix,
                      uint64_t *sorted_keys) {
   int64_t nn = t->n_nodes;
   if (nn == 0) return;
-  /* breadth-first order: level by level, children in octant order, which
-   * keeps every level sorted by prefix */
   int64_t *order = (int64_t *)malloc((size_t)nn * sizeof(int64_t));
   int64_t *pos = (int64_t *)malloc((size_t)nn * sizeof(int64_t));
-  int64_t head = 0, tail = 0;
-  order[tail++] = 0;
-  while (head < tail) {
-    int64_t v = order[head++];
-    for (int o = 0; o < 8; ++o)
-      if (t->nodes[v].child[o] != ORC_NONE) order[tail++] = t->nodes[v].child[o];
-  }
+  for (int64_t k = 0; k < nn; ++k) order[k] = k;
+  g_sort_tree = t;
+  qsort(order, (size_t)nn, sizeof(int64_t), orc_node_cmp);
   for (int64_t k = 0; k < nn; ++k) pos[order[k]] = k;
   for (int64_t k = 0; k < nn; ++k) {
     const onode *nd = &t->nodes[order[k]];
@@ -381,9 +591,10 @@ void orc_tree_export(const orc_tree *t, int8_t *level, uint64_t *prefix,
 
 /* ------------------------------------------------------------------------ */
 /* Ghost images (Sect. 2.3: periodic and shear-periodic ghost boxes).  The
- * image of a source is x + o with o = (ix W, iy W - ix s, 0), ix outer and iy
- * inner, both in [-ng, ng]; s is the shear offset (0 for periodic
- * boundaries).  Open boundaries use the single image o = 0.                 */
+ * image of a source is x + o with o = (ix Lx, iy Ly - ix s, 0), ix outer and
+ * iy inner, both in [-ng, ng]; Lx, Ly are the domain's extents (n_root W)
+ * and s is the shear offset (0 for periodic boundaries).  Open boundaries
+ * use the single image o = 0.                                               */
 
 #define ORC_MAX_IMAGES 121
 
@@ -398,8 +609,8 @@ static int orc_images(const orc_params *p, double s, double (*o)[3], int *zero) 
   for (int ix = -p->ng[0]; ix <= p->ng[0]; ++ix)
     for (int iy = -p->ng[1]; iy <= p->ng[1]; ++iy) {
       double fx = (double)ix, fy = (double)iy;
-      o[k][0] = fx * p->W;
-      o[k][1] = fy * p->W - fx * sh;
+      o[k][0] = fx * orc_L(p, 0);
+      o[k][1] = fy * orc_L(p, 1) - fx * sh;
       o[k][2] = 0.0;
       if (ix == 0 && iy == 0) *zero = k;
       ++k;
@@ -520,7 +731,8 @@ void orc_bh(const orc_params *p, const orc_tree *t, int64_t n, const double *x,
         w.y0 = x[i] - o[im][0];
         w.y1 = y[i] - o[im][1];
         w.y2 = z[i] - o[im][2];
-        orc_visit(&w, 0);
+        /* every root box's tree, in the order of the boxes' prefixes */
+        for (int64_t r = 0; r < t->n_roots; ++r) orc_visit(&w, t->roots[r]);
       }
     }
     ax[k] = w.a[0];
@@ -564,12 +776,12 @@ void orc_direct(const orc_params *p, int64_t n, int64_t n_active, const double *
 }
 
 /* ------------------------------------------------------------------------ */
-/* Shear offset of the ghost boxes: the box at +W in x slides with the mean
- * shear flow vy = -(3/2) Omega x, so its y offset at time t is
- * -(3/2) Omega W t, folded into [-W/2, W/2].                                */
+/* Shear offset of the ghost boxes: the domain copy at +Lx in x slides with
+ * the mean shear flow vy = -(3/2) Omega x, so its y offset at time t is
+ * -(3/2) Omega Lx t, folded into [-Ly/2, Ly/2].                             */
 double orc_shear_offset(const orc_params *p, double t) {
   if (p->boundary != ORC_SHEAR) return 0.0;
-  return remainder(1.5 * p->omega * p->W * t, p->W);
+  return remainder(1.5 * p->omega * orc_L(p, 0) * t, orc_L(p, 1));
 }
 
 /* Drift sub-step over tau.  Leap-frog (Sect. 3.1): x += v tau.  Epicycle
@@ -607,28 +819,30 @@ void orc_drift(const orc_params *p, int64_t n, double *x, double *y, double *z,
   }
 }
 
-/* Sect. 2.3 boundaries.  Shear-periodic in x: a particle leaving through one
- * x face re-enters through the other, shifted in y by the shear offset and
- * in vy by the shear velocity jump (3/2) Omega W.  Periodic: plain wrap.
+/* Sect. 2.3 boundaries, at the faces of the domain (extents Lx, Ly, Lz).
+ * Shear-periodic in x: a particle leaving through one x face re-enters
+ * through the other, shifted in y by the shear offset and in vy by the
+ * shear velocity jump (3/2) Omega Lx.  Periodic: plain wrap.
  * y wraps in both.  Open axes remove the particle (it becomes a tombstone:
  * NaN position, zero velocity) once it leaves the root box.                */
 void orc_boundary(const orc_params *p, int64_t n, double *x, double *y, double *z,
                   double *vx, double *vy, double *vz, double s) {
+  double Lx = orc_L(p, 0), Ly = orc_L(p, 1), Lz = orc_L(p, 2);
   double lo0 = p->x0[0], lo1 = p->x0[1], lo2 = p->x0[2];
-  double hi0 = lo0 + p->W, hi1 = lo1 + p->W, hi2 = lo2 + p->W;
-  double jump = 1.5 * p->omega * p->W;
+  double hi0 = lo0 + Lx, hi1 = lo1 + Ly, hi2 = lo2 + Lz;
+  double jump = 1.5 * p->omega * Lx;
   for (int64_t i = 0; i < n; ++i) {
     if (!(isfinite(x[i]) && isfinite(y[i]) && isfinite(z[i]))) continue;
     if (p->boundary == ORC_SHEAR) {
-      if (x[i] >= hi0) { x[i] = x[i] - p->W; y[i] = y[i] + s; vy[i] = vy[i] + jump; }
-      else if (x[i] < lo0) { x[i] = x[i] + p->W; y[i] = y[i] - s; vy[i] = vy[i] - jump; }
+      if (x[i] >= hi0) { x[i] = x[i] - Lx; y[i] = y[i] + s; vy[i] = vy[i] + jump; }
+      else if (x[i] < lo0) { x[i] = x[i] + Lx; y[i] = y[i] - s; vy[i] = vy[i] - jump; }
     } else if (p->boundary == ORC_PERIODIC) {
-      if (x[i] >= hi0) x[i] = x[i] - p->W;
-      else if (x[i] < lo0) x[i] = x[i] + p->W;
+      if (x[i] >= hi0) x[i] = x[i] - Lx;
+      else if (x[i] < lo0) x[i] = x[i] + Lx;
     }
     if (p->boundary != ORC_OPEN) {
-      if (y[i] >= hi1) y[i] = y[i] - p->W;
-      else if (y[i] < lo1) y[i] = y[i] + p->W;
+      if (y[i] >= hi1) y[i] = y[i] - Ly;
+      else if (y[i] < lo1) y[i] = y[i] + Ly;
     }
     int out = !(z[i] >= lo2 && z[i] < hi2);
     if (p->boundary == ORC_OPEN)
@@ -767,7 +981,7 @@ static int64_t orc_coll_run(const orc_params *p, int64_t n, const double *x, con
     int k = 0;
     for (int ix = -p->ng[0]; ix <= p->ng[0]; ++ix)
       for (int iy = -p->ng[1]; iy <= p->ng[1]; ++iy) {
-        w[k++] = (p->boundary == ORC_SHEAR) ? -1.5 * p->omega * p->W * (double)ix : 0.0;
+        w[k++] = (p->boundary == ORC_SHEAR) ? -1.5 * p->omega * orc_L(p, 0) * (double)ix : 0.0;
       }
     if (p->boundary == ORC_OPEN) w[0] = 0.0;
   }

@@ -10,7 +10,9 @@
  *   - Eq. (1): the Plummer-softened pairwise acceleration over N_active massive
  *     particles, summed over the ghost-box images (Sect. 2.3, Sect. 4, 4.1);
  *   - the Barnes-Hut octree of Sect. 4.2, built by one-at-a-time insertion,
- *     with bottom-up mass / centre of mass and Hernquist quadrupole moments;
+ *     with bottom-up mass / centre of mass and Hernquist quadrupole moments,
+ *     one tree per cubic root box of the domain (Sect. 2.3), and its
+ *     reconstruction after the particles moved (Sect. 4.2);
  *   - the per-particle tree walk with opening angle theta = w/R;
  *   - the drift-kick-drift step of Sect. 3 with the leap-frog drift (3.1) or
  *     the exact epicycle drift used by the symplectic epicycle integrator (3.3);
@@ -34,24 +36,32 @@ typedef struct {
   double theta;      /* critical opening angle */
   int32_t quadrupole;/* 0: monopole only, 1: add the quadrupole term */
   int32_t n_leaf;    /* max particles per leaf above the deepest level (paper: 1) */
-  double W;          /* side of the cubic root box */
-  double x0[3];      /* minimum corner of the root box */
+  double W;          /* side of each cubic root box */
+  double x0[3];      /* minimum corner of the domain (of root box 0) */
   int32_t boundary;  /* ORC_OPEN / ORC_PERIODIC / ORC_SHEAR */
   int32_t ng[2];     /* ghost rings in x and y (periodic / shear only) */
   int32_t drift;     /* ORC_LEAPFROG / ORC_EPICYCLE */
   double omega;      /* orbital frequency (shear offset, epicycle drift) */
   double omega_z;    /* vertical epicycle frequency */
+  int32_t n_root[3]; /* root boxes per axis (Sect. 2.3); 0 or 1 = one box */
 } orc_params;
 
 typedef struct orc_tree orc_tree;
 
-/* keys (UINT64_MAX for a particle outside the root box or with a NaN coordinate) */
+/* keys (UINT64_MAX for a particle outside the domain or with a NaN coordinate) */
 void orc_keys(const orc_params *p, int64_t n, const double *x, const double *y,
               const double *z, uint64_t *keys);
 
 orc_tree *orc_tree_build(const orc_params *p, int64_t n, int64_t n_active,
                          const double *x, const double *y, const double *z,
                          const double *m);
+/* Tree reconstruction of Sect. 4.2 after the particles moved to x, y, z
+ * (same particles, same masses): every particle that left the cell of its
+ * leaf (or the domain) is taken out and inserted again; cells left empty
+ * are destroyed and cells left with at most n_leaf particles become leaves
+ * again; then the moments are updated bottom-up.  Returns the number of
+ * particles re-inserted.                                                  */
+int64_t orc_tree_update(orc_tree *t, const double *x, const double *y, const double *z);
 void orc_tree_free(orc_tree *t);
 int64_t orc_tree_n_nodes(const orc_tree *t);
 int64_t orc_tree_n_live(const orc_tree *t);
