@@ -61,7 +61,7 @@ typedef enum { RB_DRIFT_LEAPFROG = 0, RB_DRIFT_EPICYCLE = 1 } rb_drift;
  *  boundary         RB_OPEN: particles leaving the root box are removed.
  *                   RB_PERIODIC: x and y wrap, z is open.
  *                   RB_SHEAR: shear-periodic in x, periodic in y, z open;
- *                   requires box_min[0] = -box_size / 2.
+ *                   requires box_min[0] = -Lx / 2.
  *  drift            RB_DRIFT_LEAPFROG: x += v tau (Sect. 3.1).
  *                   RB_DRIFT_EPICYCLE: exact solution of Hill's equations
  *                   without the perturbing force (Sect. 3.3).
@@ -70,11 +70,25 @@ typedef enum { RB_DRIFT_LEAPFROG = 0, RB_DRIFT_EPICYCLE = 1 } rb_drift;
  *                   RB_FP32_MIXED: grouped walk, FP32 interaction
  *                   arithmetic on node-relative coordinates, FP64
  *                   positions, velocities, drift, ghost offsets and sums.
- *  box_size, box_min  the cubic root box [box_min, box_min + box_size)^3
- *                   (Sect. 2.3); one root box per system.
+ *  box_size, box_min  side W of every cubic root box, and the domain's
+ *                   minimum corner (Sect. 2.3).
+ *  n_root           root boxes per axis (Sect. 2.3: an integer number of
+ *                   cubic boxes along each axis, e.g. elongated boxes; 0 or
+ *                   1 = one box, at most 256).  The domain is
+ *                   [box_min, box_min + n_root W) per axis, extents
+ *                   L = n_root W, and every root box has a tree of its own
+ *                   (cells of side W 2^-k below it).  Keys quantise the
+ *                   domain once, 2^(21-D) steps per root box per axis, where
+ *                   2^D >= every n_root, so a root box's tree is at most
+ *                   21 - D levels deep.  The exported tree lists, above the
+ *                   root boxes (levels < D), the cells of side W 2^(D-l)
+ *                   that hold them; those are never leaves and every walk
+ *                   opens them.  Single systems only (batches, collisions
+ *                   and the plane sweep refuse forests: RB_EUNSUPPORTED).
  *  n_ghost          ghost-box rings in x and y (periodic / shear only,
- *                   0..2); images are (ix W, iy W - ix s, 0), ix and iy in
- *                   [-n_ghost, n_ghost], s the shear offset.
+ *                   0..2); images are (ix Lx, iy Ly - ix s, 0), ix and iy in
+ *                   [-n_ghost, n_ghost], s the shear offset
+ *                   remainder(1.5 omega Lx t, Ly).
  *  omega, omega_z   orbital and vertical epicyclic frequency.
  *  node_factor      node capacity per particle (>= 1.5; 0 selects 3).
  *  split_images     1: one walk work item per (group, image) pair, 0: one
@@ -124,7 +138,8 @@ typedef struct {
   int32_t walk_waves;
   int32_t moments_level_log2;
   int32_t walk64_schedule;
-  int32_t reserved[2];
+  int32_t n_root[3];
+  int32_t reserved[3];
 } rb_params;
 
 /* Device SoA of the particles, caller order, all FP64. */

@@ -112,9 +112,9 @@ __global__ __launch_bounds__(256) void k_coll_geom(
   const int l = nlevel[node];
   const double w = ldexp(pi.W, -l);
   uint32_t qx = 0, qy = 0, qz = 0;
-  (void)rb_quantise(sx[f], pi.x0[0], pi.W, pi.S, qx);
-  (void)rb_quantise(sy[f], pi.x0[1], pi.W, pi.S, qy);
-  (void)rb_quantise(sz[f], pi.x0[2], pi.W, pi.S, qz);
+  (void)rb_quantise(sx[f], pi.x0[0], pi.L[0], pi.S, pi.qtop[0], qx);
+  (void)rb_quantise(sy[f], pi.x0[1], pi.L[1], pi.S, pi.qtop[1], qy);
+  (void)rb_quantise(sz[f], pi.x0[2], pi.L[2], pi.S, pi.qtop[2], qz);
   const int sft = RB_DEPTH - l;
   CollNode r;
   r.cx = pi.x0[0] + ((double)(qx >> sft) + 0.5) * w;

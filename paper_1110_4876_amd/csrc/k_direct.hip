@@ -31,7 +31,7 @@ __global__ __launch_bounds__(64) void k_direct(
     const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
     const double *__restrict__ m, uint32_t n, uint32_t n_active,
     const int64_t *__restrict__ targets, uint32_t nt, uint32_t chunk, int n_img, int ngx,
-    int ngy, int boundary, double W, double s, double G, double b2,
+    int ngy, int boundary, double Lx, double Ly, double s, double G, double b2,
     double *__restrict__ part, uint32_t *__restrict__ err) {
   __shared__ double4 src[64];
   const uint32_t t = blockIdx.x * 64 + threadIdx.x;
@@ -70,8 +70,8 @@ __global__ __launch_bounds__(64) void k_direct(
           const int ix = im / ny - ngx, iy = im % ny - ngy;
           const double fx = (double)ix, fy = (double)iy;
           const double sh = (boundary == RB_SHEAR) ? s : 0.0;
-          ox = fx * W;
-          oy = fy * W - fx * sh;
+          ox = fx * Lx;
+          oy = fy * Ly - fx * sh;
           self = (ix == 0 && iy == 0);
         }
         const double y0 = px - ox, y1 = py - oy, y2 = pz;
@@ -125,7 +125,7 @@ static void direct_chunks(uint32_t nsrc, uint32_t nt, uint64_t max_part, uint32_
 
 static void direct_kernels(const rb_particles *cp, uint32_t n, uint32_t n_active,
                            const int64_t *targets, uint32_t nt, int n_img, int ngx, int ngy,
-                           int boundary, double W, double s, double G, double b2,
+                           int boundary, double Lx, double Ly, double s, double G, double b2,
                            double *part, uint64_t max_part, uint32_t *err, double *ax,
                            double *ay, double *az, hipStream_t stream) {
   const uint32_t nsrc = n_active < n ? n_active : n;
@@ -133,7 +133,7 @@ static void direct_kernels(const rb_particles *cp, uint32_t n, uint32_t n_active
   direct_chunks(nsrc, nt, max_part, n_chunks, chunk);
   hipLaunchKernelGGL(k_direct, dim3(rb_div_up(nt, 64), n_chunks), dim3(64), 0, stream, cp->x,
                      cp->y, cp->z, cp->m, n, n_active, targets, nt, chunk, n_img, ngx, ngy,
-                     boundary, W, s, G, b2, part, err);
+                     boundary, Lx, Ly, s, G, b2, part, err);
   hipLaunchKernelGGL(k_direct_reduce, dim3(rb_div_up(nt, 256)), dim3(256), 0, stream, part, nt,
                      n_chunks, ax, ay, az);
 }
@@ -145,7 +145,7 @@ hipError_t launch_direct(rb_ctx *c, const rb_particles *cp, uint32_t n, uint32_t
   // the partial sums live in the accumulator buffer
   const uint64_t acc_doubles = (uint64_t)(c->img_split ? c->n_img : 1) * 3 * c->cap;
   direct_kernels(cp, n, n_active, targets, nt, c->n_img, c->p.n_ghost[0], c->p.n_ghost[1],
-                 c->p.boundary, c->h_patch[0].W, s, c->p.G,
+                 c->p.boundary, c->h_patch[0].L[0], c->h_patch[0].L[1], s, c->p.G,
                  c->p.softening * c->p.softening, c->d_acc, acc_doubles, c->d_err, ax, ay, az,
                  c->stream);
   return hipGetLastError();
@@ -173,14 +173,14 @@ static hipError_t direct_scratch(double **out) {
 
 hipError_t launch_direct_noalloc(const rb_params *p, const rb_particles *cp, uint32_t n,
                                  uint32_t n_active, double s, const int64_t *targets,
-                                 uint32_t nt, int n_img, double *ax, double *ay, double *az,
-                                 hipStream_t stream) {
+                                 uint32_t nt, int n_img, double Lx, double Ly, double *ax,
+                                 double *ay, double *az, hipStream_t stream) {
   if (nt == 0) return hipSuccess;
   double *part = nullptr;
   const hipError_t e = direct_scratch(&part);
   if (e != hipSuccess) return e;
   direct_kernels(cp, n, n_active, targets, nt, n_img, p->n_ghost[0], p->n_ghost[1],
-                 p->boundary, p->box_size, s, p->G, p->softening * p->softening, part,
+                 p->boundary, Lx, Ly, s, p->G, p->softening * p->softening, part,
                  RB_DIRECT_SCRATCH_DOUBLES, nullptr, ax, ay, az, stream);
   return hipGetLastError();
 }

@@ -23,9 +23,9 @@ __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ x,
   const PatchInfo pi = patch[p];
   double xs = x[s], ys = y[s], zs = z[s];
   uint32_t qx, qy, qz;
-  bool okx = rb_quantise(xs, pi.x0[0], pi.W, pi.S, qx);
-  bool oky = rb_quantise(ys, pi.x0[1], pi.W, pi.S, qy);
-  bool okz = rb_quantise(zs, pi.x0[2], pi.W, pi.S, qz);
+  bool okx = rb_quantise(xs, pi.x0[0], pi.L[0], pi.S, pi.qtop[0], qx);
+  bool oky = rb_quantise(ys, pi.x0[1], pi.L[1], pi.S, pi.qtop[1], qy);
+  bool okz = rb_quantise(zs, pi.x0[2], pi.L[2], pi.S, pi.qtop[2], qz);
   uint64_t k = RB_KEY_DEAD;
   if (okx && oky && okz) {
     k = rb_key(qx, qy, qz);

@@ -420,7 +420,7 @@ __global__ __launch_bounds__(128) void k_moments_group(
     const uint32_t *__restrict__ nskip, const uint8_t *__restrict__ nlevel,
     const uint32_t *__restrict__ lev_off, const double *__restrict__ sx,
     const double *__restrict__ sy, const double *__restrict__ sz,
-    const double *__restrict__ msrc, int L, int quad, NodeLink *__restrict__ link,
+    const double *__restrict__ msrc, int L, int nvirt, int quad, NodeLink *__restrict__ link,
     double4 *__restrict__ mcom, double *__restrict__ Sarr, double *__restrict__ Qarr,
     WNode *__restrict__ wn, int roots_only, uint32_t *__restrict__ err) {
   // two independent waves per workgroup (fewer workgroups to dispatch),
@@ -480,6 +480,7 @@ __global__ __launch_bounds__(128) void k_moments_group(
       leaf = D + 1 < RB_DEPTH ? D + 1 : RB_DEPTH;
       if (leaf < l0) leaf = l0;
     }
+    if (leaf < nvirt) leaf = nvirt;  // no leaf above the root boxes
     const int glo = c + 1;                      // first level starting at this slot
     const int lo = (lane == 0) ? l0 : c + 1;    // first such level inside the group
     // node ids of the lane's starts
@@ -763,7 +764,7 @@ hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const d
   hipLaunchKernelGGL(k_moments_group, dim3(sgrid), dim3(128), 0, c->stream, c->d_witems,
                      c->d_witems_mid, c->cap, c->d_gctr, c->d_key[0], c->d_starts, c->d_csr, c->d_start_ids, c->d_nskip,
                      c->d_nlevel, c->d_lev_off, sx, sy, sz, c->d_msrc, c->p.leaf_size,
-                     c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, wnode,
+                     (int)c->h_patch[0].nvirt, c->p.quadrupole, c->d_link, c->d_mcom, c->d_S, c->d_Q, wnode,
                      (wnode && roots_only) ? 1 : 0, c->d_err);
   // bottom large nodes are disjoint subtrees of more than G particles each
   unsigned bgrid = rb_div_up(n / (G + 1) + 1, 64);

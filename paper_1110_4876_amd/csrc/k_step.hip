@@ -35,28 +35,29 @@ __device__ __forceinline__ void rb_apply_drift(PState &q, int mode, const StepCo
   q.x = xn; q.vx = vxn; q.y = yn; q.vy = vyn; q.z = zn; q.vz = vzn;
 }
 
-// Boundaries: shear-periodic x (shift y by s and vy by 1.5 omega W), plain
-// periodic x, periodic y; an open axis turns a leaving particle into a
-// tombstone (NaN position, zero velocity).
+// Boundaries at the domain's faces (extents Lx, Ly, Lz): shear-periodic x
+// (shift y by s and vy by 1.5 omega Lx), plain periodic x, periodic y; an
+// open axis turns a leaving particle into a tombstone (NaN position, zero
+// velocity).
 __device__ __forceinline__ void rb_apply_boundary(PState &q, int boundary, const PatchInfo &pi,
                                             double omega, double s) {
 #pragma clang fp contract(off)
   if (isnan(q.x) || isnan(q.y) || isnan(q.z) || isinf(q.x) || isinf(q.y) || isinf(q.z))
     return;
-  const double W = pi.W;
+  const double Lx = pi.L[0], Ly = pi.L[1], Lz = pi.L[2];
   const double lo0 = pi.x0[0], lo1 = pi.x0[1], lo2 = pi.x0[2];
-  const double hi0 = lo0 + W, hi1 = lo1 + W, hi2 = lo2 + W;
-  const double jump = 1.5 * omega * W;
+  const double hi0 = lo0 + Lx, hi1 = lo1 + Ly, hi2 = lo2 + Lz;
+  const double jump = 1.5 * omega * Lx;
   if (boundary == RB_SHEAR) {
-    if (q.x >= hi0) { q.x = q.x - W; q.y = q.y + s; q.vy = q.vy + jump; }
-    else if (q.x < lo0) { q.x = q.x + W; q.y = q.y - s; q.vy = q.vy - jump; }
+    if (q.x >= hi0) { q.x = q.x - Lx; q.y = q.y + s; q.vy = q.vy + jump; }
+    else if (q.x < lo0) { q.x = q.x + Lx; q.y = q.y - s; q.vy = q.vy - jump; }
   } else if (boundary == RB_PERIODIC) {
-    if (q.x >= hi0) q.x = q.x - W;
-    else if (q.x < lo0) q.x = q.x + W;
+    if (q.x >= hi0) q.x = q.x - Lx;
+    else if (q.x < lo0) q.x = q.x + Lx;
   }
   if (boundary != RB_OPEN) {
-    if (q.y >= hi1) q.y = q.y - W;
-    else if (q.y < lo1) q.y = q.y + W;
+    if (q.y >= hi1) q.y = q.y - Ly;
+    else if (q.y < lo1) q.y = q.y + Ly;
   }
   bool out = !(q.z >= lo2 && q.z < hi2);
   if (boundary == RB_OPEN) out = out || !(q.x >= lo0 && q.x < hi0) || !(q.y >= lo1 && q.y < hi1);
@@ -69,9 +70,9 @@ __device__ __forceinline__ void rb_apply_boundary(PState &q, int boundary, const
 __device__ __forceinline__ uint64_t rb_state_key(const PState &q, const PatchInfo &pi,
                                                  int boundary, uint32_t *err) {
   uint32_t qx, qy, qz;
-  const bool okx = rb_quantise(q.x, pi.x0[0], pi.W, pi.S, qx);
-  const bool oky = rb_quantise(q.y, pi.x0[1], pi.W, pi.S, qy);
-  const bool okz = rb_quantise(q.z, pi.x0[2], pi.W, pi.S, qz);
+  const bool okx = rb_quantise(q.x, pi.x0[0], pi.L[0], pi.S, pi.qtop[0], qx);
+  const bool oky = rb_quantise(q.y, pi.x0[1], pi.L[1], pi.S, pi.qtop[1], qy);
+  const bool okz = rb_quantise(q.z, pi.x0[2], pi.L[2], pi.S, pi.qtop[2], qz);
   if (okx && oky && okz) return rb_key(qx, qy, qz);
   if (boundary != RB_OPEN && !isnan(q.x) && (!okx || !oky)) atomicOr(err, RB_ERR_OUTSIDE);
   return RB_KEY_DEAD;
@@ -193,9 +194,9 @@ __global__ __launch_bounds__(256) void k_post(
           const double dx = ux - mx, dy = uy - my, dz = uz - mz;
           moved = sqrt(dx * dx + dy * dy + dz * dz);
           if (boundary != RB_OPEN) {
-            const double fx = rint((ux - q.x) / pi.W);
+            const double fx = rint((ux - q.x) / pi.L[0]);
             const double sx = (boundary == RB_SHEAR) ? fx * s_end : 0.0;
-            const double fy = rint(((uy - q.y) + sx) / pi.W);
+            const double fy = rint(((uy - q.y) + sx) / pi.L[1]);
             wv = (uint16_t)(((int)fx + 2) | (((int)fy + 2) << 4));
           }
         }

@@ -113,9 +113,9 @@ __global__ __launch_bounds__(256) void k_sw_keys(
     const PatchInfo pi = patch[0];
     const double xs = x[s], ys = y[s], zs = z[s];
     uint32_t q;
-    const bool okx = rb_quantise(xs, pi.x0[0], pi.W, pi.S, q);
-    const bool oky = rb_quantise(ys, pi.x0[1], pi.W, pi.S, q);
-    const bool okz = rb_quantise(zs, pi.x0[2], pi.W, pi.S, q);
+    const bool okx = rb_quantise(xs, pi.x0[0], pi.L[0], pi.S, pi.qtop[0], q);
+    const bool oky = rb_quantise(ys, pi.x0[1], pi.L[1], pi.S, pi.qtop[1], q);
+    const bool okz = rb_quantise(zs, pi.x0[2], pi.L[2], pi.S, pi.qtop[2], q);
     uint64_t k = RB_KEY_DEAD;
     if (okx && oky && okz) {
       const double r = R[s];

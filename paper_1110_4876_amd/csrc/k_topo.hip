@@ -31,7 +31,8 @@ struct TopoRange {
 };
 
 __device__ __forceinline__ TopoRange rb_topo_range(const uint64_t *__restrict__ key,
-                                                   uint32_t st, uint32_t i, uint32_t nl, int L) {
+                                                   uint32_t st, uint32_t i, uint32_t nl, int L,
+                                                   int nvirt) {
   const uint64_t *k = key + st;
   int lf = 0;
   if (nl > (uint32_t)L) {
@@ -44,6 +45,9 @@ __device__ __forceinline__ TopoRange rb_topo_range(const uint64_t *__restrict__ 
     }
     lf = D + 1 < RB_DEPTH ? D + 1 : RB_DEPTH;
   }
+  // the cells above the root boxes are never leaves: every occupied one
+  // exists down to its root box (the root of that box's own tree)
+  if (lf < nvirt) lf = nvirt;
   TopoRange r;
   r.lo_s = (i == 0) ? 0 : rb_lcp(k[i - 1], k[i]) + 1;
   r.hi_s = lf;
@@ -68,7 +72,7 @@ __global__ __launch_bounds__(64) void k_topo_count(
     const uint64_t *__restrict__ key, const uint32_t *__restrict__ tile_start,
     const uint32_t *__restrict__ tile_end, const uint32_t *__restrict__ tile_patch,
     const uint32_t *__restrict__ starts, const uint32_t *__restrict__ nlive, int L,
-    uint32_t n_tiles, uint32_t *__restrict__ cnt) {
+    int nvirt, uint32_t n_tiles, uint32_t *__restrict__ cnt) {
   const uint32_t b = blockIdx.x, lane = threadIdx.x;
   const uint32_t p = tile_patch[b], st = starts[p], nl = nlive[p];
   const uint32_t s0 = tile_start[b], s1 = tile_end[b];
@@ -77,7 +81,7 @@ __global__ __launch_bounds__(64) void k_topo_count(
     const uint32_t s = r0 + lane;
     const bool valid = s < s1 && (s - st) < nl;
     TopoRange tr = {1, 0, 1, 0};
-    if (valid) tr = rb_topo_range(key, st, s - st, nl, L);
+    if (valid) tr = rb_topo_range(key, st, s - st, nl, L, nvirt);
     int lmin, lmax;
     rb_topo_levels(tr, valid, lmin, lmax);
 #pragma unroll
@@ -98,7 +102,7 @@ __global__ __launch_bounds__(64) void k_topo_write(
     const uint64_t *__restrict__ key, const uint32_t *__restrict__ tile_start,
     const uint32_t *__restrict__ tile_end, const uint32_t *__restrict__ tile_patch,
     const uint32_t *__restrict__ starts, uint32_t *__restrict__ nlive, uint32_t n_patch, int L,
-    uint32_t n_tiles, const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ lev_tot,
+    int nvirt, uint32_t n_tiles, const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ lev_tot,
     uint32_t node_cap, uint32_t *__restrict__ lev_off, uint32_t *__restrict__ nfirst,
     uint32_t *__restrict__ nlast, uint32_t *__restrict__ nchild,
     uint32_t *__restrict__ nlastchild, uint32_t *__restrict__ nskip,
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(64) void k_topo_write(
     const bool valid = s < s1 && (s - st) < nl;
     const uint32_t i = s - st;
     TopoRange tr = {1, 0, 1, 0};
-    if (valid) tr = rb_topo_range(key, st, i, nl, L);
+    if (valid) tr = rb_topo_range(key, st, i, nl, L, nvirt);
     // starts: first slot, level, leaf flag, first child (the start one level
     // down at the same slot); ends: last slot, last child, skip pointer.
     // Indices outside the level's range would mean inconsistent counts:
@@ -226,14 +230,15 @@ hipError_t launch_topology(rb_ctx *c) {
   const uint32_t n = (uint32_t)c->h_starts[c->P];
   if (n == 0 || c->n_tiles == 0) return hipSuccess;
   const int L = c->p.leaf_size;
+  const int nv = (int)c->h_patch[0].nvirt;
   hipLaunchKernelGGL(k_topo_count, dim3(c->n_tiles), dim3(64), 0, c->stream, c->d_key[0],
                      c->d_tile_start, c->d_tile_end, c->d_tile_patch, c->d_starts, c->d_nlive, L,
-                     c->n_tiles, c->d_cnt);
+                     nv, c->n_tiles, c->d_cnt);
   hipError_t e = launch_rowscan_levels(c);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_topo_write, dim3(c->n_tiles), dim3(64), 0, c->stream, c->d_key[0],
                      c->d_tile_start, c->d_tile_end, c->d_tile_patch, c->d_starts, c->d_nlive,
-                     c->P, L, c->n_tiles, c->d_cnt, c->d_lev_tot, (uint32_t)c->node_cap,
+                     c->P, L, nv, c->n_tiles, c->d_cnt, c->d_lev_tot, (uint32_t)c->node_cap,
                      c->d_lev_off, c->d_nfirst, c->d_nlast, c->d_nchild, c->d_nlastchild,
                      c->d_nskip, c->d_nlevel, c->d_nleaf, c->d_root, c->d_err, c->d_gctr,
                      c->d_large_cnt, c->d_sctl, c->d_csr, c->d_start_ids);

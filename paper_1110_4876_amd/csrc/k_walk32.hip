@@ -43,15 +43,16 @@ __device__ __forceinline__ double w32_uniform_d(double v) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-__device__ __forceinline__ void w32_image(int im, int ngx, int ngy, int boundary, double W,
-                                          double s, double &ox, double &oy) {
+// image ordinal -> offset (ix Lx, iy Ly - ix s, 0); Lx, Ly the domain's extents
+__device__ __forceinline__ void w32_image(int im, int ngx, int ngy, int boundary, double Lx,
+                                          double Ly, double s, double &ox, double &oy) {
   if (boundary == RB_OPEN) { ox = 0.0; oy = 0.0; return; }
   const int ny = 2 * ngy + 1;
   const int ix = im / ny - ngx, iy = im % ny - ngy;
   const double fx = (double)ix, fy = (double)iy;
   const double sh = (boundary == RB_SHEAR) ? s : 0.0;
-  ox = fx * W;
-  oy = fy * W - fx * sh;
+  ox = fx * Lx;
+  oy = fy * Ly - fx * sh;
 }
 
 // order a wave's LDS writes before its later reads (a wave runs in lockstep)
@@ -204,6 +205,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const WalkItem grp = rb_walk_item(groups, groups_mid, gi, n_big, n_mid, cap);
     const uint32_t p = grp.patch;
     const double W = patch[p].W;
+    const int nvirt = (int)patch[p].nvirt;
     const int cnt = (int)(grp.end - grp.start);
     if (cnt < 1 || cnt > 64 || grp.end > cap) {  // never emitted
       if (lane == 0) atomicOr(err, RB_ERR_TREE);
@@ -240,7 +242,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     double ax = 0.0, ay = 0.0, az = 0.0;
     if (lane < n_img) {
       double ox, oy;
-      w32_image(lane, ngx, ngy, boundary, W, shear, ox, oy);
+      w32_image(lane, ngx, ngy, boundary, patch[p].L[0], patch[p].L[1], shear, ox, oy);
       img[lane] = make_double2(ox, oy);
     }
 
@@ -302,8 +304,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       const double dy = fmax(fmax(ly - cy, cy - hy), 0.0);
       const double dz = fmax(fmax(lz - cz, cz - hz), 0.0);
       const double R2 = dx * dx + dy * dy + dz * dz;
-      const double w = ldexp(W, -(int)(lk.lvl & 255u));
-      const bool accept = alive && !single && (w * w < theta2d * R2);
+      const int lv = (int)(lk.lvl & 255u);
+      const double w = ldexp(W, -lv);
+      // cells above the root boxes are always opened
+      const bool accept = alive && !single && lv >= nvirt && (w * w < theta2d * R2);
       const bool open_leaf = alive && !single && !accept && leaf;
       const bool open_node = alive && !single && !accept && !leaf;
 
@@ -503,6 +507,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W32M_WA
     const WalkItem grp = rb_walk_item(groups, groups_mid, gi, n_big, n_mid, cap);
     const uint32_t p = grp.patch;
     const double W = patch[p].W;
+    const int nvirt = (int)patch[p].nvirt;
     const int cnt = (int)(grp.end - grp.start);
     if (cnt < 1 || cnt > 64 || grp.end > cap) {  // never emitted
       if (lane == 0) atomicOr(err, RB_ERR_TREE);
@@ -539,7 +544,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W32M_WA
     if (w == 0 && lane < nim) stk[lane] = (r0 << 5) | (uint32_t)(im0 + lane);
     if (w == 0 && lane < n_img) {
       double ox, oy;
-      w32_image(lane, ngx, ngy, boundary, W, shear, ox, oy);
+      w32_image(lane, ngx, ngy, boundary, patch[p].L[0], patch[p].L[1], shear, ox, oy);
       img[lane] = make_double2(ox, oy);
     }
     int sp = nim;  // every wave keeps the same copy
@@ -597,8 +602,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W32M_WA
       const double dy = fmax(fmax(ly - cy, cy - hy), 0.0);
       const double dz = fmax(fmax(lz - cz, cz - hz), 0.0);
       const double R2 = dx * dx + dy * dy + dz * dz;
-      const double wd = ldexp(W, -(int)(lk.lvl & 255u));
-      const bool accept = alive && !single && (wd * wd < theta2d * R2);
+      const int lv = (int)(lk.lvl & 255u);
+      const double wd = ldexp(W, -lv);
+      // cells above the root boxes are always opened
+      const bool accept = alive && !single && lv >= nvirt && (wd * wd < theta2d * R2);
       const bool open_leaf = alive && !single && !accept && leaf;
       const bool open_node = alive && !single && !accept && !leaf;
       const uint32_t nc = open_node ? ((lk.lvl >> 9) & 15u) : 0u;

@@ -41,9 +41,11 @@ __device__ __forceinline__ double rb_rsqrt64(double x) {
   return y;
 }
 
-// image ordinal -> offset (ix W, iy W - ix s, 0), ix outer, iy inner
-__device__ __forceinline__ void rb_image(int im, int ngx, int ngy, int boundary, double W,
-                                         double s, double &ox, double &oy, bool &self) {
+// image ordinal -> offset (ix Lx, iy Ly - ix s, 0), ix outer, iy inner; Lx, Ly
+// the domain's extents
+__device__ __forceinline__ void rb_image(int im, int ngx, int ngy, int boundary, double Lx,
+                                         double Ly, double s, double &ox, double &oy,
+                                         bool &self) {
   if (boundary == RB_OPEN) {
     ox = 0.0; oy = 0.0; self = true;
     return;
@@ -52,8 +54,8 @@ __device__ __forceinline__ void rb_image(int im, int ngx, int ngy, int boundary,
   const int ix = im / ny - ngx, iy = im % ny - ngy;
   const double fx = (double)ix, fy = (double)iy;
   const double sh = (boundary == RB_SHEAR) ? s : 0.0;
-  ox = fx * W;
-  oy = fy * W - fx * sh;
+  ox = fx * Lx;
+  oy = fy * Ly - fx * sh;
   self = (ix == 0 && iy == 0);
 }
 
@@ -124,6 +126,7 @@ __global__ __launch_bounds__(256) void k_walk64(
   const double W = patch[p].W;
   // (W 2^-l)^2 = fl(W W) 2^-2l exactly: scaling by a power of two is exact
   const double W2 = W * W;
+  const int nvirt = (int)patch[p].nvirt;
   const uint32_t st = patch[p].start, nl = nlive[p];
   const uint32_t s = it.start + lane;
   const bool valid = s < it.end && (s - st) < nl;
@@ -137,7 +140,7 @@ __global__ __launch_bounds__(256) void k_walk64(
   for (int im = im0; im < im1; ++im) {
     double ox, oy;
     bool self;
-    rb_image(im, ngx, ngy, boundary, W, shear, ox, oy, self);
+    rb_image(im, ngx, ngy, boundary, patch[p].L[0], patch[p].L[1], shear, ox, oy, self);
     const double y0 = px - ox, y1 = py - oy, y2 = pz;
     double ax = 0.0, ay = 0.0, az = 0.0;
     // lane k holds the mask of the lanes working on nodes of level k
@@ -180,9 +183,11 @@ __global__ __launch_bounds__(256) void k_walk64(
         } else {
           const double d0 = cx - y0, d1 = cy - y1, d2 = cz - y2;
           const double R2 = __builtin_fma(d2, d2, __builtin_fma(d1, d1, d0 * d0));
-          const bool take = me && (ldexp(W2, -2 * l) < theta2 * R2);
+          // cells above the root boxes are always opened
+          const bool root_or_below = l >= nvirt;
+          const bool take = me && root_or_below && (ldexp(W2, -2 * l) < theta2 * R2);
           const uint64_t opened = act & ~__ballot(take);
-          if (STATS && me) ++n_open;
+          if (STATS && me && root_or_below) ++n_open;
           if (take) {
             const double ri = rb_rsqrt64(R2 + b2);
             const double ri2 = ri * ri;
@@ -289,7 +294,7 @@ __global__ __launch_bounds__(64) void k_walk64_lane(
   for (int im = im0; im < im1; ++im) {
     double ox, oy;
     bool self;
-    rb_image(im, ngx, ngy, boundary, W, shear, ox, oy, self);
+    rb_image(im, ngx, ngy, boundary, patch[p].L[0], patch[p].L[1], shear, ox, oy, self);
     const double y0 = px - ox, y1 = py - oy, y2 = pz;
     double ax = 0.0, ay = 0.0, az = 0.0;
     uint32_t cur = r0, visits = 0;
@@ -315,9 +320,12 @@ __global__ __launch_bounds__(64) void k_walk64_lane(
         } else {
           const double d0 = mc.x - y0, d1 = mc.y - y1, d2 = mc.z - y2;
           const double R2 = __builtin_fma(d2, d2, __builtin_fma(d1, d1, d0 * d0));
-          const double w = ldexp(W, -(int)(lk.lvl & 255u));
-          if (STATS) ++n_open;
-          if (w * w < theta2 * R2) {
+          const int lv = (int)(lk.lvl & 255u);
+          const double w = ldexp(W, -lv);
+          // cells above the root boxes are always opened
+          const bool root_or_below = lv >= (int)patch[p].nvirt;
+          if (STATS && root_or_below) ++n_open;
+          if (root_or_below && w * w < theta2 * R2) {
             const double ri = rb_rsqrt64(R2 + b2);
             const double ri2 = ri * ri;
             const double ri3 = ri * ri2;

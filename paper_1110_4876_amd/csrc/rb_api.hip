@@ -66,6 +66,20 @@ int upload_sync(rb_ctx *c, void *dst, const void *src, size_t bytes) {
   return RB_OK;
 }
 
+// root boxes along axis a (Sect. 2.3): n_root[a], 0 meaning 1
+int n_root_of(const rb_params &p, int a) { return p.n_root[a] > 1 ? p.n_root[a] : 1; }
+
+// octree levels above the root boxes: the smallest D with 2^D >= every n_root
+uint32_t virtual_levels(const rb_params &p) {
+  int m = std::max(n_root_of(p, 0), std::max(n_root_of(p, 1), n_root_of(p, 2)));
+  uint32_t D = 0;
+  while ((1 << D) < m) ++D;
+  return D;
+}
+
+bool is_forest(const rb_params &p) { return virtual_levels(p) > 0 || n_root_of(p, 0) > 1 ||
+                                            n_root_of(p, 1) > 1 || n_root_of(p, 2) > 1; }
+
 int n_images(const rb_params &p) {
   if (p.boundary == RB_OPEN) return 1;
   return (2 * p.n_ghost[0] + 1) * (2 * p.n_ghost[1] + 1);
@@ -103,6 +117,8 @@ int validate(const rb_params *p) {
     return fail(RB_EINVAL, "moments_level_log2 must be 0 or 6..31");
   if (p->walk64_schedule < 0 || p->walk64_schedule > 2)
     return fail(RB_EINVAL, "walk64_schedule must be 0, 1 or 2");
+  for (int a = 0; a < 3; ++a)
+    if (p->n_root[a] < 0 || p->n_root[a] > 256) return fail(RB_EINVAL, "n_root must be 0..256");
   return RB_OK;
 }
 
@@ -110,14 +126,16 @@ int validate_box(const rb_params *p, double W, const double *x0) {
   if (!(W > 0.0) || !isfinite(W)) return fail(RB_EINVAL, "box_size must be finite and > 0");
   for (int a = 0; a < 3; ++a)
     if (!isfinite(x0[a])) return fail(RB_EINVAL, "box_min must be finite");
-  if (p->boundary == RB_SHEAR && x0[0] != -0.5 * W)
-    return fail(RB_EINVAL, "shear boundaries need box_min[0] = -box_size / 2");
+  if (p->boundary == RB_SHEAR && x0[0] != -0.5 * ((double)n_root_of(*p, 0) * W))
+    return fail(RB_EINVAL, "shear boundaries need box_min[0] = -n_root[0] box_size / 2");
   return RB_OK;
 }
 
-double shear_offset(const rb_params &p, double W, double t) {
+// shear offset of the ghost boxes: the domain copy at +Lx slides by
+// -(3/2) omega Lx t, folded into [-Ly/2, Ly/2]
+double shear_offset(const rb_params &p, double Lx, double Ly, double t) {
   if (p.boundary != RB_SHEAR) return 0.0;
-  return remainder(1.5 * p.omega * W * t, W);
+  return remainder(1.5 * p.omega * Lx * t, Ly);
 }
 
 // One walk work item per (group, image) pair, or per group with all its
@@ -238,13 +256,19 @@ int init_ctx(rb_ctx *c, const rb_params *p, uint32_t P, const int64_t *off, cons
   c->h_patch.resize(P);
   for (uint32_t k = 0; k < P; ++k) {
     PatchInfo &pi = c->h_patch[k];
-    pi.W = W[k];
+    // W[k] is the root box side; keys quantise the cube of side W[k] 2^D
+    const uint32_t D = virtual_levels(c->p);
+    pi.nvirt = D;
+    pi.W = ldexp(W[k], (int)D);
     for (int a = 0; a < 3; ++a) pi.x0[a] = x0[3 * k + a];
-    pi.S = 2097152.0 / W[k];
+    pi.S = (double)(1u << (RB_DEPTH - D)) / W[k];
+    for (int a = 0; a < 3; ++a) {
+      pi.L[a] = (double)n_root_of(c->p, a) * W[k];
+      pi.qtop[a] = (double)n_root_of(c->p, a) * ldexp(1.0, RB_DEPTH - (int)D) - 1.0;
+    }
     pi.start = (uint32_t)off[k];
     pi.n = (uint32_t)(off[k + 1] - off[k]);
     pi.n_active = pi.n;
-    pi.pad = 0;
     c->h_starts[k] = (uint32_t)off[k];
   }
   c->h_starts[P] = (uint32_t)off[P];
@@ -404,15 +428,15 @@ int upload_schedule(rb_ctx *c, double t, double dt, int32_t nsteps) {
   const double half = 0.5 * dt;
   for (uint32_t k = 0; k < rows; ++k) {
     for (uint32_t p = 0; p < P; ++p) {
-      const double W = c->h_patch[p].W;
+      const double Lx = c->h_patch[p].L[0], Ly = c->h_patch[p].L[1];
       if (nsteps > 0) {
         const double tk = t + (double)k * dt;
         const double th = tk + half;
         const double te = t + (double)(k + 1) * dt;
-        sched[(size_t)k * 2 * P + p] = shear_offset(c->p, W, th);
-        sched[(size_t)k * 2 * P + P + p] = shear_offset(c->p, W, te);
+        sched[(size_t)k * 2 * P + p] = shear_offset(c->p, Lx, Ly, th);
+        sched[(size_t)k * 2 * P + P + p] = shear_offset(c->p, Lx, Ly, te);
       } else {
-        sched[p] = shear_offset(c->p, W, t);
+        sched[p] = shear_offset(c->p, Lx, Ly, t);
         sched[P + p] = sched[p];
       }
     }
@@ -712,6 +736,7 @@ int rb_batch_create(rb_ctx **out, const rb_params *p, int32_t n_patch, const int
   if (!out) return fail(RB_EINVAL, "null context pointer");
   *out = nullptr;
   RB_TRY(validate(p));
+  if (is_forest(*p)) return fail(RB_EUNSUPPORTED, "batch patches are single root boxes");
   if (n_patch < 1 || !offsets || !box_size || !box_min)
     return fail(RB_EINVAL, "need n_patch >= 1 and non-null offsets / boxes");
   if (offsets[0] != 0) return fail(RB_EINVAL, "offsets[0] must be 0");
@@ -749,6 +774,7 @@ int rb_set_params(rb_ctx *c, const rb_params *p) {
   rb_params q = *p;
   q.box_size = c->p.box_size;
   for (int a = 0; a < 3; ++a) q.box_min[a] = c->p.box_min[a];
+  for (int a = 0; a < 3; ++a) q.n_root[a] = c->p.n_root[a];
   q.node_factor = nf;
   if (q.omega_z == 0.0) q.omega_z = q.omega;
   c->p = q;
@@ -877,7 +903,7 @@ int rb_direct(rb_ctx *c, const rb_particles *p, int64_t n, int64_t n_active, dou
   if (n_targets < 0 || n_targets > n) return fail(RB_EINVAL, "n_targets outside [0, n]");
   if (n_active < 0) return fail(RB_EINVAL, "n_active must be >= 0");
   if (!isfinite(t)) return fail(RB_EINVAL, "t must be finite");
-  const double s = shear_offset(c->p, c->h_patch[0].W, t);
+  const double s = shear_offset(c->p, c->h_patch[0].L[0], c->h_patch[0].L[1], t);
   RB_PHASE(PH_DIRECT, launch_direct(c, p, (uint32_t)n, (uint32_t)std::min(n_active, n), s,
                                     targets, (uint32_t)n_targets, ax, ay, az));
   return RB_OK;
@@ -897,11 +923,13 @@ int rb_direct_noalloc(const rb_params *p, const rb_particles *parts, int64_t n,
                 "holds", (long long)n_targets, RB_DIRECT_SCRATCH_DOUBLES / 3);
   if (n_active < 0) return fail(RB_EINVAL, "n_active must be >= 0");
   if (!isfinite(t)) return fail(RB_EINVAL, "t must be finite");
-  const double s = shear_offset(*p, p->box_size, t);
+  const double Lx = (double)n_root_of(*p, 0) * p->box_size;
+  const double Ly = (double)n_root_of(*p, 1) * p->box_size;
+  const double s = shear_offset(*p, Lx, Ly, t);
   const hipError_t e = launch_direct_noalloc(p, parts, (uint32_t)n,
                                              (uint32_t)std::min(n_active, n), s, targets,
-                                             (uint32_t)n_targets, n_images(*p), ax, ay, az,
-                                             (hipStream_t)hip_stream);
+                                             (uint32_t)n_targets, n_images(*p), Lx, Ly, ax, ay,
+                                             az, (hipStream_t)hip_stream);
   if (e != hipSuccess) return fail(RB_EHIP, "rb_direct_noalloc: %s", hipGetErrorString(e));
   return RB_OK;
 }
@@ -946,6 +974,7 @@ static int coll_check_args(rb_ctx *c, rb_particles *p, const double *radius, dou
   if (!isfinite(t)) return fail(RB_EINVAL, "t must be finite");
   if (!(epsilon >= 0.0 && epsilon <= 1.0)) return fail(RB_EINVAL, "epsilon outside [0, 1]");
   if (codes_cap < 0 || (codes_cap > 0 && !codes)) return fail(RB_EINVAL, "bad code buffer");
+  if (is_forest(c->p)) return fail(RB_EUNSUPPORTED, "collisions need a single root box");
   return RB_OK;
 }
 
@@ -1028,6 +1057,7 @@ int rb_set_collisions(rb_ctx *c, const double *radius, double epsilon, uint64_t 
     if (!(epsilon >= 0.0 && epsilon <= 1.0)) return fail(RB_EINVAL, "epsilon outside [0, 1]");
     if (c->node_cap >= (1ull << 27))
       return fail(RB_EUNSUPPORTED, "the collision search needs fewer than 2^27 nodes");
+    if (is_forest(c->p)) return fail(RB_EUNSUPPORTED, "collisions need a single root box");
     RB_TRY(coll_alloc(c));
     if (!c->d_cgeo) RB_TRY(dalloc(c, &c->d_cgeo, 4 * c->node_cap));
     if (!c->d_cwrap) RB_TRY(dalloc(c, &c->d_cwrap, c->cap));

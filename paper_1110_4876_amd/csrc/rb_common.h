@@ -47,15 +47,23 @@ struct __align__(64) WNode {
   float qxx, qxy, qxz, qyy, qyz;
 };
 
-// Per-patch constants (device array, one entry per patch).
+// Per-patch constants (device array, one entry per patch).  The domain is
+// n_root[a] cubic root boxes of side w0 along axis a (Sect. 2.3).  Keys
+// quantise it inside one cube of side W = w0 2^nvirt, 2^nvirt >= every
+// n_root: the first nvirt octree levels are cells above the root boxes
+// (never leaves, always opened), level nvirt holds the root boxes, and a
+// node at level l is a cube of side W 2^-l.  With one root box nvirt = 0,
+// W = w0 and L = (W, W, W).
 struct PatchInfo {
-  double W;        // root box side
-  double x0[3];    // root box minimum corner
-  double S;        // 2^21 / W, quantisation scale
+  double W;        // side of the quantised cube (root box side times 2^nvirt)
+  double x0[3];    // domain minimum corner
+  double S;        // 2^(21 - nvirt) / w0 = 2^21 / W, quantisation scale
+  double L[3];     // domain extents: n_root[a] times the root box side
+  double qtop[3];  // largest quantised coordinate: n_root[a] 2^(21 - nvirt) - 1
   uint32_t start;  // first slot of the patch
   uint32_t n;      // slots of the patch
   uint32_t n_active;
-  uint32_t pad;
+  uint32_t nvirt;  // octree levels above the root boxes
 };
 
 // Per-step time-dependent values, indexed by the device step counter.
@@ -107,16 +115,16 @@ __device__ __forceinline__ uint64_t rb_spread3(uint32_t v) {
   return x;
 }
 
-// Quantise one coordinate: q = floor((x - x0) * S), S = 2^21 / W.  The
-// subtraction and the product are each rounded on their own (neither can
-// be contracted); a value rounding up to 2^21 is clamped.  Returns false
-// outside [x0, x0 + W) or for NaN.
-__device__ __forceinline__ bool rb_quantise(double xa, double x0, double W, double S,
-                                            uint32_t &q) {
+// Quantise one coordinate: q = floor((x - x0) * S).  The subtraction and
+// the product are each rounded on their own (neither can be contracted); a
+// value rounding up to the domain's end is clamped to qtop.  Returns false
+// outside [x0, x0 + L) or for NaN.
+__device__ __forceinline__ bool rb_quantise(double xa, double x0, double L, double S,
+                                            double qtop, uint32_t &q) {
   double u = xa - x0;
-  if (!(u >= 0.0 && u < W)) return false;
+  if (!(u >= 0.0 && u < L)) return false;
   double f = floor(u * S);
-  if (f >= 2097151.0) f = 2097151.0;
+  if (f >= qtop) f = qtop;
   q = (uint32_t)f;
   return true;
 }

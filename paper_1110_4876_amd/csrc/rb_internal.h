@@ -259,5 +259,5 @@ hipError_t launch_direct(rb_ctx *c, const rb_particles *cp, uint32_t n, uint32_t
 #define RB_DIRECT_SCRATCH_DOUBLES (1u << 20)
 hipError_t launch_direct_noalloc(const rb_params *p, const rb_particles *cp, uint32_t n,
                                  uint32_t n_active, double s, const int64_t *targets,
-                                 uint32_t nt, int n_img, double *ax, double *ay, double *az,
-                                 hipStream_t stream);
+                                 uint32_t nt, int n_img, double Lx, double Ly, double *ax,
+                                 double *ay, double *az, hipStream_t stream);

@@ -69,7 +69,7 @@ class Problem:
 def base_params(**kw) -> dict:
     p = dict(G=1.0, b=0.0, theta=0.5, quadrupole=False, n_leaf=1, group_size=64,
              W=1.0, x0=(0.0, 0.0, 0.0), boundary=OPEN, ng=(0, 0), drift=LEAPFROG,
-             omega=0.0, omega_z=None)
+             omega=0.0, omega_z=None, n_root=(1, 1, 1))
     p.update(kw)
     if p["omega_z"] is None:
         p["omega_z"] = p["omega"]
@@ -121,29 +121,35 @@ def plummer(n: int, seed: int = 0, b: float = 0.01, theta: float = 0.5,
 def sheet_from_rng(rng, n: int, tau: float = 0.5, omega: float = 1.95e-4,
                    rho: float = 400.0, r_min: float = 1.0, r_max: float = 4.0,
                    sigma_v: float = 0.01, theta: float = 0.5, quadrupole: bool = True,
-                   ng=(1, 1), n_leaf: int = 1) -> Problem:
+                   ng=(1, 1), n_leaf: int = 1, n_root=(1, 1, 1)) -> Problem:
     """Shearing-sheet patch (Sect. 3.3, Sect. 7).
 
     Draw order: radii by inverse CDF of dN/dR ~ R^-3 on [r_min, r_max]
-    (n uniforms), x and y ~ U(-L/2, L/2) (n each), z ~ N(0, R_i) (n),
-    velocity dispersions N(0, sigma_v) for vx, vy, vz (n each).  The box side
-    is L = sqrt(sum(pi R^2) / tau) from the drawn radii; vy also carries the
-    mean shear flow -1.5 Omega x.  SI units, G = 6.67430e-11.
+    (n uniforms), x ~ U(-Lx/2, Lx/2) and y ~ U(-Ly/2, Ly/2) (n each),
+    z ~ N(0, R_i) (n), velocity dispersions N(0, sigma_v) for vx, vy, vz (n
+    each).  The domain is n_root[0] x n_root[1] x n_root[2] cubic root boxes
+    of side W (Sect. 2.3; elongated patches when they differ), with
+    Lx Ly = n_root[0] n_root[1] W^2 = sum(pi R^2) / tau from the drawn radii;
+    one box (the default) gives the square patch of side L = W.  vy also
+    carries the mean shear flow -1.5 Omega x.  SI units, G = 6.67430e-11.
     """
     u = rng.uniform(0.0, 1.0, n)
     a2, b2 = r_min ** -2, r_max ** -2
     R = (a2 - u * (a2 - b2)) ** -0.5
     m = 4.0 / 3.0 * math.pi * R ** 3 * rho
-    L = math.sqrt(float(np.sum(math.pi * R * R)) / tau)
-    x = rng.uniform(-L / 2, L / 2, n)
-    y = rng.uniform(-L / 2, L / 2, n)
+    nx, ny, nz = (int(v) for v in n_root)
+    W = math.sqrt(float(np.sum(math.pi * R * R)) / tau / (nx * ny))
+    Lx, Ly, Lz = nx * W, ny * W, nz * W
+    x = rng.uniform(-Lx / 2, Lx / 2, n)
+    y = rng.uniform(-Ly / 2, Ly / 2, n)
     z = rng.normal(0.0, 1.0, n) * R
     vx = rng.normal(0.0, sigma_v, n)
     vy = rng.normal(0.0, sigma_v, n) - 1.5 * omega * x
     vz = rng.normal(0.0, sigma_v, n)
-    params = base_params(G=G_SI, b=0.0, theta=theta, quadrupole=quadrupole, W=L,
-                         x0=(-L / 2, -L / 2, -L / 2), boundary=SHEAR, ng=tuple(ng),
-                         drift=EPICYCLE, omega=omega, omega_z=omega, n_leaf=n_leaf)
+    params = base_params(G=G_SI, b=0.0, theta=theta, quadrupole=quadrupole, W=W,
+                         x0=(-Lx / 2, -Ly / 2, -Lz / 2), boundary=SHEAR, ng=tuple(ng),
+                         drift=EPICYCLE, omega=omega, omega_z=omega, n_leaf=n_leaf,
+                         n_root=(nx, ny, nz))
     dt = 1e-3 * 2.0 * math.pi / omega
     return Problem(x, y, z, vx, vy, vz, m, params, n, dt, 0.0, f"sheet{n}",
                    dict(radius=R, tau=tau))

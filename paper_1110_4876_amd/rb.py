@@ -50,7 +50,8 @@ class rb_params(ctypes.Structure):
         ("walk_waves", ctypes.c_int32),
         ("moments_level_log2", ctypes.c_int32),
         ("walk64_schedule", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("n_root", ctypes.c_int32 * 3),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -170,7 +171,7 @@ def params(**kw) -> rb_params:
     p = rb_params()
     lib().rb_params_default(ctypes.byref(p))
     for k, v in kw.items():
-        if k in ("box_min", "n_ghost"):
+        if k in ("box_min", "n_ghost", "n_root"):
             arr = getattr(p, k)
             for a, val in enumerate(v):
                 arr[a] = val
@@ -188,7 +189,8 @@ def params_from_problem(pp: dict, precision: int = RB_FP64, **kw) -> rb_params:
              boundary=int(pp["boundary"]), drift=int(pp["drift"]), precision=int(precision),
              box_size=float(pp["W"]), box_min=tuple(float(v) for v in pp["x0"]),
              n_ghost=tuple(int(v) for v in pp["ng"]), omega=float(pp["omega"]),
-             omega_z=float(pp["omega_z"] if pp.get("omega_z") is not None else pp["omega"]))
+             omega_z=float(pp["omega_z"] if pp.get("omega_z") is not None else pp["omega"]),
+             n_root=tuple(int(v) for v in pp.get("n_root", (1, 1, 1))))
     d.update(kw)
     return params(**d)
 
