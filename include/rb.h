@@ -110,6 +110,17 @@ typedef enum { RB_DRIFT_LEAPFROG = 0, RB_DRIFT_EPICYCLE = 1 } rb_drift;
  *                   above; k = 0 selects 22.  6..31.  Both orders add the
  *                   same children in the same order, so the moments are
  *                   identical; only the speed differs.
+ *  reuse_topology   1: rb_step keeps the tree from one step to the next when
+ *                   it can (the tree reconstruction of Sect. 4.2).  The
+ *                   particles stay in Morton order between steps; after each
+ *                   step's sort a check compares, slot by slot, the octal
+ *                   prefix levels consecutive keys share with the last
+ *                   tree's.  The canonical tree is a function of those
+ *                   levels, so when none changed (no particle left its cell)
+ *                   the topology, node lists and work items are reused and
+ *                   only the moments are recomputed bottom-up; otherwise the
+ *                   tree is rebuilt.  Same results either way; rb_stats
+ *                   counts the reused steps.  0: rebuild every step.
  *  walk64_schedule  FP64 walk: 0 chooses by size, 1 every lane walks for its
  *                   own particle, 2 a wave walks once for its 64 particles
  *                   (each lane keeping its own decisions).  Both visit, per
@@ -139,7 +150,8 @@ typedef struct {
   int32_t moments_level_log2;
   int32_t walk64_schedule;
   int32_t n_root[3];
-  int32_t reserved[3];
+  int32_t reuse_topology;
+  int32_t reserved[2];
 } rb_params;
 
 /* Device SoA of the particles, caller order, all FP64. */
@@ -180,6 +192,7 @@ typedef struct {
   int64_t list_pp;      /* FP32-mixed: particle entries evaluated */
   double ms[16];        /* phase times in ms (see rb_phase_name) */
   int64_t calls[16];    /* timed intervals per phase (e.g. walk launches) */
+  int64_t reused_steps; /* steps that kept the last tree (reuse_topology) */
 } rb_stats_t;
 
 /* Defaults: theta 0.5, leaf 1, group 64, open box [-64, 64)^3, monopole. */

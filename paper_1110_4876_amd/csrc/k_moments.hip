@@ -252,7 +252,8 @@ __global__ __launch_bounds__(256) void k_groups(
     const uint8_t *__restrict__ nlevel, const uint32_t *__restrict__ starts, uint32_t P,
     uint32_t G, WalkItem *__restrict__ witems, WalkItem *__restrict__ witems_mid, uint32_t wcap,
     uint32_t *__restrict__ gctr, uint32_t *__restrict__ large, uint32_t *__restrict__ bottom,
-    uint32_t *__restrict__ large_cnt) {
+    uint32_t *__restrict__ large_cnt, const uint32_t *__restrict__ reuse) {
+  if (reuse && *reuse == 0u) return;  // the step keeps the last tree's items
   const uint32_t n_nodes = lev_off[RB_NLEV];
   const uint32_t lane = rb_lane();
   __shared__ uint32_t s_tot[3][4], s_base[3];
@@ -735,25 +736,25 @@ __global__ __launch_bounds__(256) void k_moments_large_level(
 }
 
 // the work items and large-node lists of the current tree (k_groups)
-hipError_t launch_groups(rb_ctx *c) {
+hipError_t launch_groups(rb_ctx *c, const uint32_t *reuse) {
   unsigned grid = rb_div_up(c->node_cap, 256);
   if (grid > 2048) grid = 2048;
   hipLaunchKernelGGL(k_groups, dim3(grid), dim3(256), 0, c->stream, c->d_lev_off, c->d_nfirst,
                      c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nleaf, c->d_nlevel,
                      c->d_starts, c->P, (uint32_t)c->p.group_size, c->d_witems,
                      c->d_witems_mid, (uint32_t)c->cap, c->d_gctr, c->d_large, c->d_bottom,
-                     c->d_large_cnt);
+                     c->d_large_cnt, reuse);
   return hipGetLastError();
 }
 
 hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const double *sz,
-                          bool roots_only) {
+                          bool roots_only, const uint32_t *reuse) {
   const uint32_t n = (uint32_t)c->h_starts[c->P];
   if (n == 0) return hipSuccess;
   const uint32_t G = (uint32_t)c->p.group_size;
   // the grouped walk's node records are written only when it will run
   WNode *const wnode = c->p.precision == RB_FP32_MIXED ? c->d_wnode : nullptr;
-  const hipError_t ge = launch_groups(c);
+  const hipError_t ge = launch_groups(c, reuse);
   if (ge != hipSuccess) return ge;
 #define RB_MARGS                                                                          \
   c->d_nfirst, c->d_nlast, c->d_nchild, c->d_nlastchild, c->d_nskip, c->d_nleaf, sx, sy, sz, \

@@ -293,8 +293,10 @@ hipError_t launch_sort(rb_ctx *c) {
 // exclusive scan of the topology's per-tile level counts: one 256-thread
 // block per (kind, level) row of n_tiles entries; row totals to row_tot.
 __global__ __launch_bounds__(256) void k_rowscan(uint32_t *__restrict__ data, uint32_t n_tiles,
-                                                 uint32_t *__restrict__ row_tot) {
+                                                 uint32_t *__restrict__ row_tot,
+                                                 const uint32_t *__restrict__ reuse) {
   __shared__ uint32_t wsum[4];
+  if (reuse && *reuse == 0u) return;  // the step keeps the last tree
   const uint32_t r = blockIdx.x, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const size_t base = (size_t)r * n_tiles;
   uint32_t carry = 0;
@@ -314,8 +316,8 @@ __global__ __launch_bounds__(256) void k_rowscan(uint32_t *__restrict__ data, ui
   if (tid == 0) row_tot[r] = carry;
 }
 
-hipError_t launch_rowscan_levels(rb_ctx *c) {
+hipError_t launch_rowscan_levels(rb_ctx *c, const uint32_t *reuse) {
   hipLaunchKernelGGL(k_rowscan, dim3(2 * RB_NLEV), dim3(256), 0, c->stream, c->d_cnt,
-                     c->n_tiles, c->d_lev_tot);
+                     c->n_tiles, c->d_lev_tot, reuse);
   return hipGetLastError();
 }

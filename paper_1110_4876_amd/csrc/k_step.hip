@@ -152,8 +152,10 @@ __global__ __launch_bounds__(256) void k_post(
     unsigned long long *__restrict__ rmax) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t k = ctr[slot], nsteps = ctr[2];
-  // the next step reads its index from the other slot
+  // the next step reads its index from the other slot; its keep-the-tree
+  // flag (ctr[6 + slot]) starts clear, raised by its check on any change
   if (s == 0 && mode != 2) ctr[1 - slot] = k + 1;
+  if (s == 0 && mode != 1) ctr[6 + (1 - slot)] = 0u;
   double moved = 0.0, rad = 0.0;
   if (s < n) {
   const uint32_t p = (P == 1) ? 0 : rb_patch_of(starts, P, s);

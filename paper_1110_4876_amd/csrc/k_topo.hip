@@ -72,7 +72,8 @@ __global__ __launch_bounds__(64) void k_topo_count(
     const uint64_t *__restrict__ key, const uint32_t *__restrict__ tile_start,
     const uint32_t *__restrict__ tile_end, const uint32_t *__restrict__ tile_patch,
     const uint32_t *__restrict__ starts, const uint32_t *__restrict__ nlive, int L,
-    int nvirt, uint32_t n_tiles, uint32_t *__restrict__ cnt) {
+    int nvirt, uint32_t n_tiles, uint32_t *__restrict__ cnt, const uint32_t *__restrict__ reuse) {
+  if (reuse && *reuse == 0u) return;  // the step keeps the last tree
   const uint32_t b = blockIdx.x, lane = threadIdx.x;
   const uint32_t p = tile_patch[b], st = starts[p], nl = nlive[p];
   const uint32_t s0 = tile_start[b], s1 = tile_end[b];
@@ -109,10 +110,20 @@ __global__ __launch_bounds__(64) void k_topo_write(
     uint8_t *__restrict__ nlevel, uint8_t *__restrict__ nleaf, uint32_t *__restrict__ root,
     uint32_t *__restrict__ err, uint32_t *__restrict__ gctr, uint32_t *__restrict__ large_cnt,
     uint32_t *__restrict__ sort_number, uint32_t *__restrict__ csr,
-    uint32_t *__restrict__ start_ids) {
+    uint32_t *__restrict__ start_ids, const uint32_t *__restrict__ reuse,
+    unsigned long long *__restrict__ stats) {
   const uint32_t b = blockIdx.x, lane = threadIdx.x;
   // the sort that produced these keys is complete: number the next one
   if (b == 0 && lane == 0) sort_number[0] += 1u;
+  if (reuse && *reuse == 0u) {
+    // the step keeps the last tree: its nodes, lists and work items stand;
+    // only the grouped walk's queue restarts
+    if (b == 0 && lane == 0) {
+      gctr[1] = 0u;
+      atomicAdd(&stats[5], 1ull);
+    }
+    return;
+  }
   // level offsets: lane l holds the first node of level l
   const uint32_t tot = (lane < RB_NLEV) ? lev_tot[lane] : 0u;
   const uint32_t lincl = rb_wave_incl_scan(tot);
@@ -226,21 +237,56 @@ __global__ __launch_bounds__(64) void k_topo_write(
   }
 }
 
-hipError_t launch_topology(rb_ctx *c) {
+hipError_t launch_topology(rb_ctx *c, const uint32_t *reuse) {
   const uint32_t n = (uint32_t)c->h_starts[c->P];
   if (n == 0 || c->n_tiles == 0) return hipSuccess;
   const int L = c->p.leaf_size;
   const int nv = (int)c->h_patch[0].nvirt;
   hipLaunchKernelGGL(k_topo_count, dim3(c->n_tiles), dim3(64), 0, c->stream, c->d_key[0],
                      c->d_tile_start, c->d_tile_end, c->d_tile_patch, c->d_starts, c->d_nlive, L,
-                     nv, c->n_tiles, c->d_cnt);
-  hipError_t e = launch_rowscan_levels(c);
+                     nv, c->n_tiles, c->d_cnt, reuse);
+  hipError_t e = launch_rowscan_levels(c, reuse);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_topo_write, dim3(c->n_tiles), dim3(64), 0, c->stream, c->d_key[0],
                      c->d_tile_start, c->d_tile_end, c->d_tile_patch, c->d_starts, c->d_nlive,
                      c->P, L, nv, c->n_tiles, c->d_cnt, c->d_lev_tot, (uint32_t)c->node_cap,
                      c->d_lev_off, c->d_nfirst, c->d_nlast, c->d_nchild, c->d_nlastchild,
                      c->d_nskip, c->d_nlevel, c->d_nleaf, c->d_root, c->d_err, c->d_gctr,
-                     c->d_large_cnt, c->d_sctl, c->d_csr, c->d_start_ids);
+                     c->d_large_cnt, c->d_sctl, c->d_csr, c->d_start_ids, reuse, c->d_stats);
+  return hipGetLastError();
+}
+
+// Whether a step can keep the last tree (Sect. 4.2: the tree persists and
+// only particles that left their cells move in it).  The canonical tree of
+// sorted keys is a function of the octal prefix level each live key shares
+// with the previous one (and of the live count): code(s) = 255 at a patch's
+// first slot, 254 past its live keys, LCP(key[s-1], key[s]) otherwise.  If
+// every slot's code equals the last tree's, that tree's topology, node
+// lists and work items are this one's; any difference raises *flag.  The
+// new codes are kept for the next step.
+__global__ __launch_bounds__(256) void k_topo_check(const uint64_t *__restrict__ key,
+                                                    const uint32_t *__restrict__ starts,
+                                                    const uint32_t *__restrict__ nlive,
+                                                    uint32_t P, uint32_t n,
+                                                    uint8_t *__restrict__ lcp,
+                                                    uint32_t *__restrict__ flag) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  bool changed = false;
+  if (s < n) {
+    const uint32_t p = (P == 1) ? 0 : rb_patch_of(starts, P, s);
+    const uint32_t st = starts[p], nl = nlive[p], i = s - st;
+    const uint8_t code = (i >= nl) ? (uint8_t)254 : (i == 0) ? (uint8_t)255
+                                                             : (uint8_t)rb_lcp(key[s - 1], key[s]);
+    changed = lcp[s] != code;
+    if (changed) lcp[s] = code;
+  }
+  if (__ballot(changed) != 0ull && rb_lane() == 0) atomicOr(flag, 1u);
+}
+
+hipError_t launch_topo_check(rb_ctx *c, uint32_t *flag) {
+  const uint32_t n = (uint32_t)c->h_starts[c->P];
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_topo_check, dim3(rb_div_up(n, 256)), dim3(256), 0, c->stream,
+                     c->d_key[0], c->d_starts, c->d_nlive, c->P, n, c->d_lcp, flag);
   return hipGetLastError();
 }

@@ -117,6 +117,8 @@ int validate(const rb_params *p) {
     return fail(RB_EINVAL, "moments_level_log2 must be 0 or 6..31");
   if (p->walk64_schedule < 0 || p->walk64_schedule > 2)
     return fail(RB_EINVAL, "walk64_schedule must be 0, 1 or 2");
+  if (p->reuse_topology != 0 && p->reuse_topology != 1)
+    return fail(RB_EINVAL, "reuse_topology must be 0 or 1");
   for (int a = 0; a < 3; ++a)
     if (p->n_root[a] < 0 || p->n_root[a] > 256) return fail(RB_EINVAL, "n_root must be 0..256");
   return RB_OK;
@@ -152,6 +154,7 @@ void set_split(rb_ctx *c) {
 // tiles of RB_TILE slots inside each patch; walk items of `g` slots
 int build_layout(rb_ctx *c) {
   const uint32_t P = c->P;
+  c->lcp_stale = true;
   c->h_tile_start.clear(); c->h_tile_end.clear(); c->h_tile_patch.clear();
   c->h_patch_tile0.assign(P + 1, 0);
   c->max_tiles_per_patch = 0;
@@ -316,6 +319,7 @@ int init_ctx(rb_ctx *c, const rb_params *p, uint32_t P, const int64_t *off, cons
   RB_HIP(hipMemsetAsync(c->d_bcnt, 0, 4 * (size_t)BS_NB * P, c->stream));
   RB_HIP(hipMemsetAsync(c->d_bctl, 0, 16, c->stream));
   RB_TRY(dalloc(c, &c->d_msrc, cap));
+  RB_TRY(dalloc(c, &c->d_lcp, cap));
   RB_TRY(dalloc(c, &c->d_cnt, 2 * RB_NLEV * max_tiles));
   RB_TRY(dalloc(c, &c->d_lev_tot, 2 * RB_NLEV));
   RB_TRY(dalloc(c, &c->d_lev_off, RB_NLEV + 2));
@@ -421,6 +425,10 @@ int upload_schedule(rb_ctx *c, double t, double dt, int32_t nsteps) {
   RB_HIP(hipEventSynchronize(c->dyn_ev));
   uint32_t *ctr = (uint32_t *)c->h_dyn;
   ctr[0] = 0u; ctr[1] = 0u; ctr[2] = rows; ctr[3] = 0u;
+  // words 6, 7: the steps' keep-the-tree flags (raised: rebuild); the first
+  // step of a call rebuilds when the tree buffers were last written elsewhere
+  ctr[6] = c->lcp_stale ? 1u : 0u;
+  ctr[7] = 0u;
   // words 4-5: the collision seed of the schedule's first step
   memcpy(c->h_dyn + 16, &c->chunk_seed, 8);
   StepConst *sc = (StepConst *)(c->h_dyn + 64);
@@ -562,6 +570,7 @@ int build_tree(rb_ctx *c, const rb_particles *p) {
   RB_PHASE(PH_TOPO, launch_topology(c));
   RB_PHASE(PH_MOMENTS, launch_moments(c, c->d_px[0][0], c->d_px[0][1], c->d_px[0][2]));
   c->fp64_partial = false;
+  c->lcp_stale = true;
   return RB_OK;
 }
 
@@ -603,9 +612,18 @@ int step_kernels(rb_ctx *c, int src) {
   const int dst = 1 - src;
   RB_PHASE(PH_SORT, launch_sort(c));
   RB_PHASE(PH_PERMUTE, launch_permute_state(c, src, dst));
-  RB_PHASE(PH_TOPO, launch_topology(c));
+  // with reuse_topology the step keeps the last tree when no particle left
+  // its cell: the check leaves the step's flag clear, and the topology and
+  // work-item kernels return at once (Sect. 4.2's tree kept across steps)
+  const uint32_t *reuse = nullptr;
+  if (c->p.reuse_topology) {
+    uint32_t *flag = c->d_ctr + 6 + src;
+    RB_PHASE(PH_TOPO, launch_topo_check(c, flag));
+    reuse = flag;
+  }
+  RB_PHASE(PH_TOPO, launch_topology(c, reuse));
   RB_PHASE(PH_MOMENTS, launch_moments(c, c->d_px[dst][0], c->d_px[dst][1], c->d_px[dst][2],
-                                      c->p.precision == RB_FP32_MIXED));
+                                      c->p.precision == RB_FP32_MIXED, reuse));
   c->fp64_partial = c->p.precision == RB_FP32_MIXED;
   if (c->coll_on) RB_PHASE(PH_COLLIDE, launch_coll_step_prep(c, dst));
   RB_TRY(walk(c, dst, src));
@@ -676,6 +694,8 @@ int run_step(rb_ctx *c, rb_particles *p, double t, double dt, int32_t nsteps) {
     const double t0 = t + (double)done * dt;
     c->chunk_seed = c->coll_seed + c->coll_steps;
     RB_TRY(upload_schedule(c, t0, dt, chunk));
+    // the steps keep the prefix-level record current only when they use it
+    c->lcp_stale = c->p.reuse_topology == 0;
     if (c->coll_on) c->coll_steps += (uint64_t)chunk;
     RB_TRY(mark(c, PH_TOTAL, true));
     RB_PHASE(PH_KEYS, launch_prologue(c, p));
@@ -782,6 +802,7 @@ int rb_set_params(rb_ctx *c, const rb_params *p) {
   (void)old_split;
   set_split(c);
   c->graph_key = -1;
+  c->lcp_stale = true;
   return RB_OK;
 }
 
@@ -975,6 +996,7 @@ static int coll_check_args(rb_ctx *c, rb_particles *p, const double *radius, dou
   if (!(epsilon >= 0.0 && epsilon <= 1.0)) return fail(RB_EINVAL, "epsilon outside [0, 1]");
   if (codes_cap < 0 || (codes_cap > 0 && !codes)) return fail(RB_EINVAL, "bad code buffer");
   if (is_forest(c->p)) return fail(RB_EUNSUPPORTED, "collisions need a single root box");
+  c->lcp_stale = true;  // the search builds its own tree in the same buffers
   return RB_OK;
 }
 
@@ -1129,6 +1151,7 @@ int rb_stats(rb_ctx *c, rb_stats_t *out) {
   out->pp = (int64_t)s[2];
   out->list_cells = (int64_t)s[3];
   out->list_pp = (int64_t)s[4];
+  out->reused_steps = (int64_t)s[5];
   for (int k = 0; k < 16; ++k) {
     out->ms[k] = c->phase_ms[k];
     out->calls[k] = c->phase_calls[k];

@@ -84,8 +84,13 @@ struct rb_ctx {
   double *d_msrc = nullptr;         // source mass of sorted slots
   int cur = 0;                      // buffer holding the sorted state
 
-  // topology
-  uint8_t *d_lcp = nullptr, *d_leaf = nullptr;
+  // topology; d_lcp: per sorted slot, the octal prefix level it shares with
+  // the previous live key of the last tree (255 first slot, 254 dead), for
+  // the check that lets rb_step keep a tree (reuse_topology); lcp_stale:
+  // the tree buffers were last written by another path, so the first step
+  // of the next rb_step call rebuilds
+  uint8_t *d_lcp = nullptr;
+  bool lcp_stale = true;
   uint32_t *d_cnt = nullptr;        // 2 * 22 * n_tiles (starts, ends)
   uint32_t *d_lev_tot = nullptr;    // 2 * 22
   uint32_t *d_lev_off = nullptr;    // 23 (+1: node total)
@@ -216,7 +221,7 @@ __device__ __forceinline__ void rb_coll_keep(uint64_t code, uint64_t (&mine)[RB_
 hipError_t launch_keys(rb_ctx *c, const double *x, const double *y, const double *z,
                        double s_unused);
 hipError_t launch_sort(rb_ctx *c);
-hipError_t launch_groups(rb_ctx *c);
+hipError_t launch_groups(rb_ctx *c, const uint32_t *reuse = nullptr);
 hipError_t launch_sweep_keys(rb_ctx *c, const rb_particles *pp, const double *radius,
                              double dt, int phi);
 hipError_t launch_sweep_pairs(rb_ctx *c, const rb_particles *pp, const double *radius,
@@ -234,12 +239,15 @@ hipError_t launch_bsort(rb_ctx *c);
 hipError_t launch_permute_state(rb_ctx *c, int src, int dst);
 hipError_t launch_permute_gravity(rb_ctx *c, const double *x, const double *y,
                                   const double *z, const double *m, uint32_t n_active_single);
-hipError_t launch_topology(rb_ctx *c);
+// reuse: the step's keep-the-tree flag (0: the last tree stands, the
+// topology kernels exit at once), or nullptr to always build
+hipError_t launch_topology(rb_ctx *c, const uint32_t *reuse = nullptr);
+hipError_t launch_topo_check(rb_ctx *c, uint32_t *flag);
 // roots_only: an FP32-mixed step, whose walk reads only the FP32 node
 // records; the FP64 records below the walk items' subtree roots are skipped
 hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const double *sz,
-                          bool roots_only = false);
-hipError_t launch_rowscan_levels(rb_ctx *c);
+                          bool roots_only = false, const uint32_t *reuse = nullptr);
+hipError_t launch_rowscan_levels(rb_ctx *c, const uint32_t *reuse = nullptr);
 hipError_t launch_walk64(rb_ctx *c, const double *sx, const double *sy, const double *sz,
                          int slot);
 hipError_t launch_walk32(rb_ctx *c, const double *sx, const double *sy, const double *sz,

@@ -51,7 +51,8 @@ class rb_params(ctypes.Structure):
         ("moments_level_log2", ctypes.c_int32),
         ("walk64_schedule", ctypes.c_int32),
         ("n_root", ctypes.c_int32 * 3),
-        ("reserved", ctypes.c_int32 * 3),
+        ("reuse_topology", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -69,7 +70,7 @@ class rb_stats_t(ctypes.Structure):
     _fields_ = [("open_tests", ctypes.c_int64), ("cells", ctypes.c_int64),
                 ("pp", ctypes.c_int64), ("list_cells", ctypes.c_int64),
                 ("list_pp", ctypes.c_int64), ("ms", ctypes.c_double * 16),
-                ("calls", ctypes.c_int64 * 16)]
+                ("calls", ctypes.c_int64 * 16), ("reused_steps", ctypes.c_int64)]
 
 
 class RBError(RuntimeError):
@@ -312,7 +313,7 @@ def rb_stats(ctx) -> dict:
     s = rb_stats_t()
     check(lib().rb_stats(ctx, ctypes.byref(s)), "rb_stats")
     out = dict(open_tests=s.open_tests, cells=s.cells, pp=s.pp, list_cells=s.list_cells,
-               list_pp=s.list_pp)
+               list_pp=s.list_pp, reused_steps=s.reused_steps)
     out["ms"] = {name: s.ms[k] for k, name in enumerate(PHASES)}
     out["calls"] = {name: int(s.calls[k]) for k, name in enumerate(PHASES)}
     return out
