@@ -169,9 +169,14 @@ def write_traffic(args):
     c_f = values(cf, "FETCH_SIZE", "copyBuffer")
     c_w = values(cw, "WRITE_SIZE", "copyBuffer")
     kname = walk_kernel_name(path, args.walk_waves)
-    w_f = values(wf, "FETCH_SIZE", kname + "<")
-    w_w = values(ww, "WRITE_SIZE", kname + "<")
+    # the timed launches only: quadrupole on, interaction counters off
+    full = kname + ("<true, false>" if kname != "k_walk32m" else f"<true, false, {args.walk_waves}>")
+    w_f = values(wf, "FETCH_SIZE", full)
+    w_w = values(ww, "WRITE_SIZE", full)
     mean = lambda v: sum(v) / len(v)
+    # the median over the launches: the steps' walks (the odd one at another
+    # opening angle, for the theta 0.5 errors, does not move it)
+    med = lambda v: sorted(v)[len(v) // 2]
     fs = copy_bytes / 1024 / mean(c_f)
     ws = copy_bytes / 1024 / mean(c_w)
     meta = {
@@ -180,12 +185,13 @@ def write_traffic(args):
                   "group_size": args.group_size, "split_images": args.split_images,
                   "walk_waves": args.walk_waves},
         "sources": list(WALK_SRC[path]), "source_sha256": walk_source_sha(path),
-        "fetch_kib_per_dispatch_raw": mean(w_f), "write_kib_per_dispatch_raw": mean(w_w),
+        "kernel_instance": full,
+        "fetch_kib_per_dispatch_raw": med(w_f), "write_kib_per_dispatch_raw": med(w_w),
         "fetch_kib_min_max": [min(w_f), max(w_f)], "write_kib_min_max": [min(w_w), max(w_w)],
         "copy_calibration": {"copy_bytes": copy_bytes, "fetch_kib_raw": mean(c_f),
                              "write_kib_raw": mean(c_w), "fetch_scale": fs, "write_scale": ws},
-        "fetch_bytes_per_launch": mean(w_f) * 1024 * fs,
-        "write_bytes_per_launch": mean(w_w) * 1024 * ws,
+        "fetch_bytes_per_launch": med(w_f) * 1024 * fs,
+        "write_bytes_per_launch": med(w_w) * 1024 * ws,
         "dispatches": len(w_f),
     }
     meta["bytes_per_launch"] = meta["fetch_bytes_per_launch"] + meta["write_bytes_per_launch"]
@@ -210,10 +216,11 @@ def traffic_entries(path):
 def build_traffic(args):
     """Turn rocprofv3 --pmc runs over every kernel of a bench run (FETCH_SIZE
     and WRITE_SIZE, plus the copy calibration runs) into HBM bytes per step
-    of the build kernels: the dispatches between the fourth and the last
-    walk launch (the timed steps) grouped by kernel, each kernel's mean
-    scaled by the copy's true bytes / counter reading and multiplied by its
-    dispatches per step.  Prints one JSON object."""
+    of the build kernels: the dispatches between the walks of the second and
+    the sixth timed step (four whole steps inside the timed call; a run of
+    --warmup 1 --steps 6 or longer has them) grouped by kernel, each
+    kernel's sum scaled by the copy's true bytes / counter reading and
+    divided by the steps.  Prints one JSON object."""
     import csv
     import glob
     cf, cw, af, aw = args.build_traffic
@@ -238,10 +245,18 @@ def build_traffic(args):
     steps = None
     for c, d in (("FETCH_SIZE", af), ("WRITE_SIZE", aw)):
         rs = rows(d, c)
-        walks = [i for i, (_, k, _) in enumerate(rs) if k.startswith("k_walk32")]
-        lo, hi = walks[3], walks[-1]
+
+        def timed_walk(k):  # a walk launch without the interaction counters
+            if not k.startswith("k_walk") or "<" not in k:
+                return False
+            targs = k[k.index("<") + 1:k.rindex(">")].split(", ")
+            return len(targs) > 1 and targs[1] == "false"
+        # walks: the first force evaluation (accuracy gate), the warm-up
+        # step(s), then the timed steps
+        walks = [i for i, (_, k, _) in enumerate(rs) if timed_walk(k)]
+        lo, hi = walks[3], walks[7]
         window = rs[lo:hi]
-        steps = sum(1 for _, k, _ in window if k.startswith("k_walk32"))
+        steps = 4
         for _, k, x in window:
             if k.startswith("k_walk") or "copyBuffer" in k or "fillBuffer" in k:
                 continue
