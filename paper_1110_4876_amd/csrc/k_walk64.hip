@@ -31,14 +31,59 @@
 // better (measured: 7,000 units per-lane faster, 16,000 wave-shared faster)
 #define RB_WALK64_SHARED_MIN 12288u
 
-// 1 / sqrt(x): hardware estimate (relative error ~2^-23) refined by two
-// Newton steps y <- y (3 - x y^2) / 2 to FP64 accuracy.
+// 1 / sqrt(x): hardware estimate y (relative error ~2^-23) refined by one
+// third-order step.  With e = 1 - x y^2, 1/sqrt(x) = y (1 - e)^(-1/2) =
+// y (1 + e/2 + 3e^2/8 + O(e^3)), so one step takes the error from 2^-23 to
+// ~2^-70, below the rounding of the last operations (about one ulp; two
+// Newton steps give about two).
 __device__ __forceinline__ double rb_rsqrt64(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double h = 0.5 * x;
-  y = y * (1.5 - h * y * y);
-  y = y * (1.5 - h * y * y);
-  return y;
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = __builtin_fma(-(x * y), y, 1.0);
+  return __builtin_fma(y * e, __builtin_fma(0.375, e, 0.5), y);
+}
+
+// The terms a particle adds (d = source - particle, rho^2 = |d|^2 + b^2):
+//   monopole   G M d / rho^3
+//   quadrupole (5/2) G (d.Q.d) d / rho^7 - G (Q d) / rho^5
+// The monopole and the radial part of the quadrupole share the factor
+// (G M + (5/2) G (d.Q.d) / rho^4) / rho^3, so a cell costs two fused
+// multiply-adds per axis.
+__device__ __forceinline__ void w64_mono(double Gm, double d0, double d1, double d2,
+                                         double r2, double &ax, double &ay, double &az) {
+  const double ri = rb_rsqrt64(r2);
+  const double f = Gm * (ri * (ri * ri));
+  ax = __builtin_fma(f, d0, ax);
+  ay = __builtin_fma(f, d1, ay);
+  az = __builtin_fma(f, d2, az);
+}
+
+template <bool QUAD>
+__device__ __forceinline__ void w64_cell(double G, double Gm, const double *q, double d0,
+                                         double d1, double d2, double rho2, double &ax,
+                                         double &ay, double &az) {
+  const double ri = rb_rsqrt64(rho2);
+  const double u = ri * ri, g = ri * u;  // rho^-2, rho^-3
+  if (QUAD) {
+    const double e0 = __builtin_fma(q[0], d0, __builtin_fma(q[1], d1, q[2] * d2));
+    const double e1 = __builtin_fma(q[1], d0, __builtin_fma(q[3], d1, q[4] * d2));
+    const double e2 = __builtin_fma(q[2], d0, __builtin_fma(q[4], d1, q[5] * d2));
+    const double dqd = __builtin_fma(d0, e0, __builtin_fma(d1, e1, d2 * e2));
+    const double gs = g * __builtin_fma((2.5 * G) * dqd, u * u, Gm);
+    const double gu = (G * g) * u;
+    ax = __builtin_fma(-gu, e0, __builtin_fma(gs, d0, ax));
+    ay = __builtin_fma(-gu, e1, __builtin_fma(gs, d1, ay));
+    az = __builtin_fma(-gu, e2, __builtin_fma(gs, d2, az));
+  } else {
+    const double f = Gm * g;
+    ax = __builtin_fma(f, d0, ax);
+    ay = __builtin_fma(f, d1, ay);
+    az = __builtin_fma(f, d2, az);
+  }
+}
+
+// |d|^2 + b^2
+__device__ __forceinline__ double w64_r2(double d0, double d1, double d2, double b2) {
+  return __builtin_fma(d0, d0, __builtin_fma(d1, d1, __builtin_fma(d2, d2, b2)));
 }
 
 // image ordinal -> offset (ix Lx, iy Ly - ix s, 0), ix outer, iy inner; Lx, Ly
@@ -174,10 +219,7 @@ __global__ __launch_bounds__(256) void k_walk64(
         if (leaf && l_count == 1) {
           if (me && !(self && l_child == s)) {
             const double d0 = cx - y0, d1 = cy - y1, d2 = cz - y2;
-            const double r2 = d0 * d0 + d1 * d1 + d2 * d2 + b2;
-            const double ri = rb_rsqrt64(r2);
-            const double f = G * cm * (ri * ri * ri);
-            ax += f * d0; ay += f * d1; az += f * d2;
+            w64_mono(G * cm, d0, d1, d2, w64_r2(d0, d1, d2, b2), ax, ay, az);
             if (STATS) ++n_pp;
           }
         } else {
@@ -189,23 +231,8 @@ __global__ __launch_bounds__(256) void k_walk64(
           const uint64_t opened = act & ~__ballot(take);
           if (STATS && me && root_or_below) ++n_open;
           if (take) {
-            const double ri = rb_rsqrt64(R2 + b2);
-            const double ri2 = ri * ri;
-            const double ri3 = ri * ri2;
-            const double f = G * cm * ri3;
-            ax += f * d0; ay += f * d1; az += f * d2;
-            if (QUAD) {
-              const double e0 = q00 * d0 + q01 * d1 + q02 * d2;
-              const double e1 = q01 * d0 + q11 * d1 + q12 * d2;
-              const double e2 = q02 * d0 + q12 * d1 + q22 * d2;
-              const double dqd = d0 * e0 + d1 * e1 + d2 * e2;
-              const double ri5 = ri3 * ri2;
-              const double g5 = G * ri5;
-              const double g7 = 2.5 * G * dqd * (ri5 * ri2);
-              ax += g7 * d0 - g5 * e0;
-              ay += g7 * d1 - g5 * e1;
-              az += g7 * d2 - g5 * e2;
-            }
+            const double q[6] = {q00, q01, q02, q11, q12, q22};
+            w64_cell<QUAD>(G, G * cm, q, d0, d1, d2, R2 + b2, ax, ay, az);
             if (STATS) ++n_cell;
           }
           if (opened != 0ull) {
@@ -218,10 +245,7 @@ __global__ __launch_bounds__(256) void k_walk64(
                 if (mj == 0.0) continue;
                 if (mine && !(self && j == s)) {
                   const double e0 = sxc[j] - y0, e1 = syc[j] - y1, e2 = szc[j] - y2;
-                  const double r2 = e0 * e0 + e1 * e1 + e2 * e2 + b2;
-                  const double ri = rb_rsqrt64(r2);
-                  const double f = G * mj * (ri * ri * ri);
-                  ax += f * e0; ay += f * e1; az += f * e2;
+                  w64_mono(G * mj, e0, e1, e2, w64_r2(e0, e1, e2, b2), ax, ay, az);
                   if (STATS) ++n_pp;
                 }
               }
@@ -311,10 +335,7 @@ __global__ __launch_bounds__(64) void k_walk64_lane(
         if (leaf && lk.count == 1) {
           if (!(self && lk.child_or_first == s)) {
             const double d0 = mc.x - y0, d1 = mc.y - y1, d2 = mc.z - y2;
-            const double r2 = d0 * d0 + d1 * d1 + d2 * d2 + b2;
-            const double ri = rb_rsqrt64(r2);
-            const double f = G * mc.w * (ri * ri * ri);
-            ax += f * d0; ay += f * d1; az += f * d2;
+            w64_mono(G * mc.w, d0, d1, d2, w64_r2(d0, d1, d2, b2), ax, ay, az);
             if (STATS) ++n_pp;
           }
         } else {
@@ -326,26 +347,8 @@ __global__ __launch_bounds__(64) void k_walk64_lane(
           const bool root_or_below = lv >= (int)patch[p].nvirt;
           if (STATS && root_or_below) ++n_open;
           if (root_or_below && w * w < theta2 * R2) {
-            const double ri = rb_rsqrt64(R2 + b2);
-            const double ri2 = ri * ri;
-            const double ri3 = ri * ri2;
-            const double f = G * mc.w * ri3;
-            ax += f * d0; ay += f * d1; az += f * d2;
-            if (QUAD) {
-              const double *q = Qarr + 6 * (size_t)cur;
-              const double q00 = q[0], q01 = q[1], q02 = q[2], q11 = q[3], q12 = q[4],
-                           q22 = q[5];
-              const double e0 = q00 * d0 + q01 * d1 + q02 * d2;
-              const double e1 = q01 * d0 + q11 * d1 + q12 * d2;
-              const double e2 = q02 * d0 + q12 * d1 + q22 * d2;
-              const double dqd = d0 * e0 + d1 * e1 + d2 * e2;
-              const double ri5 = ri3 * ri2;
-              const double g5 = G * ri5;
-              const double g7 = 2.5 * G * dqd * (ri5 * ri2);
-              ax += g7 * d0 - g5 * e0;
-              ay += g7 * d1 - g5 * e1;
-              az += g7 * d2 - g5 * e2;
-            }
+            w64_cell<QUAD>(G, G * mc.w, Qarr + 6 * (size_t)cur, d0, d1, d2, R2 + b2, ax, ay,
+                           az);
             if (STATS) ++n_cell;
           } else if (leaf) {
             const uint32_t j0 = lk.child_or_first, j1 = j0 + lk.count;
@@ -353,10 +356,7 @@ __global__ __launch_bounds__(64) void k_walk64_lane(
               const double mj = msrc[j];
               if (mj == 0.0 || (self && j == s)) continue;
               const double e0 = sx[j] - y0, e1 = sy[j] - y1, e2 = sz[j] - y2;
-              const double r2 = e0 * e0 + e1 * e1 + e2 * e2 + b2;
-              const double ri = rb_rsqrt64(r2);
-              const double f = G * mj * (ri * ri * ri);
-              ax += f * e0; ay += f * e1; az += f * e2;
+              w64_mono(G * mj, e0, e1, e2, w64_r2(e0, e1, e2, b2), ax, ay, az);
               if (STATS) ++n_pp;
             }
           } else {
