@@ -142,8 +142,9 @@ hipError_t launch_direct(rb_ctx *c, const rb_particles *cp, uint32_t n, uint32_t
                          double s, const int64_t *targets, uint32_t nt, double *ax,
                          double *ay, double *az) {
   if (nt == 0) return hipSuccess;
-  // the partial sums live in the accumulator buffer
-  const uint64_t acc_doubles = (uint64_t)(c->img_split ? c->n_img : 1) * 3 * c->cap;
+  // the partial sums live in the accumulator buffer (all of it, whatever
+  // the walk's schedule uses, so the chunking depends on the input alone)
+  const uint64_t acc_doubles = (uint64_t)c->acc_sets * 3 * c->cap;
   direct_kernels(cp, n, n_active, targets, nt, c->n_img, c->p.n_ghost[0], c->p.n_ghost[1],
                  c->p.boundary, c->h_patch[0].L[0], c->h_patch[0].L[1], s, c->p.G,
                  c->p.softening * c->p.softening, c->d_acc, acc_doubles, c->d_err, ax, ay, az,

@@ -128,7 +128,7 @@ hipError_t launch_prologue(rb_ctx *c, const rb_particles *cp) {
   return hipGetLastError();
 }
 
-// Kick with the walk's accelerations (images summed in order), second drift
+// Kick with the walk's accelerations (images and parts summed in order), second drift
 // and boundary; then, unless this is the last step, the next step's first
 // drift, boundary and keys.  Works in place on the sorted buffer.  With
 // collisions at the end of the step the work is split around them: mode 1
@@ -253,7 +253,7 @@ hipError_t launch_post(rb_ctx *c, int buf, int slot, int mode) {
   const uint32_t n = (uint32_t)c->h_starts[c->P];
   if (n == 0) return hipSuccess;
   double *const *b = c->d_px[buf];
-  const int n_acc = c->img_split ? c->n_img : 1;
+  const int n_acc = rb_n_acc(c);
 #define RB_POST_ARGS                                                                      \
   b[0], b[1], b[2], b[3], b[4], b[5], c->d_acc, c->cap, n_acc, c->d_patch, c->d_starts,    \
       c->d_nlive, c->P, n, c->p.boundary, c->p.drift, c->d_sc, c->d_sched, c->d_ctr, slot, \
@@ -294,7 +294,7 @@ hipError_t launch_epilogue(rb_ctx *c, rb_particles *cp, int buf) {
   return hipGetLastError();
 }
 
-// accelerations (images summed in order) -> caller order; slots outside the
+// accelerations (images and parts summed in order) -> caller order; slots outside the
 // tree (removed particles) get zero
 __global__ __launch_bounds__(256) void k_scatter_acc(
     const double *__restrict__ acc, uint64_t cap, int n_acc, const uint32_t *__restrict__ orig,
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(256) void k_scatter_acc(
 hipError_t launch_scatter_acc(rb_ctx *c, double *ax, double *ay, double *az) {
   const uint32_t n = (uint32_t)c->h_starts[c->P];
   if (n == 0) return hipSuccess;
-  const int n_acc = c->img_split ? c->n_img : 1;
+  const int n_acc = rb_n_acc(c);
   hipLaunchKernelGGL(k_scatter_acc, dim3(rb_div_up(n, 256)), dim3(256), 0, c->stream,
                      c->d_acc, c->cap, n_acc, c->d_orig[0], c->d_patch, c->d_starts,
                      c->d_nlive, c->P, n, ax, ay, az);

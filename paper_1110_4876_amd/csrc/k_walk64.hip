@@ -25,12 +25,6 @@
 // stackless walk on its own, with its own loads.
 #include "rb_internal.h"
 
-// work units (64 particles and one image, or all images) from which the
-// wave-shared walk is used: below, the waves are too few to hide the
-// latency of its one chain of node loads per wave, and per-lane walks do
-// better (measured: 7,000 units per-lane faster, 16,000 wave-shared faster)
-#define RB_WALK64_SHARED_MIN 12288u
-
 // 1 / sqrt(x): hardware estimate y (relative error ~2^-23) refined by one
 // third-order step.  With e = 1 - x y^2, 1/sqrt(x) = y (1 - e)^(-1/2) =
 // y (1 + e/2 + 3e^2/8 + O(e^3)), so one step takes the error from 2^-23 to
@@ -133,10 +127,10 @@ __device__ __forceinline__ uint32_t w64_uniform(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
-template <bool QUAD, bool STATS>
+template <bool QUAD, bool STATS, bool PARTS>
 __global__ __launch_bounds__(256) void k_walk64(
-    const WalkItem *__restrict__ items, uint32_t n_items, int img_split, int n_img, int ngx,
-    int ngy, int boundary, const PatchInfo *__restrict__ patch,
+    const WalkItem *__restrict__ items, uint32_t n_items, int img_split, int n_img, int parts,
+    int ngx, int ngy, int boundary, const PatchInfo *__restrict__ patch,
     const uint32_t *__restrict__ nlive, const uint32_t *__restrict__ root,
     const NodeLink *__restrict__ link_g, const double4 *__restrict__ mcom_g,
     const double *__restrict__ Q_g, const double *__restrict__ sx_g,
@@ -158,13 +152,25 @@ __global__ __launch_bounds__(256) void k_walk64(
   const uint32_t vb = x * q + (x < r ? x : r) + (b >> 3);
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t unit = vb * 4u + (threadIdx.x >> 6);  // one unit per wave
-  const uint32_t n_units = img_split ? n_items * (uint32_t)n_img : n_items;
+  // a unit: a part, an item and its image (when split).  With parts > 1
+  // part k walks the subtree of the root's child k only (the root itself is
+  // tested by every part, its term added by part 0), so a system of few
+  // items still gives many units, each with a short chain of node loads;
+  // every particle still sees each node once, and the parts' sums are added
+  // in order afterwards.  Units are part-major: neighbouring waves (and an
+  // XCD's range) walk the same subtree for neighbouring particles and share
+  // its node records in the caches.
+  const uint32_t np = PARTS ? (uint32_t)parts : 1u;
+  const uint32_t per_part = n_items * (img_split ? (uint32_t)n_img : 1u);
+  const uint32_t n_units = per_part * np;
   if (unit >= n_units) return;  // whole waves
   // a depth-first walk visits every node at most once per image: more
   // visits, or an index past the node count, mean inconsistent links
   const uint32_t n_nodes = lev_off[RB_NLEV];
-  const uint32_t item = img_split ? unit / (uint32_t)n_img : unit;
-  const int im0 = img_split ? (int)(unit % (uint32_t)n_img) : 0;
+  const int part = (int)(unit / per_part);
+  const uint32_t sub = unit % per_part;
+  const uint32_t item = img_split ? sub / (uint32_t)n_img : sub;
+  const int im0 = img_split ? (int)(sub % (uint32_t)n_img) : 0;
   const int im1 = img_split ? im0 + 1 : n_img;
   const WalkItem it = items[item];
   const uint32_t p = it.patch;
@@ -191,11 +197,45 @@ __global__ __launch_bounds__(256) void k_walk64(
     // lane k holds the mask of the lanes working on nodes of level k
     uint64_t lvm = (lane == 0) ? live : 0ull;
     uint32_t cur = r0, visits = 0;
+    // with parts, part k walks from the root (k = 0, which also adds the
+    // root's own terms) or from the root's child k (k > 0, after testing the
+    // root for its lanes here) and stops at child k + 1: in depth-first
+    // order a child's subtree ends where the next child starts (children
+    // are numbered consecutively)
+    uint32_t stop = RB_NONE;
+    if (PARTS && cur != RB_NONE) {
+      if (cur >= n_nodes) {
+        if (lane == 0) atomicOr(err, RB_ERR_TREE);
+        cur = RB_NONE;
+      } else {
+        W64Rec rc;
+        w64_fetch(link, mcom, cur, rc);
+        const int l = (int)(rc.lvl & 255u);
+        const uint32_t n_child = rc.lvl >> 9;
+        const bool inner = (rc.lvl & 256u) == 0 && rc.m != 0.0 && l < RB_DEPTH;
+        uint64_t opened = 0ull;
+        if (inner) {
+          const double d0 = rc.cx - y0, d1 = rc.cy - y1, d2 = rc.cz - y2;
+          const double R2 = __builtin_fma(d2, d2, __builtin_fma(d1, d1, d0 * d0));
+          const bool take = valid && l >= nvirt && (ldexp(W2, -2 * l) < theta2 * R2);
+          opened = live & ~__ballot(take);
+        }
+        const uint32_t k = (uint32_t)part;
+        stop = (inner && k + 1 < n_child) ? rc.child + k + 1 : RB_NONE;
+        if (part > 0) {
+          if (inner && opened != 0ull && k < n_child) {
+            if (lane == (uint32_t)(l + 1)) lvm = opened;
+            cur = rc.child + k;
+          } else {
+            cur = RB_NONE;
+          }
+        }
+      }
+    }
     // the node in hand: NodeLink {child_or_first, skip, count, lvl} and
-    // double4 {com, M}; the records of both nodes that can come next (the
-    // first child and the next node after the subtree) are requested before
-    // this one is worked on, so their loads overlap its arithmetic
-    while (cur != RB_NONE) {
+    // double4 {com, M}, read with scalar loads; the other waves on the SIMD
+    // cover their latency
+    while (cur != RB_NONE && (!PARTS || cur != stop)) {
       if (cur >= n_nodes || ++visits > n_nodes) {
         if (lane == 0) atomicOr(err, RB_ERR_TREE);
         break;
@@ -260,7 +300,7 @@ __global__ __launch_bounds__(256) void k_walk64(
     }
     if (img_split) {
       if (s < it.end) {
-        double *a = acc + (size_t)im * 3 * cap;
+        double *a = acc + ((size_t)im * np + part) * 3 * cap;
         a[s] = ax; a[cap + s] = ay; a[2 * cap + s] = az;
       }
     } else {
@@ -268,7 +308,8 @@ __global__ __launch_bounds__(256) void k_walk64(
     }
   }
   if (!img_split && s < it.end) {
-    acc[s] = tx; acc[cap + s] = ty; acc[2 * cap + s] = tz;
+    double *a = acc + (size_t)part * 3 * cap;
+    a[s] = tx; a[cap + s] = ty; a[2 * cap + s] = tz;
   }
   if (STATS) {
     unsigned long long o = n_open, c = n_cell, q2 = n_pp;
@@ -402,22 +443,27 @@ hipError_t launch_walk64(rb_ctx *c, const double *sx, const double *sy, const do
   const double b2 = c->p.softening * c->p.softening;
   const double th2 = c->p.theta * c->p.theta;
   const bool quad = c->p.quadrupole != 0, stats = (c->p.profile & 2) != 0;
-  const int sched_mode = c->p.walk64_schedule;
-  if (sched_mode == 2 || (sched_mode == 0 && units >= RB_WALK64_SHARED_MIN)) {
-    const unsigned grid = (units + 3u) / 4u;  // four waves (units) per workgroup
+  if (c->walk64_mode != 1) {
+    const int parts = c->walk_parts;
+    const unsigned grid = (units * (uint32_t)parts + 3u) / 4u;  // four waves (units) per workgroup
 #define RB_WALK64_ARGS                                                                     \
-  c->d_items64, n_items, split, c->n_img, c->p.n_ghost[0], c->p.n_ghost[1], c->p.boundary, \
+  c->d_items64, n_items, split, c->n_img, parts, c->p.n_ghost[0], c->p.n_ghost[1],          \
+      c->p.boundary,                                                                       \
       c->d_patch, c->d_nlive, c->d_root, c->d_link, c->d_mcom, c->d_Q, sx, sy, sz,         \
       c->d_msrc, c->d_sched, c->d_ctr, c->P, c->p.G, b2, th2, c->d_acc, c->cap,           \
       c->d_stats, c->d_lev_off, c->d_err, slot
-    if (quad && stats)
-      hipLaunchKernelGGL((k_walk64<true, true>), dim3(grid), dim3(256), 0, c->stream, RB_WALK64_ARGS);
-    else if (quad)
-      hipLaunchKernelGGL((k_walk64<true, false>), dim3(grid), dim3(256), 0, c->stream, RB_WALK64_ARGS);
-    else if (stats)
-      hipLaunchKernelGGL((k_walk64<false, true>), dim3(grid), dim3(256), 0, c->stream, RB_WALK64_ARGS);
-    else
-      hipLaunchKernelGGL((k_walk64<false, false>), dim3(grid), dim3(256), 0, c->stream, RB_WALK64_ARGS);
+    const dim3 g(grid), bl(256);
+    if (parts > 1) {
+      if (quad && stats) hipLaunchKernelGGL((k_walk64<true, true, true>), g, bl, 0, c->stream, RB_WALK64_ARGS);
+      else if (quad) hipLaunchKernelGGL((k_walk64<true, false, true>), g, bl, 0, c->stream, RB_WALK64_ARGS);
+      else if (stats) hipLaunchKernelGGL((k_walk64<false, true, true>), g, bl, 0, c->stream, RB_WALK64_ARGS);
+      else hipLaunchKernelGGL((k_walk64<false, false, true>), g, bl, 0, c->stream, RB_WALK64_ARGS);
+    } else {
+      if (quad && stats) hipLaunchKernelGGL((k_walk64<true, true, false>), g, bl, 0, c->stream, RB_WALK64_ARGS);
+      else if (quad) hipLaunchKernelGGL((k_walk64<true, false, false>), g, bl, 0, c->stream, RB_WALK64_ARGS);
+      else if (stats) hipLaunchKernelGGL((k_walk64<false, true, false>), g, bl, 0, c->stream, RB_WALK64_ARGS);
+      else hipLaunchKernelGGL((k_walk64<false, false, false>), g, bl, 0, c->stream, RB_WALK64_ARGS);
+    }
 #undef RB_WALK64_ARGS
     return hipGetLastError();
   }

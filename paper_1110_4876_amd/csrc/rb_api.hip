@@ -115,8 +115,8 @@ int validate(const rb_params *p) {
     return fail(RB_EINVAL, "walk_waves must be 0, 1, 2 or 4");
   if (p->moments_level_log2 != 0 && (p->moments_level_log2 < 6 || p->moments_level_log2 > 31))
     return fail(RB_EINVAL, "moments_level_log2 must be 0 or 6..31");
-  if (p->walk64_schedule < 0 || p->walk64_schedule > 2)
-    return fail(RB_EINVAL, "walk64_schedule must be 0, 1 or 2");
+  if (p->walk64_schedule < 0 || p->walk64_schedule > 3)
+    return fail(RB_EINVAL, "walk64_schedule must be 0, 1, 2 or 3");
   if (p->reuse_topology != 0 && p->reuse_topology != 1)
     return fail(RB_EINVAL, "reuse_topology must be 0 or 1");
   for (int a = 0; a < 3; ++a)
@@ -141,14 +141,33 @@ double shear_offset(const rb_params &p, double Lx, double Ly, double t) {
 }
 
 // One walk work item per (group, image) pair, or per group with all its
-// images.  The per-particle FP64 walk splits when its 64-particle items
-// would leave the chip idle; the grouped FP32 walk already draws from a
-// device queue and splits only on request.
+// images, and the FP64 walk's schedule.  Below RB_WALK64_PARTS_MAX_ITEMS
+// items the FP64 walk is split by the root's children (schedule 3, when the
+// accumulators allow it) and takes all images per item; above, one wave
+// walks for 64 particles (schedule 2).  Per-lane walks (schedule 1) remain
+// for small systems whose accumulators cannot hold the parts, with a split
+// by image when the 64-particle items would leave the chip idle.  The
+// grouped FP32 walk already draws from a device queue and splits only on
+// request.
 void set_split(rb_ctx *c) {
+  const uint32_t n_items = (uint32_t)c->h_items64.size();
+  const bool fp64 = c->p.precision == RB_FP64;
+  int mode = c->p.walk64_schedule;
+  if (mode == 0) {
+    const uint32_t units = n_items * (uint32_t)c->n_img;
+    if (n_items >= RB_WALK64_PARTS_MAX_ITEMS) mode = 2;
+    else if (c->acc_sets >= RB_WALK64_PARTS) mode = 3;
+    else mode = units >= RB_WALK64_SHARED_MIN ? 2 : 1;
+  }
   const int sp = c->p.split_images;
-  if (c->n_img <= 1 || sp == 0) { c->img_split = 0; return; }
-  if (sp == 1) { c->img_split = 1; return; }
-  c->img_split = (c->p.precision == RB_FP64 && c->h_items64.size() < 16384) ? 1 : 0;
+  if (c->n_img <= 1 || sp == 0) c->img_split = 0;
+  else if (sp == 1) c->img_split = 1;
+  else c->img_split = (fp64 && mode != 3 && n_items < 16384) ? 1 : 0;
+  // parts need an accumulator set each (d_acc is sized at creation)
+  const int sets = (c->img_split ? c->n_img : 1) * RB_WALK64_PARTS;
+  if (mode == 3 && sets > c->acc_sets) mode = 2;
+  c->walk64_mode = mode;
+  c->walk_parts = (fp64 && mode == 3) ? RB_WALK64_PARTS : 1;
 }
 
 // tiles of RB_TILE slots inside each patch; walk items of `g` slots
@@ -347,7 +366,19 @@ int init_ctx(rb_ctx *c, const rb_params *p, uint32_t P, const int64_t *off, cons
   RB_TRY(dalloc(c, &c->d_large_cnt, RB_LARGE_SLOTS));
   RB_HIP(hipMemsetAsync(c->d_large_cnt, 0, 4 * RB_LARGE_SLOTS, c->stream));
   RB_HIP(hipMemsetAsync(c->d_gctr, 0, 32, c->stream));
-  RB_TRY(dalloc(c, &c->d_acc, (uint64_t)c->n_img * 3 * cap));
+  // walk results: a set of 3 * cap doubles per image (split walks) and per
+  // part of the FP64 walk's schedule 3; the sets for parts of split walks
+  // while they cost at most 2 GiB, else those of parts of whole walks
+  // while those cost at most 2 GiB more than the images' own
+  {
+    const uint64_t set_bytes = 3ull * cap * sizeof(double);
+    const uint64_t all = (uint64_t)c->n_img * RB_WALK64_PARTS;
+    const uint64_t whole = std::max<uint64_t>(c->n_img, RB_WALK64_PARTS);
+    if (all * set_bytes <= (2ull << 30)) c->acc_sets = (int)all;
+    else if ((whole - c->n_img) * set_bytes <= (2ull << 30)) c->acc_sets = (int)whole;
+    else c->acc_sets = c->n_img;
+  }
+  RB_TRY(dalloc(c, &c->d_acc, (uint64_t)c->acc_sets * 3 * cap));
   // per-call dynamic region: step counter (16 B), StepConst, schedule
   c->sched_cap = 1024;
   c->dyn_bytes = 256 + (size_t)(c->sched_cap + 1) * 2 * P * sizeof(double);

@@ -42,6 +42,11 @@ struct rb_ctx {
   uint64_t node_cap = 0;
   int n_img = 1;             // ghost images
   int img_split = 0;         // items per image (1) or all images per item (0)
+  // FP64 walk: 1 (per-lane walks), 2 (wave-shared) or 3 (wave-shared, one
+  // unit per child subtree of the root); walk_parts = 8 with 3, else 1
+  int walk64_mode = 1;
+  int walk_parts = 1;
+  int acc_sets = 1;          // sets of 3 * cap doubles that d_acc holds
 
   // host mirrors
   std::vector<uint32_t> h_starts;  // P + 1
@@ -146,7 +151,7 @@ struct rb_ctx {
   uint64_t chunk_seed = 0;  // seed of the first step of the uploaded schedule
   double *d_cgeo = nullptr;         // 4 per node: the search's cell records
   double *d_swR = nullptr, *d_swhi = nullptr;  // plane sweep: sorted radii, interval ends
-  double *d_acc = nullptr;          // (n_img or 1) * 3 * cap
+  double *d_acc = nullptr;          // acc_sets * 3 * cap
 
   // per-call dynamic region [ctr | StepConst | schedule], uploaded from a
   // pinned staging copy; schedule per step: s_half[P], s_end[P]
@@ -248,6 +253,17 @@ hipError_t launch_topo_check(rb_ctx *c, uint32_t *flag);
 hipError_t launch_moments(rb_ctx *c, const double *sx, const double *sy, const double *sz,
                           bool roots_only = false, const uint32_t *reuse = nullptr);
 hipError_t launch_rowscan_levels(rb_ctx *c, const uint32_t *reuse = nullptr);
+// walk results summed per particle: one set per image (when split) and per
+// part of the FP64 walk, in that order
+// parts of the FP64 walk's schedule 3 (the root's children)
+#define RB_WALK64_PARTS 8
+inline int rb_n_acc(const rb_ctx *c) { return (c->img_split ? c->n_img : 1) * c->walk_parts; }
+// work units from which the wave-shared FP64 walk beats per-lane walks
+#define RB_WALK64_SHARED_MIN 12288u
+// items (of 64 particles) below which the walk split by the root's children
+// beats the plain wave-shared walk (measured: 3,125 items 20% faster,
+// 10,900 items 4% slower)
+#define RB_WALK64_PARTS_MAX_ITEMS 8192u
 hipError_t launch_walk64(rb_ctx *c, const double *sx, const double *sy, const double *sz,
                          int slot);
 hipError_t launch_walk32(rb_ctx *c, const double *sx, const double *sy, const double *sz,

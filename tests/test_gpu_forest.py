@@ -132,7 +132,7 @@ def test_forest_fp64_walk_matches_oracle(orc, name, maker, leaf, n_active):
     T = orc.Tree(p, pr.x, pr.y, pr.z, pr.m, n_active=na)
     ref = T.walk(s=orc.shear_offset(p, t))
     for split in (0, 1):
-        for sched in (1, 2):
+        for sched in (1, 2, 3):
             ctx = make_ctx(pr, leaf_size=leaf, split_images=split, walk64_schedule=sched,
                            profile=2)
             try:

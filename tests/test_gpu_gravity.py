@@ -39,7 +39,7 @@ def test_fp64_walk_matches_oracle(orc, name, maker, leaf, n_active, t):
     s = orc.shear_offset(p, t)
     ref = orc.bh(p, pr.x, pr.y, pr.z, pr.m, n_active=na, s=s)
     for split in (0, 1):
-        for sched in (1, 2):  # per-lane walks, one wave-shared walk
+        for sched in (1, 2, 3):  # per-lane walks, one wave-shared walk, one per root child
             ctx = make_ctx(pr, leaf_size=leaf, split_images=split, walk64_schedule=sched)
             try:
                 a = gravity(ctx, Dev(pr, with_v=False), na, t)
@@ -54,7 +54,7 @@ def test_periodic_images(orc):
     pr = _periodic(inputs.sheet(4000, seed=6))
     p = orc.make_params(**pr.params)
     ref = orc.bh(p, pr.x, pr.y, pr.z, pr.m)
-    for sched in (1, 2):
+    for sched in (1, 2, 3):
         ctx = make_ctx(pr, walk64_schedule=sched)
         try:
             a = gravity(ctx, Dev(pr, with_v=False), pr.n)
@@ -70,7 +70,7 @@ def test_two_ghost_rings(orc):
     p = orc.make_params(**pr.params)
     s = orc.shear_offset(p, 300.0)
     ref = orc.bh(p, pr.x, pr.y, pr.z, pr.m, s=s)
-    for sched in (1, 2):
+    for sched in (1, 2, 3):
         ctx = make_ctx(pr, walk64_schedule=sched)
         try:
             a = gravity(ctx, Dev(pr, with_v=False), pr.n, 300.0)
@@ -122,7 +122,7 @@ def test_removed_and_outside_particles_get_no_force(orc):
     pr.y[6] = 1e3
     p = orc.make_params(**pr.params)
     ref = orc.bh(p, pr.x, pr.y, pr.z, pr.m)
-    for sched in (1, 2):
+    for sched in (1, 2, 3):
         ctx = make_ctx(pr, walk64_schedule=sched)
         try:
             a = gravity(ctx, Dev(pr, with_v=False), pr.n)
@@ -177,7 +177,7 @@ def test_c1_full_size_sampled(orc, theta, split):
     p = orc.make_params(**pr.params)
     tg = inputs.sample_targets(pr.n, 4096, seed=0)
     ref = orc.bh(p, pr.x, pr.y, pr.z, pr.m, s=orc.shear_offset(p, t), targets=tg)
-    for sched in (0, 1, 2):
+    for sched in (0, 1, 2, 3):
         ctx = make_ctx(pr, split_images=split, walk64_schedule=sched)
         try:
             a = gravity(ctx, Dev(pr, with_v=False), pr.n, t)
@@ -199,7 +199,7 @@ def test_c1_interaction_counts_equal_oracle(orc, theta):
     p = orc.make_params(**pr.params)
     T = orc.Tree(p, pr.x, pr.y, pr.z, pr.m)
     T.walk(s=orc.shear_offset(p, t))
-    for split, sched in ((0, 1), (1, 1), (0, 2), (1, 2)):
+    for split, sched in ((0, 1), (1, 1), (0, 2), (1, 2), (0, 3), (1, 3)):
         ctx = make_ctx(pr, profile=2, split_images=split, walk64_schedule=sched)
         try:
             d = Dev(pr, with_v=False)
