@@ -414,7 +414,7 @@ __device__ __forceinline__ void rb_wave_sync() {
 // rb_node_moments does.  With roots_only (FP32-mixed steps, where only the
 // walk's node records are read), the FP64 records are written for the run's
 // subtree roots alone: the large nodes above them read those.
-__global__ __launch_bounds__(128) void k_moments_group(
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_moments_group(
     const WalkItem *__restrict__ items, const WalkItem *__restrict__ items_mid, uint64_t wcap,
     const uint32_t *__restrict__ gctr, const uint64_t *__restrict__ key, const uint32_t *__restrict__ starts,
     const uint32_t *__restrict__ csr, const uint32_t *__restrict__ start_ids,
@@ -427,16 +427,10 @@ __global__ __launch_bounds__(128) void k_moments_group(
   // two independent waves per workgroup (fewer workgroups to dispatch),
   // each with its own LDS slice; within a wave LDS accesses stay in order,
   // so a wave-level fence orders its writes and reads
-  __shared__ double pv_all[2][4][64];   // x y z m of the group's slots
   __shared__ double vv_all[2][13][64];  // M S com Q of the last level's nodes, by leader lane
-  __shared__ uint32_t ids_all[2][RB_NLEV][64];
-  __shared__ int s_lo_all[2][65];
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  double(*pv)[64] = pv_all[wv];
   double(*vv)[64] = vv_all[wv];
-  uint32_t(*ids)[64] = ids_all[wv];
-  int *s_lo = s_lo_all[wv];
   const uint32_t n_big = gctr[2], n_mid = gctr[3], n_nodes = lev_off[RB_NLEV];
   const uint32_t n_items = n_big + n_mid + gctr[4];
   for (uint32_t gi = 2 * blockIdx.x + wv; gi < n_items; gi += 2 * gridDim.x) {
@@ -457,10 +451,8 @@ __global__ __launch_bounds__(128) void k_moments_group(
     const uint64_t k = in ? key[s] : 0ull;
     const uint64_t kf = (f > st) ? key[f - 1] : 0ull;
     const uint32_t cs = in ? csr[s] : 0u;
-    pv[0][lane] = in ? sx[s] : 0.0;
-    pv[1][lane] = in ? sy[s] : 0.0;
-    pv[2][lane] = in ? sz[s] : 0.0;
-    pv[3][lane] = in ? msrc[s] : 0.0;
+    // a leaf's particles are read from memory where the leaf is summed (the
+    // group's slots were just read into the caches)
     // c: octal digits shared with the previous slot (-1 at a patch start)
     const uint64_t kp = __shfl_up(k, 1, 64);
     int c;
@@ -484,15 +476,10 @@ __global__ __launch_bounds__(128) void k_moments_group(
     if (leaf < nvirt) leaf = nvirt;  // no leaf above the root boxes
     const int glo = c + 1;                      // first level starting at this slot
     const int lo = (lane == 0) ? l0 : c + 1;    // first such level inside the group
-    // node ids of the lane's starts
-#pragma unroll
-    for (int l = 0; l < RB_NLEV; ++l) {
-      if (in && l >= lo && l <= leaf) {
-        const uint32_t q = cs + (uint32_t)(l - glo);
-        ids[l][lane] = (q < n_nodes) ? start_ids[q] : RB_NONE;
-      }
-    }
-    s_lo[lane] = lo;
+    // the node starting at this slot at level l: start_ids[cs + l - glo]
+    // (read from the slot-major node list when the node is stored); the
+    // node after a node ending before slot `end` is the shallowest one
+    // starting at `end`, at level lo of that lane
     int lmax = in ? leaf : 0;
     for (int d = 32; d >= 1; d >>= 1) {
       const int v = __shfl_xor(lmax, d, 64);
@@ -504,6 +491,19 @@ __global__ __launch_bounds__(128) void k_moments_group(
       const uint64_t bnd = __ballot(in && lane > 0 && c < l);
       const uint64_t above = (lane < 63) ? (bnd & (~0ull << (lane + 1))) : 0ull;
       const uint32_t end = above ? (uint32_t)(__ffsll((long long)above) - 1) : cnt;
+      // the skip target's list position, from lane `end` (every lane takes
+      // part in the shuffle)
+      const int e_src = (int)(end < 64u ? end : 63u);
+      const uint32_t q_end = (uint32_t)__shfl((int)(cs + (uint32_t)(lo - glo)), e_src, 64);
+      // this node's and its first child's list positions; the reads are
+      // issued here and waited for at the store, after the sums
+      uint32_t id = RB_NONE, id_child = RB_NONE, id_skip = gskip;
+      if (lead) {
+        const uint32_t q = cs + (uint32_t)(l - glo);
+        id = (q < n_nodes) ? start_ids[q] : RB_NONE;
+        if (l < leaf) id_child = (q + 1 < n_nodes) ? start_ids[q + 1] : RB_NONE;
+        if (end < cnt) id_skip = (q_end < n_nodes) ? start_ids[q_end] : RB_NONE;
+      }
       const bool is_leaf = lead && l == leaf;
       const uint64_t nxt = (l < RB_DEPTH) ? __ballot(in && lo <= l + 1 && l + 1 <= leaf) : 0ull;
       const uint64_t span = ((end >= 64) ? ~0ull : ((1ull << end) - 1ull)) & (~0ull << lane);
@@ -512,12 +512,10 @@ __global__ __launch_bounds__(128) void k_moments_group(
       mom_zero(a);
       if (lead) {
         if (is_leaf) {
-          for (uint32_t j = lane; j < end; ++j)
-            mom_leaf_ms(a, pv[3][j], pv[0][j], pv[1][j], pv[2][j]);
-          mom_leaf_com(a, end - lane, pv[0][lane], pv[1][lane], pv[2][lane]);
+          for (uint32_t j = s; j < f + end; ++j) mom_leaf_ms(a, msrc[j], sx[j], sy[j], sz[j]);
+          mom_leaf_com(a, end - lane, sx[s], sy[s], sz[s]);
           if (quad && a.M != 0.0 && end - lane > 1)
-            for (uint32_t j = lane; j < end; ++j)
-              mom_leaf_q(a, pv[3][j], pv[0][j], pv[1][j], pv[2][j]);
+            for (uint32_t j = s; j < f + end; ++j) mom_leaf_q(a, msrc[j], sx[j], sy[j], sz[j]);
         } else {
           for (uint64_t m = kids; m; m &= m - 1) {
             const int j = __ffsll((long long)m) - 1;
@@ -539,11 +537,10 @@ __global__ __launch_bounds__(128) void k_moments_group(
         vv[4][lane] = a.c0; vv[5][lane] = a.c1; vv[6][lane] = a.c2;
         vv[7][lane] = a.Q0; vv[8][lane] = a.Q1; vv[9][lane] = a.Q2;
         vv[10][lane] = a.Q3; vv[11][lane] = a.Q4; vv[12][lane] = a.Q5;
-        const uint32_t id = ids[l][lane];
-        const uint32_t first_child = is_leaf ? s : ids[l + 1][lane];
+        const uint32_t first_child = is_leaf ? s : id_child;
         // the next node after the subtree: the shallowest node starting at
         // the slot after this node's last one
-        const uint32_t skip = (end < cnt) ? ids[s_lo[end]][end] : gskip;
+        const uint32_t skip = id_skip;
         if (id < n_nodes && (is_leaf || first_child < n_nodes)) {
           NodeLink lk;
           lk.child_or_first = first_child;
