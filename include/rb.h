@@ -124,11 +124,11 @@ typedef enum { RB_DRIFT_LEAPFROG = 0, RB_DRIFT_EPICYCLE = 1 } rb_drift;
  *  walk64_schedule  FP64 walk: 0 chooses by size, 1 every lane walks for its
  *                   own particle, 2 a wave walks once for its 64 particles
  *                   (each lane keeping its own decisions), 3 as 2 with one
- *                   wave per child subtree of the root (8x the work units
- *                   for systems of few particles; the subtrees' sums are
- *                   added in octant order afterwards, so only their
- *                   rounding differs; a context whose accumulators for
- *                   this would exceed 2 GiB runs 2).  All visit, per
+ *                   wave per subtree two levels below the root (64x the
+ *                   work units for systems of few particles; the subtrees'
+ *                   sums are added in octant order afterwards, so only
+ *                   their rounding differs; a context whose accumulators
+ *                   for this would exceed 2 GiB runs 2).  All visit, per
  *                   particle, the same nodes; only the speed differs.
  */
 typedef struct {

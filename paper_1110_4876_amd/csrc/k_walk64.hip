@@ -127,7 +127,7 @@ __device__ __forceinline__ uint32_t w64_uniform(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
-template <bool QUAD, bool STATS, bool PARTS>
+template <bool QUAD, bool STATS, int PD>
 __global__ __launch_bounds__(256) void k_walk64(
     const WalkItem *__restrict__ items, uint32_t n_items, int img_split, int n_img, int parts,
     int ngx, int ngy, int boundary, const PatchInfo *__restrict__ patch,
@@ -152,15 +152,15 @@ __global__ __launch_bounds__(256) void k_walk64(
   const uint32_t vb = x * q + (x < r ? x : r) + (b >> 3);
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t unit = vb * 4u + (threadIdx.x >> 6);  // one unit per wave
-  // a unit: a part, an item and its image (when split).  With parts > 1
-  // part k walks the subtree of the root's child k only (the root itself is
-  // tested by every part, its term added by part 0), so a system of few
-  // items still gives many units, each with a short chain of node loads;
-  // every particle still sees each node once, and the parts' sums are added
-  // in order afterwards.  Units are part-major: neighbouring waves (and an
+  // a unit: a part, an item and its image (when split).  With parts, each
+  // part walks one subtree two levels below the root (64 parts), so a
+  // system of few items still gives many units, each with a short chain of
+  // node loads; every particle still sees each node once, and the parts'
+  // sums are added in order afterwards.  Units are part-major: neighbouring waves (and an
   // XCD's range) walk the same subtree for neighbouring particles and share
   // its node records in the caches.
-  const uint32_t np = PARTS ? (uint32_t)parts : 1u;
+  // PD levels below the root are split: 8^PD parts (parts == 8^PD)
+  const uint32_t np = PD ? (uint32_t)parts : 1u;
   const uint32_t per_part = n_items * (img_split ? (uint32_t)n_img : 1u);
   const uint32_t n_units = per_part * np;
   if (unit >= n_units) return;  // whole waves
@@ -197,45 +197,68 @@ __global__ __launch_bounds__(256) void k_walk64(
     // lane k holds the mask of the lanes working on nodes of level k
     uint64_t lvm = (lane == 0) ? live : 0ull;
     uint32_t cur = r0, visits = 0;
-    // with parts, part k walks from the root (k = 0, which also adds the
-    // root's own terms) or from the root's child k (k > 0, after testing the
-    // root for its lanes here) and stops at child k + 1: in depth-first
-    // order a child's subtree ends where the next child starts (children
-    // are numbered consecutively)
+    // With parts, the octal digits of part k name a path below the root:
+    // k = c (PD = 1) walks the subtree of the root's child c, k = 8 c + g
+    // (PD = 2) that of grandchild g of child c.  Before that the part tests
+    // the nodes on the path for its lanes (only the lanes that opened them
+    // go on); a node's own terms belong to the first part below it (part 0
+    // for the root, 8 c for child c), as does a leaf on the path (walked
+    // below).  A part stops where its subtree ends: at the next sibling
+    // (children are numbered consecutively, and in depth-first order a
+    // subtree ends where the next sibling starts), or after the parent's
+    // subtree for the last child.
     uint32_t stop = RB_NONE;
-    if (PARTS && cur != RB_NONE) {
-      if (cur >= n_nodes) {
-        if (lane == 0) atomicOr(err, RB_ERR_TREE);
-        cur = RB_NONE;
-      } else {
+    if (PD > 0 && cur != RB_NONE) {
+      const uint32_t digit[2] = {PD == 2 ? (uint32_t)part >> 3 : (uint32_t)part,
+                                 (uint32_t)part & 7u};
+      uint32_t v = cur, after = RB_NONE;
+      uint64_t act = live;
+      cur = RB_NONE;
+#pragma unroll
+      for (int depth = 0; depth < PD; ++depth) {
+        if (v >= n_nodes) {
+          if (lane == 0) atomicOr(err, RB_ERR_TREE);
+          break;
+        }
         W64Rec rc;
-        w64_fetch(link, mcom, cur, rc);
+        w64_fetch(link, mcom, v, rc);
         const int l = (int)(rc.lvl & 255u);
         const uint32_t n_child = rc.lvl >> 9;
-        const bool inner = (rc.lvl & 256u) == 0 && rc.m != 0.0 && l < RB_DEPTH;
-        uint64_t opened = 0ull;
-        if (inner) {
-          const double d0 = rc.cx - y0, d1 = rc.cy - y1, d2 = rc.cz - y2;
-          const double R2 = __builtin_fma(d2, d2, __builtin_fma(d1, d1, d0 * d0));
-          const bool take = valid && l >= nvirt && (ldexp(W2, -2 * l) < theta2 * R2);
-          opened = live & ~__ballot(take);
+        const bool owner = depth == 0 ? part == 0 : digit[1] == 0u;
+        if (rc.m == 0.0 || l > RB_DEPTH) break;
+        if ((rc.lvl & 256u) != 0u) {  // a leaf: its owner walks it
+          if (owner) { cur = v; stop = after; }
+          break;
         }
-        const uint32_t k = (uint32_t)part;
-        stop = (inner && k + 1 < n_child) ? rc.child + k + 1 : RB_NONE;
-        if (part > 0) {
-          if (inner && opened != 0ull && k < n_child) {
-            if (lane == (uint32_t)(l + 1)) lvm = opened;
-            cur = rc.child + k;
-          } else {
-            cur = RB_NONE;
+        const bool me = ((act >> lane) & 1ull) != 0;
+        const double d0 = rc.cx - y0, d1 = rc.cy - y1, d2 = rc.cz - y2;
+        const double R2 = __builtin_fma(d2, d2, __builtin_fma(d1, d1, d0 * d0));
+        const bool root_or_below = l >= nvirt;
+        const bool take = me && root_or_below && (ldexp(W2, -2 * l) < theta2 * R2);
+        const uint64_t opened = act & ~__ballot(take);
+        if (owner) {
+          if (STATS && me && root_or_below) ++n_open;
+          if (take) {
+            const w64_dbl_p qn = Qarr + 6 * (size_t)v;
+            const double q[6] = {qn[0], qn[1], qn[2], qn[3], qn[4], qn[5]};
+            w64_cell<QUAD>(G, G * rc.m, q, d0, d1, d2, R2 + b2, ax, ay, az);
+            if (STATS) ++n_cell;
           }
         }
+        const uint32_t dg = digit[depth];
+        if (opened == 0ull || dg >= n_child || l >= RB_DEPTH) break;
+        const uint32_t w = rc.child + dg;
+        after = (dg + 1u < n_child) ? w + 1u : rc.skip;
+        if (lane == (uint32_t)(l + 1)) lvm = opened;
+        act = opened;
+        v = w;
+        if (depth == PD - 1) { cur = w; stop = after; }
       }
     }
     // the node in hand: NodeLink {child_or_first, skip, count, lvl} and
     // double4 {com, M}, read with scalar loads; the other waves on the SIMD
     // cover their latency
-    while (cur != RB_NONE && (!PARTS || cur != stop)) {
+    while (cur != RB_NONE && (PD == 0 || cur != stop)) {
       if (cur >= n_nodes || ++visits > n_nodes) {
         if (lane == 0) atomicOr(err, RB_ERR_TREE);
         break;
@@ -453,17 +476,17 @@ hipError_t launch_walk64(rb_ctx *c, const double *sx, const double *sy, const do
       c->d_msrc, c->d_sched, c->d_ctr, c->P, c->p.G, b2, th2, c->d_acc, c->cap,           \
       c->d_stats, c->d_lev_off, c->d_err, slot
     const dim3 g(grid), bl(256);
-    if (parts > 1) {
-      if (quad && stats) hipLaunchKernelGGL((k_walk64<true, true, true>), g, bl, 0, c->stream, RB_WALK64_ARGS);
-      else if (quad) hipLaunchKernelGGL((k_walk64<true, false, true>), g, bl, 0, c->stream, RB_WALK64_ARGS);
-      else if (stats) hipLaunchKernelGGL((k_walk64<false, true, true>), g, bl, 0, c->stream, RB_WALK64_ARGS);
-      else hipLaunchKernelGGL((k_walk64<false, false, true>), g, bl, 0, c->stream, RB_WALK64_ARGS);
-    } else {
-      if (quad && stats) hipLaunchKernelGGL((k_walk64<true, true, false>), g, bl, 0, c->stream, RB_WALK64_ARGS);
-      else if (quad) hipLaunchKernelGGL((k_walk64<true, false, false>), g, bl, 0, c->stream, RB_WALK64_ARGS);
-      else if (stats) hipLaunchKernelGGL((k_walk64<false, true, false>), g, bl, 0, c->stream, RB_WALK64_ARGS);
-      else hipLaunchKernelGGL((k_walk64<false, false, false>), g, bl, 0, c->stream, RB_WALK64_ARGS);
-    }
+#define RB_W64_LAUNCH(PD)                                                                          \
+  do {                                                                                             \
+    if (quad && stats) hipLaunchKernelGGL((k_walk64<true, true, PD>), g, bl, 0, c->stream, RB_WALK64_ARGS);   \
+    else if (quad) hipLaunchKernelGGL((k_walk64<true, false, PD>), g, bl, 0, c->stream, RB_WALK64_ARGS);      \
+    else if (stats) hipLaunchKernelGGL((k_walk64<false, true, PD>), g, bl, 0, c->stream, RB_WALK64_ARGS);     \
+    else hipLaunchKernelGGL((k_walk64<false, false, PD>), g, bl, 0, c->stream, RB_WALK64_ARGS);               \
+  } while (0)
+    if (parts == 64) RB_W64_LAUNCH(2);
+    else if (parts == 8) RB_W64_LAUNCH(1);
+    else RB_W64_LAUNCH(0);
+#undef RB_W64_LAUNCH
 #undef RB_WALK64_ARGS
     return hipGetLastError();
   }

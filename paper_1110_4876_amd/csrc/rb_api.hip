@@ -164,10 +164,12 @@ void set_split(rb_ctx *c) {
   else if (sp == 1) c->img_split = 1;
   else c->img_split = (fp64 && mode != 3 && n_items < 16384) ? 1 : 0;
   // parts need an accumulator set each (d_acc is sized at creation)
-  const int sets = (c->img_split ? c->n_img : 1) * RB_WALK64_PARTS;
-  if (mode == 3 && sets > c->acc_sets) mode = 2;
+  const int per = c->img_split ? c->n_img : 1;
+  int parts = (n_items < RB_WALK64_PARTS2_MAX_ITEMS) ? RB_WALK64_PARTS2 : RB_WALK64_PARTS;
+  if (per * parts > c->acc_sets) parts = RB_WALK64_PARTS;
+  if (mode == 3 && per * parts > c->acc_sets) mode = 2;
   c->walk64_mode = mode;
-  c->walk_parts = (fp64 && mode == 3) ? RB_WALK64_PARTS : 1;
+  c->walk_parts = (fp64 && mode == 3) ? parts : 1;
 }
 
 // tiles of RB_TILE slots inside each patch; walk items of `g` slots
@@ -367,16 +369,17 @@ int init_ctx(rb_ctx *c, const rb_params *p, uint32_t P, const int64_t *off, cons
   RB_HIP(hipMemsetAsync(c->d_large_cnt, 0, 4 * RB_LARGE_SLOTS, c->stream));
   RB_HIP(hipMemsetAsync(c->d_gctr, 0, 32, c->stream));
   // walk results: a set of 3 * cap doubles per image (split walks) and per
-  // part of the FP64 walk's schedule 3; the sets for parts of split walks
-  // while they cost at most 2 GiB, else those of parts of whole walks
-  // while those cost at most 2 GiB more than the images' own
+  // part of the FP64 walk's schedule 3; the first of these that costs at
+  // most 2 GiB more than the images' own: 64 parts of split walks, 64 parts
+  // of whole walks, 8 parts of split walks, 8 parts of whole walks
   {
-    const uint64_t set_bytes = 3ull * cap * sizeof(double);
-    const uint64_t all = (uint64_t)c->n_img * RB_WALK64_PARTS;
-    const uint64_t whole = std::max<uint64_t>(c->n_img, RB_WALK64_PARTS);
-    if (all * set_bytes <= (2ull << 30)) c->acc_sets = (int)all;
-    else if ((whole - c->n_img) * set_bytes <= (2ull << 30)) c->acc_sets = (int)whole;
-    else c->acc_sets = c->n_img;
+    const uint64_t set_bytes = 3ull * cap * sizeof(double), budget = 2ull << 30;
+    const uint64_t ni = (uint64_t)c->n_img;
+    const uint64_t cand[4] = {ni * RB_WALK64_PARTS2, std::max<uint64_t>(ni, RB_WALK64_PARTS2),
+                              ni * RB_WALK64_PARTS, std::max<uint64_t>(ni, RB_WALK64_PARTS)};
+    c->acc_sets = (int)ni;
+    for (uint64_t k : cand)
+      if ((k - ni) * set_bytes <= budget) { c->acc_sets = (int)k; break; }
   }
   RB_TRY(dalloc(c, &c->d_acc, (uint64_t)c->acc_sets * 3 * cap));
   // per-call dynamic region: step counter (16 B), StepConst, schedule

@@ -242,3 +242,35 @@ def test_c1_snapshots_along_a_run(orc):
             assert err.max() <= 1e-10, (upto, err.max())
     finally:
         rb.rb_destroy(ctx)
+
+
+@pytest.mark.parametrize("n", [20000, 80000])
+def test_parts_schedule_matches_oracle(orc, n):
+    # schedule 3 splits the walk by subtrees below the root: 64 parts for
+    # 20,000 particles (313 items), 8 parts for 80,000 (1,250 items).  Every
+    # particle still makes the oracle walk's decisions: its accelerations
+    # agree to rounding and the interaction counts are equal.
+    import torch
+    from gpu_util import Dev, make_ctx, rms_rel
+    from paper_1110_4876_amd import rb
+    pr = inputs.sheet(n, seed=3).with_params(theta=0.3)
+    t = 0.5 * pr.dt
+    p = orc.make_params(**pr.params)
+    s = orc.shear_offset(p, t)
+    T = orc.Tree(p, pr.x, pr.y, pr.z, pr.m)
+    T.walk(s=s)
+    tg = inputs.sample_targets(pr.n, 2048, seed=4)
+    ref = orc.bh(p, pr.x, pr.y, pr.z, pr.m, s=s, targets=tg)
+    ctx = make_ctx(pr, profile=2, split_images=0, walk64_schedule=3)
+    try:
+        d = Dev(pr, with_v=False)
+        ax = torch.empty(pr.n, dtype=torch.float64, device="cuda")
+        ay, az = torch.empty_like(ax), torch.empty_like(ax)
+        rb.rb_gravity(ctx, d.parts, pr.n, pr.n, t, ax, ay, az)
+        st = rb.rb_stats(ctx)
+        a = torch.stack([ax, ay, az], dim=1).cpu().numpy()
+    finally:
+        rb.rb_destroy(ctx)
+    assert rms_rel(a[tg], ref) <= TOL_BH, rms_rel(a[tg], ref)
+    for k in ("open_tests", "cells", "pp"):
+        assert st[k] == T.stats[k], (k, st[k], T.stats[k])
