@@ -428,9 +428,11 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
   // each with its own LDS slice; within a wave LDS accesses stay in order,
   // so a wave-level fence orders its writes and reads
   __shared__ double vv_all[2][13][64];  // M S com Q of the last level's nodes, by leader lane
+  __shared__ double pv_all[2][4][64];   // x y z m of the group's slots
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   double(*vv)[64] = vv_all[wv];
+  double(*pv)[64] = pv_all[wv];
   const uint32_t n_big = gctr[2], n_mid = gctr[3], n_nodes = lev_off[RB_NLEV];
   const uint32_t n_items = n_big + n_mid + gctr[4];
   for (uint32_t gi = 2 * blockIdx.x + wv; gi < n_items; gi += 2 * gridDim.x) {
@@ -451,8 +453,10 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     const uint64_t k = in ? key[s] : 0ull;
     const uint64_t kf = (f > st) ? key[f - 1] : 0ull;
     const uint32_t cs = in ? csr[s] : 0u;
-    // a leaf's particles are read from memory where the leaf is summed (the
-    // group's slots were just read into the caches)
+    pv[0][lane] = in ? sx[s] : 0.0;
+    pv[1][lane] = in ? sy[s] : 0.0;
+    pv[2][lane] = in ? sz[s] : 0.0;
+    pv[3][lane] = in ? msrc[s] : 0.0;
     // c: octal digits shared with the previous slot (-1 at a patch start)
     const uint64_t kp = __shfl_up(k, 1, 64);
     int c;
@@ -477,15 +481,21 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     const int glo = c + 1;                      // first level starting at this slot
     const int lo = (lane == 0) ? l0 : c + 1;    // first such level inside the group
     // the node starting at this slot at level l: start_ids[cs + l - glo]
-    // (read from the slot-major node list when the node is stored); the
-    // node after a node ending before slot `end` is the shallowest one
-    // starting at `end`, at level lo of that lane
+    // (the slot-major node list); the node after a node ending before slot
+    // `end` is the shallowest one starting at `end`, at level lo of that lane
     int lmax = in ? leaf : 0;
     for (int d = 32; d >= 1; d >>= 1) {
       const int v = __shfl_xor(lmax, d, 64);
       lmax = v > lmax ? v : lmax;
     }
     rb_wave_sync();
+    // this lane's node id at the level in hand, read one level ahead; its
+    // node one level deeper (the first child) is the last level's id
+    uint32_t id_ahead = RB_NONE, id_below = RB_NONE;
+    if (in && lo <= lmax && lmax <= leaf) {
+      const uint32_t q = cs + (uint32_t)(lmax - glo);
+      id_ahead = (q < n_nodes) ? start_ids[q] : RB_NONE;
+    }
     for (int l = lmax; l >= l0; --l) {
       const bool lead = in && lo <= l && l <= leaf;
       const uint64_t bnd = __ballot(in && lane > 0 && c < l);
@@ -495,14 +505,20 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
       // part in the shuffle)
       const int e_src = (int)(end < 64u ? end : 63u);
       const uint32_t q_end = (uint32_t)__shfl((int)(cs + (uint32_t)(lo - glo)), e_src, 64);
-      // this node's and its first child's list positions; the reads are
-      // issued here and waited for at the store, after the sums
+      // this node's id (read one level ahead), its first child's (this
+      // lane's node one level deeper) and the skip target's (read here,
+      // waited for at the store, after the sums)
       uint32_t id = RB_NONE, id_child = RB_NONE, id_skip = gskip;
       if (lead) {
-        const uint32_t q = cs + (uint32_t)(l - glo);
-        id = (q < n_nodes) ? start_ids[q] : RB_NONE;
-        if (l < leaf) id_child = (q + 1 < n_nodes) ? start_ids[q + 1] : RB_NONE;
+        id = id_ahead;
+        if (l < leaf) id_child = id_below;
         if (end < cnt) id_skip = (q_end < n_nodes) ? start_ids[q_end] : RB_NONE;
+      }
+      id_below = id;
+      id_ahead = RB_NONE;
+      if (in && lo <= l - 1 && l - 1 <= leaf && l - 1 >= l0) {
+        const uint32_t q = cs + (uint32_t)(l - 1 - glo);
+        id_ahead = (q < n_nodes) ? start_ids[q] : RB_NONE;
       }
       const bool is_leaf = lead && l == leaf;
       const uint64_t nxt = (l < RB_DEPTH) ? __ballot(in && lo <= l + 1 && l + 1 <= leaf) : 0ull;
@@ -512,10 +528,10 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
       mom_zero(a);
       if (lead) {
         if (is_leaf) {
-          for (uint32_t j = s; j < f + end; ++j) mom_leaf_ms(a, msrc[j], sx[j], sy[j], sz[j]);
-          mom_leaf_com(a, end - lane, sx[s], sy[s], sz[s]);
+          for (uint32_t j = lane; j < end; ++j) mom_leaf_ms(a, pv[3][j], pv[0][j], pv[1][j], pv[2][j]);
+          mom_leaf_com(a, end - lane, pv[0][lane], pv[1][lane], pv[2][lane]);
           if (quad && a.M != 0.0 && end - lane > 1)
-            for (uint32_t j = s; j < f + end; ++j) mom_leaf_q(a, msrc[j], sx[j], sy[j], sz[j]);
+            for (uint32_t j = lane; j < end; ++j) mom_leaf_q(a, pv[3][j], pv[0][j], pv[1][j], pv[2][j]);
         } else {
           for (uint64_t m = kids; m; m &= m - 1) {
             const int j = __ffsll((long long)m) - 1;
