@@ -127,8 +127,11 @@ __device__ __forceinline__ uint32_t w64_uniform(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
+// One wave per workgroup: a wave's slot on the CU is refilled as soon as it
+// ends (with four waves per workgroup the slot waits for the slowest of the
+// four; measured 2.6-5% slower).
 template <bool QUAD, bool STATS, int PD>
-__global__ __launch_bounds__(256) void k_walk64(
+__global__ __launch_bounds__(64) void k_walk64(
     const WalkItem *__restrict__ items, uint32_t n_items, int img_split, int n_img, int parts,
     int ngx, int ngy, int boundary, const PatchInfo *__restrict__ patch,
     const uint32_t *__restrict__ nlive, const uint32_t *__restrict__ root,
@@ -151,12 +154,12 @@ __global__ __launch_bounds__(256) void k_walk64(
   const uint32_t q = nb >> 3, r = nb & 7u, x = b & 7u;
   const uint32_t vb = x * q + (x < r ? x : r) + (b >> 3);
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t unit = vb * 4u + (threadIdx.x >> 6);  // one unit per wave
+  const uint32_t unit = vb;  // one unit per wave
   // a unit: a part, an item and its image (when split).  With parts, each
-  // part walks one subtree two levels below the root (64 parts), so a
-  // system of few items still gives many units, each with a short chain of
-  // node loads; every particle still sees each node once, and the parts'
-  // sums are added in order afterwards.  Units are part-major: neighbouring waves (and an
+  // part walks one subtree one or two levels below the root (8 or 64
+  // parts), so a system of few items still gives many units, each with a
+  // short chain of node loads; every particle still sees each node once,
+  // and the parts' sums are added in order afterwards.  Units are part-major: neighbouring waves (and an
   // XCD's range) walk the same subtree for neighbouring particles and share
   // its node records in the caches.
   // PD levels below the root are split: 8^PD parts (parts == 8^PD)
@@ -468,14 +471,14 @@ hipError_t launch_walk64(rb_ctx *c, const double *sx, const double *sy, const do
   const bool quad = c->p.quadrupole != 0, stats = (c->p.profile & 2) != 0;
   if (c->walk64_mode != 1) {
     const int parts = c->walk_parts;
-    const unsigned grid = (units * (uint32_t)parts + 3u) / 4u;  // four waves (units) per workgroup
+    const unsigned grid = units * (uint32_t)parts;  // one unit per wave and workgroup
 #define RB_WALK64_ARGS                                                                     \
   c->d_items64, n_items, split, c->n_img, parts, c->p.n_ghost[0], c->p.n_ghost[1],          \
       c->p.boundary,                                                                       \
       c->d_patch, c->d_nlive, c->d_root, c->d_link, c->d_mcom, c->d_Q, sx, sy, sz,         \
       c->d_msrc, c->d_sched, c->d_ctr, c->P, c->p.G, b2, th2, c->d_acc, c->cap,           \
       c->d_stats, c->d_lev_off, c->d_err, slot
-    const dim3 g(grid), bl(256);
+    const dim3 g(grid), bl(64);
 #define RB_W64_LAUNCH(PD)                                                                          \
   do {                                                                                             \
     if (quad && stats) hipLaunchKernelGGL((k_walk64<true, true, PD>), g, bl, 0, c->stream, RB_WALK64_ARGS);   \
