@@ -300,17 +300,26 @@ __global__ __launch_bounds__(256) void k_rowscan(uint32_t *__restrict__ data, ui
   const uint32_t r = blockIdx.x, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const size_t base = (size_t)r * n_tiles;
   uint32_t carry = 0;
-  for (uint32_t off = 0; off < n_tiles; off += 256) {
-    const uint32_t i = off + tid;
-    const uint32_t v = (i < n_tiles) ? data[base + i] : 0u;
-    const uint32_t incl = rb_wave_incl_scan(v);
+  // 1024 entries per round: four consecutive ones per thread, summed in the
+  // thread, then the threads' totals scanned across the block
+  for (uint32_t off = 0; off < n_tiles; off += 1024) {
+    const uint32_t i0 = off + 4 * tid;
+    uint32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = (i0 + k < n_tiles) ? data[base + i0 + k] : 0u;
+    const uint32_t s1 = v[0], s2 = s1 + v[1], s3 = s2 + v[2], s4 = s3 + v[3];
+    const uint32_t incl = rb_wave_incl_scan(s4);
     if (lane == 63) wsum[w] = incl;
     __syncthreads();
     uint32_t add = 0;
     for (uint32_t q = 0; q < w; ++q) add += wsum[q];
     const uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
     __syncthreads();
-    if (i < n_tiles) data[base + i] = carry + add + incl - v;
+    const uint32_t ex = carry + add + incl - s4;  // before the thread's first entry
+    const uint32_t out[4] = {ex, ex + s1, ex + s2, ex + s3};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (i0 + k < n_tiles) data[base + i0 + k] = out[k];
     carry += tot;
   }
   if (tid == 0) row_tot[r] = carry;

@@ -12,7 +12,7 @@
 #define RB_NONE 0xFFFFFFFFu                // absent node / end of walk
 #define RB_KEY_DEAD 0xFFFFFFFFFFFFFFFFull  // key of a removed / outside particle
 #define RB_TILE_MIN 64                     // slots per topology tile
-#define RB_TILE_MAX 1024
+#define RB_TILE_MAX 512
 #define RB_MAX_IMAGES 25                   // (2*2+1)^2 for two ghost rings
 
 // device error word bits (reported by the next synchronising call)
