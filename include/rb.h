@@ -121,7 +121,8 @@ typedef enum { RB_DRIFT_LEAPFROG = 0, RB_DRIFT_EPICYCLE = 1 } rb_drift;
  *                   only the moments are recomputed bottom-up; otherwise the
  *                   tree is rebuilt.  Same results either way; rb_stats
  *                   counts the reused steps.  0: rebuild every step.
- *  walk64_schedule  FP64 walk: 0 chooses by size, 1 every lane walks for its
+ *  walk64_schedule  FP64 walk: 0 chooses (3 when the accumulators allow it,
+ *                   else 2 or 1 by size), 1 every lane walks for its
  *                   own particle, 2 a wave walks once for its 64 particles
  *                   (each lane keeping its own decisions), 3 as 2 with one
  *                   wave per subtree two levels below the root (64x the

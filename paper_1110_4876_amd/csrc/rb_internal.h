@@ -265,10 +265,6 @@ hipError_t launch_rowscan_levels(rb_ctx *c, const uint32_t *reuse = nullptr);
 inline int rb_n_acc(const rb_ctx *c) { return (c->img_split ? c->n_img : 1) * c->walk_parts; }
 // work units from which the wave-shared FP64 walk beats per-lane walks
 #define RB_WALK64_SHARED_MIN 12288u
-// items (of 64 particles) below which the walk split by the root's children
-// beats the plain wave-shared walk (measured: 3,125 items 20% faster,
-// 10,900 items 4% slower)
-#define RB_WALK64_PARTS_MAX_ITEMS 8192u
 hipError_t launch_walk64(rb_ctx *c, const double *sx, const double *sy, const double *sz,
                          int slot);
 hipError_t launch_walk32(rb_ctx *c, const double *sx, const double *sy, const double *sz,
