@@ -12,12 +12,12 @@
 // and walks the tree once for all of them.  The node in hand is the same
 // for the whole wave, so its record is read with scalar loads; each lane
 // tests it against its own particle.  A lane takes part in a node only if
-// it opened every ancestor of that node: the lanes that opened a node at
-// level l are kept as a 64-bit mask for level l + 1 (lane k of a vector
-// register holds the mask of level k), and a node at level l is worked on
-// by the lanes of mask l.  Lanes that accept a cell add its monopole (and
-// quadrupole) term; the wave descends to the children when any lane opened
-// it and moves on to the next node after the subtree otherwise.  Every lane
+// it opened every ancestor of that node; each lane keeps the deepest level
+// down to which it did so along the current path, and a node of level l is
+// its when that level is at least l.  Lanes that accept a cell add its
+// monopole (and quadrupole) term; the wave descends to the children when
+// any lane opened it and moves on to the next node after the subtree
+// otherwise.  Every lane
 // thus sees exactly the nodes, in exactly the order, that its own
 // stackless walk (child link when opening, skip link otherwise) would.
 // k_walk64_lane (few work units, where the wave's single chain of dependent
@@ -102,12 +102,6 @@ __device__ __forceinline__ void rb_image(int im, int ngx, int ngy, int boundary,
 // uniform over the wave, so these become scalar loads.
 typedef __attribute__((address_space(4))) const uint32_t *w64_u32_p;
 typedef __attribute__((address_space(4))) const double *w64_dbl_p;
-
-__device__ __forceinline__ uint64_t w64_readlane(uint64_t v, int l) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
-  return ((uint64_t)hi << 32) | lo;
-}
 
 // a node's walk record, in scalar registers
 struct W64Rec {
@@ -197,8 +191,6 @@ __global__ __launch_bounds__(64) void k_walk64(
     rb_image(im, ngx, ngy, boundary, patch[p].L[0], patch[p].L[1], shear, ox, oy, self);
     const double y0 = px - ox, y1 = py - oy, y2 = pz;
     double ax = 0.0, ay = 0.0, az = 0.0;
-    // lane k holds the mask of the lanes working on nodes of level k
-    uint64_t lvm = (lane == 0) ? live : 0ull;
     uint32_t cur = r0, visits = 0;
     // With parts, the octal digits of part k name a path below the root:
     // k = c (PD = 1) walks the subtree of the root's child c, k = 8 c + g
@@ -211,6 +203,8 @@ __global__ __launch_bounds__(64) void k_walk64(
     // subtree ends where the next sibling starts), or after the parent's
     // subtree for the last child.
     uint32_t stop = RB_NONE;
+    uint64_t act0 = live;  // lanes active at the start node, and its level
+    int l0 = 0;
     if (PD > 0 && cur != RB_NONE) {
       const uint32_t digit[2] = {PD == 2 ? (uint32_t)part >> 3 : (uint32_t)part,
                                  (uint32_t)part & 7u};
@@ -230,7 +224,7 @@ __global__ __launch_bounds__(64) void k_walk64(
         const bool owner = depth == 0 ? part == 0 : digit[1] == 0u;
         if (rc.m == 0.0 || l > RB_DEPTH) break;
         if ((rc.lvl & 256u) != 0u) {  // a leaf: its owner walks it
-          if (owner) { cur = v; stop = after; }
+          if (owner) { cur = v; stop = after; act0 = act; l0 = l; }
           break;
         }
         const bool me = ((act >> lane) & 1ull) != 0;
@@ -252,78 +246,103 @@ __global__ __launch_bounds__(64) void k_walk64(
         if (opened == 0ull || dg >= n_child || l >= RB_DEPTH) break;
         const uint32_t w = rc.child + dg;
         after = (dg + 1u < n_child) ? w + 1u : rc.skip;
-        if (lane == (uint32_t)(l + 1)) lvm = opened;
         act = opened;
         v = w;
-        if (depth == PD - 1) { cur = w; stop = after; }
+        if (depth == PD - 1) { cur = w; stop = after; act0 = opened; l0 = l + 1; }
       }
     }
+    // A lane works on a node of level l when it opened every ancestor of
+    // the node.  Along the path from the root to the node in hand those are
+    // the levels 0..a of a prefix, and alev holds a (below the start node's
+    // level when the lane takes no part): a node of level l is the lane's
+    // when alev >= l.  When the wave descends from a node of level l, the
+    // lanes working on it set alev to l + 1 if they opened it and to l if
+    // they did not; nothing else changes alev.  A lane that opened the
+    // parent of a node keeps alev >= its level through the earlier
+    // siblings' subtrees (every change there sets alev to a deeper level),
+    // and one that did not never works below the parent, so alev >= l
+    // is exactly the rule.
+    int alev = ((act0 >> lane) & 1ull) ? l0 : -1;
     // the node in hand: NodeLink {child_or_first, skip, count, lvl} and
     // double4 {com, M}, read with scalar loads; the other waves on the SIMD
-    // cover their latency
-    while (cur != RB_NONE && (PD == 0 || cur != stop)) {
-      if (cur >= n_nodes || ++visits > n_nodes) {
-        if (lane == 0) atomicOr(err, RB_ERR_TREE);
-        break;
-      }
+    // cover their latency.  A walk ends at its stop node (RB_NONE for the
+    // whole tree); an index past the node count before that, or more
+    // visits than nodes, mean inconsistent links.
+    while (cur != stop && max(cur, visits) < n_nodes) {
+      ++visits;
       W64Rec rc;
       w64_fetch(link, mcom, cur, rc);
-      const uint32_t l_child = rc.child, l_skip = rc.skip, l_count = rc.count, l_lvl = rc.lvl;
-      const double cx = rc.cx, cy = rc.cy, cz = rc.cz, cm = rc.m;
-      const bool internal = (l_lvl & 256u) == 0;
-      double q00 = 0.0, q01 = 0.0, q02 = 0.0, q11 = 0.0, q12 = 0.0, q22 = 0.0;
-      if (QUAD && !(l_count == 1 && !internal)) {
-        const w64_dbl_p qn = Qarr + 6 * (size_t)cur;
-        q00 = qn[0]; q01 = qn[1]; q02 = qn[2]; q11 = qn[3]; q12 = qn[4]; q22 = qn[5];
-      }
-      uint32_t next = l_skip;
-      const int l = (int)(l_lvl & 255u);
-      if (cm != 0.0 && l <= RB_DEPTH) {
-        const uint64_t act = w64_readlane(lvm, l);
-        const bool me = ((act >> lane) & 1ull) != 0;
-        const bool leaf = (l_lvl & 256u) != 0;
-        if (leaf && l_count == 1) {
-          if (me && !(self && l_child == s)) {
-            const double d0 = cx - y0, d1 = cy - y1, d2 = cz - y2;
-            w64_mono(G * cm, d0, d1, d2, w64_r2(d0, d1, d2, b2), ax, ay, az);
-            if (STATS) ++n_pp;
-          }
+      const uint32_t lv = rc.lvl;
+      const int l = (int)(lv & 255u);
+      const bool leaf = (lv & 256u) != 0;
+      const double d0 = rc.cx - y0, d1 = rc.cy - y1, d2 = rc.cz - y2;
+      uint32_t next = rc.skip;
+      if (rc.m != 0.0) {
+        const bool me = alev >= l;
+        const bool single = leaf && rc.count == 1;
+        // a single-particle leaf is taken by every lane but its own
+        // particle's; a cell below the root boxes by the lanes it passes
+        bool take;
+        double rho2;
+        uint64_t opened = 0ull;
+        if (single) {
+          take = me && !(self && rc.child == s);
+          rho2 = w64_r2(d0, d1, d2, b2);
         } else {
-          const double d0 = cx - y0, d1 = cy - y1, d2 = cz - y2;
           const double R2 = __builtin_fma(d2, d2, __builtin_fma(d1, d1, d0 * d0));
           // cells above the root boxes are always opened
           const bool root_or_below = l >= nvirt;
-          const bool take = me && root_or_below && (ldexp(W2, -2 * l) < theta2 * R2);
-          const uint64_t opened = act & ~__ballot(take);
+          take = me && root_or_below && (ldexp(W2, -2 * l) < theta2 * R2);
+          opened = __ballot(me && !take);
+          rho2 = R2 + b2;
           if (STATS && me && root_or_below) ++n_open;
-          if (take) {
-            const double q[6] = {q00, q01, q02, q11, q12, q22};
-            w64_cell<QUAD>(G, G * cm, q, d0, d1, d2, R2 + b2, ax, ay, az);
-            if (STATS) ++n_cell;
+        }
+        if (take) {
+          // one body for both: a single-particle leaf's quadrupole is
+          // exactly zero (the build adds none for one particle), and with
+          // Q d = 0 and d.Q.d = 0 the cell's terms reduce exactly to the
+          // point mass's G M d / rho^3
+          const double ri = rb_rsqrt64(rho2);
+          const double u = ri * ri, g = ri * u;
+          double e0 = 0.0, e1 = 0.0, e2 = 0.0, dqd = 0.0;
+          if (QUAD) {
+            const w64_dbl_p qn = Qarr + 6 * (size_t)cur;
+            const double q0 = qn[0], q1 = qn[1], q2 = qn[2], q3 = qn[3], q4 = qn[4], q5 = qn[5];
+            e0 = __builtin_fma(q0, d0, __builtin_fma(q1, d1, q2 * d2));
+            e1 = __builtin_fma(q1, d0, __builtin_fma(q3, d1, q4 * d2));
+            e2 = __builtin_fma(q2, d0, __builtin_fma(q4, d1, q5 * d2));
+            dqd = __builtin_fma(d0, e0, __builtin_fma(d1, e1, d2 * e2));
           }
-          if (opened != 0ull) {
-            if (leaf) {
-              // a bucket leaf that failed the test: its members one by one
-              const bool mine = ((opened >> lane) & 1ull) != 0;
-              const uint32_t j0 = l_child, j1 = j0 + l_count;
-              for (uint32_t j = j0; j < j1; ++j) {
-                const double mj = msrc[j];
-                if (mj == 0.0) continue;
-                if (mine && !(self && j == s)) {
-                  const double e0 = sxc[j] - y0, e1 = syc[j] - y1, e2 = szc[j] - y2;
-                  w64_mono(G * mj, e0, e1, e2, w64_r2(e0, e1, e2, b2), ax, ay, az);
-                  if (STATS) ++n_pp;
-                }
+          const double gs = g * __builtin_fma((2.5 * G) * dqd, u * u, G * rc.m);
+          const double gu = (G * g) * u;
+          ax = __builtin_fma(-gu, e0, __builtin_fma(gs, d0, ax));
+          ay = __builtin_fma(-gu, e1, __builtin_fma(gs, d1, ay));
+          az = __builtin_fma(-gu, e2, __builtin_fma(gs, d2, az));
+          if (STATS) { if (single) ++n_pp; else ++n_cell; }
+        }
+        if (opened != 0ull) {
+          if (leaf) {
+            // a bucket leaf that failed the test: its members one by one
+            const bool mine = ((opened >> lane) & 1ull) != 0;
+            const uint32_t j0 = rc.child, j1 = j0 + rc.count;
+            for (uint32_t j = j0; j < j1; ++j) {
+              const double mj = msrc[j];
+              if (mj == 0.0) continue;
+              if (mine && !(self && j == s)) {
+                const double f0 = sxc[j] - y0, f1 = syc[j] - y1, f2 = szc[j] - y2;
+                w64_mono(G * mj, f0, f1, f2, w64_r2(f0, f1, f2, b2), ax, ay, az);
+                if (STATS) ++n_pp;
               }
-            } else if (l < RB_DEPTH) {
-              if (lane == (uint32_t)(l + 1)) lvm = opened;
-              next = l_child;
             }
+          } else {
+            if (me) alev = take ? l : l + 1;
+            next = rc.child;
           }
         }
       }
       cur = w64_uniform(next);
     }
+    if (cur != stop && lane == 0) atomicOr(err, RB_ERR_TREE);
     if (img_split) {
       if (s < it.end) {
         double *a = acc + ((size_t)im * np + part) * 3 * cap;
