@@ -657,11 +657,11 @@ def gravity_run(args, sysm, wdesc):
         finally:
             rb.rb_destroy(ctx)
 
-    def interactions(theta):
+    def interactions(theta, t=None, X=None):
         """per-particle FP64 walk counts at theta, leaf 1 (the algorithmic work)"""
         ctx = sysm.create(rb.RB_FP64, theta=theta, leaf_size=1, profile=2)
         try:
-            sysm.gravity(ctx, t_kick)
+            sysm.gravity(ctx, t_kick if t is None else t, X)
             s = rb.rb_stats(ctx)
             s["n_nodes"] = rb.rb_tree_info(ctx)[0]
         finally:
@@ -670,19 +670,28 @@ def gravity_run(args, sysm, wdesc):
                  (FLOP_QUAD if quad else FLOP_MONO) * s["cells"])
         return s, flops
 
-    def executed(knobs):
+    def executed(knobs, t=None, X=None):
         """the grouped FP32 walk's own evaluated list entries (all lanes)"""
         ctx = sysm.create(rb.RB_FP32_MIXED, profile=2, **knobs)
         try:
-            sysm.gravity(ctx, t_kick)
+            sysm.gravity(ctx, t_kick if t is None else t, X)
             s = rb.rb_stats(ctx)
         finally:
             rb.rb_destroy(ctx)
         return s
 
-    def timed(prec, knobs, use_graph, profile):
-        """warm-up, then exactly K steps in one call from the initial state"""
+    def simpson(a, m, b, keys):
+        """the mean over the run of a count that varies smoothly, from its
+        values at the start, the middle and the end (Simpson's rule)"""
+        return {k: (a[k] + 4 * m[k] + b[k]) / 6 for k in keys}
+
+    k_mid = args.steps // 2
+
+    def timed(prec, knobs, use_graph, profile, mid=False):
+        """warm-up, then exactly K steps from the initial state: in one call,
+        or (mid) in two halves with a copy of the state between them"""
         ctx = sysm.create(prec, use_graph=use_graph, profile=profile, **knobs)
+        M = None
         try:
             W = sysm.clone()
             sysm.step(ctx, W, 0.0, args.warmup)
@@ -691,14 +700,19 @@ def gravity_run(args, sysm, wdesc):
             T = sysm.clone()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            sysm.step(ctx, T, 0.0, args.steps)
+            if mid:
+                sysm.step(ctx, T, 0.0, k_mid)
+                M = {k: v.clone() for k, v in T.items()}
+                sysm.step(ctx, T, k_mid * sysm.dt, args.steps - k_mid)
+            else:
+                sysm.step(ctx, T, 0.0, args.steps)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             rb.rb_sync(ctx)
             s = rb.rb_stats(ctx)
         finally:
             rb.rb_destroy(ctx)
-        return t1 - t0, s, T
+        return t1 - t0, s, T, M
 
     results = {}
     paths = ["fp64", "fp32"] if args.precision == "both" else [args.precision]
@@ -755,16 +769,31 @@ def gravity_run(args, sysm, wdesc):
             f"group={knobs['group_size']} split={knobs['split_images']} "
             f"waves={knobs['walk_waves']} graph={use_graph} ({source}): "
             f"rms={err['rms']:.3e} max={err['max']:.3e}")
-        st, flops = interactions(knobs["theta"])
+        st0, flops0 = interactions(knobs["theta"])
         # The timed run records no HIP events (an event between two kernels
         # costs a few microseconds of idle GPU); the walk launches are timed
         # in a second, eager pass of the same K steps with HIP events around
         # every walk launch on the context's stream.
-        secs, _, T = timed(prec, knobs, use_graph, 0)
-        _, s2, _ = timed(prec, knobs, 0, 4)
+        secs, _, T, _ = timed(prec, knobs, use_graph, 0)
+        _, s2, _, M = timed(prec, knobs, 0, 4, mid=k_mid > 0)
+        if M is None:
+            M = sysm.clone()
+        t_mid = k_mid * sysm.dt + t_kick
         t_end = args.steps * sysm.dt + t_kick
         err_end = errors_at(prec, knobs, T, t_end, sysm.direct(tg, t_end, T))
-        del T
+        # The system evolves over the timed steps (a sheet's particles settle
+        # into denser wakes) and a walk late in the run does more work than
+        # an early one: the work of the timed walks is the mean of the counts
+        # over the run, by Simpson's rule from the start, the middle and the
+        # end of the run.
+        stm, flopsm = interactions(knobs["theta"], t_mid, M)
+        st1, flops1 = interactions(knobs["theta"], t_end, T)
+        st = simpson(st0, stm, st1, ("open_tests", "cells", "pp", "n_nodes"))
+        flops = (flops0 + 4 * flopsm + flops1) / 6
+        if path == "fp32":
+            ex = simpson(executed(knobs), executed(knobs, t_mid, M), executed(knobs, t_end, T),
+                         ("list_cells", "list_pp"))
+        del T, M
         # the nominal opening angle 0.5, same launch shape, initial state
         err_05 = errors_at(prec, dict(knobs, theta=0.5), None, t_kick, ref)
         ms_step = secs * 1e3 / args.steps
@@ -780,12 +809,19 @@ def gravity_run(args, sysm, wdesc):
                  particle_steps_per_s=n * args.steps / secs,
                  walk_ms=walk_ms, walk_launches=s2["calls"]["walk"],
                  interactions=dict(open_tests=st["open_tests"], cells=st["cells"],
-                                   pp=st["pp"]),
+                                   pp=st["pp"],
+                                   note="mean over the timed run: Simpson's rule from the "
+                                        "counts at its start, middle and end"),
+                 interactions_start=dict(open_tests=st0["open_tests"], cells=st0["cells"],
+                                         pp=st0["pp"]),
+                 interactions_middle=dict(open_tests=stm["open_tests"], cells=stm["cells"],
+                                          pp=stm["pp"]),
+                 interactions_end_of_run=dict(open_tests=st1["open_tests"],
+                                              cells=st1["cells"], pp=st1["pp"]),
                  algorithmic_flops_per_walk=flops,
                  algorithmic_tflops=flops / (walk_ms * 1e-3) / 1e12,
                  interactions_per_s=(st["cells"] + st["pp"]) / (walk_ms * 1e-3))
         if path == "fp32":
-            ex = executed(knobs)
             ex_flops = (FLOP_QUAD if quad else FLOP_MONO) * ex["list_cells"] + \
                 FLOP_MONO * ex["list_pp"]
             r["executed"] = dict(list_cells=ex["list_cells"], list_pp=ex["list_pp"],
