@@ -194,3 +194,32 @@ def test_clustered_ties_and_removed(orc, n_dead):
     for k in ("keys", "perm", "level", "prefix", "first", "count", "is_leaf"):
         np.testing.assert_array_equal(g[k], ref[k], err_msg=k)
     np.testing.assert_array_equal(g["com"], ref["com"])
+
+
+@pytest.mark.parametrize("level_log2", [None, 6])
+def test_single_particle_leaves_are_point_masses(level_log2):
+    # The FP64 walk evaluates a single-particle leaf through the cell terms;
+    # they equal the point mass's term exactly only because the build puts
+    # the leaf's centre of mass at the particle itself and leaves its
+    # quadrupole exactly zero (Sect. 4.2: a leaf's moments are those of its
+    # particles).  Both moment paths: groups and large nodes in one
+    # workgroup, and level by level (forced above 64 slots).
+    from gpu_util import Dev, export, make_ctx
+    from paper_1110_4876_amd import rb
+    kw = {} if level_log2 is None else dict(moments_level_log2=level_log2)
+    for pr, leaf in ((inputs.sheet(20000, seed=2), 1),
+                     (inputs.plummer(8000, seed=7, quadrupole=True), 4)):
+        ctx = make_ctx(pr, leaf_size=leaf, **kw)
+        try:
+            d = Dev(pr, with_v=False)
+            rb.rb_tree_build(ctx, d.parts, d.n, d.n)
+            g = export(ctx)
+        finally:
+            rb.rb_destroy(ctx)
+        one = (g["is_leaf"] != 0) & (g["count"] == 1)
+        assert one.sum() > 100
+        assert (g["Q"][one] == 0.0).all()
+        src = g["perm"][g["first"][one]]
+        pos = np.stack([pr.x[src], pr.y[src], pr.z[src]], axis=1)
+        np.testing.assert_array_equal(g["com"][one], pos)
+        np.testing.assert_array_equal(g["M"][one], pr.m[src])
