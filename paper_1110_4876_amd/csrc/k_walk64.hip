@@ -123,11 +123,11 @@ __device__ __forceinline__ uint32_t w64_uniform(uint32_t v) {
 
 // One wave per workgroup: a wave's slot on the CU is refilled as soon as it
 // ends (with four waves per workgroup the slot waits for the slowest of the
-// four; measured 2.6-5% slower).  Eight waves per SIMD: the register
-// budget that allows them (78 scalar registers, against 106
-// unbounded) moves only set-up values out to vector lanes, none of the node
-// loop's, and the extra waves cover more of the node loads' latency
-// (measured 10% faster on the 256-patch ensemble).
+// four; measured 2.6-5% slower).  Eight waves per SIMD: the register budget
+// that allows them (78 scalar registers, against 106 unbounded) moves only
+// set-up values out to vector lanes, none of the node loop's, and the extra
+// waves cover more of the node loads' latency (measured 10% faster on the
+// 256-patch ensemble).
 template <bool QUAD, bool STATS, int PD>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_walk64(
     const WalkItem *__restrict__ items, uint32_t n_items, int img_split, int n_img, int parts,
@@ -145,22 +145,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
   const w64_dbl_p Qarr = (w64_dbl_p)Q_g;
   const w64_dbl_p msrc = (w64_dbl_p)msrc_g;
   const w64_dbl_p sxc = (w64_dbl_p)sx_g, syc = (w64_dbl_p)sy_g, szc = (w64_dbl_p)sz_g;
-  // Workgroups are dealt to the eight XCDs in turn; block b is given work
-  // unit (b mod 8)-th eighth of the units, so each XCD's L2 holds the nodes
-  // of one Morton-contiguous eighth of the particles.
+  // Workgroups are dealt to the eight XCDs in turn; block b takes its unit
+  // from the (b mod 8)-th eighth of the units, so each XCD's L2 holds the
+  // nodes of one contiguous eighth of the units.
   const uint32_t nb = gridDim.x, b = blockIdx.x;
   const uint32_t q = nb >> 3, r = nb & 7u, x = b & 7u;
   const uint32_t vb = x * q + (x < r ? x : r) + (b >> 3);
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t unit = vb;  // one unit per wave
   // a unit: a part, an item and its image (when split).  With parts, each
-  // part walks one subtree one or two levels below the root (8 or 64
-  // parts), so a system of few items still gives many units, each with a
-  // short chain of node loads; every particle still sees each node once,
-  // and the parts' sums are added in order afterwards.  Units are part-major: neighbouring waves (and an
-  // XCD's range) walk the same subtree for neighbouring particles and share
-  // its node records in the caches.
-  // PD levels below the root are split: 8^PD parts (parts == 8^PD)
+  // part walks one subtree one or two levels below the root (PD levels:
+  // 8^PD parts), so a system of few items still gives many units, each with
+  // a short chain of node loads; every particle still sees each node once,
+  // and the parts' sums are added in order afterwards.  Units are
+  // part-major: neighbouring waves (and an XCD's range) walk the same
+  // subtree for neighbouring particles and share its node records in the
+  // caches.
   const uint32_t np = PD ? (uint32_t)parts : 1u;
   const uint32_t per_part = n_items * (img_split ? (uint32_t)n_img : 1u);
   const uint32_t n_units = per_part * np;
