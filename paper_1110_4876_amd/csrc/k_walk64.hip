@@ -139,7 +139,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     const double *__restrict__ msrc_g, const double *__restrict__ sched,
     const uint32_t *__restrict__ ctr, uint32_t P, double G, double b2, double theta2,
     double *__restrict__ acc, uint64_t cap, unsigned long long *__restrict__ stats,
-    const uint32_t *__restrict__ lev_off, uint32_t *__restrict__ err, int slot) {
+    const uint32_t *__restrict__ lev_off, uint32_t *__restrict__ err, int slot,
+    const uint32_t *__restrict__ order, uint32_t *__restrict__ cost) {
   const w64_u32_p link = (w64_u32_p)link_g;
   const w64_dbl_p mcom = (w64_dbl_p)mcom_g;
   const w64_dbl_p Qarr = (w64_dbl_p)Q_g;
@@ -152,7 +153,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
   const uint32_t q = nb >> 3, r = nb & 7u, x = b & 7u;
   const uint32_t vb = x * q + (x < r ? x : r) + (b >> 3);
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t unit = vb;  // one unit per wave
   // a unit: a part, an item and its image (when split).  With parts, each
   // part walks one subtree one or two levels below the root (PD levels:
   // 8^PD parts), so a system of few items still gives many units, each with
@@ -164,7 +164,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
   const uint32_t np = PD ? (uint32_t)parts : 1u;
   const uint32_t per_part = n_items * (img_split ? (uint32_t)n_img : 1u);
   const uint32_t n_units = per_part * np;
-  if (unit >= n_units) return;  // whole waves
+  if (vb >= n_units) return;  // whole waves
+  // one unit per wave: in the order given (a permutation of the units), or
+  // the unit at the wave's own position
+  const uint32_t unit = order ? w64_uniform(order[vb]) : vb;
   // a depth-first walk visits every node at most once per image: more
   // visits, or an index past the node count, mean inconsistent links
   const uint32_t n_nodes = lev_off[RB_NLEV];
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
   if (valid) { px = sx_g[s]; py = sy_g[s]; pz = sz_g[s]; }
   const uint64_t live = __ballot(valid);
   const uint32_t r0 = live ? w64_uniform(root[p]) : RB_NONE;
-  uint32_t n_open = 0, n_cell = 0, n_pp = 0;
+  uint32_t n_open = 0, n_cell = 0, n_pp = 0, n_visits = 0;
   double tx = 0.0, ty = 0.0, tz = 0.0;
   for (int im = im0; im < im1; ++im) {
     double ox, oy;
@@ -347,6 +350,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
       cur = w64_uniform(next);
     }
     if (cur != stop && lane == 0) atomicOr(err, RB_ERR_TREE);
+    n_visits += visits;
     if (img_split) {
       if (s < it.end) {
         double *a = acc + ((size_t)im * np + part) * 3 * cap;
@@ -360,6 +364,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     double *a = acc + (size_t)part * 3 * cap;
     a[s] = tx; a[cap + s] = ty; a[2 * cap + s] = tz;
   }
+  if (cost && lane == 0) cost[unit] = n_visits;
   if (STATS) {
     unsigned long long o = n_open, c = n_cell, q2 = n_pp;
     for (int d = 32; d >= 1; d >>= 1) {
@@ -483,6 +488,75 @@ __global__ __launch_bounds__(64) void k_walk64_lane(
   }
 }
 
+// Dispatch order of the 64-part walk's units.  Near-field units take
+// several times longer than the median one, and in part-major order some
+// start late and leave the chip with a tail of a few waves.  Each wave
+// records its unit's node visits; before the next launch the units that
+// cost the most (about the top 1/32 by the last launch's visits) move to
+// the front of their XCD's share of the grid, and the rest keep their
+// part-major order.  The order decides only which wave starts first: every
+// unit writes its own accumulator set, so the sums do not depend on it.
+__global__ __launch_bounds__(1024) void k_w64_order(const uint32_t *__restrict__ cost,
+                                                    uint32_t *__restrict__ order,
+                                                    uint32_t n_units) {
+  __shared__ uint32_t hist[33];
+  __shared__ uint32_t cnt[1024];
+  __shared__ uint32_t heavy_in[8];
+  __shared__ uint32_t thr_s;
+  const uint32_t t = threadIdx.x;
+  if (t < 33) hist[t] = 0;
+  __syncthreads();
+  // units by the bit length of their cost
+  for (uint32_t u = t; u < n_units; u += 1024) {
+    const uint32_t v = cost[u];
+    atomicAdd(&hist[v ? 32 - __clz(v) : 0], 1u);
+  }
+  __syncthreads();
+  if (t == 0) {
+    // heavy: a cost of bit length b or more, for the largest b that takes
+    // at least n_units / 32 units (none while no costs are known)
+    uint32_t acc = 0, thr = 0xFFFFFFFFu;
+    for (int b = 32; b >= 1; --b) {
+      acc += hist[b];
+      if (acc > 0 && acc >= n_units / 32) {
+        thr = 1u << (b - 1);
+        break;
+      }
+    }
+    thr_s = thr;
+  }
+  __syncthreads();
+  const uint32_t thr = thr_s;
+  // the walk's mapping: XCD x runs positions [x q + min(x, r), ...) of the
+  // grid in order; 128 threads per share, each a contiguous run of it
+  const uint32_t q = n_units >> 3, r = n_units & 7u;
+  const uint32_t x = t >> 7, lt = t & 127u;
+  const uint32_t lo = x * q + (x < r ? x : r), len = q + (x < r ? 1u : 0u);
+  const uint32_t run = (len + 127u) / 128u;
+  const uint32_t c0 = lo + (lt * run < len ? lt * run : len);
+  const uint32_t c1 = lo + ((lt + 1u) * run < len ? (lt + 1u) * run : len);
+  uint32_t h = 0;
+  for (uint32_t u = c0; u < c1; ++u) h += cost[u] >= thr ? 1u : 0u;
+  cnt[t] = h;
+  __syncthreads();
+  if (lt == 0) {  // exclusive scan of the share's 128 counts
+    uint32_t sum = 0;
+    for (uint32_t k = 0; k < 128u; ++k) {
+      const uint32_t v = cnt[t + k];
+      cnt[t + k] = sum;
+      sum += v;
+    }
+    heavy_in[x] = sum;
+  }
+  __syncthreads();
+  uint32_t hp = lo + cnt[t];                                  // heavy units first
+  uint32_t lp = lo + heavy_in[x] + ((c0 - lo) - cnt[t]);      // then the others
+  for (uint32_t u = c0; u < c1; ++u) {
+    if (cost[u] >= thr) order[hp++] = u;
+    else order[lp++] = u;
+  }
+}
+
 hipError_t launch_walk64(rb_ctx *c, const double *sx, const double *sy, const double *sz,
                          int slot) {
   const uint32_t n_items = (uint32_t)c->h_items64.size();
@@ -495,12 +569,19 @@ hipError_t launch_walk64(rb_ctx *c, const double *sx, const double *sy, const do
   if (c->walk64_mode != 1) {
     const int parts = c->walk_parts;
     const unsigned grid = units * (uint32_t)parts;  // one unit per wave and workgroup
+    // the 64-part walk runs its costliest units first (by the last launch)
+    const bool ordered = parts == RB_WALK64_PARTS2 && grid <= RB_WALK64_ORDER_CAP;
+    const uint32_t *order = ordered ? c->d_w64_order : nullptr;
+    uint32_t *cost = ordered ? c->d_w64_cost : nullptr;
+    if (ordered)
+      hipLaunchKernelGGL(k_w64_order, dim3(1), dim3(1024), 0, c->stream, c->d_w64_cost,
+                         c->d_w64_order, grid);
 #define RB_WALK64_ARGS                                                                     \
   c->d_items64, n_items, split, c->n_img, parts, c->p.n_ghost[0], c->p.n_ghost[1],          \
       c->p.boundary,                                                                       \
       c->d_patch, c->d_nlive, c->d_root, c->d_link, c->d_mcom, c->d_Q, sx, sy, sz,         \
       c->d_msrc, c->d_sched, c->d_ctr, c->P, c->p.G, b2, th2, c->d_acc, c->cap,           \
-      c->d_stats, c->d_lev_off, c->d_err, slot
+      c->d_stats, c->d_lev_off, c->d_err, slot, order, cost
     const dim3 g(grid), bl(64);
 #define RB_W64_LAUNCH(PD)                                                                          \
   do {                                                                                             \

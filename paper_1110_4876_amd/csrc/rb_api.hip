@@ -382,6 +382,9 @@ int init_ctx(rb_ctx *c, const rb_params *p, uint32_t P, const int64_t *off, cons
       if ((k - ni) * set_bytes <= budget) { c->acc_sets = (int)k; break; }
   }
   RB_TRY(dalloc(c, &c->d_acc, (uint64_t)c->acc_sets * 3 * cap));
+  RB_TRY(dalloc(c, &c->d_w64_cost, RB_WALK64_ORDER_CAP));
+  RB_TRY(dalloc(c, &c->d_w64_order, RB_WALK64_ORDER_CAP));
+  RB_HIP(hipMemsetAsync(c->d_w64_cost, 0, 4 * (size_t)RB_WALK64_ORDER_CAP, c->stream));
   // per-call dynamic region: step counter (16 B), StepConst, schedule
   c->sched_cap = 1024;
   c->dyn_bytes = 256 + (size_t)(c->sched_cap + 1) * 2 * P * sizeof(double);

@@ -152,6 +152,9 @@ struct rb_ctx {
   double *d_cgeo = nullptr;         // 4 per node: the search's cell records
   double *d_swR = nullptr, *d_swhi = nullptr;  // plane sweep: sorted radii, interval ends
   double *d_acc = nullptr;          // acc_sets * 3 * cap
+  // the 64-part FP64 walk's units: node visits of the last launch, and the
+  // dispatch order built from them (RB_WALK64_ORDER_CAP entries each)
+  uint32_t *d_w64_cost = nullptr, *d_w64_order = nullptr;
 
   // per-call dynamic region [ctr | StepConst | schedule], uploaded from a
   // pinned staging copy; schedule per step: s_half[P], s_end[P]
@@ -262,6 +265,9 @@ hipError_t launch_rowscan_levels(rb_ctx *c, const uint32_t *reuse = nullptr);
 #define RB_WALK64_PARTS 8
 #define RB_WALK64_PARTS2 64
 #define RB_WALK64_PARTS2_MAX_ITEMS 1024u
+// units of the 64-part walk that get a cost-ordered dispatch (at most
+// RB_WALK64_PARTS2_MAX_ITEMS items of 64 parts)
+#define RB_WALK64_ORDER_CAP 65536u
 inline int rb_n_acc(const rb_ctx *c) { return (c->img_split ? c->n_img : 1) * c->walk_parts; }
 // work units from which the wave-shared FP64 walk beats per-lane walks
 #define RB_WALK64_SHARED_MIN 12288u
