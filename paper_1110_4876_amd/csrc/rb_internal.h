@@ -268,6 +268,7 @@ hipError_t launch_rowscan_levels(rb_ctx *c, const uint32_t *reuse = nullptr);
 // units of the 64-part walk that get a cost-ordered dispatch (at most
 // RB_WALK64_PARTS2_MAX_ITEMS items of 64 parts)
 #define RB_WALK64_ORDER_CAP 65536u
+#define RB_WALK64_ORDER_MIN 4096u
 inline int rb_n_acc(const rb_ctx *c) { return (c->img_split ? c->n_img : 1) * c->walk_parts; }
 // work units from which the wave-shared FP64 walk beats per-lane walks
 #define RB_WALK64_SHARED_MIN 12288u
