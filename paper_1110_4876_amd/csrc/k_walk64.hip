@@ -140,18 +140,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     const uint32_t *__restrict__ ctr, uint32_t P, double G, double b2, double theta2,
     double *__restrict__ acc, uint64_t cap, unsigned long long *__restrict__ stats,
     const uint32_t *__restrict__ lev_off, uint32_t *__restrict__ err, int slot,
-    const uint32_t *__restrict__ order, uint32_t *__restrict__ cost) {
+    uint32_t *__restrict__ ord) {
   const w64_u32_p link = (w64_u32_p)link_g;
   const w64_dbl_p mcom = (w64_dbl_p)mcom_g;
   const w64_dbl_p Qarr = (w64_dbl_p)Q_g;
   const w64_dbl_p msrc = (w64_dbl_p)msrc_g;
   const w64_dbl_p sxc = (w64_dbl_p)sx_g, syc = (w64_dbl_p)sy_g, szc = (w64_dbl_p)sz_g;
-  // Workgroups are dealt to the eight XCDs in turn; block b takes its unit
-  // from the (b mod 8)-th eighth of the units, so each XCD's L2 holds the
-  // nodes of one contiguous eighth of the units.
-  const uint32_t nb = gridDim.x, b = blockIdx.x;
-  const uint32_t q = nb >> 3, r = nb & 7u, x = b & 7u;
-  const uint32_t vb = x * q + (x < r ? x : r) + (b >> 3);
   const uint32_t lane = threadIdx.x & 63u;
   // a unit: a part, an item and its image (when split).  With parts, each
   // part walks one subtree one or two levels below the root (PD levels:
@@ -164,10 +158,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
   const uint32_t np = PD ? (uint32_t)parts : 1u;
   const uint32_t per_part = n_items * (img_split ? (uint32_t)n_img : 1u);
   const uint32_t n_units = per_part * np;
-  if (vb >= n_units) return;  // whole waves
-  // one unit per wave: in the order given (a permutation of the units), or
-  // the unit at the wave's own position
-  const uint32_t unit = order ? w64_uniform(order[vb]) : vb;
+  // One unit per wave.  Workgroups are dealt to the eight XCDs in turn;
+  // block b takes its unit from the (b mod 8)-th eighth of the units, so
+  // each XCD's L2 holds the nodes of one contiguous eighth of them.  An
+  // ordered launch (ctl) first runs the units listed as costly (the first
+  // RB_WALK64_HEAVY_MAX blocks, spread over all XCDs), then the rest in
+  // that order; a listed unit's own block there has nothing left to do.
+  // (only the 64-part instance is ever launched ordered)
+  constexpr bool ORD = PD == 2;
+  W64Ctl *const ctl = ORD ? (W64Ctl *)ord : nullptr;
+  uint32_t unit = 0;
+  bool run;
+  if (ORD && ctl && blockIdx.x < RB_WALK64_HEAVY_MAX) {  // a listed unit
+    // XCD x = b mod 8 runs the list of its own share
+    const uint32_t x = blockIdx.x & 7u, j = blockIdx.x >> 3;
+    run = j < min(ctl->cnt[ctl->cur & 1u][x], RB_WALK64_HEAVY_MAX / 8u);
+    if (run) unit = w64_uniform(ord[RB_W64_HEAVY_OFF + x * (RB_WALK64_HEAVY_MAX / 8u) + j]);
+    run = run && unit < n_units;
+  } else {  // the units in order (XCD x = b mod 8 either way)
+    const uint32_t off = (ORD && ctl) ? RB_WALK64_HEAVY_MAX : 0u;
+    const uint32_t b = blockIdx.x - off, nb = gridDim.x - off;
+    const uint32_t q = nb >> 3, r = nb & 7u, x = b & 7u;
+    unit = x * q + (x < r ? x : r) + (b >> 3);
+    run = unit < n_units;  // whole waves
+    if (ORD && ctl && run) run = w64_uniform(ord[RB_W64_TAG_OFF + unit]) != ctl->cur;
+  }
+  if (!run) return;
   // a depth-first walk visits every node at most once per image: more
   // visits, or an index past the node count, mean inconsistent links
   const uint32_t n_nodes = lev_off[RB_NLEV];
@@ -364,7 +380,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     double *a = acc + (size_t)part * 3 * cap;
     a[s] = tx; a[cap + s] = ty; a[2 * cap + s] = tz;
   }
-  if (cost && lane == 0) cost[unit] = n_visits;
+  if (ORD && ctl && lane == 0) ord[RB_W64_COST_OFF + unit] = n_visits;
   if (STATS) {
     unsigned long long o = n_open, c = n_cell, q2 = n_pp;
     for (int d = 32; d >= 1; d >>= 1) {
@@ -490,70 +506,75 @@ __global__ __launch_bounds__(64) void k_walk64_lane(
 
 // Dispatch order of the 64-part walk's units.  Near-field units take
 // several times longer than the median one, and in part-major order some
-// start late and leave the chip with a tail of a few waves.  Each wave
-// records its unit's node visits; before the next launch the units that
-// cost the most (about the top 1/32 by the last launch's visits) move to
-// the front of their XCD's share of the grid, and the rest keep their
-// part-major order.  The order decides only which wave starts first: every
-// unit writes its own accumulator set, so the sums do not depend on it.
-__global__ __launch_bounds__(1024) void k_w64_order(const uint32_t *__restrict__ cost,
-                                                    uint32_t *__restrict__ order,
-                                                    uint32_t n_units) {
-  __shared__ uint32_t hist[33];
-  __shared__ uint32_t cnt[1024];
-  __shared__ uint32_t heavy_in[8];
-  __shared__ uint32_t thr_s;
-  const uint32_t t = threadIdx.x;
-  if (t < 33) hist[t] = 0;
-  __syncthreads();
-  // units by the bit length of their cost
-  for (uint32_t u = t; u < n_units; u += 1024) {
-    const uint32_t v = cost[u];
-    atomicAdd(&hist[v ? 32 - __clz(v) : 0], 1u);
-  }
-  __syncthreads();
-  if (t == 0) {
-    // heavy: a cost of bit length b or more, for the largest b that takes
-    // at least n_units / 32 units (none while no costs are known)
-    uint32_t acc = 0, thr = 0xFFFFFFFFu;
-    for (int b = 32; b >= 1; --b) {
-      acc += hist[b];
-      if (acc > 0 && acc >= n_units / 32) {
-        thr = 1u << (b - 1);
-        break;
+// start late and leave the chip with a tail of a few waves.  The walk
+// records each unit's node visits; before the next launch the units that
+// cost at least the threshold (about the top 1/32, from the costs one
+// launch earlier) are listed to run first, the rest keeping their
+// part-major order.  The
+// order decides only which wave starts first: every unit writes its own
+// accumulator set, so the sums do not depend on it.
+__global__ __launch_bounds__(1024) void k_w64_list(uint32_t *__restrict__ ord,
+                                                   uint32_t n_units) {
+  __shared__ uint32_t lh[33];
+  __shared__ uint32_t last;
+  W64Ctl *const ctl = (W64Ctl *)ord;
+  const uint32_t t = threadIdx.x, lane = t & 63u, u = blockIdx.x * 1024u + t;
+  const bool in = u < n_units;
+  const uint32_t v = in ? ord[RB_W64_COST_OFF + u] : 0u;
+  const uint32_t e = ctl->epoch;
+  const bool heavy = in && v >= ctl->thr;
+  // the XCD share of the walk's grid the unit belongs to (share x starts at
+  // unit x q + min(x, r)); a wave's 64 units span at most two shares, and
+  // each share's listed units are counted with one atomic per wave
+  const uint32_t q = n_units >> 3, r = n_units & 7u;
+  const uint32_t x = u < r * (q + 1u) ? u / (q + 1u) : r + (u - r * (q + 1u)) / q;
+  uint64_t todo = __ballot(heavy);
+  while (todo) {
+    const uint32_t xl = (uint32_t)__shfl((int)x, __ffsll((long long)todo) - 1, 64);
+    const uint64_t mine = __ballot(heavy && x == xl);
+    uint32_t base = 0;
+    if (lane == (uint32_t)(__ffsll((long long)mine) - 1))
+      base = atomicAdd(&ctl->cnt[e & 1u][xl], (uint32_t)__popcll(mine));
+    base = (uint32_t)__shfl((int)base, __ffsll((long long)mine) - 1, 64);
+    if (heavy && x == xl) {
+      const uint32_t k = base + (uint32_t)__popcll(mine & ((1ull << lane) - 1ull));
+      if (k < RB_WALK64_HEAVY_MAX / 8u) {
+        ord[RB_W64_HEAVY_OFF + xl * (RB_WALK64_HEAVY_MAX / 8u) + k] = u;
+        ord[RB_W64_TAG_OFF + u] = e;
       }
     }
-    thr_s = thr;
+    todo &= ~mine;
   }
+  // the costs by bit length, block by block into the launch's histogram
+  if (t < 33u) lh[t] = 0u;
   __syncthreads();
-  const uint32_t thr = thr_s;
-  // the walk's mapping: XCD x runs positions [x q + min(x, r), ...) of the
-  // grid in order; 128 threads per share, each a contiguous run of it
-  const uint32_t q = n_units >> 3, r = n_units & 7u;
-  const uint32_t x = t >> 7, lt = t & 127u;
-  const uint32_t lo = x * q + (x < r ? x : r), len = q + (x < r ? 1u : 0u);
-  const uint32_t run = (len + 127u) / 128u;
-  const uint32_t c0 = lo + (lt * run < len ? lt * run : len);
-  const uint32_t c1 = lo + ((lt + 1u) * run < len ? (lt + 1u) * run : len);
-  uint32_t h = 0;
-  for (uint32_t u = c0; u < c1; ++u) h += cost[u] >= thr ? 1u : 0u;
-  cnt[t] = h;
+  if (in) atomicAdd(&lh[v ? 32 - __clz(v) : 0], 1u);
   __syncthreads();
-  if (lt == 0) {  // exclusive scan of the share's 128 counts
-    uint32_t sum = 0;
-    for (uint32_t k = 0; k < 128u; ++k) {
-      const uint32_t v = cnt[t + k];
-      cnt[t + k] = sum;
-      sum += v;
+  if (t < 33u && lh[t] != 0u) atomicAdd(&ctl->hist[t], lh[t]);
+  __threadfence();
+  __syncthreads();
+  if (t == 0) last = atomicAdd(&ctl->done, 1u) == gridDim.x - 1u ? 1u : 0u;
+  __syncthreads();
+  if (last == 0u || t >= 64u) return;
+  // the last block: the next threshold is the largest power of two such
+  // that at least n_units / 32 units cost that much or more (none while no
+  // unit reached it)
+  __threadfence();
+  const uint32_t h = t < 33u ? atomicExch(&ctl->hist[t], 0u) : 0u;
+  uint32_t acc = 0, thr = 0xFFFFFFFFu;
+  for (int bl = 32; bl >= 1; --bl) {
+    acc += (uint32_t)__builtin_amdgcn_readlane((int)h, bl);
+    if (acc > 0 && acc >= n_units / 32u) {
+      thr = 1u << (bl - 1);
+      break;
     }
-    heavy_in[x] = sum;
   }
-  __syncthreads();
-  uint32_t hp = lo + cnt[t];                                  // heavy units first
-  uint32_t lp = lo + heavy_in[x] + ((c0 - lo) - cnt[t]);      // then the others
-  for (uint32_t u = c0; u < c1; ++u) {
-    if (cost[u] >= thr) order[hp++] = u;
-    else order[lp++] = u;
+  if (t == 0) {
+    ctl->thr = thr;
+    ctl->cur = e;
+    ctl->epoch = e + 1u;
+    for (int k = 0; k < 8; ++k) ctl->cnt[(e + 1u) & 1u][k] = 0u;
+    ctl->done = 0u;
   }
 }
 
@@ -568,23 +589,24 @@ hipError_t launch_walk64(rb_ctx *c, const double *sx, const double *sy, const do
   const bool quad = c->p.quadrupole != 0, stats = (c->p.profile & 2) != 0;
   if (c->walk64_mode != 1) {
     const int parts = c->walk_parts;
-    const unsigned grid = units * (uint32_t)parts;  // one unit per wave and workgroup
+    unsigned grid = units * (uint32_t)parts;  // one unit per wave and workgroup
     // the 64-part walk runs its costliest units first (by the last launch;
     // measured: the top 1/32 first beats 1/16 and 1/64, and below
-    // RB_WALK64_ORDER_MIN units the ordering kernel costs more than it saves)
+    // RB_WALK64_ORDER_MIN units the listing costs more than it saves)
     const bool ordered = parts == RB_WALK64_PARTS2 && grid >= RB_WALK64_ORDER_MIN &&
                          grid <= RB_WALK64_ORDER_CAP;
-    const uint32_t *order = ordered ? c->d_w64_order : nullptr;
-    uint32_t *cost = ordered ? c->d_w64_cost : nullptr;
-    if (ordered)
-      hipLaunchKernelGGL(k_w64_order, dim3(1), dim3(1024), 0, c->stream, c->d_w64_cost,
-                         c->d_w64_order, grid);
+    uint32_t *ord = ordered ? c->d_w64_ord : nullptr;
+    if (ordered) {
+      hipLaunchKernelGGL(k_w64_list, dim3(rb_div_up(grid, 1024)), dim3(1024), 0, c->stream, ord,
+                         grid);
+      grid += RB_WALK64_HEAVY_MAX;
+    }
 #define RB_WALK64_ARGS                                                                     \
   c->d_items64, n_items, split, c->n_img, parts, c->p.n_ghost[0], c->p.n_ghost[1],          \
       c->p.boundary,                                                                       \
       c->d_patch, c->d_nlive, c->d_root, c->d_link, c->d_mcom, c->d_Q, sx, sy, sz,         \
       c->d_msrc, c->d_sched, c->d_ctr, c->P, c->p.G, b2, th2, c->d_acc, c->cap,           \
-      c->d_stats, c->d_lev_off, c->d_err, slot, order, cost
+      c->d_stats, c->d_lev_off, c->d_err, slot, ord
     const dim3 g(grid), bl(64);
 #define RB_W64_LAUNCH(PD)                                                                          \
   do {                                                                                             \

@@ -382,9 +382,16 @@ int init_ctx(rb_ctx *c, const rb_params *p, uint32_t P, const int64_t *off, cons
       if ((k - ni) * set_bytes <= budget) { c->acc_sets = (int)k; break; }
   }
   RB_TRY(dalloc(c, &c->d_acc, (uint64_t)c->acc_sets * 3 * cap));
-  RB_TRY(dalloc(c, &c->d_w64_cost, RB_WALK64_ORDER_CAP));
-  RB_TRY(dalloc(c, &c->d_w64_order, RB_WALK64_ORDER_CAP));
-  RB_HIP(hipMemsetAsync(c->d_w64_cost, 0, 4 * (size_t)RB_WALK64_ORDER_CAP, c->stream));
+  RB_TRY(dalloc(c, &c->d_w64_ord, RB_W64_ORD_WORDS));
+  RB_HIP(hipMemsetAsync(c->d_w64_ord, 0, 4 * (size_t)RB_W64_ORD_WORDS, c->stream));
+  {
+    static_assert(sizeof(W64Ctl) <= 4 * RB_W64_COST_OFF, "control block");
+    W64Ctl ctl{};
+    ctl.epoch = 1;          // tags start at 0: no unit is listed
+    ctl.thr = 0xFFFFFFFFu;  // nothing listed until a launch has measured costs
+    RB_HIP(hipMemcpyAsync(c->d_w64_ord, &ctl, sizeof(ctl), hipMemcpyHostToDevice, c->stream));
+    RB_HIP(hipStreamSynchronize(c->stream));
+  }
   // per-call dynamic region: step counter (16 B), StepConst, schedule
   c->sched_cap = 1024;
   c->dyn_bytes = 256 + (size_t)(c->sched_cap + 1) * 2 * P * sizeof(double);

@@ -32,6 +32,20 @@ __device__ __forceinline__ WalkItem rb_walk_item(const WalkItem *__restrict__ it
   return items[(uint32_t)cap - 1u - (gi - n_big - n_mid)];
 }
 
+// Control block of the 64-part FP64 walk's dispatch order.  Before each
+// walk the listing kernel lists the units whose last cost reached the
+// threshold, under the launch number `epoch`, and histograms the costs (by
+// bit length); its last block turns the histogram into the next threshold,
+// publishes the number as `cur` for the walk and starts the next one.
+struct W64Ctl {
+  uint32_t done;       // blocks of the running listing that have finished
+  uint32_t epoch;      // the number the next listing tags with
+  uint32_t cur;        // the number of the listing the next walk runs by
+  uint32_t thr;        // cost from which a unit is listed
+  uint32_t cnt[2][8];  // units listed per XCD share, under an odd / even number
+  uint32_t hist[33];   // costs of the listing's units by bit length
+};
+
 struct rb_ctx {
   rb_params p;
   int device = 0;
@@ -152,9 +166,11 @@ struct rb_ctx {
   double *d_cgeo = nullptr;         // 4 per node: the search's cell records
   double *d_swR = nullptr, *d_swhi = nullptr;  // plane sweep: sorted radii, interval ends
   double *d_acc = nullptr;          // acc_sets * 3 * cap
-  // the 64-part FP64 walk's units: node visits of the last launch, and the
-  // dispatch order built from them (RB_WALK64_ORDER_CAP entries each)
-  uint32_t *d_w64_cost = nullptr, *d_w64_order = nullptr;
+  // the 64-part FP64 walk's dispatch order, one buffer: the control block,
+  // then per unit (RB_WALK64_ORDER_CAP each) the node visits of the last
+  // launch and the launch number that lists it to run first, then the list
+  // (RB_WALK64_HEAVY_MAX)
+  uint32_t *d_w64_ord = nullptr;
 
   // per-call dynamic region [ctr | StepConst | schedule], uploaded from a
   // pinned staging copy; schedule per step: s_half[P], s_end[P]
@@ -269,6 +285,12 @@ hipError_t launch_rowscan_levels(rb_ctx *c, const uint32_t *reuse = nullptr);
 // RB_WALK64_PARTS2_MAX_ITEMS items of 64 parts)
 #define RB_WALK64_ORDER_CAP 65536u
 #define RB_WALK64_ORDER_MIN 4096u
+#define RB_WALK64_HEAVY_MAX 4096u  // 8 lists (one per XCD share) of 512
+// offsets (in 32-bit words) in the order buffer
+#define RB_W64_COST_OFF 64u
+#define RB_W64_TAG_OFF (RB_W64_COST_OFF + RB_WALK64_ORDER_CAP)
+#define RB_W64_HEAVY_OFF (RB_W64_TAG_OFF + RB_WALK64_ORDER_CAP)
+#define RB_W64_ORD_WORDS (RB_W64_HEAVY_OFF + RB_WALK64_HEAVY_MAX)
 inline int rb_n_acc(const rb_ctx *c) { return (c->img_split ? c->n_img : 1) * c->walk_parts; }
 // work units from which the wave-shared FP64 walk beats per-lane walks
 #define RB_WALK64_SHARED_MIN 12288u

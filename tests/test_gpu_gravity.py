@@ -165,6 +165,24 @@ def test_gravity_is_deterministic():
     np.testing.assert_array_equal(a, b)
 
 
+def test_ordered_dispatch_keeps_the_sums():
+    # the 64-part FP64 walk dispatches its costliest units first, by the node
+    # visits of the previous launch: the first call runs in part-major order,
+    # the later ones reordered, and every unit still writes its own
+    # accumulator set, so the forces agree bit for bit
+    from gpu_util import Dev, gravity, make_ctx
+    from paper_1110_4876_amd import rb
+    pr = inputs.sheet(50000, seed=0).with_params(theta=0.26)
+    ctx = make_ctx(pr)
+    try:
+        d = Dev(pr, with_v=False)
+        out = [gravity(ctx, d, pr.n, 0.0) for _ in range(3)]
+    finally:
+        rb.rb_destroy(ctx)
+    np.testing.assert_array_equal(out[0], out[1])
+    np.testing.assert_array_equal(out[0], out[2])
+
+
 @pytest.mark.parametrize("theta,split", [(0.3, 1), (0.3, 0), (0.5, -1)])
 def test_c1_full_size_sampled(orc, theta, split):
     # the 50,000-particle sheet patch at full size: sampled targets of the
