@@ -510,9 +510,10 @@ __global__ __launch_bounds__(64) void k_walk64_lane(
 // records each unit's node visits; before the next launch the units that
 // cost at least the threshold (about the top 1/32, from the costs one
 // launch earlier) are listed to run first, the rest keeping their
-// part-major order.  The
-// order decides only which wave starts first: every unit writes its own
-// accumulator set, so the sums do not depend on it.
+// part-major order.  The order decides only which wave starts first: every
+// unit writes its own accumulator set, so the sums do not depend on it.
+// Launched for at least RB_WALK64_ORDER_MIN units (so a share holds at
+// least 512).
 __global__ __launch_bounds__(1024) void k_w64_list(uint32_t *__restrict__ ord,
                                                    uint32_t n_units) {
   __shared__ uint32_t lh[33];
@@ -527,7 +528,7 @@ __global__ __launch_bounds__(1024) void k_w64_list(uint32_t *__restrict__ ord,
   // unit x q + min(x, r)); a wave's 64 units span at most two shares, and
   // each share's listed units are counted with one atomic per wave
   const uint32_t q = n_units >> 3, r = n_units & 7u;
-  const uint32_t x = u < r * (q + 1u) ? u / (q + 1u) : r + (u - r * (q + 1u)) / q;
+  const uint32_t x = u < r * (q + 1u) ? u / (q + 1u) : q ? r + (u - r * (q + 1u)) / q : 7u;
   uint64_t todo = __ballot(heavy);
   while (todo) {
     const uint32_t xl = (uint32_t)__shfl((int)x, __ffsll((long long)todo) - 1, 64);
