@@ -109,11 +109,23 @@ struct W64Rec {
   double cx, cy, cz, m;
 };
 
+// A node's record.  With OFF32 the byte offsets of the node's records
+// (16 v, 32 v and 48 v for its quadrupole) fit 32 bits, and the scalar
+// loads take them as a register offset to the arrays' base, sparing the
+// 64-bit address arithmetic of every visit.
+template <bool OFF32>
+__device__ __forceinline__ const void *w64_at(const void *base, uint32_t v, uint32_t bytes) {
+  typedef __attribute__((address_space(4))) const char *cbyte;
+  if (OFF32) return (const void *)((cbyte)base + v * bytes);
+  return (const void *)((cbyte)base + (size_t)v * bytes);
+}
+
+template <bool OFF32>
 __device__ __forceinline__ void w64_fetch(w64_u32_p link, w64_dbl_p mcom, uint32_t v,
                                           W64Rec &r) {
-  const w64_u32_p lp = link + 4 * (size_t)v;
+  const w64_u32_p lp = (w64_u32_p)w64_at<OFF32>((const void *)link, v, 16u);
   r.child = lp[0]; r.skip = lp[1]; r.count = lp[2]; r.lvl = lp[3];
-  const w64_dbl_p mp = mcom + 4 * (size_t)v;
+  const w64_dbl_p mp = (w64_dbl_p)w64_at<OFF32>((const void *)mcom, v, 32u);
   r.cx = mp[0]; r.cy = mp[1]; r.cz = mp[2]; r.m = mp[3];
 }
 
@@ -128,7 +140,7 @@ __device__ __forceinline__ uint32_t w64_uniform(uint32_t v) {
 // set-up values out to vector lanes, none of the node loop's, and the extra
 // waves cover more of the node loads' latency (measured 10% faster on the
 // 256-patch ensemble).
-template <bool QUAD, bool STATS, int PD>
+template <bool QUAD, bool STATS, int PD, bool OFF32>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_walk64(
     const WalkItem *__restrict__ items, uint32_t n_items, int img_split, int n_img, int parts,
     int ngx, int ngy, int boundary, const PatchInfo *__restrict__ patch,
@@ -241,7 +253,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
           break;
         }
         W64Rec rc;
-        w64_fetch(link, mcom, v, rc);
+        w64_fetch<OFF32>(link, mcom, v, rc);
         const int l = (int)(rc.lvl & 255u);
         const uint32_t n_child = rc.lvl >> 9;
         const bool owner = depth == 0 ? part == 0 : digit[1] == 0u;
@@ -259,7 +271,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         if (owner) {
           if (STATS && me && root_or_below) ++n_open;
           if (take) {
-            const w64_dbl_p qn = Qarr + 6 * (size_t)v;
+            const w64_dbl_p qn = (w64_dbl_p)w64_at<OFF32>((const void *)Qarr, v, 48u);
             const double q[6] = {qn[0], qn[1], qn[2], qn[3], qn[4], qn[5]};
             w64_cell<QUAD>(G, G * rc.m, q, d0, d1, d2, R2 + b2, ax, ay, az);
             if (STATS) ++n_cell;
@@ -294,7 +306,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     while (cur != stop && max(cur, visits) < n_nodes) {
       ++visits;
       W64Rec rc;
-      w64_fetch(link, mcom, cur, rc);
+      w64_fetch<OFF32>(link, mcom, cur, rc);
       const uint32_t lv = rc.lvl;
       const int l = (int)(lv & 255u);
       const bool leaf = (lv & 256u) != 0;
@@ -329,7 +341,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
           const double u = ri * ri, g = ri * u;
           double e0 = 0.0, e1 = 0.0, e2 = 0.0, dqd = 0.0;
           if (QUAD) {
-            const w64_dbl_p qn = Qarr + 6 * (size_t)cur;
+            const w64_dbl_p qn = (w64_dbl_p)w64_at<OFF32>((const void *)Qarr, cur, 48u);
             const double q0 = qn[0], q1 = qn[1], q2 = qn[2], q3 = qn[3], q4 = qn[4], q5 = qn[5];
             e0 = __builtin_fma(q0, d0, __builtin_fma(q1, d1, q2 * d2));
             e1 = __builtin_fma(q1, d0, __builtin_fma(q3, d1, q4 * d2));
@@ -609,12 +621,16 @@ hipError_t launch_walk64(rb_ctx *c, const double *sx, const double *sy, const do
       c->d_msrc, c->d_sched, c->d_ctr, c->P, c->p.G, b2, th2, c->d_acc, c->cap,           \
       c->d_stats, c->d_lev_off, c->d_err, slot, ord
     const dim3 g(grid), bl(64);
+    // 32-bit byte offsets of the node records (48 bytes for a quadrupole)
+    const bool off32 = c->node_cap * 48ull < (1ull << 32);
 #define RB_W64_LAUNCH(PD)                                                                          \
   do {                                                                                             \
-    if (quad && stats) hipLaunchKernelGGL((k_walk64<true, true, PD>), g, bl, 0, c->stream, RB_WALK64_ARGS);   \
-    else if (quad) hipLaunchKernelGGL((k_walk64<true, false, PD>), g, bl, 0, c->stream, RB_WALK64_ARGS);      \
-    else if (stats) hipLaunchKernelGGL((k_walk64<false, true, PD>), g, bl, 0, c->stream, RB_WALK64_ARGS);     \
-    else hipLaunchKernelGGL((k_walk64<false, false, PD>), g, bl, 0, c->stream, RB_WALK64_ARGS);               \
+    if (quad && stats) hipLaunchKernelGGL((k_walk64<true, true, PD, false>), g, bl, 0, c->stream, RB_WALK64_ARGS); \
+    else if (quad && off32) hipLaunchKernelGGL((k_walk64<true, false, PD, true>), g, bl, 0, c->stream, RB_WALK64_ARGS); \
+    else if (quad) hipLaunchKernelGGL((k_walk64<true, false, PD, false>), g, bl, 0, c->stream, RB_WALK64_ARGS); \
+    else if (stats) hipLaunchKernelGGL((k_walk64<false, true, PD, false>), g, bl, 0, c->stream, RB_WALK64_ARGS); \
+    else if (off32) hipLaunchKernelGGL((k_walk64<false, false, PD, true>), g, bl, 0, c->stream, RB_WALK64_ARGS); \
+    else hipLaunchKernelGGL((k_walk64<false, false, PD, false>), g, bl, 0, c->stream, RB_WALK64_ARGS); \
   } while (0)
     if (parts == 64) RB_W64_LAUNCH(2);
     else if (parts == 8) RB_W64_LAUNCH(1);
