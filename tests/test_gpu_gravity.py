@@ -165,22 +165,35 @@ def test_gravity_is_deterministic():
     np.testing.assert_array_equal(a, b)
 
 
-def test_ordered_dispatch_keeps_the_sums():
+ORDERED_CASES = [
+    ("sheet50k", lambda: inputs.sheet(50000, seed=0).with_params(theta=0.26), 0.0),
+    ("plummer20k", lambda: inputs.plummer(20000, seed=2).with_params(theta=0.4), 0.0),
+    ("sheet10k_two_rings", lambda: inputs.sheet(10000, seed=7, ng=(2, 2)), 300.0),
+]
+
+
+@pytest.mark.parametrize("name,maker,t", ORDERED_CASES, ids=[c[0] for c in ORDERED_CASES])
+def test_ordered_dispatch_keeps_the_sums(orc, name, maker, t):
     # the 64-part FP64 walk dispatches its costliest units first, by the node
     # visits of the previous launch: the first call runs in part-major order,
-    # the later ones reordered, and every unit still writes its own
-    # accumulator set, so the forces agree bit for bit
-    from gpu_util import Dev, gravity, make_ctx
+    # the third reordered, and every unit still writes its own accumulator
+    # set, so the forces agree bit for bit -- with one image (open), nine and
+    # twenty-five -- and the reordered call still meets the oracle
+    from gpu_util import Dev, gravity, make_ctx, rms_rel
     from paper_1110_4876_amd import rb
-    pr = inputs.sheet(50000, seed=0).with_params(theta=0.26)
-    ctx = make_ctx(pr)
+    pr = maker()
+    ctx = make_ctx(pr, split_images=0, walk64_schedule=3)
     try:
         d = Dev(pr, with_v=False)
-        out = [gravity(ctx, d, pr.n, 0.0) for _ in range(3)]
+        out = [gravity(ctx, d, pr.n, t) for _ in range(3)]
     finally:
         rb.rb_destroy(ctx)
     np.testing.assert_array_equal(out[0], out[1])
     np.testing.assert_array_equal(out[0], out[2])
+    p = orc.make_params(**pr.params)
+    tg = inputs.sample_targets(pr.n, 1024, seed=9)
+    ref = orc.bh(p, pr.x, pr.y, pr.z, pr.m, s=orc.shear_offset(p, t), targets=tg)
+    assert rms_rel(out[2][tg], ref) <= TOL_BH, rms_rel(out[2][tg], ref)
 
 
 @pytest.mark.parametrize("theta,split", [(0.3, 1), (0.3, 0), (0.5, -1)])
