@@ -529,6 +529,7 @@ __global__ __launch_bounds__(64) void k_walk64_lane(
 __global__ __launch_bounds__(1024) void k_w64_list(uint32_t *__restrict__ ord,
                                                    uint32_t n_units) {
   __shared__ uint32_t lh[33];
+  __shared__ uint32_t lcnt[8], lbase[8];
   __shared__ uint32_t last;
   W64Ctl *const ctl = (W64Ctl *)ord;
   const uint32_t t = threadIdx.x, lane = t & 63u, u = blockIdx.x * 1024u + t;
@@ -536,32 +537,48 @@ __global__ __launch_bounds__(1024) void k_w64_list(uint32_t *__restrict__ ord,
   const uint32_t v = in ? ord[RB_W64_COST_OFF + u] : 0u;
   const uint32_t e = ctl->epoch;
   const bool heavy = in && v >= ctl->thr;
+  if (t < 33u) lh[t] = 0u;
+  if (t < 8u) lcnt[t] = 0u;
+  __syncthreads();
   // the XCD share of the walk's grid the unit belongs to (share x starts at
-  // unit x q + min(x, r)); a wave's 64 units span at most two shares, and
-  // each share's listed units are counted with one atomic per wave
+  // unit x q + min(x, r)); a wave's 64 units span at most two shares.  Each
+  // wave takes its listed units' places in the block's count of each share
+  // (one LDS atomic per wave and share), and the block then reserves its
+  // places in the share's list with one atomic per share.
   const uint32_t q = n_units >> 3, r = n_units & 7u;
   const uint32_t x = u < r * (q + 1u) ? u / (q + 1u) : q ? r + (u - r * (q + 1u)) / q : 7u;
+  uint32_t k = 0;
   uint64_t todo = __ballot(heavy);
   while (todo) {
     const uint32_t xl = (uint32_t)__shfl((int)x, __ffsll((long long)todo) - 1, 64);
     const uint64_t mine = __ballot(heavy && x == xl);
     uint32_t base = 0;
     if (lane == (uint32_t)(__ffsll((long long)mine) - 1))
-      base = atomicAdd(&ctl->cnt[e & 1u][xl], (uint32_t)__popcll(mine));
+      base = atomicAdd(&lcnt[xl], (uint32_t)__popcll(mine));
     base = (uint32_t)__shfl((int)base, __ffsll((long long)mine) - 1, 64);
-    if (heavy && x == xl) {
-      const uint32_t k = base + (uint32_t)__popcll(mine & ((1ull << lane) - 1ull));
-      if (k < RB_WALK64_HEAVY_MAX / 8u) {
-        ord[RB_W64_HEAVY_OFF + xl * (RB_WALK64_HEAVY_MAX / 8u) + k] = u;
-        ord[RB_W64_TAG_OFF + u] = e;
-      }
-    }
+    if (heavy && x == xl) k = base + (uint32_t)__popcll(mine & ((1ull << lane) - 1ull));
     todo &= ~mine;
   }
-  // the costs by bit length, block by block into the launch's histogram
-  if (t < 33u) lh[t] = 0u;
   __syncthreads();
-  if (in) atomicAdd(&lh[v ? 32 - __clz(v) : 0], 1u);
+  if (t < 8u && lcnt[t] != 0u) lbase[t] = atomicAdd(&ctl->cnt[e & 1u][t], lcnt[t]);
+  __syncthreads();
+  if (heavy) {
+    k += lbase[x];
+    if (k < RB_WALK64_HEAVY_MAX / 8u) {
+      ord[RB_W64_HEAVY_OFF + x * (RB_WALK64_HEAVY_MAX / 8u) + k] = u;
+      ord[RB_W64_TAG_OFF + u] = e;
+    }
+  }
+  // the costs by bit length, block by block into the launch's histogram
+  // (one LDS atomic per wave and bit length present)
+  const uint32_t bl = v ? 32u - (uint32_t)__clz(v) : 0u;
+  uint64_t hm = __ballot(in);
+  while (hm) {
+    const uint32_t bb = (uint32_t)__shfl((int)bl, __ffsll((long long)hm) - 1, 64);
+    const uint64_t m = __ballot(in && bl == bb);
+    if (lane == (uint32_t)(__ffsll((long long)m) - 1)) atomicAdd(&lh[bb], (uint32_t)__popcll(m));
+    hm &= ~m;
+  }
   __syncthreads();
   if (t < 33u && lh[t] != 0u) atomicAdd(&ctl->hist[t], lh[t]);
   __threadfence();
@@ -586,7 +603,7 @@ __global__ __launch_bounds__(1024) void k_w64_list(uint32_t *__restrict__ ord,
     ctl->thr = thr;
     ctl->cur = e;
     ctl->epoch = e + 1u;
-    for (int k = 0; k < 8; ++k) ctl->cnt[(e + 1u) & 1u][k] = 0u;
+    for (int j = 0; j < 8; ++j) ctl->cnt[(e + 1u) & 1u][j] = 0u;
     ctl->done = 0u;
   }
 }
