@@ -592,7 +592,7 @@ def main():
         build_traffic(args)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     steps_d, warm_d = DEFAULT_STEPS[args.workload]
