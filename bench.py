@@ -169,8 +169,14 @@ def write_traffic(args):
     c_f = values(cf, "FETCH_SIZE", "copyBuffer")
     c_w = values(cw, "WRITE_SIZE", "copyBuffer")
     kname = walk_kernel_name(path, args.walk_waves)
-    # the timed launches only: quadrupole on, interaction counters off
-    full = kname + ("<true, false>" if kname != "k_walk32m" else f"<true, false, {args.walk_waves}>")
+    # the timed launches only: quadrupole on, interaction counters off (the
+    # FP64 walk's name goes on with its schedule and record addressing)
+    if kname == "k_walk64":
+        full = "k_walk64<true, false, "
+    elif kname == "k_walk32m":
+        full = f"k_walk32m<true, false, {args.walk_waves}>"
+    else:
+        full = "k_walk32<true, false>"
     w_f = values(wf, "FETCH_SIZE", full)
     w_w = values(ww, "WRITE_SIZE", full)
     mean = lambda v: sum(v) / len(v)
@@ -179,11 +185,13 @@ def write_traffic(args):
     med = lambda v: sorted(v)[len(v) // 2]
     fs = copy_bytes / 1024 / mean(c_f)
     ws = copy_bytes / 1024 / mean(c_w)
+    knobs = {"theta": args.theta, "leaf_size": args.leaf_size,
+             "group_size": args.group_size, "split_images": args.split_images,
+             "walk_waves": args.walk_waves}
+    if path == "fp64":  # no groups or waves per item
+        knobs["group_size"], knobs["walk_waves"] = None, None
     meta = {
-        "kernel": kname, "workload": args.workload,
-        "knobs": {"theta": args.theta, "leaf_size": args.leaf_size,
-                  "group_size": args.group_size, "split_images": args.split_images,
-                  "walk_waves": args.walk_waves},
+        "kernel": kname, "workload": args.workload, "knobs": knobs,
         "sources": list(WALK_SRC[path]), "source_sha256": walk_source_sha(path),
         "kernel_instance": full,
         "fetch_kib_per_dispatch_raw": med(w_f), "write_kib_per_dispatch_raw": med(w_w),
@@ -854,12 +862,20 @@ def gravity_run(args, sysm, wdesc):
     tf = os.path.join(ROOT, "profiles", f"walk_{main_path}_{args.workload}_traffic.json")
     # only for the same kernel sources at the same operating point
     knobs = {k: r[k] for k in KNOBS}
-    if main_path == "fp64":
-        knobs["group_size"], knobs["walk_waves"] = 64, 1
     for meta in traffic_entries(tf):
         if (meta.get("source_sha256") == walk_source_sha(main_path) and
                 meta.get("knobs") == knobs):
             traffic = meta.get("bytes_per_launch")
+    traffic64 = None
+    if "fp64" in results:
+        knobs64 = {k: results["fp64"][k] for k in KNOBS}
+        tf64 = os.path.join(ROOT, "profiles", f"walk_fp64_{args.workload}_traffic.json")
+        for meta in traffic_entries(tf64):
+            if (meta.get("source_sha256") == walk_source_sha("fp64") and
+                    meta.get("knobs") == knobs64):
+                traffic64 = meta.get("bytes_per_launch")
+    if main_path == "fp64":
+        traffic = traffic64
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                 "kernel": walk_kernel_name(main_path, r["walk_waves"])}
@@ -867,7 +883,7 @@ def gravity_run(args, sysm, wdesc):
         r64 = results["fp64"]
         a64 = r64["algorithmic_flops_per_walk"] / (r64["walk_ms"] * 1e-3)
         r64["roofline"] = {"bound": "alu", "achieved": a64 / 1e12, "peak": PEAK_F64 / 1e12,
-                           "unit": "TFLOP/s", "frac": a64 / PEAK_F64,
+                           "unit": "TFLOP/s", "frac": a64 / PEAK_F64, "traffic": traffic64,
                            "kernel": walk_kernel_name("fp64", 1)}
 
     cpu = None
