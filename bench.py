@@ -143,12 +143,13 @@ def walk_kernel_name(path, walk_waves):
     return "k_walk32m" if walk_waves and walk_waves > 1 else "k_walk32"
 
 
-def write_traffic(args):
+def write_traffic(args, out_dir=None):
     """Turn four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE, KiB per
     dispatch, for a plain device copy of known size and for the walk at the
     operating point given by the knob options) into HBM bytes per walk
     launch: each walk counter is scaled by true bytes / counter reading of
-    the copy.  Writes profiles/walk_<path>_<workload>_traffic.json."""
+    the copy.  Writes walk_<path>_<workload>_traffic.json in out_dir
+    (profiles/ by default) and returns the entry."""
     import csv
     import glob
 
@@ -203,7 +204,8 @@ def write_traffic(args):
         "dispatches": len(w_f),
     }
     meta["bytes_per_launch"] = meta["fetch_bytes_per_launch"] + meta["write_bytes_per_launch"]
-    out = os.path.join(ROOT, "profiles", f"walk_{path}_{args.workload}_traffic.json")
+    out = os.path.join(out_dir or os.path.join(ROOT, "profiles"),
+                       f"walk_{path}_{args.workload}_traffic.json")
     # one entry per operating point: a new measurement replaces the entry of
     # the same knobs
     entries = traffic_entries(out)
@@ -211,6 +213,7 @@ def write_traffic(args):
     with open(out, "w") as fh:
         json.dump({"entries": entries}, fh, indent=1)
     print(json.dumps(meta))
+    return meta
 
 
 def traffic_entries(path):
